@@ -1,0 +1,136 @@
+"""Synthetic workloads for the axisymmetric two-layer PML-BIE problem.
+
+This module holds input data only: wavenumbers, interface shapes, PML
+parameters, discretisation sizes and incidences, plus the seeded draws for
+the randomised shapes.  It contains none of the method's arithmetic, so both
+the oracle and the HIP path may import it.
+
+Interface family (shared by every workload): a graph z = h~(rho) with
+
+    h(rho)  = [sum_i a_i exp(-((rho - c_i)/w_i)^2)] * (cos(f rho) if f else 1)
+    h~(rho) = h(rho) - h(a1)  for rho < a1,   0 for rho >= a1,
+
+so the curve is continuous at the start of the PML (rho = a1) and flat inside
+it.  The generating curve runs from the axis (rho = 0) to the outer PML edge
+rho = a1 + T and is cut into four segments [0, a1/2], [a1/2, a1],
+[a1, a1 + T/2], [a1 + T/2, a1 + T]; each segment holds `nodes_per_segment`
+Gauss-Legendre nodes in sub-panels of 16.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Tuple
+
+import numpy as np
+
+PANEL_NODES = 16
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    k1: complex
+    k2: complex
+    bumps: Tuple[Tuple[float, float, float], ...]  # (amplitude, centre, width)
+    cos_freq: float
+    a1: float
+    T: float
+    S: float
+    a2: float
+    T2: float
+    S2: float
+    p: int
+    nodes_per_segment: int
+    n_theta: int
+    # incidences: ("point", rho*, z*) or ("plane", phi_inc)
+    incidences: Tuple[Tuple, ...] = field(default_factory=tuple)
+
+    @property
+    def m_max(self) -> int:
+        return self.n_theta // 4
+
+    @property
+    def n_sub(self) -> int:
+        assert self.nodes_per_segment % PANEL_NODES == 0
+        return self.nodes_per_segment // PANEL_NODES
+
+    @property
+    def seg_breaks(self) -> List[float]:
+        a1, T = self.a1, self.T
+        return [0.0, 0.5 * a1, a1, a1 + 0.5 * T, a1 + T]
+
+    @property
+    def n_nodes(self) -> int:
+        return 4 * self.nodes_per_segment
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def small() -> Workload:
+    """Plain FP64, small: k1 = 2 pi, k2 = 3 pi, h = 0.3 exp(-rho^2), PML
+    rho in [2, 3], sigma0 = 2, 64 nodes per segment, 64 theta samples,
+    point source on the axis at (0, 0, 1)."""
+    return Workload(
+        name="small",
+        k1=2 * math.pi, k2=3 * math.pi,
+        bumps=((0.3, 0.0, 1.0),), cos_freq=0.0,
+        a1=2.0, T=1.0, S=2.0, a2=2.0, T2=1.0, S2=2.0, p=6,
+        nodes_per_segment=64, n_theta=64,
+        incidences=(("point", 0.0, 1.0),),
+    )
+
+
+def paper_scale() -> Workload:
+    """Plain FP64 at paper scale: k1 = 10, k2 = 15,
+    h = 0.5 exp(-rho^2/2) cos(2 rho), PML rho in [4, 5.5], sigma0 = 3,
+    512 nodes per segment (2048 nodes, 4096 unknowns per mode), 256 theta
+    samples (modes -128..128), point source at (0.3, 0, 1.2)."""
+    return Workload(
+        name="paper_scale",
+        k1=10.0, k2=15.0,
+        bumps=((0.5, 0.0, math.sqrt(2.0)),), cos_freq=2.0,
+        a1=4.0, T=1.5, S=3.0, a2=3.0, T2=1.5, S2=3.0, p=6,
+        nodes_per_segment=512, n_theta=256,
+        incidences=(("point", 0.3, 1.2),),
+    )
+
+
+def largest(seed: int = 11162) -> Workload:
+    """Largest one-GPU case: k1 = 20, k2 = 30, three Gaussian ring bumps with
+    amplitudes U[0.2, 0.5], centres U[0, 3], widths U[0.5, 2]; PML
+    rho in [5, 7], sigma0 = 3; 1024 nodes per segment, 512 theta samples,
+    16 plane waves with polar angles (pi/3) i / 15."""
+    rng = np.random.default_rng(seed)
+    amps = rng.uniform(0.2, 0.5, 3)
+    cents = rng.uniform(0.0, 3.0, 3)
+    widths = rng.uniform(0.5, 2.0, 3)
+    bumps = tuple((float(a), float(c), float(w)) for a, c, w in zip(amps, cents, widths))
+    incs = tuple(("plane", math.pi / 3 * i / 15) for i in range(16))
+    return Workload(
+        name="largest",
+        k1=20.0, k2=30.0, bumps=bumps, cos_freq=0.0,
+        a1=5.0, T=2.0, S=3.0, a2=4.0, T2=2.0, S2=3.0, p=6,
+        nodes_per_segment=1024, n_theta=512, incidences=incs,
+    )
+
+
+def tiny(nodes_per_segment: int = 16, n_theta: int = 32, **kw) -> Workload:
+    """A reduced version of the small workload (used for oracle-vs-kernel
+    parity on the CPU side and for fast end-to-end checks)."""
+    w = small().with_(name="tiny", nodes_per_segment=nodes_per_segment, n_theta=n_theta)
+    return w.with_(**kw) if kw else w
+
+
+ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny}
+
+
+def seeded_pairs(n_nodes: int, count: int, seed: int) -> np.ndarray:
+    """Seeded (target, source) index pairs with target != source."""
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, n_nodes, count)
+    j = rng.integers(0, n_nodes - 1, count)
+    j = np.where(j >= i, j + 1, j)
+    return np.stack([i, j], axis=1).astype(np.int64)
