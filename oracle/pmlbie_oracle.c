@@ -57,11 +57,13 @@ static const double WG[4] = {
 
 typedef void (*vfun)(double x, void *ctx, cplx *out);
 
-/* One GK15 panel: kronrod result in res, max |K - G| returned. */
+/* One GK15 panel: kronrod result in res, max |K - G| returned, and in
+   *absint the largest Kronrod estimate of int |f_j| (the rounding floor). */
 static double gk15(vfun f, void *ctx, int nout, double a, double b, cplx *res,
-                   cplx *tmp, cplx *gsum) {
+                   cplx *tmp, cplx *gsum, double *absint) {
   double c = 0.5 * (a + b), h = 0.5 * (b - a);
   for (int j = 0; j < nout; ++j) { res[j] = 0; gsum[j] = 0; }
+  double amax = 0.0;
   for (int q = 0; q < 15; ++q) {
     int idx = q < 8 ? q : 14 - q;
     double x = q < 8 ? c - h * XGK[q] : c + h * XGK[14 - q];
@@ -72,8 +74,11 @@ static double gk15(vfun f, void *ctx, int nout, double a, double b, cplx *res,
     for (int j = 0; j < nout; ++j) {
       res[j] += wk * tmp[j];
       if (wg != 0.0) gsum[j] += wg * tmp[j];
+      double m = wk * cabs(tmp[j]);
+      if (m > amax) amax = m;
     }
   }
+  *absint = amax * h;
   double err = 0;
   for (int j = 0; j < nout; ++j) {
     res[j] *= h;
@@ -84,12 +89,14 @@ static double gk15(vfun f, void *ctx, int nout, double a, double b, cplx *res,
   return err;
 }
 
-typedef struct { double a, b, err; int depth; } ivl;
+typedef struct { double a, b, err, absint; int depth; } ivl;
 
 /*
  * Globally adaptive vector quadrature: keep bisecting the interval with the
  * largest error estimate until the summed estimate is below
- * max(abstol, reltol * max_j |I_j|) or the interval budget is spent.
+ * max(abstol, reltol * max_j |I_j|, 1e-15 * int |f|) -- the last term is the
+ * rounding floor below which no quadrature of f can resolve the integral --
+ * or the interval budget is spent.
  * Returns the number of intervals used (negative if the budget ran out).
  */
 static int adapt(vfun f, void *ctx, int nout, const double *brk, int nbrk,
@@ -102,31 +109,32 @@ static int adapt(vfun f, void *ctx, int nout, const double *brk, int nbrk,
   for (int s = 0; s + 1 < nbrk; ++s) {
     if (!(brk[s + 1] > brk[s])) continue;
     iv[n].a = brk[s]; iv[n].b = brk[s + 1]; iv[n].depth = 0;
-    iv[n].err = gk15(f, ctx, nout, brk[s], brk[s + 1], store + (size_t)n * nout, tmp, gs);
+    iv[n].err = gk15(f, ctx, nout, brk[s], brk[s + 1], store + (size_t)n * nout, tmp, gs, &iv[n].absint);
     ++n;
   }
   int ok = 1;
   for (;;) {
-    double tot = 0, scale = 0;
+    double tot = 0, scale = 0, absint = 0;
     int worst = -1;
     double werr = -1;
     for (int j = 0; j < nout; ++j) result[j] = 0;
     for (int s = 0; s < n; ++s) {
       tot += iv[s].err;
+      absint += iv[s].absint;
       if (iv[s].err > werr && iv[s].depth < 200) { werr = iv[s].err; worst = s; }
       cplx *r = store + (size_t)s * nout;
       for (int j = 0; j < nout; ++j) result[j] += r[j];
     }
     for (int j = 0; j < nout; ++j) { double m = cabs(result[j]); if (m > scale) scale = m; }
-    double tol = fmax(abstol, reltol * scale);
+    double tol = fmax(abstol, fmax(reltol * scale, 1e-15 * absint));
     if (tot <= tol || worst < 0) break;
     if (n + 1 >= maxivl) { ok = 0; break; }
     double a = iv[worst].a, b = iv[worst].b, m = 0.5 * (a + b);
     int d = iv[worst].depth + 1;
     iv[worst].b = m; iv[worst].depth = d;
-    iv[worst].err = gk15(f, ctx, nout, a, m, store + (size_t)worst * nout, tmp, gs);
+    iv[worst].err = gk15(f, ctx, nout, a, m, store + (size_t)worst * nout, tmp, gs, &iv[worst].absint);
     iv[n].a = m; iv[n].b = b; iv[n].depth = d;
-    iv[n].err = gk15(f, ctx, nout, m, b, store + (size_t)n * nout, tmp, gs);
+    iv[n].err = gk15(f, ctx, nout, m, b, store + (size_t)n * nout, tmp, gs, &iv[n].absint);
     ++n;
   }
   free(iv); free(store); free(tmp);
