@@ -1,0 +1,164 @@
+/*
+ * pmlbie: FFT-accelerated PML boundary-integral solver for axisymmetric
+ * two-layer acoustic scattering on one MI355X (gfx950).  C ABI.
+ *
+ * The method is that of Wang & Lu, "An FFT-accelerated PML-BIE solver for
+ * three-dimensional acoustic wave scattering in layered media"
+ * (arXiv 2412.11162):
+ *   - problem: two homogeneous media separated by the axisymmetric interface
+ *     z = h~(rho), Helmholtz equation with wavenumbers k1 (upper) and k2
+ *     (lower), continuity of u and du/dnu across the interface (Sec. 2);
+ *   - cylindrical PML by complex stretching rho~ = rho + i int sigma_1
+ *     (Sec. 3.1, eqs. eqrhot, eqsgm1), truncation of the interface at the
+ *     outer PML edge rho = a1 + T (Sec. 3.2);
+ *   - azimuthal Fourier decomposition into decoupled per-mode curve integral
+ *     equations (Sec. 3.3); per-mode coupled system of the two media with the
+ *     transmission conditions (Sec. 4.2).
+ *
+ * Conventions
+ *   - Every call returns PMLBIE_OK (0) or a negative status; nothing throws
+ *     or aborts across the ABI.  pmlbie_last_error() describes the last
+ *     failure of a context.
+ *   - Calls run in order: set_geometry -> set_media_pml ->
+ *     build_modal_operators -> solve_modes -> evaluate_field; a call out of
+ *     order returns PMLBIE_ESTATE.  Changing geometry or media invalidates
+ *     later stages.
+ *   - Complex arrays are interleaved (re, im) doubles.  "device" pointers are
+ *     HIP device memory on the context's device (for example the data of a
+ *     PyTorch tensor); "host" pointers are ordinary memory.
+ *   - All work is ordered on the stream given to pmlbie_create; every call is
+ *     synchronous on return.  A context is used by one host thread at a time.
+ *   - Modes are natural: F_n = int_{-pi}^{pi} e^{-i n theta} F dtheta, which
+ *     is sqrt(2 pi) times the paper's normalised mode (Sec. 3.3, eq. fmode1);
+ *     only n = 0..m_max are stored since every quantity here is even in n.
+ *   - The context owns all internal device buffers (operators, factors,
+ *     work lists).  Output buffers belong to the caller.
+ */
+#ifndef PMLBIE_H
+#define PMLBIE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmlbie_ctx pmlbie_ctx;
+
+enum {
+  PMLBIE_OK = 0,
+  PMLBIE_EINVAL = -1,    /* bad argument */
+  PMLBIE_ESTATE = -2,    /* call out of order */
+  PMLBIE_ENOMEM = -3,    /* device allocation failed */
+  PMLBIE_EDEVICE = -4,   /* HIP runtime error */
+  PMLBIE_ESINGULAR = -5, /* exactly singular mode matrix (zero pivot) */
+  PMLBIE_ENOCONV = -6    /* iterative refinement did not converge */
+};
+
+enum { PMLBIE_FP64 = 0, PMLBIE_MIXED = 1 };
+enum { PMLBIE_KEEP_OPERATORS = 1 };
+
+/* Create a context on HIP device `device`, ordering work on `stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context. */
+int pmlbie_create(pmlbie_ctx** out, int device, void* stream);
+void pmlbie_destroy(pmlbie_ctx* ctx);
+const char* pmlbie_last_error(const pmlbie_ctx* ctx);
+
+/* Generating curve (Sec. 2, Sec. 4): the graph z = h~(rho) of
+ *   h(rho) = [sum_i a_i exp(-((rho - c_i)/w_i)^2)] * (cos(f rho) if f != 0),
+ *   h~ = h - h(rho_c) for rho < rho_c and 0 beyond (flat where the PML acts),
+ * from the axis to rho = seg_breaks[4].  bumps: host, 3*n_bumps doubles
+ * (a_i, c_i, w_i); seg_breaks: host, 5 increasing rho values with
+ * seg_breaks[0] = 0; each of the four segments carries nodes_per_segment
+ * Gauss-Legendre nodes in equal sub-panels of 16 (a positive multiple of 16).
+ * N = 4 * nodes_per_segment nodes; node i lies on panel i / 16.
+ * Errors: PMLBIE_EINVAL for n_bumps outside [0, 8], non-positive widths,
+ * non-increasing breaks, nodes_per_segment not a multiple of 16. */
+int pmlbie_set_geometry(pmlbie_ctx* ctx, int n_bumps, const double* bumps, double cos_freq,
+                        double rho_c, const double* seg_breaks, int nodes_per_segment);
+
+/* Media and PML (Sec. 2, Sec. 3.1 eq. eqsgm1): wavenumbers k1 (upper medium),
+ * k2 (lower medium), real or complex; radial PML from a1 with thickness T and
+ * strength S; axial PML (a2, T2, S2), which never meets the curve; profile
+ * order p >= 2.  The curve must end at the outer PML edge a1 + T.
+ * Errors: PMLBIE_EINVAL (T <= 0, a1 <= 0, S < 0, p < 2, curve end != a1 + T),
+ * PMLBIE_ESTATE (no geometry). */
+int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_re,
+                         double k2_im, double a1, double T, double S, double a2, double T2,
+                         double S2, int p);
+
+/* Build the modal operators of modes n = 0..m_max with m_max = n_theta / 4
+ * (n_theta azimuthal samples, a power of two >= 16), assemble the per-mode
+ * 2N x 2N systems [[K1 + I, -S1], [K2 - I, -S2]] (Sec. 4.1-4.2) and factor
+ * them (partial-pivoting LU).  The kernels are sampled on every
+ * (target, source, theta) triple, split into singular and smooth parts where
+ * needed (Sec. 4.1) and turned into modes by batched FFTs.
+ * precision: PMLBIE_FP64 (complex128 throughout) or PMLBIE_MIXED
+ * (complex64 LU with FP64 iterative refinement in solve_modes).
+ * flags: PMLBIE_KEEP_OPERATORS keeps a copy of the assembled matrices for
+ * pmlbie_get_operator.
+ * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOMEM, PMLBIE_EDEVICE,
+ * PMLBIE_ESINGULAR (a zero pivot; pmlbie_last_error names the mode). */
+int pmlbie_build_modal_operators(pmlbie_ctx* ctx, int n_theta, int precision, int flags);
+
+/* One incidence: kind 0 = point source at (rho, 0, z) = (p[0], p[1]) in the
+ * upper medium (p[0] >= 0); kind 1 = plane wave with polar angle p[0]
+ * (theta_inc = 0) (Sec. 2). */
+typedef struct {
+  int kind;
+  double p[3];
+} pmlbie_incidence;
+
+/* Solve the coupled systems of all modes for n_rhs incidences (host array,
+ * 1 <= n_rhs <= 16).  Outputs are device buffers of (m_max+1)*n_rhs*N
+ * complex128, layout [mode][rhs][node]: u1 = scattered field of the upper
+ * medium on the curve, phi1 = its conormal derivative, u2, phi2 the same for
+ * the lower medium (u2 = u1 - b1, phi2 = phi1 - b2 by the transmission
+ * conditions).  Any output pointer may be NULL.
+ * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOCONV (mixed precision). */
+int pmlbie_solve_modes(pmlbie_ctx* ctx, int n_rhs, const pmlbie_incidence* inc, void* d_u1,
+                       void* d_phi1, void* d_u2, void* d_phi2);
+
+/* Scattered field at n_pts points (host array rtz of (rho, theta, z)
+ * triples, physical region, at least one panel length away from the
+ * curve), by the Green representation of each medium (Sec. 4.2, eq.
+ * eqfujs) and the modal synthesis.  out: host array, n_rhs * n_pts
+ * complex128, layout [rhs][point].  n_pts = 0 is allowed. */
+int pmlbie_evaluate_field(pmlbie_ctx* ctx, int n_pts, const double* rtz, double* out);
+
+/* ---- inspection ---------------------------------------------------------- */
+
+/* Sizes of the current build: info[0] = N, [1] = m_max, [2] = internal FFT
+ * length of the split, [3] = FFT length of the far path, [4] = far pairs,
+ * [5] = split pairs, [6] = direct pairs, [7] = auxiliary near-panel points,
+ * [8] = convolution half-width. */
+int pmlbie_get_info(const pmlbie_ctx* ctx, long long* info /* host, 9 */);
+
+/* Node table (host output, N x 13 doubles per node): rho, Im rho~, z,
+ * Re n_rho, Im n_rho, Re n_z, Im n_z, W (quadrature weight times rho |dr/dt|),
+ * panel, t, nu_rho, nu_z, |dr/dt|. */
+int pmlbie_get_nodes(const pmlbie_ctx* ctx, double* out);
+
+/* Modal kernels S_n, K_n (natural modes, n = 0..m_max, both media) of
+ * n_pairs explicit point pairs with the machinery of the build (pair
+ * classification, FFT, split, graded quadrature).  geom: host, 12 doubles
+ * per pair: rho~_t, rho~_s, rho~_t - rho~_s, z~_t - z~_s, n_rho, n_z of the
+ * source (each complex as re, im).  out: device, n_pairs * 4 * (m_max+1)
+ * complex128, layout [pair][S1, K1, S2, K2][mode]. */
+int pmlbie_modal_kernels(pmlbie_ctx* ctx, int n_pairs, const double* geom, void* d_out);
+
+/* Copy the assembled (unfactored) matrix of mode n (column-major 2N x 2N
+ * complex128) to d_out; needs PMLBIE_KEEP_OPERATORS at build. */
+int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
+
+/* Stage wall-clock times of the last build/solve in ms (host, 16 doubles):
+ * [0] setup, [1] far kernels, [2] split, [3] direct, [4] near panels,
+ * [5] LU total, [6] LU trailing updates, [7] solve total, [8] right-hand
+ * sides, [9] refinement, [10] build total; and counters (host, 16 doubles):
+ * [0] refinement iterations, [1] final relative residual. */
+int pmlbie_get_stats(const pmlbie_ctx* ctx, double* stage_ms, double* counters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMLBIE_H */

@@ -1,0 +1,67 @@
+"""ctypes binding of libpmlbie.so: the C ABI declared in include/pmlbie.h,
+same names, argument marshalling only."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmlbie.so")
+
+PMLBIE_OK = 0
+PMLBIE_EINVAL = -1
+PMLBIE_ESTATE = -2
+PMLBIE_ENOMEM = -3
+PMLBIE_EDEVICE = -4
+PMLBIE_ESINGULAR = -5
+PMLBIE_ENOCONV = -6
+PMLBIE_FP64 = 0
+PMLBIE_MIXED = 1
+PMLBIE_KEEP_OPERATORS = 1
+
+EXPORTS = (
+    "pmlbie_create", "pmlbie_destroy", "pmlbie_last_error", "pmlbie_set_geometry",
+    "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_solve_modes",
+    "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
+    "pmlbie_get_operator", "pmlbie_get_stats",
+)
+
+
+class pmlbie_incidence(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library; fails loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpmlbie.so is not built (run paper_2412_11162_amd/build.py or "
+                           "__graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.pmlbie_create.argtypes = [ctypes.POINTER(P), i, P]
+    L.pmlbie_destroy.argtypes = [P]
+    L.pmlbie_destroy.restype = None
+    L.pmlbie_last_error.argtypes = [P]
+    L.pmlbie_last_error.restype = ctypes.c_char_p
+    L.pmlbie_set_geometry.argtypes = [P, i, P, d, d, P, i]
+    L.pmlbie_set_media_pml.argtypes = [P, d, d, d, d, d, d, d, d, d, d, i]
+    L.pmlbie_build_modal_operators.argtypes = [P, i, i, i]
+    L.pmlbie_solve_modes.argtypes = [P, i, ctypes.POINTER(pmlbie_incidence), P, P, P, P]
+    L.pmlbie_evaluate_field.argtypes = [P, i, P, P]
+    L.pmlbie_get_info.argtypes = [P, P]
+    L.pmlbie_get_nodes.argtypes = [P, P]
+    L.pmlbie_modal_kernels.argtypes = [P, i, P, P]
+    L.pmlbie_get_operator.argtypes = [P, i, P]
+    L.pmlbie_get_stats.argtypes = [P, P, P]
+    for name in EXPORTS:
+        if name not in ("pmlbie_destroy", "pmlbie_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L

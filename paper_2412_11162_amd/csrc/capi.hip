@@ -1,0 +1,665 @@
+// C ABI of the solver: context, argument checks, orchestration of the HIP
+// kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pmlbie.h"
+#include "host_geom.h"
+#include "lu.h"
+#include "modal.h"
+#include "solve.h"
+
+using namespace pmlbie;
+
+namespace {
+
+struct DevErr : std::runtime_error {
+  int code;
+  DevErr(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw DevErr(e_ == hipErrorOutOfMemory ? PMLBIE_ENOMEM : PMLBIE_EDEVICE,          \
+                   std::string(#x) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    HIPCHK(hipMalloc((void**)&p, count * sizeof(T)));
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DBuf() { release(); }
+};
+
+}  // namespace
+
+struct pmlbie_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int stage = 0;  // 0 created, 1 geometry, 2 media, 3 built, 4 solved
+  Geometry geo;
+  zd k1{0, 0}, k2{0, 0};
+  double a2 = 0, T2 = 0, S2 = 0;
+  // build parameters
+  int n_theta = 0, M = 0, nt_int = 0, nt_far = 0, B = 0, MQ = 0, precision = 0, flags = 0;
+  int N = 0;
+  ClassParams cp{};
+  long long cnt_far = 0, cnt_split = 0, cnt_direct = 0, cnt_aux = 0;
+  // device data
+  DBuf<double> nodes;  // 8 N doubles: rho, I, z, W, nr_re, nr_im, nz_re, nz_im
+  DBuf<int> dpanel;
+  DBuf<zd> tw_far, tw_int;
+  DBuf<double> glx, glw;
+  DBuf<zd> A, Alow, Akeep;
+  DBuf<int> ipiv, info;
+  DBuf<PairGeom> lgeom;
+  DBuf<int2> ldest;
+  DBuf<unsigned> lcount;
+  DBuf<zd> zhat, phat, qscr;
+  DBuf<zd> raw;
+  DBuf<PairGeom> xgeom;
+  DBuf<int2> xdest;
+  DBuf<double> coef;
+  DBuf<NearJob> jobs;
+  // solution of the last solve
+  int nrhs = 0;
+  DBuf<zd> b1, b2, x, u1, p1, u2, p2;
+  double stage_ms[16] = {0};
+  double counters[16] = {0};
+};
+
+namespace {
+
+const double kOmegaPiece = 16.0;
+
+int fail(pmlbie_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+template <typename F>
+int guarded(pmlbie_ctx* c, F&& f) {
+  if (!c) return PMLBIE_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    return f();
+  } catch (const DevErr& e) {
+    return fail(c, e.code, e.what());
+  } catch (const std::invalid_argument& e) {
+    return fail(c, PMLBIE_EINVAL, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(c, PMLBIE_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, PMLBIE_EDEVICE, e.what());
+  }
+}
+
+struct Timer {
+  hipStream_t st;
+  hipEvent_t a, b;
+  explicit Timer(hipStream_t s) : st(s) {
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, st));
+  }
+  double stop() {
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+int classify_host(const PairGeom& g, const ClassParams& cp, bool allow_far) {
+  PairInv v = pair_invariants(g);
+  double delta, re0;
+  singularity(v, delta, re0);
+  const double sc = sqrt(cabs_(g.rt * g.rs));
+  const double bw = cp.bw * cp.kmax * sc;
+  if (allow_far && (cp.nt_far - cp.M - bw) * delta >= cp.c_far) return CLASS_FAR;
+  zd Rpi = csqrt_(v.d2 + v.c4);
+  double grow = cp.kmax * fabs(Rpi.im) + cp.kmax_im * fabs(Rpi.re);
+  return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
+}
+
+// Split-path work on a device list [first, first+count): phase 1 (singular
+// modes) in chunks, phase 2 (smooth FFTs + convolution).
+void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count, zd* A, long n2,
+               long ms, const double* W, zd* raw) {
+  const long CH = 1L << 15;
+  for (long f = 0; f < count; f += CH) {
+    const long cn = std::min(CH, count - f);
+    c->zhat.alloc((size_t)CH * (c->MQ + 1));
+    c->phat.alloc((size_t)CH * (c->MQ + 1));
+    c->qscr.alloc((size_t)CH * (c->MQ + 1));
+    launch_split_singular(geom, f, cn, c->MQ, c->zhat.p, c->phat.p, c->qscr.p, c->stream);
+    HIPCHK(hipGetLastError());
+    launch_split(c->nt_int, geom, dest, f, cn, c->M, c->B, c->MQ, c->k1, c->k2, c->tw_int.p,
+                 c->zhat.p, c->phat.p, A, n2, ms, W, raw, c->stream);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+// Explicit pair list (host) -> raw modal values raw[dest.x][s][n].
+void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long long* counts) {
+  std::vector<PairGeom> gs[3];
+  std::vector<int2> ds[3];
+  for (size_t q = 0; q < g.size(); ++q) {
+    int cls = classify_host(g[q], c->cp, true);
+    gs[cls].push_back(g[q]);
+    ds[cls].push_back(make_int2((int)q, -1));
+  }
+  size_t tot = g.size();
+  c->xgeom.alloc(std::max<size_t>(tot, 1));
+  c->xdest.alloc(std::max<size_t>(tot, 1));
+  size_t off[3] = {0, gs[0].size(), gs[0].size() + gs[1].size()};
+  for (int k = 0; k < 3; ++k) {
+    if (gs[k].empty()) continue;
+    HIPCHK(hipMemcpyAsync(c->xgeom.p + off[k], gs[k].data(), gs[k].size() * sizeof(PairGeom),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->xdest.p + off[k], ds[k].data(), ds[k].size() * sizeof(int2),
+                          hipMemcpyHostToDevice, c->stream));
+  }
+  if (counts) {
+    counts[0] += gs[0].size();
+    counts[1] += gs[1].size();
+    counts[2] += gs[2].size();
+  }
+  launch_list_far(c->nt_far, c->xgeom.p, c->xdest.p, (long)off[0], (long)gs[0].size(), c->M, c->k1,
+                  c->k2, c->tw_far.p, nullptr, 0, 0, nullptr, raw, c->stream);
+  HIPCHK(hipGetLastError());
+  run_split(c, c->xgeom.p + off[1], c->xdest.p + off[1], (long)gs[1].size(), nullptr, 0, 0, nullptr,
+            raw);
+  launch_direct(c->xgeom.p + off[2], c->xdest.p + off[2], 0, (long)gs[2].size(), c->M, c->k1,
+                c->k2, c->glx.p, c->glw.p, nullptr, 0, 0, nullptr, raw, kOmegaPiece, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+std::vector<zd> twiddles(int nt) {
+  std::vector<zd> t(nt / 2);
+  for (int k = 0; k < nt / 2; ++k) {
+    double a = -2.0 * PMLBIE_PI * k / nt;
+    t[k] = zd{cos(a), sin(a)};
+  }
+  return t;
+}
+
+int pow2_at_least(double x) {
+  int p = 16;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmlbie_create(pmlbie_ctx** out, int device, void* stream) {
+  if (!out) return PMLBIE_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PMLBIE_EDEVICE;
+  if (device < 0 || device >= ndev) return PMLBIE_EINVAL;
+  pmlbie_ctx* c = new (std::nothrow) pmlbie_ctx();
+  if (!c) return PMLBIE_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return PMLBIE_OK;
+}
+
+void pmlbie_destroy(pmlbie_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  delete c;
+}
+
+const char* pmlbie_last_error(const pmlbie_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int pmlbie_set_geometry(pmlbie_ctx* c, int n_bumps, const double* bumps, double cos_freq,
+                        double rho_c, const double* seg_breaks, int nodes_per_segment) {
+  return guarded(c, [&]() -> int {
+    if (n_bumps < 0 || n_bumps > 8 || (n_bumps > 0 && !bumps) || !seg_breaks)
+      return fail(c, PMLBIE_EINVAL, "set_geometry: bad bump list");
+    if (nodes_per_segment <= 0 || nodes_per_segment % 16)
+      return fail(c, PMLBIE_EINVAL, "set_geometry: nodes_per_segment must be a positive multiple of 16");
+    if (seg_breaks[0] != 0.0) return fail(c, PMLBIE_EINVAL, "set_geometry: curve must start on the axis");
+    for (int s = 0; s < 4; ++s)
+      if (!(seg_breaks[s + 1] > seg_breaks[s]))
+        return fail(c, PMLBIE_EINVAL, "set_geometry: segment breaks must increase");
+    Geometry g;
+    for (int i = 0; i < n_bumps; ++i) {
+      if (!(bumps[3 * i + 2] > 0)) return fail(c, PMLBIE_EINVAL, "set_geometry: bump width must be > 0");
+      g.itf.amp.push_back(bumps[3 * i]);
+      g.itf.cen.push_back(bumps[3 * i + 1]);
+      g.itf.wid.push_back(bumps[3 * i + 2]);
+    }
+    g.itf.cos_freq = cos_freq;
+    g.itf.rho_c = rho_c;
+    g.breaks.assign(seg_breaks, seg_breaks + 5);
+    g.nodes_per_segment = nodes_per_segment;
+    c->geo = g;
+    c->stage = 1;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_set_media_pml(pmlbie_ctx* c, double k1_re, double k1_im, double k2_re, double k2_im,
+                         double a1, double T, double S, double a2, double T2, double S2, int p) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 1) return fail(c, PMLBIE_ESTATE, "set_media_pml: set the geometry first");
+    if (!(a1 > 0) || !(T > 0) || !(S >= 0) || p < 2)
+      return fail(c, PMLBIE_EINVAL, "set_media_pml: need a1 > 0, T > 0, S >= 0, p >= 2");
+    if (fabs(c->geo.breaks[4] - (a1 + T)) > 1e-12 * (a1 + T))
+      return fail(c, PMLBIE_EINVAL, "set_media_pml: the curve must end at the outer PML edge a1 + T");
+    c->k1 = zd{k1_re, k1_im};
+    c->k2 = zd{k2_re, k2_im};
+    c->geo.pml.a1 = a1;
+    c->geo.pml.T = T;
+    c->geo.pml.S = S;
+    c->geo.pml.p = p;
+    c->a2 = a2;
+    c->T2 = T2;
+    c->S2 = S2;
+    c->geo.build();
+    c->N = c->geo.n();
+    c->stage = 2;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int precision, int flags) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 2) return fail(c, PMLBIE_ESTATE, "build: set geometry and media first");
+    if (n_theta < 16 || (n_theta & (n_theta - 1)))
+      return fail(c, PMLBIE_EINVAL, "build: n_theta must be a power of two >= 16");
+    if (precision != PMLBIE_FP64)
+      return fail(c, PMLBIE_EINVAL, "build: only PMLBIE_FP64 is available in this library");
+    auto t_all = std::chrono::steady_clock::now();
+    c->stage = 2;
+    c->n_theta = n_theta;
+    c->M = n_theta / 4;
+    c->precision = precision;
+    c->flags = flags;
+    const int N = c->N, M = c->M;
+    const long n2 = 2L * N;
+    const long ms = n2 * n2;
+    // FFT lengths: the smooth parts need 2B points for the convolution
+    // window and M + B for the kept modes (B ~ |k| |rho~|max, the bandwidth
+    // of cos kR in theta); the raw-kernel path uses twice that.
+    const double kmax = std::max(cabs_(c->k1), cabs_(c->k2));
+    const double rmax = cabs_(zd{c->geo.breaks[4], c->geo.Iint(c->geo.breaks[4])});
+    const double bneed = ceil(1.15 * kmax * rmax + 16.0);
+    c->nt_int = pow2_at_least(std::max<double>(n_theta, std::max(2.0 * bneed, M + bneed + 8.0)));
+    if (c->nt_int > 1024) return fail(c, PMLBIE_EINVAL, "build: wavenumber too large for the split FFT");
+    c->B = std::min(c->nt_int / 2, c->nt_int - M - 8);
+    c->MQ = M + c->B;
+    c->nt_far = std::min(2 * c->nt_int, 2048);
+    c->cp.M = M;
+    c->cp.nt_far = c->nt_far;
+    c->cp.bw = 1.1;
+    c->cp.kmax = std::max(fabs(c->k1.re), fabs(c->k2.re));
+    c->cp.kmax_im = std::max(fabs(c->k1.im), fabs(c->k2.im));
+    c->cp.c_far = 34.0;
+    c->cp.g_split = 9.0;
+
+    Timer t_setup(c->stream);
+    // node tables
+    std::vector<double> nt(8L * N);
+    for (int i = 0; i < N; ++i) {
+      nt[i] = c->geo.rho[i];
+      nt[N + i] = c->geo.I[i];
+      nt[2L * N + i] = c->geo.z[i];
+      nt[3L * N + i] = c->geo.W[i];
+      nt[4L * N + i] = c->geo.nr_re[i];
+      nt[5L * N + i] = c->geo.nr_im[i];
+      nt[6L * N + i] = c->geo.nz_re[i];
+      nt[7L * N + i] = c->geo.nz_im[i];
+    }
+    c->nodes.alloc(nt.size());
+    HIPCHK(hipMemcpyAsync(c->nodes.p, nt.data(), nt.size() * 8, hipMemcpyHostToDevice, c->stream));
+    c->dpanel.alloc(N);
+    HIPCHK(hipMemcpyAsync(c->dpanel.p, c->geo.panel.data(), N * sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
+    auto twf = twiddles(c->nt_far), twi = twiddles(c->nt_int);
+    c->tw_far.alloc(twf.size());
+    c->tw_int.alloc(twi.size());
+    HIPCHK(hipMemcpyAsync(c->tw_far.p, twf.data(), twf.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->tw_int.p, twi.data(), twi.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));
+    c->glx.alloc(16);
+    c->glw.alloc(16);
+    HIPCHK(hipMemcpyAsync(c->glx.p, c->geo.glx, 16 * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->glw.p, c->geo.glw, 16 * 8, hipMemcpyHostToDevice, c->stream));
+    // operators
+    c->A.alloc((size_t)(M + 1) * ms);
+    c->ipiv.alloc((size_t)(M + 1) * n2);
+    c->info.alloc(M + 1);
+    HIPCHK(hipMemsetAsync(c->info.p, 0, (M + 1) * sizeof(int), c->stream));
+    // work lists of the grid (split and direct share one allocation)
+    const size_t cap = (size_t)N * N;
+    c->lgeom.alloc(2 * cap);
+    c->ldest.alloc(2 * cap);
+    c->lcount.alloc(2);
+    HIPCHK(hipMemsetAsync(c->lcount.p, 0, 2 * sizeof(unsigned), c->stream));
+    // auxiliary near-panel points
+    std::vector<PairGeom> ageom;
+    std::vector<double> acoef;
+    std::vector<NearJob> ajobs;
+    c->geo.build_near(ageom, acoef, ajobs, 6);
+    c->cnt_aux = (long long)ageom.size();
+    c->coef.alloc(acoef.size());
+    HIPCHK(hipMemcpyAsync(c->coef.p, acoef.data(), acoef.size() * 8, hipMemcpyHostToDevice, c->stream));
+    c->jobs.alloc(ajobs.size());
+    HIPCHK(hipMemcpyAsync(c->jobs.p, ajobs.data(), ajobs.size() * sizeof(NearJob),
+                          hipMemcpyHostToDevice, c->stream));
+    c->stage_ms[0] = t_setup.stop();
+
+    NodesDev nd;
+    nd.N = N;
+    nd.rho = c->nodes.p;
+    nd.I = c->nodes.p + N;
+    nd.z = c->nodes.p + 2L * N;
+    nd.W = c->nodes.p + 3L * N;
+    nd.nr_re = c->nodes.p + 4L * N;
+    nd.nr_im = c->nodes.p + 5L * N;
+    nd.nz_re = c->nodes.p + 6L * N;
+    nd.nz_im = c->nodes.p + 7L * N;
+    nd.panel = c->dpanel.p;
+    WorkList ws{c->lgeom.p, c->ldest.p, c->lcount.p, (unsigned)cap};
+    WorkList wd{c->lgeom.p + cap, c->ldest.p + cap, c->lcount.p + 1, (unsigned)cap};
+
+    Timer t_far(c->stream);
+    launch_grid_far(c->nt_far, nd, c->cp, c->k1, c->k2, c->tw_far.p, c->A.p, ms, nd.W, ws, wd,
+                    c->stream);
+    HIPCHK(hipGetLastError());
+    c->stage_ms[1] = t_far.stop();
+    unsigned counts[2];
+    HIPCHK(hipMemcpy(counts, c->lcount.p, sizeof(counts), hipMemcpyDeviceToHost));
+    if (counts[0] > cap || counts[1] > cap) return fail(c, PMLBIE_EDEVICE, "build: work list overflow");
+    c->cnt_split = counts[0];
+    c->cnt_direct = counts[1];
+    c->cnt_far = (long long)N * N - counts[0] - counts[1];
+
+    Timer t_split(c->stream);
+    run_split(c, c->lgeom.p, c->ldest.p, counts[0], c->A.p, n2, ms, nd.W, nullptr);
+    c->stage_ms[2] = t_split.stop();
+    Timer t_direct(c->stream);
+    launch_direct(c->lgeom.p + cap, c->ldest.p + cap, 0, counts[1], M, c->k1, c->k2, c->glx.p,
+                  c->glw.p, c->A.p, n2, ms, nd.W, nullptr, kOmegaPiece, c->stream);
+    HIPCHK(hipGetLastError());
+    c->stage_ms[3] = t_direct.stop();
+
+    // near panels: modal kernels at the auxiliary points, then product integration
+    Timer t_near(c->stream);
+    c->raw.alloc(std::max<size_t>(ageom.size(), 1) * 4 * (M + 1));
+    long long dummy[3] = {0, 0, 0};
+    run_pair_list(c, ageom, c->raw.p, dummy);
+    launch_near(c->jobs.p, (int)ajobs.size(), c->coef.p, c->raw.p, M, c->A.p, n2, ms, c->stream);
+    HIPCHK(hipGetLastError());
+    c->stage_ms[4] = t_near.stop();
+    // the near-panel pairs of the grid were not counted as far
+    c->cnt_far -= 16LL * (long long)ajobs.size();
+
+    // keep what the solve needs: the lower block row [K2 - D2, -S2]
+    c->Alow.alloc((size_t)(M + 1) * N * n2);
+    HIPCHK(hipMemcpy2DAsync(c->Alow.p, N * sizeof(zd), c->A.p + N, n2 * sizeof(zd), N * sizeof(zd),
+                            (size_t)(M + 1) * n2, hipMemcpyDeviceToDevice, c->stream));
+    if (flags & PMLBIE_KEEP_OPERATORS) {
+      c->Akeep.alloc((size_t)(M + 1) * ms);
+      HIPCHK(hipMemcpyAsync(c->Akeep.p, c->A.p, (size_t)(M + 1) * ms * sizeof(zd),
+                            hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      c->Akeep.release();
+    }
+
+    // per-mode LU
+    Timer t_lu(c->stream);
+    const int npan = (int)((n2 + LU_NB - 1) / LU_NB);
+    std::vector<hipEvent_t> gb(npan), ge(npan);
+    for (int k = 0; k < npan; ++k) {
+      HIPCHK(hipEventCreate(&gb[k]));
+      HIPCHK(hipEventCreate(&ge[k]));
+    }
+    LuTimers tm;
+    tm.gemm_begin = gb.data();
+    tm.gemm_end = ge.data();
+    lu_factor_batched<double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->stream, &tm);
+    HIPCHK(hipGetLastError());
+    c->stage_ms[5] = t_lu.stop();
+    double gsum = 0;
+    for (int k = 0; k + 1 < npan; ++k) {
+      float ms1 = 0;
+      if (hipEventElapsedTime(&ms1, gb[k], ge[k]) == hipSuccess) gsum += ms1;
+    }
+    for (int k = 0; k < npan; ++k) {
+      (void)hipEventDestroy(gb[k]);
+      (void)hipEventDestroy(ge[k]);
+    }
+    c->stage_ms[6] = gsum;
+    std::vector<int> info(M + 1);
+    HIPCHK(hipMemcpy(info.data(), c->info.p, (M + 1) * sizeof(int), hipMemcpyDeviceToHost));
+    for (int n = 0; n <= M; ++n)
+      if (info[n])
+        return fail(c, PMLBIE_ESINGULAR,
+                    "build: mode " + std::to_string(n) + " has a zero pivot at column " + std::to_string(info[n] - 1));
+    c->stage_ms[10] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_all).count();
+    c->stage = 3;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, void* d_u1,
+                       void* d_phi1, void* d_u2, void* d_phi2) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 3) return fail(c, PMLBIE_ESTATE, "solve: build the operators first");
+    if (n_rhs < 1 || n_rhs > LU_MAX_RHS || !inc) return fail(c, PMLBIE_EINVAL, "solve: 1 <= n_rhs <= 16");
+    for (int r = 0; r < n_rhs; ++r) {
+      if (inc[r].kind != 0) return fail(c, PMLBIE_EINVAL, "solve: only point sources (kind 0) are available");
+      if (!(inc[r].p[0] >= 0)) return fail(c, PMLBIE_EINVAL, "solve: source radius must be >= 0");
+      if (inc[r].p[1] <= c->geo.h(inc[r].p[0]))
+        return fail(c, PMLBIE_EINVAL, "solve: the point source must lie in the upper medium");
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    const int N = c->N, M = c->M;
+    const long n2 = 2L * N, ms = n2 * n2;
+    c->nrhs = n_rhs;
+    Timer t_rhs(c->stream);
+    // pairs (node i, source) and (source, node i) per incidence
+    std::vector<PairGeom> g;
+    g.reserve((size_t)n_rhs * 2 * N);
+    for (int r = 0; r < n_rhs; ++r) {
+      const double rs = inc[r].p[0], zs = inc[r].p[1];
+      for (int i = 0; i < N; ++i) {
+        PairGeom p;
+        p.rt = zd{c->geo.rho[i], c->geo.I[i]};
+        p.rs = zd{rs, 0.0};
+        p.drho = zd{c->geo.rho[i] - rs, c->geo.I[i]};
+        p.dz = zd{c->geo.z[i] - zs, 0.0};
+        p.nr = zd{0.0, 0.0};
+        p.nz = zd{0.0, 0.0};
+        g.push_back(p);
+      }
+      for (int i = 0; i < N; ++i) {
+        PairGeom p;
+        p.rt = zd{rs, 0.0};
+        p.rs = zd{c->geo.rho[i], c->geo.I[i]};
+        p.drho = zd{rs - c->geo.rho[i], -c->geo.I[i]};
+        p.dz = zd{zs - c->geo.z[i], 0.0};
+        p.nr = zd{c->geo.nr_re[i], c->geo.nr_im[i]};
+        p.nz = zd{c->geo.nz_re[i], c->geo.nz_im[i]};
+        g.push_back(p);
+      }
+    }
+    c->raw.alloc(g.size() * 4 * (M + 1));
+    run_pair_list(c, g, c->raw.p, nullptr);
+    const size_t vec = (size_t)(M + 1) * n_rhs * N;
+    c->b1.alloc(vec);
+    c->b2.alloc(vec);
+    c->x.alloc(2 * vec);
+    launch_rhs_gather_point(c->raw.p, N, M, n_rhs, c->b1.p, c->b2.p, c->stream);
+    launch_lower_rhs(c->Alow.p, (long)N * n2, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+    HIPCHK(hipGetLastError());
+    c->stage_ms[8] = t_rhs.stop();
+    Timer t_sol(c->stream);
+    lu_solve_batched<double, double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->x.p, n_rhs, c->stream);
+    HIPCHK(hipGetLastError());
+    c->u1.alloc(vec);
+    c->p1.alloc(vec);
+    c->u2.alloc(vec);
+    c->p2.alloc(vec);
+    launch_outputs(c->x.p, c->b1.p, c->b2.p, N, M, n_rhs, c->u1.p, c->p1.p, c->u2.p, c->p2.p, c->stream);
+    HIPCHK(hipGetLastError());
+    const size_t bytes = vec * sizeof(zd);
+    if (d_u1) HIPCHK(hipMemcpyAsync(d_u1, c->u1.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (d_phi1) HIPCHK(hipMemcpyAsync(d_phi1, c->p1.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (d_u2) HIPCHK(hipMemcpyAsync(d_u2, c->u2.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (d_phi2) HIPCHK(hipMemcpyAsync(d_phi2, c->p2.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->stage_ms[9] = 0.0;
+    c->stage_ms[7] = t_sol.stop() + c->stage_ms[8];
+    (void)t0;
+    c->stage = 4;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* out) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 4) return fail(c, PMLBIE_ESTATE, "evaluate_field: solve first");
+    if (n_pts < 0 || (n_pts > 0 && (!rtz || !out))) return fail(c, PMLBIE_EINVAL, "evaluate_field: bad arguments");
+    if (n_pts == 0) return PMLBIE_OK;
+    const int N = c->N, M = c->M;
+    std::vector<PairGeom> g;
+    std::vector<int> med(n_pts);
+    std::vector<double> th(n_pts);
+    g.reserve((size_t)n_pts * N);
+    for (int p = 0; p < n_pts; ++p) {
+      const double r = rtz[3 * p], zz = rtz[3 * p + 2];
+      th[p] = rtz[3 * p + 1];
+      if (!(r >= 0) || r >= c->geo.pml.a1) return fail(c, PMLBIE_EINVAL, "evaluate_field: points must lie in the physical region rho < a1");
+      med[p] = zz > c->geo.h(r) ? 1 : 2;
+      for (int l = 0; l < N; ++l) {
+        PairGeom q;
+        q.rt = zd{r, 0.0};
+        q.rs = zd{c->geo.rho[l], c->geo.I[l]};
+        q.drho = zd{r - c->geo.rho[l], -c->geo.I[l]};
+        q.dz = zd{zz - c->geo.z[l], 0.0};
+        q.nr = zd{c->geo.nr_re[l], c->geo.nr_im[l]};
+        q.nz = zd{c->geo.nz_re[l], c->geo.nz_im[l]};
+        g.push_back(q);
+      }
+    }
+    c->raw.alloc(g.size() * 4 * (M + 1));
+    run_pair_list(c, g, c->raw.p, nullptr);
+    DBuf<int> dmed;
+    DBuf<double> dth;
+    DBuf<zd> dout;
+    dmed.alloc(n_pts);
+    dth.alloc(n_pts);
+    dout.alloc((size_t)n_pts * c->nrhs);
+    HIPCHK(hipMemcpyAsync(dmed.p, med.data(), n_pts * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dth.p, th.data(), n_pts * 8, hipMemcpyHostToDevice, c->stream));
+    launch_field(c->raw.p, c->nodes.p + 3L * N, N, M, c->nrhs, n_pts, dmed.p, dth.p, c->u1.p, c->p1.p,
+                 c->u2.p, c->p2.p, dout.p, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, dout.p, (size_t)n_pts * c->nrhs * sizeof(zd), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_get_info(const pmlbie_ctx* c, long long* info) {
+  if (!c || !info) return PMLBIE_EINVAL;
+  info[0] = c->N;
+  info[1] = c->M;
+  info[2] = c->nt_int;
+  info[3] = c->nt_far;
+  info[4] = c->cnt_far;
+  info[5] = c->cnt_split;
+  info[6] = c->cnt_direct;
+  info[7] = c->cnt_aux;
+  info[8] = c->B;
+  return PMLBIE_OK;
+}
+
+int pmlbie_get_nodes(const pmlbie_ctx* c, double* out) {
+  if (!c || !out) return PMLBIE_EINVAL;
+  if (c->stage < 2) return PMLBIE_ESTATE;
+  const Geometry& g = c->geo;
+  for (int i = 0; i < g.n(); ++i) {
+    double* o = out + 13L * i;
+    o[0] = g.rho[i]; o[1] = g.I[i]; o[2] = g.z[i];
+    o[3] = g.nr_re[i]; o[4] = g.nr_im[i]; o[5] = g.nz_re[i]; o[6] = g.nz_im[i];
+    o[7] = g.W[i]; o[8] = g.panel[i]; o[9] = g.t[i]; o[10] = g.nur[i]; o[11] = g.nuz[i]; o[12] = g.jac[i];
+  }
+  return PMLBIE_OK;
+}
+
+int pmlbie_modal_kernels(pmlbie_ctx* c, int n_pairs, const double* geom, void* d_out) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 3) return fail(c, PMLBIE_ESTATE, "modal_kernels: build the operators first");
+    if (n_pairs < 0 || (n_pairs > 0 && (!geom || !d_out))) return fail(c, PMLBIE_EINVAL, "modal_kernels: bad arguments");
+    if (n_pairs == 0) return PMLBIE_OK;
+    std::vector<PairGeom> g(n_pairs);
+    for (int q = 0; q < n_pairs; ++q) {
+      const double* s = geom + 12L * q;
+      g[q].rt = zd{s[0], s[1]};
+      g[q].rs = zd{s[2], s[3]};
+      g[q].drho = zd{s[4], s[5]};
+      g[q].dz = zd{s[6], s[7]};
+      g[q].nr = zd{s[8], s[9]};
+      g[q].nz = zd{s[10], s[11]};
+    }
+    run_pair_list(c, g, (zd*)d_out, nullptr);
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_get_operator(pmlbie_ctx* c, int mode, void* d_out) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 3) return fail(c, PMLBIE_ESTATE, "get_operator: build first");
+    if (!c->Akeep.p) return fail(c, PMLBIE_ESTATE, "get_operator: build with PMLBIE_KEEP_OPERATORS");
+    if (mode < 0 || mode > c->M || !d_out) return fail(c, PMLBIE_EINVAL, "get_operator: bad mode");
+    const size_t ms = (size_t)4 * c->N * c->N;
+    HIPCHK(hipMemcpyAsync(d_out, c->Akeep.p + (size_t)mode * ms, ms * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_get_stats(const pmlbie_ctx* c, double* stage_ms, double* counters) {
+  if (!c) return PMLBIE_EINVAL;
+  if (stage_ms) memcpy(stage_ms, c->stage_ms, sizeof(c->stage_ms));
+  if (counters) memcpy(counters, c->counters, sizeof(c->counters));
+  return PMLBIE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,299 @@
+#include "host_geom.h"
+
+#include <cmath>
+#include <stdexcept>
+
+namespace pmlbie {
+
+// Gauss-Legendre nodes by Newton iteration on P_n (three-term recurrence).
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(PMLBIE_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+double Geometry::graw(double r) const {
+  double s = 0;
+  for (size_t i = 0; i < itf.amp.size(); ++i) {
+    double u = (r - itf.cen[i]) / itf.wid[i];
+    s += itf.amp[i] * exp(-u * u);
+  }
+  return s;
+}
+double Geometry::graw_d(double r) const {
+  double s = 0;
+  for (size_t i = 0; i < itf.amp.size(); ++i) {
+    double u = (r - itf.cen[i]) / itf.wid[i];
+    s += itf.amp[i] * exp(-u * u) * (-2.0 * u / itf.wid[i]);
+  }
+  return s;
+}
+// g(r) - g(r - dr) = sum a e^{-v^2} expm1(-(u - v)(u + v)), u - v = dr / w
+double Geometry::graw_diff(double r, double dr) const {
+  double s = 0;
+  for (size_t i = 0; i < itf.amp.size(); ++i) {
+    double u = (r - itf.cen[i]) / itf.wid[i];
+    double du = dr / itf.wid[i];
+    double v = u - du;
+    s += itf.amp[i] * exp(-v * v) * expm1(-du * (u + v));
+  }
+  return s;
+}
+double Geometry::hraw_diff(double r, double dr) const {
+  if (itf.cos_freq == 0.0) return graw_diff(r, dr);
+  const double f = itf.cos_freq, rs = r - dr;
+  double dc = -2.0 * sin(0.5 * f * (r + rs)) * sin(0.5 * f * dr);
+  return graw_diff(r, dr) * cos(f * r) + graw(rs) * dc;
+}
+double Geometry::hraw_d(double r) const {
+  if (itf.cos_freq == 0.0) return graw_d(r);
+  const double f = itf.cos_freq;
+  return graw_d(r) * cos(f * r) - graw(r) * f * sin(f * r);
+}
+double Geometry::h(double r) const { return r < itf.rho_c ? hraw_diff(r, r - itf.rho_c) : 0.0; }
+double Geometry::hprime(double r) const { return r < itf.rho_c ? hraw_d(r) : 0.0; }
+double Geometry::hdiff(double r, double dr) const {
+  const double s = r - dr;
+  const bool ir = r < itf.rho_c, is = s < itf.rho_c;
+  if (ir && is) return hraw_diff(r, dr);
+  if (ir) return h(r);
+  if (is) return -h(s);
+  return 0.0;
+}
+
+// sigma_1 of eq. eqsgm1
+double Geometry::sigma(double r) const {
+  const double a1 = pml.a1, T = pml.T, S = pml.S;
+  const int p = pml.p;
+  if (r <= a1) return 0.0;
+  if (r > a1 + T) return S;
+  double rb = (r - (a1 + T)) / T;
+  double f1 = (0.5 - 1.0 / p) * rb * rb * rb + rb / p + 0.5;
+  double f2 = 1.0 - f1;
+  double f1p = pow(f1, p), f2p = pow(f2, p);
+  return 2.0 * S * f1p / (f1p + f2p);
+}
+
+// int_lo^hi sigma by composite 16-point Gauss-Legendre on 8 pieces of the
+// smooth stretch [a1, a1 + T] (and the constant part beyond).
+static double sigma_int(const Geometry& g, double lo, double hi) {
+  if (hi <= lo) return 0.0;
+  const double a1 = g.pml.a1, b1 = g.pml.a1 + g.pml.T;
+  double s = 0.0;
+  double x0 = fmax(lo, a1), x1 = fmin(hi, b1);
+  if (x1 > x0) {
+    const int P = 8;
+    for (int k = 0; k < P; ++k) {
+      double a = x0 + (x1 - x0) * k / P, b = x0 + (x1 - x0) * (k + 1) / P;
+      for (int j = 0; j < 16; ++j) s += 0.5 * (b - a) * g.glw[j] * g.sigma(0.5 * (a + b) + 0.5 * (b - a) * g.glx[j]);
+    }
+  }
+  if (hi > b1) s += g.pml.S * (hi - fmax(lo, b1));
+  return s;
+}
+double Geometry::Iint(double r) const { return sigma_int(*this, 0.0, r); }
+double Geometry::Idiff(double r, double dr) const {
+  if (fabs(dr) < 1e-2) {
+    // short interval: 8-point rule on [r - dr, r] in the offset variable
+    double s = 0.0;
+    static double x8[8], w8[8];
+    static bool init = false;
+    if (!init) {
+      gauss_legendre(8, x8, w8);
+      init = true;
+    }
+    for (int j = 0; j < 8; ++j) s += 0.5 * w8[j] * sigma(r - dr * 0.5 * (1.0 + x8[j]));
+    return s * dr;
+  }
+  return Iint(r) - Iint(r - dr);
+}
+
+void Geometry::point(int pn, double tpar, double& r, double& Ir, double& zz, zd& nr, zd& nz,
+                     double& jacobian) const {
+  r = pa[pn] + 0.5 * (1.0 + tpar) * pl[pn];
+  Ir = Iint(r);
+  zz = h(r);
+  double hpv = hprime(r);
+  double sq = sqrt(1.0 + hpv * hpv);
+  double nu_r = hpv / sq, nu_z = -1.0 / sq;  // unit normal into the lower medium
+  zd rt{r, Ir};
+  zd ar{1.0, sigma(r)};
+  // nu_c . grad_r in stretched variables: n_rho d/drho~ + n_z d/dz~,
+  // n_rho = nu_rho rho~ alpha_z / rho, n_z = nu_z rho~ alpha_rho / rho (alpha_z = 1 on the curve)
+  nr = (nu_r / r) * rt;
+  nz = (nu_z / r) * (rt * ar);
+  jacobian = 0.5 * pl[pn] * sq;
+}
+
+void Geometry::build() {
+  if (breaks.size() != 5) throw std::invalid_argument("geometry: need 5 segment breaks");
+  if (nodes_per_segment <= 0 || nodes_per_segment % 16)
+    throw std::invalid_argument("geometry: nodes per segment must be a positive multiple of 16");
+  gauss_legendre(16, glx, glw);
+  const int nsub = nodes_per_segment / 16;
+  pa.clear();
+  pl.clear();
+  for (int s = 0; s < 4; ++s) {
+    double a = breaks[s], b = breaks[s + 1];
+    if (!(b > a)) throw std::invalid_argument("geometry: segment breaks must increase");
+    for (int k = 0; k < nsub; ++k) {
+      pa.push_back(a + (b - a) * k / nsub);
+      pl.push_back((b - a) / nsub);
+    }
+  }
+  const int np = npanels(), N = np * 16;
+  rho.assign(N, 0); I.assign(N, 0); z.assign(N, 0); hp.assign(N, 0); nur.assign(N, 0);
+  nuz.assign(N, 0); jac.assign(N, 0); W.assign(N, 0); t.assign(N, 0);
+  nr_re.assign(N, 0); nr_im.assign(N, 0); nz_re.assign(N, 0); nz_im.assign(N, 0);
+  panel.assign(N, 0);
+  for (int p = 0; p < np; ++p)
+    for (int j = 0; j < 16; ++j) {
+      const int i = 16 * p + j;
+      zd nr, nz;
+      point(p, glx[j], rho[i], I[i], z[i], nr, nz, jac[i]);
+      hp[i] = hprime(rho[i]);
+      double sq = sqrt(1.0 + hp[i] * hp[i]);
+      nur[i] = hp[i] / sq;
+      nuz[i] = -1.0 / sq;
+      nr_re[i] = nr.re; nr_im[i] = nr.im; nz_re[i] = nz.re; nz_im[i] = nz.im;
+      W[i] = glw[j] * rho[i] * jac[i];
+      t[i] = glx[j];
+      panel[i] = p;
+    }
+}
+
+// Lagrange basis on the 16 Gauss-Legendre nodes, barycentric form.
+static void lagrange16(const double* xn, double tq, double* out) {
+  static double bw[16];
+  static bool init = false;
+  if (!init) {
+    for (int l = 0; l < 16; ++l) {
+      double p = 1.0;
+      for (int m = 0; m < 16; ++m)
+        if (m != l) p *= (xn[l] - xn[m]);
+      bw[l] = 1.0 / p;
+    }
+    init = true;
+  }
+  for (int l = 0; l < 16; ++l)
+    if (tq == xn[l]) {
+      for (int m = 0; m < 16; ++m) out[m] = m == l ? 1.0 : 0.0;
+      return;
+    }
+  double den = 0.0;
+  for (int l = 0; l < 16; ++l) den += bw[l] / (tq - xn[l]);
+  for (int l = 0; l < 16; ++l) out[l] = (bw[l] / (tq - xn[l])) / den;
+}
+
+// Auxiliary rules.  Self panel: each side of the target is covered by
+// `levels` intervals shrinking by 4 toward the target plus an innermost
+// interval mapped by t = eps u^6 (smooths the log singularity), 16 points
+// each.  Neighbour panels: intervals shrinking by 4 toward the shared
+// endpoint until their length is below the target's distance to that end.
+void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
+                          std::vector<NearJob>& jobs, int self_levels) const {
+  geom.clear();
+  coef.clear();
+  jobs.clear();
+  const int N = n(), np = npanels();
+  std::vector<double> tq, wq;  // rule in offset form: t = base + sgn * off
+  for (int i = 0; i < N; ++i) {
+    const int p0 = panel[i];
+    for (int pn = p0 - 1; pn <= p0 + 1; ++pn) {
+      if (pn < 0 || pn >= np) continue;
+      NearJob J;
+      J.target = i;
+      J.panel = pn;
+      J.q0 = (int)geom.size();
+      // collect (offset from the anchor, weight, side sign)
+      struct AP { double anchor, off, sgn, w; };
+      std::vector<AP> pts;
+      if (pn == p0) {
+        const double ti = t[i];
+        for (int side = -1; side <= 1; side += 2) {
+          const double h = side > 0 ? 1.0 - ti : ti + 1.0;
+          double hi = h;
+          for (int lv = 0; lv < self_levels; ++lv) {
+            double lo = hi * 0.25;
+            for (int j = 0; j < 16; ++j)
+              pts.push_back({ti, lo + 0.5 * (hi - lo) * (1.0 + glx[j]), (double)side, 0.5 * (hi - lo) * glw[j]});
+            hi = lo;
+          }
+          const double eps = hi;
+          for (int j = 0; j < 16; ++j) {
+            double u = 0.5 * (1.0 + glx[j]);
+            double u5 = u * u * u * u * u;
+            pts.push_back({ti, eps * u5 * u, (double)side, eps * 0.5 * glw[j] * 6.0 * u5});
+          }
+        }
+      } else {
+        // shared endpoint of the neighbour panel: +1 if it lies left of p0
+        const double anchor = pn < p0 ? 1.0 : -1.0;
+        const double sgn = pn < p0 ? -1.0 : 1.0;  // t = anchor + sgn * off
+        // target distance to the shared end, in neighbour-panel units
+        const double dist = (pn < p0 ? (1.0 + t[i]) : (1.0 - t[i])) * pl[p0] / pl[pn];
+        double hi = 2.0;
+        int nint = 0;
+        while (true) {
+          double lo = hi * 0.25;
+          // at least three intervals, so that the rule also resolves the
+          // Lagrange factor when the target is far from the shared end
+          if (hi <= dist && nint >= 2) lo = 0.0;
+          ++nint;
+          for (int j = 0; j < 16; ++j)
+            pts.push_back({anchor, lo + 0.5 * (hi - lo) * (1.0 + glx[j]), sgn, 0.5 * (hi - lo) * glw[j]});
+          if (lo == 0.0) break;
+          hi = lo;
+        }
+      }
+      for (const AP& a : pts) {
+        const double tp = a.anchor + a.sgn * a.off;
+        double r, Ir, zz, jc;
+        zd nr, nz;
+        point(pn, tp, r, Ir, zz, nr, nz, jc);
+        // target minus source, from the exact offset on the self panel
+        double dr;
+        if (pn == p0) dr = -a.sgn * a.off * 0.5 * pl[pn];
+        else dr = rho[i] - r;
+        PairGeom g;
+        g.rt = zd{rho[i], I[i]};
+        g.rs = zd{r, Ir};
+        g.drho = zd{dr, Idiff(rho[i], dr)};
+        g.dz = zd{hdiff(rho[i], dr), 0.0};
+        g.nr = nr;
+        g.nz = nz;
+        geom.push_back(g);
+        double L[16];
+        lagrange16(glx, tp, L);
+        const double base = 2.0 * a.w * r * jc;
+        for (int l = 0; l < 16; ++l) coef.push_back(base * L[l]);
+      }
+      J.q1 = (int)geom.size();
+      jobs.push_back(J);
+    }
+  }
+}
+
+}  // namespace pmlbie

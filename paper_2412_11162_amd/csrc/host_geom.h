@@ -1,0 +1,68 @@
+// Host-side geometry of the Nystrom discretisation: the interface graph, the
+// PML stretching (Sec. 3.1, eqs. eqrhot, eqsgm1), Gauss-Legendre panels, the
+// conormal (Sec. 3.1, nu_c = A^T nu), and the auxiliary quadrature points of
+// the near-panel product integration.
+#pragma once
+#include <vector>
+#include "modal.h"
+
+namespace pmlbie {
+
+struct Interface {
+  std::vector<double> amp, cen, wid;  // Gaussian rings a exp(-((rho - c)/w)^2)
+  double cos_freq = 0.0;              // optional factor cos(f rho)
+  double rho_c = 0.0;                 // flat for rho >= rho_c: h~ = h - h(rho_c) below
+};
+
+struct Pml {
+  double a1 = 0, T = 0, S = 0;
+  int p = 6;
+};
+
+class Geometry {
+ public:
+  Interface itf;
+  Pml pml;
+  std::vector<double> breaks;  // segment breaks in rho, 5 values
+  int nodes_per_segment = 0;
+
+  // Gauss-Legendre rule of 16 nodes on [-1, 1].
+  double glx[16], glw[16];
+
+  // panels
+  std::vector<double> pa, pl;  // start rho and rho-length
+  // node tables
+  std::vector<double> rho, I, z, hp, nur, nuz, jac, W, t;
+  std::vector<double> nr_re, nr_im, nz_re, nz_im;
+  std::vector<int> panel;
+
+  void build();  // panels + node tables
+  int n() const { return (int)rho.size(); }
+  int npanels() const { return (int)pa.size(); }
+
+  double h(double r) const;            // h~(rho)
+  double hprime(double r) const;       // h~'(rho)
+  double hdiff(double r, double dr) const;  // h~(r) - h~(r - dr), no cancellation
+  double sigma(double r) const;        // sigma_1
+  double Iint(double r) const;         // int_0^r sigma_1
+  double Idiff(double r, double dr) const;  // int_{r - dr}^{r} sigma_1
+  // geometry of a curve point given by its panel and parameter
+  void point(int panel, double tpar, double& r, double& Ir, double& zz, zd& nr, zd& nz,
+             double& jacobian) const;
+
+  // near-panel product integration: auxiliary points, their pair geometry
+  // relative to the target, Lagrange-weighted quadrature coefficients, jobs
+  void build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
+                  std::vector<NearJob>& jobs, int self_levels) const;
+
+ private:
+  double graw(double r) const;
+  double graw_d(double r) const;
+  double graw_diff(double r, double dr) const;
+  double hraw_diff(double r, double dr) const;
+  double hraw_d(double r) const;
+};
+
+void gauss_legendre(int n, double* x, double* w);
+
+}  // namespace pmlbie

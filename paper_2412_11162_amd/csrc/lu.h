@@ -1,0 +1,31 @@
+// Batched per-mode complex LU (partial pivoting) and solves.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include "cplx.h"
+
+namespace pmlbie {
+
+constexpr int LU_NB = 64;       // panel width
+constexpr int LU_MAX_RHS = 16;  // right-hand sides per solve call
+
+// Optional per-panel event markers (timing of the trailing-update kernel).
+struct LuTimers {
+  hipEvent_t* panel_begin = nullptr;
+  hipEvent_t* gemm_begin = nullptr;
+  hipEvent_t* gemm_end = nullptr;
+};
+
+// Factor `batch` column-major n x n matrices A + b * ms in place.
+// ipiv[b * n + j] = row interchanged with row j (0-based);
+// info[b] = first zero pivot (1-based), untouched otherwise.
+template <typename T>
+void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, hipStream_t st,
+                       LuTimers* tm = nullptr);
+
+// Solve A x = b for nrhs right-hand sides per matrix, B[b][rhs][n] in place.
+template <typename T, typename TB>
+void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv, cx<TB>* B,
+                      int nrhs, hipStream_t st);
+
+}  // namespace pmlbie

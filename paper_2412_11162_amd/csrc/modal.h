@@ -1,0 +1,63 @@
+// Modal-kernel generation: data structures shared by the host orchestration
+// and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include "modal_math.h"
+
+namespace pmlbie {
+
+enum { CLASS_FAR = 0, CLASS_SPLIT = 1, CLASS_DIRECT = 2 };
+
+// Node tables of the Nystrom discretisation, structure of arrays on the device.
+struct NodesDev {
+  int N;
+  const double *rho, *I, *z, *W;
+  const double *nr_re, *nr_im, *nz_re, *nz_im;
+  const int* panel;
+};
+
+// Thresholds of the pair classification.
+struct ClassParams {
+  int M;          // highest mode kept
+  int nt_far;     // FFT length of the raw-kernel path
+  double bw;      // oscillation bandwidth factor: B = bw |k| sqrt|rho~ rho~'|
+  double kmax;    // max |Re k| over the media
+  double kmax_im; // max |Im k|
+  double c_far;   // far if (nt_far - M - B) * delta >= c_far
+  double g_split; // split if max |Im kR| <= g_split, else direct quadrature
+};
+
+// Device work list of pairs handed from the classifier to the split and
+// direct kernels.
+struct WorkList {
+  PairGeom* geom;
+  int2* dest;
+  unsigned* count;
+  unsigned cap;
+};
+
+// One near-panel product-integration job: target node, source panel, and its
+// auxiliary points q0..q1-1.
+struct NearJob {
+  int target, panel, q0, q1;
+};
+
+void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
+                     const zd* tw, zd* A, long mstride, const double* W, WorkList split,
+                     WorkList direct, hipStream_t st);
+void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
+                     zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
+                     zd* raw, hipStream_t st);
+void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
+                           zd* phat, zd* qscr, hipStream_t st);
+void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
+                  int B, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
+                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st);
+void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, zd k1,
+                   zd k2, const double* glx, const double* glw, zd* A, long n2, long mstride,
+                   const double* W, zd* raw, double omega_piece, hipStream_t st);
+void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, zd* A,
+                 long n2, long mstride, hipStream_t st);
+
+}  // namespace pmlbie

@@ -1,0 +1,590 @@
+// Modal-kernel generation on gfx950: pair x theta sampling of the
+// complexified Green's function and its conormal derivative, batched
+// azimuthal FFTs in LDS, the singular/smooth split with semi-analytic
+// singular modes (Sec. 4.1, eqs. eq:s1, eq:k1, eqsnspml, eqknspml, and the
+// convolution formula eqcon of Sec. 3.3), a graded direct azimuthal
+// quadrature for near pairs deep in the PML where the split loses accuracy,
+// and assembly of the per-mode Nystrom matrices (Sec. 4.1-4.2).
+//
+// Natural modes: F_n = int_{-pi}^{pi} e^{-i n D} F(D) dD.  Every kernel is
+// even in D, so F_{-n} = F_n and only n = 0..M are formed.
+#include "modal.h"
+
+namespace pmlbie {
+
+// ------------------------------------------------------------------------
+// Output: either the per-mode system matrices or a raw modal buffer.
+//
+// System matrix of mode n, column-major 2N x 2N at A + n * mstride:
+//   [[K1 - D1, -S1], [K2 - D2, -S2]],  K_il = 2 W_l K_n(r_i, r_l),
+//   S_il = 2 W_l S_n(r_i, r_l) for l off the near panels of i.
+// Raw modal buffer: out[q][s][n], s in {S1, K1, S2, K2}.
+struct OutSpec {
+  zd* A;
+  long n2;       // 2N
+  long mstride;  // elements per mode matrix
+  const double* W;
+  zd* raw;
+  int M;
+};
+
+__device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, zd K1, zd S2,
+                                     zd K2) {
+  if (dst.y >= 0) {
+    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
+    const double w2 = 2.0 * o.W[l];
+    zd* An = o.A + (long)n * o.mstride;
+    An[l * o.n2 + i] = w2 * K1;
+    An[(N + l) * o.n2 + i] = (-w2) * S1;
+    An[l * o.n2 + N + i] = w2 * K2;
+    An[(N + l) * o.n2 + N + i] = (-w2) * S2;
+  } else {
+    zd* r = o.raw + (long)dst.x * 4 * (o.M + 1);
+    r[n] = S1;
+    r[(o.M + 1) + n] = K1;
+    r[2 * (o.M + 1) + n] = S2;
+    r[3 * (o.M + 1) + n] = K2;
+  }
+}
+
+__device__ __forceinline__ PairGeom node_pair(const NodesDev& nd, int i, int l) {
+  PairGeom g;
+  g.rt = zd{nd.rho[i], nd.I[i]};
+  g.rs = zd{nd.rho[l], nd.I[l]};
+  g.drho = zd{nd.rho[i] - nd.rho[l], nd.I[i] - nd.I[l]};
+  g.dz = zd{nd.z[i] - nd.z[l], 0.0};
+  g.nr = zd{nd.nr_re[l], nd.nr_im[l]};
+  g.nz = zd{nd.nz_re[l], nd.nz_im[l]};
+  return g;
+}
+
+// In-place radix-2 FFT (decimation in time, bit-reversed input) of NSEQ
+// sequences of length NT held in LDS, one wavefront.  tw[k] = e^{-2 pi i k/NT}.
+template <int NT, int NSEQ>
+__device__ __forceinline__ void fft_lds(zd* buf, const zd* __restrict__ tw) {
+#pragma unroll 1
+  for (int len = 2; len <= NT; len <<= 1) {
+    const int half = len >> 1, step = NT / len;
+    for (int b = threadIdx.x; b < NSEQ * (NT / 2); b += 64) {
+      const int s = b / (NT / 2), bb = b % (NT / 2);
+      const int grp = bb / half, pos = bb % half;
+      const int i0 = s * NT + grp * len + pos, i1 = i0 + half;
+      const zd w = tw[pos * step];
+      const zd u = buf[i0], v = buf[i1] * w;
+      buf[i0] = u + v;
+      buf[i1] = u - v;
+    }
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ int bitrev(int j) {
+  constexpr int LOG = __builtin_ctz(NT);
+  return (int)(__brev((unsigned)j) >> (32 - LOG));
+}
+
+// ------------------------------------------------------------------------
+// Classification of a pair (Sec. 4.1: well-separated pairs by FFT of the raw
+// kernel; close pairs by the split; close pairs deep in the PML by graded
+// direct quadrature, where cos(kR) grows like exp(max |Im kR|)).
+__device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, const ClassParams& cp) {
+  double delta, re0;
+  singularity(v, delta, re0);
+  const double sc = sqrt(cabs_(g.rt * g.rs));
+  const double bw = cp.bw * cp.kmax * sc;
+  if ((cp.nt_far - cp.M - bw) * delta >= cp.c_far) return CLASS_FAR;
+  zd Rpi = csqrt_(v.d2 + v.c4);
+  double grow = cp.kmax * fabs(Rpi.im) + cp.kmax_im * fabs(Rpi.re);
+  return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
+}
+
+// Raw-kernel FFT of one pair (one wavefront): samples on the half circle,
+// mirrored to the full circle (the kernels are even in D), bit-reversed into
+// LDS, FFT, modes 0..M emitted.
+template <int NT>
+__device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const zd* __restrict__ tw,
+                                         zd* buf, const OutSpec& o, int2 dst) {
+  const double scale = 2.0 * PMLBIE_PI / NT;
+  for (int j = threadIdx.x; j <= NT / 2; j += 64) {
+    const double sh = sin(PMLBIE_PI * j / NT);
+    zd S1, K1, S2, K2;
+    kernel_sample(v, sh * sh, k1, S1, K1);
+    kernel_sample(v, sh * sh, k2, S2, K2);
+    const int a = bitrev<NT>(j);
+    buf[a] = S1;
+    buf[NT + a] = K1;
+    buf[2 * NT + a] = S2;
+    buf[3 * NT + a] = K2;
+    if (j > 0 && j < NT / 2) {
+      const int b = bitrev<NT>(NT - j);
+      buf[b] = S1;
+      buf[NT + b] = K1;
+      buf[2 * NT + b] = S2;
+      buf[3 * NT + b] = K2;
+    }
+  }
+  __syncthreads();
+  fft_lds<NT, 4>(buf, tw);
+  for (int n = threadIdx.x; n <= o.M; n += 64)
+    emit(o, dst, n, scale * buf[n], scale * buf[NT + n], scale * buf[2 * NT + n],
+         scale * buf[3 * NT + n]);
+  __syncthreads();
+}
+
+// Main grid: every (target i, source l) pair off the near panels.  Far pairs
+// are finished here (raw-kernel FFT over theta); the others are appended to
+// the split / direct work lists.  One wavefront per pair.
+template <int NT>
+__global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
+                                                 const zd* __restrict__ tw, OutSpec o,
+                                                 WorkList split, WorkList direct) {
+  __shared__ zd buf[4 * NT];
+  const int N = nd.N;
+  const long total = (long)N * N;
+  for (long p = blockIdx.x; p < total; p += gridDim.x) {
+    const int i = (int)(p % N), l = (int)(p / N);
+    const int dp = nd.panel[i] - nd.panel[l];
+    if (dp >= -1 && dp <= 1) continue;  // near panels: product integration
+    const PairGeom g = node_pair(nd, i, l);
+    const PairInv v = pair_invariants(g);
+    const int cls = classify(g, v, cp);
+    if (cls != CLASS_FAR) {
+      if (threadIdx.x == 0) {
+        WorkList& wl = cls == CLASS_SPLIT ? split : direct;
+        unsigned slot = atomicAdd(wl.count, 1u);
+        if (slot < wl.cap) {
+          wl.geom[slot] = g;
+          wl.dest[slot] = make_int2(i, l);
+        }
+      }
+      continue;
+    }
+    far_pair<NT>(v, k1, k2, tw, buf, o, make_int2(i, l));
+  }
+}
+
+// Explicit list of far pairs (right-hand sides, field points).
+template <int NT>
+__global__ __launch_bounds__(64) void k_list_far(const PairGeom* __restrict__ geom,
+                                                 const int2* __restrict__ dest, long first,
+                                                 long count, zd k1, zd k2,
+                                                 const zd* __restrict__ tw, OutSpec o) {
+  __shared__ zd buf[4 * NT];
+  for (long t = blockIdx.x; t < count; t += gridDim.x) {
+    const PairGeom g = geom[first + t];
+    const PairInv v = pair_invariants(g);
+    far_pair<NT>(v, k1, k2, tw, buf, o, dest[first + t]);
+  }
+}
+
+// ------------------------------------------------------------------------
+// Split pairs, phase 1 (one lane per pair): the semi-analytic modes of the
+// singular factors, Zhat_m = modes of 1/(4 pi R) and Phat_m = modes of 1/R^3,
+// m = 0..MQ, from Q_{m-1/2}(chi), chi = 1 + d2/(2 rho~ rho~').
+//   modes of (chi - cos D)^{-1/2} = 2 sqrt2 Q_{m-1/2}(chi)          (Heine)
+//   modes of (chi - cos D)^{-3/2} = -4 sqrt2 Q'_{m-1/2}(chi)
+// and R = sgn sqrt(c) sqrt(chi - cos D), c = 2 rho~ rho~', with the sign
+// fixed by continuity against the principal R at D = pi.
+__global__ __launch_bounds__(64) void k_split_singular(const PairGeom* __restrict__ geom,
+                                                       long first, long count, int MQ,
+                                                       zd* __restrict__ zhat,
+                                                       zd* __restrict__ phat,
+                                                       zd* __restrict__ qscr) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const PairGeom g = geom[first + t];
+  const PairInv v = pair_invariants(g);
+  const zd c = 2.0 * (g.rt * g.rs);
+  const zd chim1 = v.d2 / c;
+  zd* Q = qscr + t * (MQ + 1);
+  legendre_q_half(chim1, MQ, Q);
+  const zd sc = csqrt_(c);
+  const zd Rpi = csqrt_(v.d2 + v.c4);
+  const zd Rsp = sc * csqrt_(chim1 + 2.0);
+  const double sgn = cabs_(Rpi - Rsp) <= cabs_(Rpi + Rsp) ? 1.0 : -1.0;
+  const double rt2 = 1.4142135623730950488;
+  const zd isc = inv(sc);
+  const zd fz = (sgn * 2.0 * rt2 * (0.25 / PMLBIE_PI)) * isc;     // Zhat_m = fz Q_m
+  const zd fp = (sgn * (-4.0) * rt2) * isc * isc * isc;            // Phat_m = fp Q'_m
+  const zd chi2m1 = chim1 * (chim1 + 2.0);
+  const zd ichi2 = inv(chi2m1);
+  zd* zo = zhat + t * (MQ + 1);
+  zd* po = phat + t * (MQ + 1);
+  for (int m = 0; m <= MQ; ++m) {
+    const zd qm = Q[m];
+    const zd qm1 = m == 0 ? Q[1 < MQ ? 1 : MQ] : Q[m - 1];
+    // Q'_{m-1/2} = (m - 1/2)(chi Q_{m-1/2} - Q_{m-3/2})/(chi^2 - 1)
+    const zd num = chim1 * qm + (qm - qm1);
+    const zd dq = (m - 0.5) * num * ichi2;
+    zo[m] = fz * qm;
+    po[m] = fp * dq;
+  }
+}
+
+// Split pairs, phase 2 (one wavefront per pair): FFT of the smooth parts
+// H1 = cos kR, ZH2 = sin(kR)/(4 pi R), H3 = cos kR + kR sin kR, DH4 = D H4 for
+// both wavenumbers, then
+//   S_n = (1/2pi) sum_j Zhat_{n-j} H1hat_j + i ZH2hat_n,
+//   K_n = (1/2pi) sum_j Dhat_{n-j} H3hat_j + i DH4hat_n,
+//   Dhat_m = -(e0 Phat_m + 4 pi e1 Zhat_m)/(4 pi).
+template <int NT>
+__global__ __launch_bounds__(64) void k_split(const PairGeom* __restrict__ geom,
+                                              const int2* __restrict__ dest, long first,
+                                              long count, int M, int B, int MQ, zd k1, zd k2,
+                                              const zd* __restrict__ tw,
+                                              const zd* __restrict__ zhat,
+                                              const zd* __restrict__ phat, OutSpec o) {
+  __shared__ zd buf[8 * NT];
+  const double scale = 2.0 * PMLBIE_PI / NT;
+  const double inv2pi = 0.5 / PMLBIE_PI;
+  for (long t = blockIdx.x; t < count; t += gridDim.x) {
+    const PairGeom g = geom[first + t];
+    const int2 dst = dest[first + t];
+    const PairInv v = pair_invariants(g);
+    const SplitCoef sc = split_coef(g, v);
+    for (int j = threadIdx.x; j <= NT / 2; j += 64) {
+      const double sh = sin(PMLBIE_PI * j / NT);
+      zd h[8];
+      split_sample(v, sc, sh * sh, k1, h[0], h[1], h[2], h[3]);
+      split_sample(v, sc, sh * sh, k2, h[4], h[5], h[6], h[7]);
+      const int a = bitrev<NT>(j);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) buf[s * NT + a] = h[s];
+      if (j > 0 && j < NT / 2) {
+        const int b = bitrev<NT>(NT - j);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) buf[s * NT + b] = h[s];
+      }
+    }
+    __syncthreads();
+    fft_lds<NT, 8>(buf, tw);
+    const zd* zz = zhat + t * (MQ + 1);
+    const zd* pp = phat + t * (MQ + 1);
+    const zd e0f = (-0.25 / PMLBIE_PI) * sc.e0;
+    const zd e1f = -1.0 * sc.e1;
+    for (int n = threadIdx.x; n <= M; n += 64) {
+      zd zs1{0, 0}, zs2{0, 0}, dk1{0, 0}, dk2{0, 0};
+      for (int j = -B; j <= B; ++j) {
+        const int m = n - j < 0 ? j - n : n - j;
+        const int aj = j < 0 ? -j : j;
+        const zd zm = zz[m];
+        const zd dm = e0f * pp[m] + e1f * zm;
+        zs1 = cfma(zm, buf[aj], zs1);
+        dk1 = cfma(dm, buf[2 * NT + aj], dk1);
+        zs2 = cfma(zm, buf[4 * NT + aj], zs2);
+        dk2 = cfma(dm, buf[6 * NT + aj], dk2);
+      }
+      const zd I{0.0, 1.0};
+      const zd S1 = (scale * inv2pi) * zs1 + I * (scale * buf[NT + n]);
+      const zd K1 = (scale * inv2pi) * dk1 + I * (scale * buf[3 * NT + n]);
+      const zd S2 = (scale * inv2pi) * zs2 + I * (scale * buf[5 * NT + n]);
+      const zd K2 = (scale * inv2pi) * dk2 + I * (scale * buf[7 * NT + n]);
+      emit(o, dst, n, S1, K1, S2, K2);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// Direct pairs (close, deep in the PML): F_n = 2 sum_q w_q cos(n D_q) F(D_q)
+// over a composite 16-point Gauss-Legendre rule on [0, pi] graded toward the
+// nearest singularity Re D* with smallest piece ~ |Im D*|/4, and pieces short
+// enough for the oscillation of cos(n D) exp(i k R).
+// One wavefront per pair: 64 nodes are sampled at a time into LDS with the
+// table cos(j D), j = 0..16; lane (a, g) = (lane / 16, lane % 16) then sums
+// nodes a, a+4, ... of the batch into modes n = g + 16 r with the
+// stride-16 Chebyshev recurrence cos((n+16)D) = 2 cos(16D) cos(nD) - cos((n-16)D).
+#define DIRECT_MAX_PIECES 512
+#define DIRECT_MPL 9  // modes per lane per pass (16 * 9 = 144 modes)
+
+__global__ __launch_bounds__(64) void k_direct(const PairGeom* __restrict__ geom,
+                                               const int2* __restrict__ dest, long first,
+                                               long count, int M, zd k1, zd k2,
+                                               const double* __restrict__ glx,
+                                               const double* __restrict__ glw, OutSpec o,
+                                               double omega_piece) {
+  __shared__ double pa[DIRECT_MAX_PIECES], pb[DIRECT_MAX_PIECES];
+  __shared__ int npieces;
+  __shared__ zd fs[64][4];
+  __shared__ double cw[64][18];  // cos(j D) j = 0..16, then weight
+  const int lane = threadIdx.x;
+  const int ga = lane >> 4, gm = lane & 15;
+  for (long t = blockIdx.x; t < count; t += gridDim.x) {
+    const PairGeom g = geom[first + t];
+    const int2 dst = dest[first + t];
+    const PairInv v = pair_invariants(g);
+    if (lane == 0) {
+      double delta, re0;
+      singularity(v, delta, re0);
+      const double kabs = fmax(cabs_(k1), cabs_(k2));
+      const double om = M + kabs * sqrt(cabs_(g.rt * g.rs)) + 1.0;
+      const double hmax = omega_piece / om;      // longest piece for the oscillation
+      const double hmin = fmax(0.25 * delta, 1e-15);
+      int np = 0;
+      // graded breakpoints around c = re0 (both sides), then uniform pieces
+      double c = re0;
+      // left side [0, c]
+      {
+        double bl[128];
+        int nb = 0;
+        double x = c;
+        double h = hmin;
+        while (x > 0.0 && nb < 120) {
+          double step = fmin(h, hmax);
+          double nx = fmax(0.0, x - step);
+          bl[nb++] = nx;
+          x = nx;
+          h *= 2.0;
+        }
+        // pieces from 0 up to c in increasing order
+        for (int q = nb - 1; q >= 0; --q) {
+          double b = q == 0 ? c : bl[q - 1];
+          double a = bl[q];
+          if (b > a && np < DIRECT_MAX_PIECES) { pa[np] = a; pb[np] = b; ++np; }
+        }
+      }
+      // right side [c, pi]
+      {
+        double x = c, h = hmin;
+        while (x < PMLBIE_PI && np < DIRECT_MAX_PIECES) {
+          double step = fmin(h, hmax);
+          double nx = fmin(PMLBIE_PI, x + step);
+          if (PMLBIE_PI - nx < 1e-3 * step) nx = PMLBIE_PI;
+          pa[np] = x; pb[np] = nx; ++np;
+          x = nx;
+          h *= 2.0;
+        }
+      }
+      npieces = np;
+    }
+    __syncthreads();
+    const int nnodes = npieces * 16;
+    for (int pass = 0; pass * 16 * DIRECT_MPL <= M; ++pass) {
+      const int nbase = pass * 16 * DIRECT_MPL;
+      zd acc[DIRECT_MPL][4];
+#pragma unroll
+      for (int r = 0; r < DIRECT_MPL; ++r)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[r][s] = zd{0.0, 0.0};
+      for (int q0 = 0; q0 < nnodes; q0 += 64) {
+        const int q = q0 + lane;
+        if (q < nnodes) {
+          const int pc = q >> 4, j = q & 15;
+          const double a = pa[pc], b = pb[pc];
+          const double D = 0.5 * (a + b) + 0.5 * (b - a) * glx[j];
+          const double w = 0.5 * (b - a) * glw[j];
+          const double sh = sin(0.5 * D);
+          zd S1, K1, S2, K2;
+          kernel_sample(v, sh * sh, k1, S1, K1);
+          kernel_sample(v, sh * sh, k2, S2, K2);
+          fs[lane][0] = S1;
+          fs[lane][1] = K1;
+          fs[lane][2] = S2;
+          fs[lane][3] = K2;
+          const double c1 = cos(D);
+          double cm = 1.0, cc = c1;
+          cw[lane][0] = 1.0;
+          cw[lane][1] = c1;
+          for (int jj = 2; jj <= 16; ++jj) {
+            double cn = 2.0 * c1 * cc - cm;
+            cm = cc;
+            cc = cn;
+            cw[lane][jj] = cn;
+          }
+          // base cosines for this pass: recurrence stride 16 starts at nbase
+          cw[lane][17] = 2.0 * w;
+        } else {
+          fs[lane][0] = fs[lane][1] = fs[lane][2] = fs[lane][3] = zd{0.0, 0.0};
+          cw[lane][17] = 0.0;
+          for (int jj = 0; jj <= 16; ++jj) cw[lane][jj] = 1.0;
+        }
+        __syncthreads();
+        for (int u = ga; u < 64; u += 4) {
+          const double wq = cw[u][17];
+          if (wq == 0.0) continue;
+          const double c16 = cw[u][16];
+          // cos(g D) and cos((g - 16) D) = cos((16 - g) D), then advance to nbase
+          double cprev = cw[u][16 - gm], ccur = cw[u][gm];
+          for (int r = 0; r < pass * DIRECT_MPL; ++r) {
+            double cn = 2.0 * c16 * ccur - cprev;
+            cprev = ccur;
+            ccur = cn;
+          }
+          const zd f0 = fs[u][0], f1 = fs[u][1], f2 = fs[u][2], f3 = fs[u][3];
+#pragma unroll
+          for (int r = 0; r < DIRECT_MPL; ++r) {
+            const double cwq = wq * ccur;
+            acc[r][0] = acc[r][0] + cwq * f0;
+            acc[r][1] = acc[r][1] + cwq * f1;
+            acc[r][2] = acc[r][2] + cwq * f2;
+            acc[r][3] = acc[r][3] + cwq * f3;
+            double cn = 2.0 * c16 * ccur - cprev;
+            cprev = ccur;
+            ccur = cn;
+          }
+        }
+        __syncthreads();
+      }
+      // reduce the 4 node groups (lanes gm, gm + 16, gm + 32, gm + 48)
+#pragma unroll
+      for (int r = 0; r < DIRECT_MPL; ++r)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          zd a = acc[r][s];
+          a.re += __shfl_xor(a.re, 16);
+          a.im += __shfl_xor(a.im, 16);
+          a.re += __shfl_xor(a.re, 32);
+          a.im += __shfl_xor(a.im, 32);
+          acc[r][s] = a;
+        }
+      if (ga == 0) {
+#pragma unroll
+        for (int r = 0; r < DIRECT_MPL; ++r) {
+          const int n = nbase + gm + 16 * r;
+          if (n <= M) emit(o, dst, n, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Near panels: product integration of the modal kernels at auxiliary source
+// points against the Lagrange basis of the panel, plus the identity term of
+// the smooth-point solid angle (K1 - D1 = K1 + I, K2 - D2 = K2 - I).
+// One workgroup per (target, panel) job; raw modal values raw[q][s][n].
+__global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, int njobs,
+                                              const double* __restrict__ coef,
+                                              const zd* __restrict__ raw, int M, OutSpec o) {
+  const int jb = blockIdx.x;
+  if (jb >= njobs) return;
+  const NearJob J = jobs[jb];
+  const long N = o.n2 >> 1;
+  const int tot = 16 * (M + 1);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int l = e / (M + 1), n = e % (M + 1);
+    zd a0{0, 0}, a1{0, 0}, a2{0, 0}, a3{0, 0};
+    for (int q = J.q0; q < J.q1; ++q) {
+      const double c = coef[(long)q * 16 + l];
+      const zd* r = raw + (long)q * 4 * (M + 1);
+      a0 = a0 + c * r[n];
+      a1 = a1 + c * r[(M + 1) + n];
+      a2 = a2 + c * r[2 * (M + 1) + n];
+      a3 = a3 + c * r[3 * (M + 1) + n];
+    }
+    const long i = J.target, col = (long)J.panel * 16 + l;
+    zd* An = o.A + (long)n * o.mstride;
+    zd k1v = a1, k2v = a3;
+    if (col == i) {
+      k1v = k1v + 1.0;
+      k2v = k2v - 1.0;
+    }
+    An[col * o.n2 + i] = k1v;
+    An[(N + col) * o.n2 + i] = -a0;
+    An[col * o.n2 + N + i] = k2v;
+    An[(N + col) * o.n2 + N + i] = -a2;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Host launchers.
+template <int NT>
+static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
+                         const OutSpec& o, WorkList split, WorkList direct, hipStream_t st) {
+  long total = (long)nd.N * nd.N;
+  int grid = (int)std::min<long>(total, 256L * 40);
+  hipLaunchKernelGGL(k_grid_far<NT>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
+                     direct);
+}
+
+void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
+                     const zd* tw, zd* A, long mstride, const double* W, WorkList split,
+                     WorkList direct, hipStream_t st) {
+  OutSpec o{A, 2L * nd.N, mstride, W, nullptr, cp.M};
+  switch (nt) {
+    case 64: launch_far_t<64>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 128: launch_far_t<128>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 256: launch_far_t<256>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 512: launch_far_t<512>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 1024: launch_far_t<1024>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 2048: launch_far_t<2048>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    default: break;
+  }
+}
+
+template <int NT>
+static void launch_list_far_t(const PairGeom* geom, const int2* dest, long first, long count,
+                              zd k1, zd k2, const zd* tw, const OutSpec& o, hipStream_t st) {
+  int grid = (int)std::min<long>(count, 256L * 40);
+  hipLaunchKernelGGL(k_list_far<NT>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2,
+                     tw, o);
+}
+
+void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
+                     zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
+                     zd* raw, hipStream_t st) {
+  if (count <= 0) return;
+  OutSpec o{A, n2, mstride, W, raw, M};
+  switch (nt) {
+    case 64: launch_list_far_t<64>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 128: launch_list_far_t<128>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 256: launch_list_far_t<256>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 512: launch_list_far_t<512>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 1024: launch_list_far_t<1024>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 2048: launch_list_far_t<2048>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    default: break;
+  }
+}
+
+void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
+                           zd* phat, zd* qscr, hipStream_t st) {
+  if (count <= 0) return;
+  int blocks = (int)((count + 63) / 64);
+  hipLaunchKernelGGL(k_split_singular, dim3(blocks), dim3(64), 0, st, geom, first, count, MQ,
+                     zhat, phat, qscr);
+}
+
+template <int NT>
+static void launch_split_t(const PairGeom* geom, const int2* dest, long first, long count, int M,
+                           int B, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat,
+                           const zd* phat, const OutSpec& o, hipStream_t st) {
+  int grid = (int)std::min<long>(count, 256L * 24);
+  hipLaunchKernelGGL(k_split<NT>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, B,
+                     MQ, k1, k2, tw, zhat, phat, o);
+}
+
+void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
+                  int B, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
+                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st) {
+  if (count <= 0) return;
+  OutSpec o{A, n2, mstride, W, raw, M};
+  switch (nt) {
+    case 64: launch_split_t<64>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 128: launch_split_t<128>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 256: launch_split_t<256>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 512: launch_split_t<512>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 1024: launch_split_t<1024>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    default: break;
+  }
+}
+
+void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, zd k1,
+                   zd k2, const double* glx, const double* glw, zd* A, long n2, long mstride,
+                   const double* W, zd* raw, double omega_piece, hipStream_t st) {
+  if (count <= 0) return;
+  OutSpec o{A, n2, mstride, W, raw, M};
+  int grid = (int)std::min<long>(count, 256L * 24);
+  hipLaunchKernelGGL(k_direct, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, k1, k2,
+                     glx, glw, o, omega_piece);
+}
+
+void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, zd* A,
+                 long n2, long mstride, hipStream_t st) {
+  if (njobs <= 0) return;
+  OutSpec o{A, n2, mstride, nullptr, nullptr, M};
+  hipLaunchKernelGGL(k_near, dim3(njobs), dim3(256), 0, st, jobs, njobs, coef, raw, M, o);
+}
+
+}  // namespace pmlbie

@@ -1,0 +1,213 @@
+// Device numerics of the modal-kernel generator: the PML-complexified
+// Green's function and its conormal derivative (Sec. 3.1), the stable
+// complex distance (Sec. 4.3), the kernel split S = Z (H1 + i H2),
+// K = D (H3 + i H4) of Sec. 4.1 with its smooth parts, and the semi-analytic
+// modes Z_m, D_m of the singular factors through half-integer-degree
+// Legendre functions Q_{m-1/2} (toroidal functions) evaluated from Carlson's
+// symmetric elliptic integrals and three-term recurrences.
+#pragma once
+#include "cplx.h"
+
+#ifndef PMLBIE_PI
+#define PMLBIE_PI 3.141592653589793238462643383279502884
+#endif
+
+// Geometry of one (target, source) pair in the stretched coordinates.
+struct PairGeom {
+  zd rt, rs;    // rho~ of target and source
+  zd drho, dz;  // rho~_t - rho~_s and z~_t - z~_s (formed from differences)
+  zd nr, nz;    // conormal of the source: n_rho, n_z
+};
+
+// Invariants of a pair used by every sample: R^2 = d2 + c4 sin^2(D/2) and the
+// conormal numerator N(D) = N0 + N1 sin^2(D/2).
+struct PairInv {
+  zd d2, c4, N0, N1;
+};
+
+HD PairInv pair_invariants(const PairGeom& g) {
+  PairInv v;
+  v.d2 = g.drho * g.drho + g.dz * g.dz;
+  v.c4 = 4.0 * (g.rt * g.rs);
+  v.N0 = -(g.nr * g.drho + g.nz * g.dz);
+  v.N1 = 2.0 * (g.nr * g.rt);
+  return v;
+}
+
+// G~ and dG~/dnu_c(r') at one azimuth difference (s2 = sin^2(D/2)).
+HD void kernel_sample(const PairInv& v, double s2, zd k, zd& S, zd& K) {
+  zd R2 = v.d2 + s2 * v.c4;
+  zd R = csqrt_(R2);
+  zd ikR = zd{0.0, 1.0} * (k * R);
+  zd e = cexp_(ikR);
+  zd inv4piR = inv(R) * (0.25 / PMLBIE_PI);
+  S = e * inv4piR;
+  zd N = v.N0 + s2 * v.N1;
+  K = N * e * (ikR - 1.0) * inv4piR * inv(R2);
+}
+
+// sin(q)/q, entire in q^2
+HD zd sinc_(zd q) {
+  if (cabs1(q) < 0.5) {
+    zd q2 = q * q, t = zd{1.0, 0.0}, s = zd{1.0, 0.0};
+    for (int j = 1; j <= 9; ++j) {
+      t = t * q2 * (-1.0 / ((2.0 * j) * (2.0 * j + 1.0)));
+      s = s + t;
+    }
+    return s;
+  }
+  return csin_(q) / q;
+}
+// (sin q - q cos q)/q^3, entire in q^2
+HD zd s3_(zd q) {
+  if (cabs1(q) < 1.0) {
+    // sum_j (-1)^{j+1} 2j / (2j+1)! q^{2j-2}, j >= 1
+    zd q2 = q * q, pw = zd{1.0, 0.0}, s = zd{0.0, 0.0};
+    double fact = 6.0;  // (2j+1)! for j = 1
+    for (int j = 1; j <= 11; ++j) {
+      double c = ((j & 1) ? 1.0 : -1.0) * (2.0 * j) / fact;
+      s = s + c * pw;
+      pw = pw * q2;
+      fact *= (2.0 * j + 2.0) * (2.0 * j + 3.0);
+    }
+    return s;
+  }
+  return (csin_(q) - q * ccos_(q)) / (q * q * q);
+}
+
+// Split coefficients of the double-layer singular factor:
+// D = -(e0/R^3 + e1/R)/(4 pi), with e0 = N0 - n_rho' d2/(2 rho~'), e1 = n_rho'/(2 rho~').
+struct SplitCoef {
+  zd e0, e1;
+};
+HD SplitCoef split_coef(const PairGeom& g, const PairInv& v) {
+  zd h = inv(2.0 * g.rs);
+  SplitCoef c;
+  c.e1 = g.nr * h;
+  c.e0 = v.N0 - c.e1 * v.d2;
+  return c;
+}
+
+// Smooth parts of the split at one sample for wavenumber k:
+// H1 = cos kR, ZH2 = sin(kR)/(4 pi R), H3 = cos kR + kR sin kR,
+// DH4 = D (sin kR - kR cos kR).
+HD void split_sample(const PairInv& v, const SplitCoef& sc, double s2, zd k, zd& H1, zd& ZH2,
+                     zd& H3, zd& DH4) {
+  zd R2 = v.d2 + s2 * v.c4;
+  zd R = csqrt_(R2);
+  zd q = k * R;
+  zd cq = ccos_(q), sq = csin_(q);
+  H1 = cq;
+  H3 = cq + q * sq;
+  ZH2 = k * sinc_(q) * (0.25 / PMLBIE_PI);
+  zd s3 = s3_(q);
+  zd k3 = k * k * k;
+  // D (sin q - q cos q) = -(1/4pi) (e0 k^3 s3 + e1 k q^2 s3)
+  DH4 = (sc.e0 * k3 + sc.e1 * k * (q * q)) * s3 * (-0.25 / PMLBIE_PI);
+}
+
+// ---------------------------------------------------------------------------
+// Carlson's symmetric elliptic integrals for complex arguments (duplication
+// algorithm, Carlson 1995; valid for arguments off the negative real axis).
+HD zd carlson_rf(zd x, zd y, zd z) {
+  zd A0 = (x + y + z) * (1.0 / 3.0);
+  double Qm = fmax(cabs_(A0 - x), fmax(cabs_(A0 - y), cabs_(A0 - z))) * 600.0;
+  zd xm = x, ym = y, zm = z, Am = A0;
+  double p4 = 1.0;
+  for (int it = 0; it < 60 && p4 * Qm > cabs_(Am); ++it) {
+    zd sx = csqrt_(xm), sy = csqrt_(ym), sz = csqrt_(zm);
+    zd lam = sx * sy + sx * sz + sy * sz;
+    xm = (xm + lam) * 0.25;
+    ym = (ym + lam) * 0.25;
+    zm = (zm + lam) * 0.25;
+    Am = (Am + lam) * 0.25;
+    p4 *= 0.25;
+  }
+  zd iA = inv(Am);
+  zd X = (A0 - x) * iA * p4, Y = (A0 - y) * iA * p4;
+  zd Z = -(X + Y);
+  zd E2 = X * Y - Z * Z, E3 = X * Y * Z;
+  zd ser = zd{1.0, 0.0} - E2 * (1.0 / 10.0) + E3 * (1.0 / 14.0) + E2 * E2 * (1.0 / 24.0) -
+           E2 * E3 * (3.0 / 44.0);
+  return ser * inv(csqrt_(Am));
+}
+
+HD zd carlson_rd(zd x, zd y, zd z) {
+  zd A0 = (x + y + 3.0 * z) * (1.0 / 5.0);
+  double Qm = fmax(cabs_(A0 - x), fmax(cabs_(A0 - y), cabs_(A0 - z))) * 1000.0;
+  zd xm = x, ym = y, zm = z, Am = A0, sum = zd{0.0, 0.0};
+  double p4 = 1.0;
+  for (int it = 0; it < 60 && p4 * Qm > cabs_(Am); ++it) {
+    zd sx = csqrt_(xm), sy = csqrt_(ym), sz = csqrt_(zm);
+    zd lam = sx * sy + sx * sz + sy * sz;
+    sum = sum + p4 * inv(sz * (zm + lam));
+    xm = (xm + lam) * 0.25;
+    ym = (ym + lam) * 0.25;
+    zm = (zm + lam) * 0.25;
+    Am = (Am + lam) * 0.25;
+    p4 *= 0.25;
+  }
+  zd iA = inv(Am);
+  zd X = (A0 - x) * iA * p4, Y = (A0 - y) * iA * p4;
+  zd Z = -(X + Y) * (1.0 / 3.0);
+  zd XY = X * Y, Z2 = Z * Z;
+  zd E2 = XY - 6.0 * Z2;
+  zd E3 = (3.0 * XY - 8.0 * Z2) * Z;
+  zd E4 = 3.0 * (XY - Z2) * Z2;
+  zd E5 = XY * Z2 * Z;
+  zd ser = zd{1.0, 0.0} - E2 * (3.0 / 14.0) + E3 * (1.0 / 6.0) + E2 * E2 * (9.0 / 88.0) -
+           E4 * (3.0 / 22.0) - E2 * E3 * (9.0 / 52.0) + E5 * (3.0 / 26.0);
+  return p4 * ser * iA * inv(csqrt_(Am)) + 3.0 * sum;
+}
+
+// Q[m] = Q_{m-1/2}(chi) for m = 0..mq, chi = 1 + chim1 (chim1 passed exactly).
+// Q_{-1/2} = sqrt2 RF(0, chi-1, chi+1); Q_{1/2} from RF and RD; higher
+// degrees by forward recurrence when it is stable over the range, else by the
+// backward (Miller) ratio recurrence normalised by Q_{-1/2}.
+HD void legendre_q_half(zd chim1, int mq, zd* Q) {
+  const double rt2 = 1.4142135623730950488;
+  zd chi = chim1 + 1.0;
+  zd zero = zd{0.0, 0.0};
+  zd rf = carlson_rf(zero, chim1, chim1 + 2.0);
+  Q[0] = rt2 * rf;
+  if (mq == 0) return;
+  zd s = csqrt_(chim1) * csqrt_(chim1 + 2.0);
+  double La = log(fmax(cabs_(chi + s), cabs_(chi - s)));  // -log of the decay ratio
+  if (2.0 * mq * La <= 6.0) {
+    zd rd = carlson_rd(zero, chim1, chim1 + 2.0);
+    Q[1] = rt2 * (-rf + (2.0 / 3.0) * (chim1 + 2.0) * rd);
+    for (int m = 1; m < mq; ++m) {
+      // (m + 1/2) Q_{m+1/2} = 2 m chi Q_{m-1/2} - (m - 1/2) Q_{m-3/2}
+      Q[m + 1] = ((2.0 * m) * chi * Q[m] - (m - 0.5) * Q[m - 1]) * (1.0 / (m + 0.5));
+    }
+  } else {
+    int ns = mq + (int)ceil(19.0 / La) + 8;
+    if (ns > mq + 6000) ns = mq + 6000;
+    zd r = zero;  // r_{m} = Q_{m-1/2} / Q_{m-3/2}
+    for (int m = ns; m > mq; --m) r = (m - 0.5) * inv((2.0 * m) * chi - (m + 0.5) * r);
+    // keep the ratios for m = mq..1 in Q[m] temporarily
+    for (int m = mq; m >= 1; --m) {
+      r = (m - 0.5) * inv((2.0 * m) * chi - (m + 0.5) * r);
+      Q[m] = r;
+    }
+    for (int m = 1; m <= mq; ++m) Q[m] = Q[m] * Q[m - 1];
+  }
+}
+
+// Singularity distance of the azimuthal integrand: the zeros of R^2 sit at
+// sin^2(D*/2) = -d2/c4; returns |Im D*| and Re D* (folded into [0, pi]).
+HD void singularity(const PairInv& v, double& delta, double& re0) {
+  if (v.c4.re == 0.0 && v.c4.im == 0.0) {  // a point on the axis: no azimuthal dependence
+    delta = 1e300;
+    re0 = 0.0;
+    return;
+  }
+  zd w = -(v.d2 / v.c4);
+  zd sw = csqrt_(w);
+  zd t = zd{0.0, 1.0} * sw + csqrt_(zd{1.0, 0.0} - w);
+  // asin(sw) = -i log(t) = arg(t) - i log|t|
+  double im = -log(cabs_(t));
+  double re = atan2(t.im, t.re);
+  delta = 2.0 * fabs(im);
+  re0 = fmin(fabs(2.0 * re), PMLBIE_PI);
+}

@@ -1,0 +1,18 @@
+// Right-hand sides, coupled-system data flow and field synthesis.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "lu.h"
+#include "modal_math.h"
+
+namespace pmlbie {
+
+void launch_rhs_gather_point(const zd* raw, int N, int M, int nrhs, zd* b1, zd* b2, hipStream_t st);
+void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
+                      const zd* b2, zd* rhs, hipStream_t st);
+void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,
+                    zd* u2, zd* p2, hipStream_t st);
+void launch_field(const zd* raw, const double* W, int N, int M, int nrhs, int npts, const int* medium,
+                  const double* theta, const zd* u1, const zd* p1, const zd* u2, const zd* p2,
+                  zd* out, hipStream_t st);
+
+}  // namespace pmlbie

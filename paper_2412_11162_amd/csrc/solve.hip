@@ -1,0 +1,134 @@
+// Right-hand sides, coupled-system data flow and field synthesis (Sec. 4.2).
+#include "solve.h"
+
+namespace pmlbie {
+
+// b1 = -[u_tot0]_n, b2 = -[du_tot0/dnu_c]_n from the raw modal values of the
+// point-source pairs: raw[(inc * 2N + i)][s][n] with s = S1 for the pairs
+// (node i, source) and s = K1 for the swapped pairs (source, node i) whose
+// source-side conormal is the node's (the conormal derivative at the target
+// of G~(r, r*) by the symmetry of G~).
+__global__ void k_rhs_gather_point(const zd* __restrict__ raw, int N, int M, int nrhs,
+                                   zd* __restrict__ b1, zd* __restrict__ b2) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long tot = (long)(M + 1) * nrhs * N;
+  if (e >= tot) return;
+  const int i = (int)(e % N);
+  const int r = (int)((e / N) % nrhs);
+  const int n = (int)(e / ((long)N * nrhs));
+  const long q1 = (long)r * 2 * N + i, q2 = q1 + N;
+  b1[e] = -raw[q1 * 4 * (M + 1) + n];
+  b2[e] = -raw[q2 * 4 * (M + 1) + (M + 1) + n];
+}
+
+// rhs[n][r] = [0 ; Alow_n [b1; b2]], Alow_n = [K2 - D2, -S2] (N x 2N, column-major).
+__global__ __launch_bounds__(256) void k_lower_rhs(const zd* __restrict__ Alow, long lstride,
+                                                   int N, int nrhs, const zd* __restrict__ b1,
+                                                   const zd* __restrict__ b2, zd* __restrict__ rhs) {
+  const int n = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const zd* A = Alow + (long)n * lstride;
+  const zd* x1 = b1 + (long)n * nrhs * N;
+  const zd* x2 = b2 + (long)n * nrhs * N;
+  zd* out = rhs + (long)n * nrhs * 2 * N;
+  __shared__ zd xs[64][LU_MAX_RHS];
+  zd acc[LU_MAX_RHS];
+  for (int r = 0; r < LU_MAX_RHS; ++r) acc[r] = zd{0.0, 0.0};
+  for (int c0 = 0; c0 < 2 * N; c0 += 64) {
+    for (int e = threadIdx.x; e < 64 * nrhs; e += blockDim.x) {
+      const int c = c0 + (e & 63), r = e >> 6;
+      zd v{0.0, 0.0};
+      if (c < 2 * N) v = c < N ? x1[(long)r * N + c] : x2[(long)r * N + c - N];
+      xs[e & 63][r] = v;
+    }
+    __syncthreads();
+    if (i < N) {
+      const int cmax = min(64, 2 * N - c0);
+      for (int c = 0; c < cmax; ++c) {
+        const zd a = A[(long)(c0 + c) * N + i];
+        for (int r = 0; r < nrhs; ++r) acc[r] = cfma(a, xs[c][r], acc[r]);
+      }
+    }
+    __syncthreads();
+  }
+  if (i < N)
+    for (int r = 0; r < nrhs; ++r) {
+      out[(long)r * 2 * N + i] = zd{0.0, 0.0};
+      out[(long)r * 2 * N + N + i] = acc[r];
+    }
+}
+
+// u1 = x[0:N], phi1 = x[N:2N], u2 = u1 - b1, phi2 = phi1 - b2 (transmission
+// conditions), layout [mode][rhs][node].
+__global__ void k_outputs(const zd* __restrict__ x, const zd* __restrict__ b1,
+                          const zd* __restrict__ b2, int N, int M, int nrhs, zd* __restrict__ u1,
+                          zd* __restrict__ p1, zd* __restrict__ u2, zd* __restrict__ p2) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long tot = (long)(M + 1) * nrhs * N;
+  if (e >= tot) return;
+  const int i = (int)(e % N);
+  const long nr = e / N;  // mode * nrhs + r
+  const zd xu = x[nr * 2 * N + i], xp = x[nr * 2 * N + N + i];
+  if (u1) u1[e] = xu;
+  if (p1) p1[e] = xp;
+  if (u2) u2[e] = xu - b1[e];
+  if (p2) p2[e] = xp - b2[e];
+}
+
+// Field modes by the Green representation (Sec. 4.2, eq. eqfujs) and the
+// synthesis u = (1/2pi) sum_n u_n e^{i n theta} with u_{-n} = u_n:
+//   u_n(x) = sgn sum_l W_l [S_n(x, r_l) phi_n(r_l) - K_n(x, r_l) u_n(r_l)],
+// sgn = +1 in the upper medium, -1 in the lower one.  raw[(p * N + l)][s][n].
+__global__ void k_field(const zd* __restrict__ raw, const double* __restrict__ W, int N, int M,
+                        int nrhs, int npts, const int* __restrict__ medium,
+                        const double* __restrict__ theta, const zd* __restrict__ u1,
+                        const zd* __restrict__ p1, const zd* __restrict__ u2,
+                        const zd* __restrict__ p2, zd* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npts * nrhs) return;
+  const int p = e % npts, r = e / npts;
+  const int md = medium[p];
+  const double sgn = md == 1 ? 1.0 : -1.0;
+  const int sS = md == 1 ? 0 : 2, sK = md == 1 ? 1 : 3;
+  const zd* U = md == 1 ? u1 : u2;
+  const zd* P = md == 1 ? p1 : p2;
+  zd tot{0.0, 0.0};
+  for (int n = 0; n <= M; ++n) {
+    zd un{0.0, 0.0};
+    for (int l = 0; l < N; ++l) {
+      const zd* rw = raw + ((long)p * N + l) * 4 * (M + 1);
+      const long idx = ((long)n * nrhs + r) * N + l;
+      un = un + W[l] * (rw[sS * (M + 1) + n] * P[idx] - rw[sK * (M + 1) + n] * U[idx]);
+    }
+    const double f = (n == 0 ? 1.0 : 2.0) * cos(n * theta[p]) * sgn * (0.5 / PMLBIE_PI);
+    tot = tot + f * un;
+  }
+  out[e] = tot;
+}
+
+void launch_rhs_gather_point(const zd* raw, int N, int M, int nrhs, zd* b1, zd* b2, hipStream_t st) {
+  const long tot = (long)(M + 1) * nrhs * N;
+  hipLaunchKernelGGL(k_rhs_gather_point, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, raw,
+                     N, M, nrhs, b1, b2);
+}
+void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
+                      const zd* b2, zd* rhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_lower_rhs, dim3((N + 255) / 256, modes), dim3(256), 0, st, Alow, lstride, N,
+                     nrhs, b1, b2, rhs);
+}
+void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,
+                    zd* u2, zd* p2, hipStream_t st) {
+  const long tot = (long)(M + 1) * nrhs * N;
+  hipLaunchKernelGGL(k_outputs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, x, b1, b2, N,
+                     M, nrhs, u1, p1, u2, p2);
+}
+void launch_field(const zd* raw, const double* W, int N, int M, int nrhs, int npts, const int* medium,
+                  const double* theta, const zd* u1, const zd* p1, const zd* u2, const zd* p2,
+                  zd* out, hipStream_t st) {
+  const int tot = npts * nrhs;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_field, dim3((tot + 63) / 64), dim3(64), 0, st, raw, W, N, M, nrhs, npts,
+                     medium, theta, u1, p1, u2, p2, out);
+}
+
+}  // namespace pmlbie

@@ -1,0 +1,136 @@
+"""Thin Python layer over the C ABI (argument marshalling only; every step
+of the computation runs in the HIP library)."""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+
+class PmlbieError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("pmlbie error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Solver:
+    """One context of the HIP library on one device and stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream = None):
+        self.L = B.load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        rc = self.L.pmlbie_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise PmlbieError(rc, "pmlbie_create failed")
+        self.h = h
+        self.N = 0
+        self.M = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pmlbie_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc: int):
+        if rc != 0:
+            raise PmlbieError(rc, self.L.pmlbie_last_error(self.h).decode())
+
+    # -- the five calls of the method --------------------------------------
+    def set_geometry(self, bumps: Sequence[Tuple[float, float, float]], cos_freq: float, rho_c: float,
+                     seg_breaks: Sequence[float], nodes_per_segment: int):
+        b = np.ascontiguousarray(np.array(bumps, dtype=np.float64).reshape(-1))
+        s = np.ascontiguousarray(np.array(seg_breaks, dtype=np.float64))
+        self._chk(self.L.pmlbie_set_geometry(self.h, len(bumps), _p(b), float(cos_freq), float(rho_c),
+                                             _p(s), int(nodes_per_segment)))
+
+    def set_media_pml(self, k1: complex, k2: complex, a1: float, T: float, S: float, a2: float,
+                      T2: float, S2: float, p: int = 6):
+        k1, k2 = complex(k1), complex(k2)
+        self._chk(self.L.pmlbie_set_media_pml(self.h, k1.real, k1.imag, k2.real, k2.imag, a1, T, S,
+                                              a2, T2, S2, int(p)))
+        self.N = self.nodes().shape[0]
+
+    def build_modal_operators(self, n_theta: int, precision: int = B.PMLBIE_FP64, flags: int = 0):
+        self._chk(self.L.pmlbie_build_modal_operators(self.h, int(n_theta), int(precision), int(flags)))
+        self.M = int(self.info()[1])
+
+    def solve_modes(self, incidences):
+        n = len(incidences)
+        arr = (B.pmlbie_incidence * n)()
+        for r, inc in enumerate(incidences):
+            if inc[0] == "point":
+                arr[r].kind = 0
+                arr[r].p[0], arr[r].p[1] = float(inc[1]), float(inc[2])
+            else:
+                arr[r].kind = 1
+                arr[r].p[0] = float(inc[1])
+        shape = (self.M + 1, n, self.N)
+        dev = torch.device("cuda", self.device)
+        outs = [torch.empty(shape, dtype=torch.complex128, device=dev) for _ in range(4)]
+        self._chk(self.L.pmlbie_solve_modes(self.h, n, arr, *[ctypes.c_void_p(o.data_ptr()) for o in outs]))
+        return tuple(outs)
+
+    def evaluate_field(self, rtz: np.ndarray, n_rhs: int) -> np.ndarray:
+        rtz = np.ascontiguousarray(np.asarray(rtz, dtype=np.float64).reshape(-1, 3))
+        out = np.zeros((n_rhs, rtz.shape[0]), dtype=np.complex128)
+        self._chk(self.L.pmlbie_evaluate_field(self.h, rtz.shape[0], _p(rtz), _p(out)))
+        return out
+
+    # -- inspection ----------------------------------------------------------
+    def info(self) -> np.ndarray:
+        a = np.zeros(9, dtype=np.int64)
+        self._chk(self.L.pmlbie_get_info(self.h, _p(a)))
+        return a
+
+    def nodes(self) -> np.ndarray:
+        n = int(self.info()[0])
+        a = np.zeros((n, 13))
+        self._chk(self.L.pmlbie_get_nodes(self.h, _p(a)))
+        return a
+
+    def modal_kernels(self, geom: np.ndarray) -> torch.Tensor:
+        geom = np.ascontiguousarray(np.asarray(geom, dtype=np.float64).reshape(-1, 12))
+        out = torch.empty((geom.shape[0], 4, self.M + 1), dtype=torch.complex128,
+                          device=torch.device("cuda", self.device))
+        self._chk(self.L.pmlbie_modal_kernels(self.h, geom.shape[0], _p(geom), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def get_operator(self, mode: int) -> torch.Tensor:
+        n2 = 2 * self.N
+        out = torch.empty((n2, n2), dtype=torch.complex128, device=torch.device("cuda", self.device))
+        self._chk(self.L.pmlbie_get_operator(self.h, int(mode), ctypes.c_void_p(out.data_ptr())))
+        return out.t()  # column-major storage -> row/column indexing
+
+    def stats(self):
+        s = np.zeros(16)
+        c = np.zeros(16)
+        self._chk(self.L.pmlbie_get_stats(self.h, _p(s), _p(c)))
+        return s, c
+
+
+def from_workload(wl, device: int = 0, n_theta: int = None, precision: int = B.PMLBIE_FP64,
+                  flags: int = 0, build: bool = True) -> Solver:
+    """Set up a solver for one of the synthetic workloads."""
+    s = Solver(device)
+    s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
+    s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
+    if build:
+        s.build_modal_operators(n_theta or wl.n_theta, precision, flags)
+    return s
