@@ -31,6 +31,7 @@
  * Sec. 4.1 (nu_rho = 0 wherever sigma_1 != 0, and sigma_2 = 0 on the curve).
  */
 #include <complex.h>
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -94,9 +95,10 @@ typedef struct { double a, b, err, absint; int depth; } ivl;
 /*
  * Globally adaptive vector quadrature: keep bisecting the interval with the
  * largest error estimate until the summed estimate is below
- * max(abstol, reltol * max_j |I_j|, 1e-15 * int |f|) -- the last term is the
- * rounding floor below which no quadrature of f can resolve the integral --
- * or the interval budget is spent.
+ * max(abstol, reltol * max_j |I_j|, 200 eps int |f|) -- the last term is the
+ * rounding floor below which no quadrature of f can resolve the integral; an
+ * interval whose estimate is within 50 eps of its own int |f| is not split
+ * further -- or the interval budget is spent.
  * Returns the number of intervals used (negative if the budget ran out).
  */
 static int adapt(vfun f, void *ctx, int nout, const double *brk, int nbrk,
@@ -121,12 +123,14 @@ static int adapt(vfun f, void *ctx, int nout, const double *brk, int nbrk,
     for (int s = 0; s < n; ++s) {
       tot += iv[s].err;
       absint += iv[s].absint;
-      if (iv[s].err > werr && iv[s].depth < 200) { werr = iv[s].err; worst = s; }
+      /* an interval whose estimate is at its own rounding level is final */
+      int at_floor = iv[s].err <= 50.0 * DBL_EPSILON * iv[s].absint;
+      if (iv[s].err > werr && iv[s].depth < 200 && !at_floor) { werr = iv[s].err; worst = s; }
       cplx *r = store + (size_t)s * nout;
       for (int j = 0; j < nout; ++j) result[j] += r[j];
     }
     for (int j = 0; j < nout; ++j) { double m = cabs(result[j]); if (m > scale) scale = m; }
-    double tol = fmax(abstol, fmax(reltol * scale, 1e-15 * absint));
+    double tol = fmax(abstol, fmax(reltol * scale, 200.0 * DBL_EPSILON * absint));
     if (tot <= tol || worst < 0) break;
     if (n + 1 >= maxivl) { ok = 0; break; }
     double a = iv[worst].a, b = iv[worst].b, m = 0.5 * (a + b);
