@@ -3,7 +3,7 @@
 
 One step = the whole hot path on the paper-scale workload (k1 = 10, k2 = 15,
 h = 0.5 exp(-rho^2/2) cos(2 rho), PML rho in [4, 5.5], sigma0 = 3,
-2048 curve nodes, 256 azimuthal samples -> modes 0..128, point source at
+2048 curve nodes, 256 azimuthal samples with modes 0..128 kept, point source at
 (0.3, 0, 1.2)): geometry and media set-up, pair x theta sampling of the
 kernels, far / split / direct modal kernels, near-panel product integration,
 assembly, per-mode LU of the 129 systems of size 4096, right-hand sides and
@@ -82,7 +82,7 @@ def main():
     def step():
         s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
         s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
-        s.build_modal_operators(wl.n_theta)
+        s.build_modal_operators(wl.n_theta, wl.m_max)
         return s.solve_modes(list(wl.incidences))
 
     for _ in range(args.warmup):

@@ -87,8 +87,8 @@ int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_
                          double k2_im, double a1, double T, double S, double a2, double T2,
                          double S2, int p);
 
-/* Build the modal operators of modes n = 0..m_max with m_max = n_theta / 4
- * (n_theta azimuthal samples, a power of two >= 16), assemble the per-mode
+/* Build the modal operators of modes n = 0..m_max (n_theta azimuthal
+ * samples, a power of two >= 16; 0 <= m_max <= n_theta / 2), assemble the per-mode
  * 2N x 2N systems [[K1 + I, -S1], [K2 - I, -S2]] (Sec. 4.1-4.2) and factor
  * them (partial-pivoting LU).  The kernels are sampled on every
  * (target, source, theta) triple, split into singular and smooth parts where
@@ -99,7 +99,8 @@ int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_
  * pmlbie_get_operator.
  * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOMEM, PMLBIE_EDEVICE,
  * PMLBIE_ESINGULAR (a zero pivot; pmlbie_last_error names the mode). */
-int pmlbie_build_modal_operators(pmlbie_ctx* ctx, int n_theta, int precision, int flags);
+int pmlbie_build_modal_operators(pmlbie_ctx* ctx, int n_theta, int m_max, int precision,
+                                 int flags);
 
 /* One incidence: kind 0 = point source at (rho, 0, z) = (p[0], p[1]) in the
  * upper medium (p[0] >= 0); kind 1 = plane wave with polar angle p[0]
@@ -147,7 +148,7 @@ int pmlbie_get_nodes(const pmlbie_ctx* ctx, double* out);
  * complex128, layout [pair][S1, K1, S2, K2][mode]. */
 int pmlbie_modal_kernels(pmlbie_ctx* ctx, int n_pairs, const double* geom, void* d_out);
 
-/* Copy the assembled (unfactored) matrix of mode n (column-major 2N x 2N
+/* Copy the assembled (unfactored) matrix of mode n (row-major 2N x 2N
  * complex128) to d_out; needs PMLBIE_KEEP_OPERATORS at build. */
 int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
 

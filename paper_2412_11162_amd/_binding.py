@@ -52,7 +52,7 @@ def load():
     L.pmlbie_last_error.restype = ctypes.c_char_p
     L.pmlbie_set_geometry.argtypes = [P, i, P, d, d, P, i]
     L.pmlbie_set_media_pml.argtypes = [P, d, d, d, d, d, d, d, d, d, d, i]
-    L.pmlbie_build_modal_operators.argtypes = [P, i, i, i]
+    L.pmlbie_build_modal_operators.argtypes = [P, i, i, i, i]
     L.pmlbie_solve_modes.argtypes = [P, i, ctypes.POINTER(pmlbie_incidence), P, P, P, P]
     L.pmlbie_evaluate_field.argtypes = [P, i, P, P]
     L.pmlbie_get_info.argtypes = [P, P]

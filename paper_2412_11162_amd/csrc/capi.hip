@@ -297,17 +297,19 @@ int pmlbie_set_media_pml(pmlbie_ctx* c, double k1_re, double k1_im, double k2_re
   });
 }
 
-int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int precision, int flags) {
+int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int precision, int flags) {
   return guarded(c, [&]() -> int {
     if (c->stage < 2) return fail(c, PMLBIE_ESTATE, "build: set geometry and media first");
     if (n_theta < 16 || (n_theta & (n_theta - 1)))
       return fail(c, PMLBIE_EINVAL, "build: n_theta must be a power of two >= 16");
+    if (m_max < 0 || m_max > n_theta / 2)
+      return fail(c, PMLBIE_EINVAL, "build: need 0 <= m_max <= n_theta / 2");
     if (precision != PMLBIE_FP64)
       return fail(c, PMLBIE_EINVAL, "build: only PMLBIE_FP64 is available in this library");
     auto t_all = std::chrono::steady_clock::now();
     c->stage = 2;
     c->n_theta = n_theta;
-    c->M = n_theta / 4;
+    c->M = m_max;
     c->precision = precision;
     c->flags = flags;
     const int N = c->N, M = c->M;
@@ -431,8 +433,9 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int precision, int 
 
     // keep what the solve needs: the lower block row [K2 - D2, -S2]
     c->Alow.alloc((size_t)(M + 1) * N * n2);
-    HIPCHK(hipMemcpy2DAsync(c->Alow.p, N * sizeof(zd), c->A.p + N, n2 * sizeof(zd), N * sizeof(zd),
-                            (size_t)(M + 1) * n2, hipMemcpyDeviceToDevice, c->stream));
+    for (int n = 0; n <= M; ++n)
+      HIPCHK(hipMemcpyAsync(c->Alow.p + (size_t)n * N * n2, c->A.p + (size_t)n * ms + (size_t)N * n2,
+                            (size_t)N * n2 * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
     if (flags & PMLBIE_KEEP_OPERATORS) {
       c->Akeep.alloc((size_t)(M + 1) * ms);
       HIPCHK(hipMemcpyAsync(c->Akeep.p, c->A.p, (size_t)(M + 1) * ms * sizeof(zd),

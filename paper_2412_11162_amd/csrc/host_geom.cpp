@@ -114,16 +114,25 @@ static double sigma_int(const Geometry& g, double lo, double hi) {
   return s;
 }
 double Geometry::Iint(double r) const { return sigma_int(*this, 0.0, r); }
+// Panels never straddle a1 (a segment break), so sigma is smooth on each and
+// one 16-point rule from the panel start is exact to rounding.
+double Geometry::Ipanel(int p, double r) const {
+  const double a = pa[p];
+  if (r <= pml.a1) return 0.0;
+  double s = 0.0;
+  for (int j = 0; j < 16; ++j) s += 0.5 * (r - a) * glw[j] * sigma(a + 0.5 * (r - a) * (1.0 + glx[j]));
+  return Ipa[p] + s;
+}
 double Geometry::Idiff(double r, double dr) const {
   if (fabs(dr) < 1e-2) {
     // short interval: 8-point rule on [r - dr, r] in the offset variable
+    static const struct R8 {
+      double x[8], w[8];
+      R8() { gauss_legendre(8, x, w); }
+    } r8;
+    const double* x8 = r8.x;
+    const double* w8 = r8.w;
     double s = 0.0;
-    static double x8[8], w8[8];
-    static bool init = false;
-    if (!init) {
-      gauss_legendre(8, x8, w8);
-      init = true;
-    }
     for (int j = 0; j < 8; ++j) s += 0.5 * w8[j] * sigma(r - dr * 0.5 * (1.0 + x8[j]));
     return s * dr;
   }
@@ -133,7 +142,7 @@ double Geometry::Idiff(double r, double dr) const {
 void Geometry::point(int pn, double tpar, double& r, double& Ir, double& zz, zd& nr, zd& nz,
                      double& jacobian) const {
   r = pa[pn] + 0.5 * (1.0 + tpar) * pl[pn];
-  Ir = Iint(r);
+  Ir = Ipanel(pn, r);
   zz = h(r);
   double hpv = hprime(r);
   double sq = sqrt(1.0 + hpv * hpv);
@@ -164,6 +173,8 @@ void Geometry::build() {
     }
   }
   const int np = npanels(), N = np * 16;
+  Ipa.assign(np, 0.0);
+  for (int p = 0; p < np; ++p) Ipa[p] = Iint(pa[p]);
   rho.assign(N, 0); I.assign(N, 0); z.assign(N, 0); hp.assign(N, 0); nur.assign(N, 0);
   nuz.assign(N, 0); jac.assign(N, 0); W.assign(N, 0); t.assign(N, 0);
   nr_re.assign(N, 0); nr_im.assign(N, 0); nz_re.assign(N, 0); nz_im.assign(N, 0);
@@ -186,16 +197,12 @@ void Geometry::build() {
 
 // Lagrange basis on the 16 Gauss-Legendre nodes, barycentric form.
 static void lagrange16(const double* xn, double tq, double* out) {
-  static double bw[16];
-  static bool init = false;
-  if (!init) {
-    for (int l = 0; l < 16; ++l) {
-      double p = 1.0;
-      for (int m = 0; m < 16; ++m)
-        if (m != l) p *= (xn[l] - xn[m]);
-      bw[l] = 1.0 / p;
-    }
-    init = true;
+  double bw[16];
+  for (int l = 0; l < 16; ++l) {
+    double p = 1.0;
+    for (int m = 0; m < 16; ++m)
+      if (m != l) p *= (xn[l] - xn[m]);
+    bw[l] = 1.0 / p;
   }
   for (int l = 0; l < 16; ++l)
     if (tq == xn[l]) {
@@ -214,20 +221,24 @@ static void lagrange16(const double* xn, double tq, double* out) {
 // endpoint until their length is below the target's distance to that end.
 void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
                           std::vector<NearJob>& jobs, int self_levels) const {
-  geom.clear();
-  coef.clear();
-  jobs.clear();
   const int N = n(), np = npanels();
-  std::vector<double> tq, wq;  // rule in offset form: t = base + sgn * off
+  struct Local {
+    std::vector<PairGeom> g;
+    std::vector<double> c;
+    std::vector<NearJob> j;
+  };
+  std::vector<Local> loc(N);
+#pragma omp parallel for schedule(dynamic, 8)
   for (int i = 0; i < N; ++i) {
+    Local& L = loc[i];
     const int p0 = panel[i];
     for (int pn = p0 - 1; pn <= p0 + 1; ++pn) {
       if (pn < 0 || pn >= np) continue;
       NearJob J;
       J.target = i;
       J.panel = pn;
-      J.q0 = (int)geom.size();
-      // collect (offset from the anchor, weight, side sign)
+      J.q0 = (int)L.g.size();
+      // points as (anchor, offset, side sign, weight): t = anchor + sgn * off
       struct AP { double anchor, off, sgn, w; };
       std::vector<AP> pts;
       if (pn == p0) {
@@ -251,7 +262,7 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
       } else {
         // shared endpoint of the neighbour panel: +1 if it lies left of p0
         const double anchor = pn < p0 ? 1.0 : -1.0;
-        const double sgn = pn < p0 ? -1.0 : 1.0;  // t = anchor + sgn * off
+        const double sgn = pn < p0 ? -1.0 : 1.0;
         // target distance to the shared end, in neighbour-panel units
         const double dist = (pn < p0 ? (1.0 + t[i]) : (1.0 - t[i])) * pl[p0] / pl[pn];
         double hi = 2.0;
@@ -280,17 +291,38 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
         PairGeom g;
         g.rt = zd{rho[i], I[i]};
         g.rs = zd{r, Ir};
-        g.drho = zd{dr, Idiff(rho[i], dr)};
+        g.drho = zd{dr, fabs(dr) < 1e-2 ? Idiff(rho[i], dr) : I[i] - Ir};
         g.dz = zd{hdiff(rho[i], dr), 0.0};
         g.nr = nr;
         g.nz = nz;
-        geom.push_back(g);
-        double L[16];
-        lagrange16(glx, tp, L);
+        L.g.push_back(g);
+        double Lg[16];
+        lagrange16(glx, tp, Lg);
         const double base = 2.0 * a.w * r * jc;
-        for (int l = 0; l < 16; ++l) coef.push_back(base * L[l]);
+        for (int l = 0; l < 16; ++l) L.c.push_back(base * Lg[l]);
       }
-      J.q1 = (int)geom.size();
+      J.q1 = (int)L.g.size();
+      L.j.push_back(J);
+    }
+  }
+  size_t tot = 0, totj = 0;
+  for (const Local& L : loc) {
+    tot += L.g.size();
+    totj += L.j.size();
+  }
+  geom.clear();
+  coef.clear();
+  jobs.clear();
+  geom.reserve(tot);
+  coef.reserve(tot * 16);
+  jobs.reserve(totj);
+  for (const Local& L : loc) {
+    const int base = (int)geom.size();
+    geom.insert(geom.end(), L.g.begin(), L.g.end());
+    coef.insert(coef.end(), L.c.begin(), L.c.end());
+    for (NearJob J : L.j) {
+      J.q0 += base;
+      J.q1 += base;
       jobs.push_back(J);
     }
   }

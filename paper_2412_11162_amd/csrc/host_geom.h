@@ -31,6 +31,7 @@ class Geometry {
 
   // panels
   std::vector<double> pa, pl;  // start rho and rho-length
+  std::vector<double> Ipa;     // Im rho~ at each panel start
   // node tables
   std::vector<double> rho, I, z, hp, nur, nuz, jac, W, t;
   std::vector<double> nr_re, nr_im, nz_re, nz_im;
@@ -45,6 +46,7 @@ class Geometry {
   double hdiff(double r, double dr) const;  // h~(r) - h~(r - dr), no cancellation
   double sigma(double r) const;        // sigma_1
   double Iint(double r) const;         // int_0^r sigma_1
+  double Ipanel(int p, double r) const;  // int_0^r sigma_1 for r on panel p
   double Idiff(double r, double dr) const;  // int_{r - dr}^{r} sigma_1
   // geometry of a curve point given by its panel and parameter
   void point(int panel, double tpar, double& r, double& Ir, double& zz, zd& nr, zd& nz,

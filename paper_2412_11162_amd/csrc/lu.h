@@ -6,7 +6,7 @@
 
 namespace pmlbie {
 
-constexpr int LU_NB = 64;       // panel width
+constexpr int LU_NB = 128;      // panel width
 constexpr int LU_MAX_RHS = 16;  // right-hand sides per solve call
 
 // Optional per-panel event markers (timing of the trailing-update kernel).
@@ -16,7 +16,7 @@ struct LuTimers {
   hipEvent_t* gemm_end = nullptr;
 };
 
-// Factor `batch` column-major n x n matrices A + b * ms in place.
+// Factor `batch` row-major n x n matrices A + b * ms in place (n <= 8192).
 // ipiv[b * n + j] = row interchanged with row j (0-based);
 // info[b] = first zero pivot (1-based), untouched otherwise.
 template <typename T>

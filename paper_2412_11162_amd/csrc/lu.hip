@@ -1,11 +1,16 @@
 // Batched per-mode complex LU with partial pivoting and the matching solves
 // (the per-mode dense solve of Sec. 4.2, eqs. eqntdpsi1/2, done as one
-// 2N x 2N system per mode).  Right-looking blocked algorithm, panel width NB:
-//   1. panel factorisation (one workgroup per matrix),
-//   2. row interchanges of the trailing columns fused with the triangular
-//      solve U12 = L11^{-1} A12,
-//   3. trailing update A22 -= L21 U12 on the matrix cores (MFMA), complex
-//      products as four real MFMA products.
+// 2N x 2N system per mode).  Matrices are stored row-major.
+//
+// Right-looking blocked algorithm with panel width LU_NB:
+//   1. panel factorisation, one workgroup per matrix: the panel is walked in
+//      sub-panels of 4 columns held in registers (pivot search, row exchange
+//      and rank-1 updates never leave the chip), each followed by the update
+//      of the panel columns to its right;
+//   2. the triangular solve U12 = L11^{-1} A12 (the row interchanges of the
+//      trailing columns are done by the panel kernel as each pivot is chosen);
+//   3. trailing update A22 -= L21 U12 on the matrix cores (MFMA), a complex
+//      product as four real MFMA products.
 // Row interchanges are not applied to the columns left of the current panel:
 // the forward solve applies each panel's interchanges to the right-hand side
 // just before using that panel's columns of L, which are stored in the row
@@ -17,13 +22,16 @@ namespace pmlbie {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+constexpr int PNL_T = 1024;  // threads of the panel kernel
+constexpr int SUB = 4;       // register sub-panel width
+
 template <typename T>
 __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     T ov = __shfl_xor(v, off);
     int oi = __shfl_xor(idx, off);
-    if (ov > v || (ov == v && oi < idx)) {
+    if (ov > v || (ov == v && (unsigned)oi < (unsigned)idx)) {
       v = ov;
       idx = oi;
     }
@@ -31,134 +39,237 @@ __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorisation: columns [k0, k0 + nb), rows [k0, n).
-template <typename T>
-__global__ __launch_bounds__(256) void k_panel(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                               int nb, int* __restrict__ ipiv,
-                                               int* __restrict__ info) {
+// Panel factorisation: columns [k0, k0 + nb), rows [k0, n).  Thread t owns the
+// local rows t, t + PNL_T, ... (local row = row - k0); RPT rows per thread.
+template <typename T, int RPT>
+__global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms, int n, int k0,
+                                                 int nb, int* __restrict__ ipiv,
+                                                 int* __restrict__ info) {
   cx<T>* a = A + (long)blockIdx.x * ms;
   int* piv = ipiv + (long)blockIdx.x * n;
-  __shared__ T sv[4];
-  __shared__ int si[4];
-  __shared__ cx<T> prow[LU_NB];
-  __shared__ int sp;
-  __shared__ cx<T> sinv;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int j = 0; j < nb; ++j) {
-    const int c = k0 + j;
-    const cx<T>* col = a + (long)c * n;
-    T best = T(-1);
-    int bi = c;
-    for (int r = c + tid; r < n; r += 256) {
-      T v = cabs1(col[r]);
-      if (v > best) {
-        best = v;
-        bi = r;
-      }
+  const int m = n - k0;
+  __shared__ T sv[PNL_T / 64];
+  __shared__ int si[PNL_T / 64];
+  __shared__ cx<T> prow[SUB];
+  __shared__ cx<T> sx[2][SUB];
+  __shared__ cx<T> sinv;
+  __shared__ int sp;
+  __shared__ cx<T> L8[SUB][SUB];
+  __shared__ cx<T> Ur[SUB][LU_NB];
+  __shared__ cx<T> Ls[PNL_T][SUB];
+  const cx<T> zero{T(0), T(0)};
+  cx<T> x[RPT][SUB];
+  for (int s0 = 0; s0 < nb; s0 += SUB) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int rl = tid + PNL_T * q;
+      const cx<T>* src = a + (long)(k0 + rl) * n + k0 + s0;
+#pragma unroll
+      for (int jj = 0; jj < SUB; ++jj) x[q][jj] = rl < m ? src[jj] : zero;
     }
-    wave_argmax(best, bi);
-    if (lane == 0) {
-      sv[wid] = best;
-      si[wid] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      T b = sv[0];
-      int p = si[0];
-      for (int w = 1; w < 4; ++w)
-        if (sv[w] > b || (sv[w] == b && si[w] < p)) {
-          b = sv[w];
-          p = si[w];
+#pragma unroll
+    for (int jj = 0; jj < SUB; ++jj) {
+      const int cl = s0 + jj;
+      T best = T(-1);
+      int bi = -1;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int rl = tid + PNL_T * q;
+        if (rl >= cl && rl < m) {
+          const T v = cabs1(x[q][jj]);
+          if (v > best) {
+            best = v;
+            bi = rl;
+          }
         }
-      sp = p;
-      piv[c] = p;
-      if (b == T(0)) {
-        if (info[blockIdx.x] == 0) info[blockIdx.x] = c + 1;
-        sinv = cx<T>{T(0), T(0)};
+      }
+      wave_argmax(best, bi);
+      if (lane == 0) {
+        sv[wid] = best;
+        si[wid] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        T b = sv[0];
+        int p = si[0];
+        for (int w = 1; w < PNL_T / 64; ++w)
+          if (sv[w] > b || (sv[w] == b && (unsigned)si[w] < (unsigned)p)) {
+            b = sv[w];
+            p = si[w];
+          }
+        if (p < 0) p = cl;
+        sp = p;
+        piv[k0 + cl] = k0 + p;
+        if (!(b > T(0)) && info[blockIdx.x] == 0) info[blockIdx.x] = k0 + cl + 1;
+      }
+      __syncthreads();
+      const int p = sp;
+      // the diagonal row cl < LU_NB <= PNL_T lives in slot 0 of thread cl
+      const int op = p % PNL_T, qp = p / PNL_T;
+      if (p != cl) {
+        if (tid == cl)
+#pragma unroll
+          for (int j2 = 0; j2 < SUB; ++j2) sx[0][j2] = x[0][j2];
+        if (tid == op)
+#pragma unroll
+          for (int q = 0; q < RPT; ++q)
+            if (q == qp)
+#pragma unroll
+              for (int j2 = 0; j2 < SUB; ++j2) sx[1][j2] = x[q][j2];
+        // the rest of the two rows in memory: the other panel columns and the
+        // trailing columns (the interchange of the trailing matrix happens here)
+        for (int c = tid; c < m; c += PNL_T)
+          if (c < s0 || c >= s0 + SUB) {
+            cx<T>* r1 = a + (long)(k0 + cl) * n + k0 + c;
+            cx<T>* r2 = a + (long)(k0 + p) * n + k0 + c;
+            const cx<T> t1 = *r1;
+            *r1 = *r2;
+            *r2 = t1;
+          }
+        __syncthreads();
+        if (tid == cl)
+#pragma unroll
+          for (int j2 = 0; j2 < SUB; ++j2) x[0][j2] = sx[1][j2];
+        if (tid == op)
+#pragma unroll
+          for (int q = 0; q < RPT; ++q)
+            if (q == qp)
+#pragma unroll
+              for (int j2 = 0; j2 < SUB; ++j2) x[q][j2] = sx[0][j2];
+      }
+      if (tid == cl) {
+#pragma unroll
+        for (int j2 = 0; j2 < SUB; ++j2) prow[j2] = x[0][j2];
+        const cx<T> pv = x[0][jj];
+        sinv = (pv.re != T(0) || pv.im != T(0)) ? inv(pv) : zero;
+      }
+      __syncthreads();
+      const cx<T> ip = sinv;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int rl = tid + PNL_T * q;
+        if (rl > cl && rl < m) {
+          const cx<T> l = x[q][jj] * ip;
+          x[q][jj] = l;
+#pragma unroll
+          for (int j2 = jj + 1; j2 < SUB; ++j2) x[q][j2] = x[q][j2] - l * prow[j2];
+        }
+      }
+      __syncthreads();
+    }
+    // write the sub-panel back
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int rl = tid + PNL_T * q;
+      if (rl < m) {
+        cx<T>* dst = a + (long)(k0 + rl) * n + k0 + s0;
+#pragma unroll
+        for (int jj = 0; jj < SUB; ++jj) dst[jj] = x[q][jj];
+      }
+    }
+    const int wr = nb - s0 - SUB;  // panel columns right of the sub-panel
+    if (wr <= 0) continue;
+    // U rows of the sub-panel: Ur = L8^{-1} A[s0 .. s0+SUB-1][right part]
+    if (tid >= s0 && tid < s0 + SUB)
+#pragma unroll
+      for (int jj = 0; jj < SUB; ++jj) L8[tid - s0][jj] = x[0][jj];
+    __syncthreads();  // row exchanges in memory and L8 visible
+    for (int e = tid; e < SUB * wr; e += PNL_T) {
+      const int r = e / wr, c = e % wr;
+      Ur[r][c] = a[(long)(k0 + s0 + r) * n + k0 + s0 + SUB + c];
+    }
+    __syncthreads();
+    for (int c = tid; c < wr; c += PNL_T) {
+#pragma unroll
+      for (int r = 1; r < SUB; ++r) {
+        cx<T> acc = Ur[r][c];
+#pragma unroll
+        for (int j = 0; j < r; ++j) acc = acc - L8[r][j] * Ur[j][c];
+        Ur[r][c] = acc;
       }
     }
     __syncthreads();
-    const int p = sp;
-    if (p != c) {
-      for (int cc = k0 + tid; cc < k0 + nb; cc += 256) {
-        cx<T> t0 = a[(long)cc * n + c];
-        a[(long)cc * n + c] = a[(long)cc * n + p];
-        a[(long)cc * n + p] = t0;
+    for (int e = tid; e < SUB * wr; e += PNL_T) {
+      const int r = e / wr, c = e % wr;
+      a[(long)(k0 + s0 + r) * n + k0 + s0 + SUB + c] = Ur[r][c];
+    }
+    // rows below: A[r][right] -= L[r][0..SUB-1] Ur, one block of PNL_T rows at
+    // a time with L staged in LDS so that the row segments are read coalesced
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int base = PNL_T * q;
+      if (base >= m) break;
+#pragma unroll
+      for (int jj = 0; jj < SUB; ++jj) Ls[tid][jj] = x[q][jj];
+      __syncthreads();
+      const int rlo = max(base, s0 + SUB), rhi = min(base + PNL_T, m);
+      const int nr = rhi - rlo;
+      for (int e = tid; e < nr * wr; e += PNL_T) {
+        const int rr = e / wr, c = e % wr;
+        const int rl = rlo + rr;
+        cx<T>* dst = a + (long)(k0 + rl) * n + k0 + s0 + SUB + c;
+        cx<T> acc = *dst;
+#pragma unroll
+        for (int j = 0; j < SUB; ++j) acc = acc - Ls[rl - base][j] * Ur[j][c];
+        *dst = acc;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int cc = c + 1 + tid; cc < k0 + nb; cc += 256) prow[cc - k0] = a[(long)cc * n + c];
-    if (tid == 0) {
-      cx<T> pv = a[(long)c * n + c];
-      if (pv.re != T(0) || pv.im != T(0)) sinv = inv(pv);
-    }
-    __syncthreads();
-    const cx<T> ip = sinv;
-    cx<T>* colc = a + (long)c * n;
-    for (int r = c + 1 + tid; r < n; r += 256) {
-      cx<T> l = colc[r] * ip;
-      colc[r] = l;
-      for (int cc = c + 1; cc < k0 + nb; ++cc) {
-        cx<T>* dst = a + (long)cc * n + r;
-        *dst = *dst - l * prow[cc - k0];
-      }
-    }
-    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Row interchanges + U12 = L11^{-1} A12 for a tile of 64 trailing columns.
-// Thread (col = tid % 64, rg = tid / 64) holds rows rg, rg + 4, ... of the
-// panel rows of its column.
+// U12 = L11^{-1} A12 for a tile of 64 trailing columns.  Thread
+// (col = tid % 64, rg = tid / 64) holds panel rows rg, rg + 4, ... of its
+// column; L11 is staged through LDS in blocks of 32 columns.
 template <typename T>
-__global__ __launch_bounds__(256) void k_swap_trsm(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                                   int nb, const int* __restrict__ ipiv) {
+__global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, int n, int k0,
+                                              int nb) {
   cx<T>* a = A + (long)blockIdx.y * ms;
-  const int* piv = ipiv + (long)blockIdx.y * n;
   const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
   const int c = k0 + nb + blockIdx.x * 64 + cl;
   const bool act = c < n;
+  constexpr int JB = 32;
   __shared__ cx<T> xs[64];
-  __shared__ int spv[LU_NB];
-  for (int j = tid; j < nb; j += 256) spv[j] = piv[k0 + j];
-  __syncthreads();
-  cx<T>* colp = a + (long)(act ? c : 0) * n;
-  if (act && rg == 0) {
-    for (int j = 0; j < nb; ++j) {
-      const int p = spv[j];
-      if (p != k0 + j) {
-        cx<T> t0 = colp[k0 + j];
-        colp[k0 + j] = colp[p];
-        colp[p] = t0;
-      }
-    }
-  }
-  __syncthreads();
+  __shared__ cx<T> Lb[LU_NB][JB + 1];
   constexpr int R = LU_NB / 4;
   cx<T> x[R];
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int r = rg + 4 * t;
-    x[t] = (act && r < nb) ? colp[k0 + r] : cx<T>{T(0), T(0)};
+    x[t] = (act && r < nb) ? a[(long)(k0 + r) * n + c] : cx<T>{T(0), T(0)};
   }
-  for (int j = 0; j < nb; ++j) {
-    if ((j & 3) == rg) xs[cl] = x[j >> 2];
+  for (int j0 = 0; j0 < nb; j0 += JB) {
     __syncthreads();
-    const cx<T> xj = xs[cl];
-    const cx<T>* Lc = a + (long)(k0 + j) * n + k0;
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const int r = rg + 4 * t;
-      if (r > j && r < nb) x[t] = x[t] - Lc[r] * xj;
+    for (int e = tid; e < nb * JB; e += 256) {
+      const int r = e / JB, jj = e % JB;
+      Lb[r][jj] = j0 + jj < nb ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
+    const int jend = min(JB, nb - j0);
+    for (int jj = 0; jj < jend; ++jj) {
+      const int j = j0 + jj;
+      if ((j & 3) == rg) {
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+          if (t == (j >> 2)) xs[cl] = x[t];
+      }
+      __syncthreads();
+      const cx<T> xj = xs[cl];
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int r = rg + 4 * t;
+        if (r > j && r < nb) x[t] = x[t] - Lb[r][jj] * xj;
+      }
+      __syncthreads();
+    }
   }
   if (act) {
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       const int r = rg + 4 * t;
-      if (r < nb) colp[k0 + r] = x[t];
+      if (r < nb) a[(long)(k0 + r) * n + c] = x[t];
     }
   }
 }
@@ -166,15 +277,13 @@ __global__ __launch_bounds__(256) void k_swap_trsm(cx<T>* __restrict__ A, long m
 // ---------------------------------------------------------------------------
 // Trailing update C -= L21 U12 on MFMA.  Workgroup tile 64 x 64 (complex),
 // four waves of 32 x 32, K staged through LDS in chunks of 16.
-// The MFMA computes the transposed tile C^T = U12^T L21^T so that each lane's
-// accumulators map to 16 consecutive rows of a column of C.
 template <typename T> struct mfma_t;
 template <> struct mfma_t<double> {
   typedef v4d acc;
   __device__ __forceinline__ static acc op(double x, double y, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
   }
-  // lane l, register j -> (row of C^T tile, col) = (l/16 + 4j, l%16)
+  // lane l, register j -> row of the 16 x 16 output tile (column = l % 16)
   __device__ __forceinline__ static int rowof(int lane, int j) { return (lane >> 4) + 4 * j; }
 };
 template <> struct mfma_t<float> {
@@ -190,14 +299,14 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
                                                      int k0, int nb) {
   typedef typename mfma_t<T>::acc acc_t;
   cx<T>* a = A + (long)blockIdx.z * ms;
-  const int m0 = k0 + nb;  // first trailing row/column
-  const int r0 = m0 + blockIdx.x * 64;  // tile rows of C
-  const int c0 = m0 + blockIdx.y * 64;  // tile columns of C
+  const int m0 = k0 + nb;
+  const int r0 = m0 + blockIdx.y * 64;  // tile rows of C
+  const int c0 = m0 + blockIdx.x * 64;  // tile columns of C
   constexpr int KC = 16;
-  __shared__ T Lre[KC][64 + 1], Lim[KC][64 + 1];  // L21 chunk: [k][row]
-  __shared__ T Ure[KC][64 + 1], Uim[KC][64 + 1];  // U12 chunk: [k][col]
+  __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4];  // L21 chunk: [k][row]
+  __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4];  // U12 chunk: [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = (wid & 1) * 32, wc = (wid >> 1) * 32;  // wave sub-tile offsets
+  const int wr = (wid & 1) * 32, wc = (wid >> 1) * 32;
   acc_t cr[2][2], ci[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -206,57 +315,68 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
       cr[x][y] = acc_t{0, 0, 0, 0};
       ci[x][y] = acc_t{0, 0, 0, 0};
     }
-  for (int kk = 0; kk < nb; kk += KC) {
-    // load L21[r0 .. r0+63][k0+kk .. +15] and U12[k0+kk .. +15][c0 .. c0+63]
-    for (int e = tid; e < 64 * KC; e += 256) {
-      const int rr = e & 63, k = e >> 6;
-      const int gr = r0 + rr, gk = k0 + kk + k;
-      cx<T> v = (gr < n && kk + k < nb) ? a[(long)gk * n + gr] : cx<T>{T(0), T(0)};
-      Lre[k][rr] = v.re;
-      Lim[k][rr] = v.im;
+  // global -> register prefetch of the next K chunk overlaps the MFMA work
+  // on the current one; each thread moves 4 elements of L21 and of U12
+  cx<T> pl[4], pu[4];
+  auto gload = [&](int kk) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int k = e % KC, rr = e / KC;  // row-major L21: k contiguous
+      const int gr = r0 + rr, gk = kk + k;
+      pl[t] = (gr < n && gk < nb) ? a[(long)gr * n + k0 + gk] : cx<T>{T(0), T(0)};
+      const int cc = e & 63, ku = e >> 6;  // row-major U12: columns contiguous
+      const int gc = c0 + cc, gku = kk + ku;
+      pu[t] = (gc < n && gku < nb) ? a[(long)(k0 + gku) * n + gc] : cx<T>{T(0), T(0)};
     }
-    for (int e = tid; e < 64 * KC; e += 256) {
-      const int k = e % KC, cc = e / KC;
-      const int gc = c0 + cc, gk = k0 + kk + k;
-      cx<T> v = (gc < n && kk + k < nb) ? a[(long)gc * n + gk] : cx<T>{T(0), T(0)};
-      Ure[k][cc] = v.re;
-      Uim[k][cc] = v.im;
+  };
+  gload(0);
+  for (int kk = 0; kk < nb; kk += KC) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int k = e % KC, rr = e / KC;
+      Lre[k][rr] = pl[t].re;
+      Lim[k][rr] = pl[t].im;
+      const int cc = e & 63, ku = e >> 6;
+      Ure[ku][cc] = pu[t].re;
+      Uim[ku][cc] = pu[t].im;
     }
     __syncthreads();
+    if (kk + KC < nb) gload(kk + KC);
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       const int kx = k4 + (lane >> 4), lx = lane & 15;
-      T ur[2], ui[2], lr[2], li[2];
+      T lr[2], li[2], ur[2], ui[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        ur[t] = Ure[kx][wc + 16 * t + lx];   // X = U^T: X[p][k] = U[k][col p]
-        ui[t] = Uim[kx][wc + 16 * t + lx];
-        lr[t] = Lre[kx][wr + 16 * t + lx];   // Y = L^T: Y[k][q] = L[row q][k]
+        lr[t] = Lre[kx][wr + 16 * t + lx];  // X[p][k] = L[row p][k]
         li[t] = Lim[kx][wr + 16 * t + lx];
+        ur[t] = Ure[kx][wc + 16 * t + lx];  // Y[k][q] = U[k][col q]
+        ui[t] = Uim[kx][wc + 16 * t + lx];
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)      // column sub-tile (U)
+      for (int x = 0; x < 2; ++x)      // row sub-tile
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {  // row sub-tile (L)
-          cr[x][y] = mfma_t<T>::op(ur[x], lr[y], cr[x][y]);
-          cr[x][y] = mfma_t<T>::op(-ui[x], li[y], cr[x][y]);
-          ci[x][y] = mfma_t<T>::op(ur[x], li[y], ci[x][y]);
-          ci[x][y] = mfma_t<T>::op(ui[x], lr[y], ci[x][y]);
+        for (int y = 0; y < 2; ++y) {  // column sub-tile
+          cr[x][y] = mfma_t<T>::op(lr[x], ur[y], cr[x][y]);
+          cr[x][y] = mfma_t<T>::op(-li[x], ui[y], cr[x][y]);
+          ci[x][y] = mfma_t<T>::op(lr[x], ui[y], ci[x][y]);
+          ci[x][y] = mfma_t<T>::op(li[x], ur[y], ci[x][y]);
         }
     }
     __syncthreads();
   }
-  // C^T tile (p = column offset, q = row offset): lane -> q = lane % 16.
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int gc = c0 + wc + 16 * x + mfma_t<T>::rowof(lane, j);
-        const int gr = r0 + wr + 16 * y + (lane & 15);
+        const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
+        const int gc = c0 + wc + 16 * y + (lane & 15);
         if (gc < n && gr < n) {
-          cx<T>* p = a + (long)gc * n + gr;
+          cx<T>* p = a + (long)gr * n + gc;
           cx<T> v = *p;
           v.re -= cr[x][y][j];
           v.im -= ci[x][y][j];
@@ -275,7 +395,7 @@ __global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long
   const cx<T>* a = A + (long)blockIdx.x * ms;
   const int* piv = ipiv + (long)blockIdx.x * n;
   cx<TB>* b = B + (long)blockIdx.x * nrhs * n;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   __shared__ cx<TB> yb[LU_NB][LU_MAX_RHS];
   // forward: panel by panel
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
@@ -292,32 +412,34 @@ __global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long
       }
     }
     __syncthreads();
-    // unit lower triangular block, sequential in j; threads over (row, rhs)
     for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
       for (int e = tid; e < nb * nrhs; e += 256) {
         const int r = e % nb, s = e / nb;
         if (r > j) {
-          cx<T> l = a[(long)(k0 + j) * n + k0 + r];
-          cx<TB> lc{(TB)l.re, (TB)l.im};
-          yb[r][s] = yb[r][s] - lc * yb[j][s];
+          const cx<T> l = a[(long)(k0 + r) * n + k0 + j];
+          yb[r][s] = yb[r][s] - cx<TB>{(TB)l.re, (TB)l.im} * yb[j][s];
         }
       }
       __syncthreads();
     }
     for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
     __syncthreads();
-    // update rows below
-    for (int r = k0 + nb + tid; r < n; r += 256) {
+    // rows below: one wavefront per row, lanes over the panel columns
+    for (int r = k0 + nb + wid; r < n; r += 4) {
+      const cx<T>* row = a + (long)r * n + k0;
       for (int s = 0; s < nrhs; ++s) {
-        cx<TB> acc = b[(long)s * n + r];
-        for (int j = 0; j < nb; ++j) {
-          cx<T> l = a[(long)(k0 + j) * n + r];
-          cx<TB> lc{(TB)l.re, (TB)l.im};
-          acc = acc - lc * yb[j][s];
+        cx<TB> acc{TB(0), TB(0)};
+        for (int j = lane; j < nb; j += 64) {
+          const cx<T> l = row[j];
+          acc = acc + cx<TB>{(TB)l.re, (TB)l.im} * yb[j][s];
         }
-        b[(long)s * n + r] = acc;
+        for (int off = 32; off >= 1; off >>= 1) {
+          acc.re += __shfl_xor(acc.re, off);
+          acc.im += __shfl_xor(acc.im, off);
+        }
+        if (lane == 0) b[(long)s * n + r] = b[(long)s * n + r] - acc;
       }
     }
     __syncthreads();
@@ -329,32 +451,34 @@ __global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long
     __syncthreads();
     for (int j = nb - 1; j >= 0; --j) {
       if (tid < nrhs) {
-        cx<T> u = a[(long)(k0 + j) * n + k0 + j];
-        cx<TB> uc{(TB)u.re, (TB)u.im};
-        yb[j][tid] = yb[j][tid] / uc;
+        const cx<T> u = a[(long)(k0 + j) * n + k0 + j];
+        yb[j][tid] = yb[j][tid] / cx<TB>{(TB)u.re, (TB)u.im};
       }
       __syncthreads();
       for (int e = tid; e < nb * nrhs; e += 256) {
         const int r = e % nb, s = e / nb;
         if (r < j) {
-          cx<T> u = a[(long)(k0 + j) * n + k0 + r];
-          cx<TB> uc{(TB)u.re, (TB)u.im};
-          yb[r][s] = yb[r][s] - uc * yb[j][s];
+          const cx<T> u = a[(long)(k0 + r) * n + k0 + j];
+          yb[r][s] = yb[r][s] - cx<TB>{(TB)u.re, (TB)u.im} * yb[j][s];
         }
       }
       __syncthreads();
     }
     for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
     __syncthreads();
-    for (int r = tid; r < k0; r += 256) {
+    for (int r = wid; r < k0; r += 4) {
+      const cx<T>* row = a + (long)r * n + k0;
       for (int s = 0; s < nrhs; ++s) {
-        cx<TB> acc = b[(long)s * n + r];
-        for (int j = 0; j < nb; ++j) {
-          cx<T> u = a[(long)(k0 + j) * n + r];
-          cx<TB> uc{(TB)u.re, (TB)u.im};
-          acc = acc - uc * yb[j][s];
+        cx<TB> acc{TB(0), TB(0)};
+        for (int j = lane; j < nb; j += 64) {
+          const cx<T> u = row[j];
+          acc = acc + cx<TB>{(TB)u.re, (TB)u.im} * yb[j][s];
         }
-        b[(long)s * n + r] = acc;
+        for (int off = 32; off >= 1; off >>= 1) {
+          acc.re += __shfl_xor(acc.re, off);
+          acc.im += __shfl_xor(acc.im, off);
+        }
+        if (lane == 0) b[(long)s * n + r] = b[(long)s * n + r] - acc;
       }
     }
     __syncthreads();
@@ -362,17 +486,26 @@ __global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long
 }
 
 // ---------------------------------------------------------------------------
+template <typename T, int RPT>
+static void launch_panel(cx<T>* A, long ms, int n, int k0, int nb, int batch, int* ipiv, int* info,
+                         hipStream_t st) {
+  hipLaunchKernelGGL((k_panel<T, RPT>), dim3(batch), dim3(PNL_T), 0, st, A, ms, n, k0, nb, ipiv, info);
+}
+
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, hipStream_t st,
                        LuTimers* tm) {
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
-    if (tm && tm->panel_begin) hipEventRecord(tm->panel_begin[k0 / LU_NB], st);
-    hipLaunchKernelGGL(k_panel<T>, dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv, info);
+    const int m = n - k0;
+    if (m <= 1 * PNL_T) launch_panel<T, 1>(A, ms, n, k0, nb, batch, ipiv, info, st);
+    else if (m <= 2 * PNL_T) launch_panel<T, 2>(A, ms, n, k0, nb, batch, ipiv, info, st);
+    else if (m <= 4 * PNL_T) launch_panel<T, 4>(A, ms, n, k0, nb, batch, ipiv, info, st);
+    else launch_panel<T, 8>(A, ms, n, k0, nb, batch, ipiv, info, st);
     const int rest = n - k0 - nb;
     if (rest > 0) {
       dim3 g1((rest + 63) / 64, batch);
-      hipLaunchKernelGGL(k_swap_trsm<T>, g1, dim3(256), 0, st, A, ms, n, k0, nb, ipiv);
+      hipLaunchKernelGGL(k_trsm<T>, g1, dim3(256), 0, st, A, ms, n, k0, nb);
       if (tm && tm->gemm_begin) hipEventRecord(tm->gemm_begin[k0 / LU_NB], st);
       dim3 g2((rest + 63) / 64, (rest + 63) / 64, batch);
       hipLaunchKernelGGL(k_gemm_update<T>, g2, dim3(256), 0, st, A, ms, n, k0, nb);

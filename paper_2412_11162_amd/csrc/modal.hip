@@ -15,7 +15,7 @@ namespace pmlbie {
 // ------------------------------------------------------------------------
 // Output: either the per-mode system matrices or a raw modal buffer.
 //
-// System matrix of mode n, column-major 2N x 2N at A + n * mstride:
+// System matrix of mode n, row-major 2N x 2N at A + n * mstride:
 //   [[K1 - D1, -S1], [K2 - D2, -S2]],  K_il = 2 W_l K_n(r_i, r_l),
 //   S_il = 2 W_l S_n(r_i, r_l) for l off the near panels of i.
 // Raw modal buffer: out[q][s][n], s in {S1, K1, S2, K2}.
@@ -34,10 +34,10 @@ __device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, z
     const long i = dst.x, l = dst.y, N = o.n2 >> 1;
     const double w2 = 2.0 * o.W[l];
     zd* An = o.A + (long)n * o.mstride;
-    An[l * o.n2 + i] = w2 * K1;
-    An[(N + l) * o.n2 + i] = (-w2) * S1;
-    An[l * o.n2 + N + i] = w2 * K2;
-    An[(N + l) * o.n2 + N + i] = (-w2) * S2;
+    An[i * o.n2 + l] = w2 * K1;
+    An[i * o.n2 + N + l] = (-w2) * S1;
+    An[(N + i) * o.n2 + l] = w2 * K2;
+    An[(N + i) * o.n2 + N + l] = (-w2) * S2;
   } else {
     zd* r = o.raw + (long)dst.x * 4 * (o.M + 1);
     r[n] = S1;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd
   const int N = nd.N;
   const long total = (long)N * N;
   for (long p = blockIdx.x; p < total; p += gridDim.x) {
-    const int i = (int)(p % N), l = (int)(p / N);
+    const int l = (int)(p % N), i = (int)(p / N);  // neighbouring sources write neighbouring columns
     const int dp = nd.panel[i] - nd.panel[l];
     if (dp >= -1 && dp <= 1) continue;  // near panels: product integration
     const PairGeom g = node_pair(nd, i, l);
@@ -481,10 +481,10 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
       k1v = k1v + 1.0;
       k2v = k2v - 1.0;
     }
-    An[col * o.n2 + i] = k1v;
-    An[(N + col) * o.n2 + i] = -a0;
-    An[col * o.n2 + N + i] = k2v;
-    An[(N + col) * o.n2 + N + i] = -a2;
+    An[i * o.n2 + col] = k1v;
+    An[i * o.n2 + N + col] = -a0;
+    An[(N + i) * o.n2 + col] = k2v;
+    An[(N + i) * o.n2 + N + col] = -a2;
   }
 }
 

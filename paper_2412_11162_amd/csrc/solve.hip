@@ -21,41 +21,34 @@ __global__ void k_rhs_gather_point(const zd* __restrict__ raw, int N, int M, int
   b2[e] = -raw[q2 * 4 * (M + 1) + (M + 1) + n];
 }
 
-// rhs[n][r] = [0 ; Alow_n [b1; b2]], Alow_n = [K2 - D2, -S2] (N x 2N, column-major).
+// rhs[n][r] = [0 ; Alow_n [b1; b2]], Alow_n = [K2 - D2, -S2] (N x 2N, row-major):
+// one wavefront per row, lanes over the columns.
 __global__ __launch_bounds__(256) void k_lower_rhs(const zd* __restrict__ Alow, long lstride,
                                                    int N, int nrhs, const zd* __restrict__ b1,
                                                    const zd* __restrict__ b2, zd* __restrict__ rhs) {
   const int n = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const zd* A = Alow + (long)n * lstride;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const zd* row = Alow + (long)n * lstride + (long)i * 2 * N;
   const zd* x1 = b1 + (long)n * nrhs * N;
   const zd* x2 = b2 + (long)n * nrhs * N;
   zd* out = rhs + (long)n * nrhs * 2 * N;
-  __shared__ zd xs[64][LU_MAX_RHS];
-  zd acc[LU_MAX_RHS];
-  for (int r = 0; r < LU_MAX_RHS; ++r) acc[r] = zd{0.0, 0.0};
-  for (int c0 = 0; c0 < 2 * N; c0 += 64) {
-    for (int e = threadIdx.x; e < 64 * nrhs; e += blockDim.x) {
-      const int c = c0 + (e & 63), r = e >> 6;
-      zd v{0.0, 0.0};
-      if (c < 2 * N) v = c < N ? x1[(long)r * N + c] : x2[(long)r * N + c - N];
-      xs[e & 63][r] = v;
+  for (int r = 0; r < nrhs; ++r) {
+    zd acc{0.0, 0.0};
+    for (int c = lane; c < 2 * N; c += 64) {
+      const zd xv = c < N ? x1[(long)r * N + c] : x2[(long)r * N + c - N];
+      acc = cfma(row[c], xv, acc);
     }
-    __syncthreads();
-    if (i < N) {
-      const int cmax = min(64, 2 * N - c0);
-      for (int c = 0; c < cmax; ++c) {
-        const zd a = A[(long)(c0 + c) * N + i];
-        for (int r = 0; r < nrhs; ++r) acc[r] = cfma(a, xs[c][r], acc[r]);
-      }
+    for (int off = 32; off >= 1; off >>= 1) {
+      acc.re += __shfl_xor(acc.re, off);
+      acc.im += __shfl_xor(acc.im, off);
     }
-    __syncthreads();
-  }
-  if (i < N)
-    for (int r = 0; r < nrhs; ++r) {
+    if (lane == 0) {
       out[(long)r * 2 * N + i] = zd{0.0, 0.0};
-      out[(long)r * 2 * N + N + i] = acc[r];
+      out[(long)r * 2 * N + N + i] = acc;
     }
+  }
 }
 
 // u1 = x[0:N], phi1 = x[N:2N], u2 = u1 - b1, phi2 = phi1 - b2 (transmission
@@ -113,7 +106,7 @@ void launch_rhs_gather_point(const zd* raw, int N, int M, int nrhs, zd* b1, zd* 
 }
 void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_lower_rhs, dim3((N + 255) / 256, modes), dim3(256), 0, st, Alow, lstride, N,
+  hipLaunchKernelGGL(k_lower_rhs, dim3((N + 3) / 4, modes), dim3(256), 0, st, Alow, lstride, N,
                      nrhs, b1, b2, rhs);
 }
 void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,

@@ -67,8 +67,10 @@ class Solver:
                                               a2, T2, S2, int(p)))
         self.N = self.nodes().shape[0]
 
-    def build_modal_operators(self, n_theta: int, precision: int = B.PMLBIE_FP64, flags: int = 0):
-        self._chk(self.L.pmlbie_build_modal_operators(self.h, int(n_theta), int(precision), int(flags)))
+    def build_modal_operators(self, n_theta: int, m_max: int, precision: int = B.PMLBIE_FP64,
+                              flags: int = 0):
+        self._chk(self.L.pmlbie_build_modal_operators(self.h, int(n_theta), int(m_max), int(precision),
+                                                      int(flags)))
         self.M = int(self.info()[1])
 
     def solve_modes(self, incidences):
@@ -116,7 +118,7 @@ class Solver:
         n2 = 2 * self.N
         out = torch.empty((n2, n2), dtype=torch.complex128, device=torch.device("cuda", self.device))
         self._chk(self.L.pmlbie_get_operator(self.h, int(mode), ctypes.c_void_p(out.data_ptr())))
-        return out.t()  # column-major storage -> row/column indexing
+        return out  # row-major storage
 
     def stats(self):
         s = np.zeros(16)
@@ -125,12 +127,13 @@ class Solver:
         return s, c
 
 
-def from_workload(wl, device: int = 0, n_theta: int = None, precision: int = B.PMLBIE_FP64,
-                  flags: int = 0, build: bool = True) -> Solver:
+def from_workload(wl, device: int = 0, n_theta: int = None, m_max: int = None,
+                  precision: int = B.PMLBIE_FP64, flags: int = 0, build: bool = True) -> Solver:
     """Set up a solver for one of the synthetic workloads."""
     s = Solver(device)
     s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
     s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
     if build:
-        s.build_modal_operators(n_theta or wl.n_theta, precision, flags)
+        s.build_modal_operators(n_theta or wl.n_theta, wl.m_max if m_max is None else m_max,
+                                precision, flags)
     return s

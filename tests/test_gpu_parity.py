@@ -1,0 +1,253 @@
+"""Parity of the HIP path against the FP64 oracle on the MI355X.
+
+Bars: modal kernels and assembled matrix entries within 1e-10 (normwise:
+max |difference| / max |oracle| over the compared entries of one mode and
+one block), boundary data within 1e-8 (per mode and right-hand side,
+||x_gpu - x_oracle|| / ||x_oracle|| on x = [u1; phi1; u2; phi2]; modes whose
+data vanish by symmetry -- below 1e-9 of the largest mode, where both sides
+hold only rounding noise amplified by the condition number -- are compared
+absolutely against 1e-8 of the largest).
+Every call goes through the C ABI.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_TOL = 1e-10
+BOUNDARY_TOL = 1e-8
+
+
+def _solver(wl, **kw):
+    from paper_2412_11162_amd.solver import from_workload
+    return from_workload(wl, **kw)
+
+
+def _normwise(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def _boundary_err(gpu, ref):
+    """gpu, ref: tuples of [modes, N] arrays (u1, phi1, u2, phi2)."""
+    x_g = np.concatenate(gpu, axis=1)
+    x_r = np.concatenate(ref, axis=1)
+    big = np.max(np.linalg.norm(x_r, axis=1))
+    errs = []
+    for j in range(x_r.shape[0]):
+        nr = np.linalg.norm(x_r[j])
+        d = np.linalg.norm(x_g[j] - x_r[j])
+        errs.append(d / nr if nr > 1e-9 * big else d / big)
+    return np.array(errs)
+
+
+# --------------------------------------------------------------- tiny, full
+
+@pytest.fixture(scope="module")
+def tiny_ref():
+    import oracle
+    wl = workloads.tiny()
+    g = oracle.geometry(wl)
+    modes = list(range(wl.m_max + 1))
+    A, S, K = oracle.assemble(g, modes)
+    inc = wl.incidences[0]
+    b1, b2 = oracle.rhs_point_source(g, modes, inc[1], inc[2])
+    sol = oracle.solve(g, modes, b1, b2, A=A)
+    return wl, g, A, sol
+
+
+def test_tiny_operators_all_modes(tiny_ref):
+    wl, g, A, _ = tiny_ref
+    from paper_2412_11162_amd._binding import PMLBIE_KEEP_OPERATORS
+    s = _solver(wl, flags=PMLBIE_KEEP_OPERATORS)
+    N = g.n
+    assert s.N == N
+    for n in range(wl.m_max + 1):
+        G = s.get_operator(n).cpu().numpy()
+        for bi in range(2):
+            for bj in range(2):
+                blk = (slice(bi * N, (bi + 1) * N), slice(bj * N, (bj + 1) * N))
+                assert _normwise(G[blk], A[n][blk]) <= KERNEL_TOL, (n, bi, bj)
+
+
+def test_tiny_boundary_data(tiny_ref):
+    wl, g, A, sol = tiny_ref
+    s = _solver(wl)
+    out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(list(wl.incidences))]
+    errs = _boundary_err(out, sol[:4])
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+
+
+def test_tiny_node_table_matches_oracle_geometry(tiny_ref):
+    wl, g, _, _ = tiny_ref
+    s = _solver(wl, build=False)
+    nd = s.nodes()
+    assert np.max(np.abs(nd[:, 0] - g.rho)) <= 1e-15
+    assert np.max(np.abs(nd[:, 1] - g.I)) <= 1e-14
+    assert np.max(np.abs(nd[:, 2] - g.z)) <= 1e-15
+    assert np.max(np.abs(nd[:, 7] - g.W)) <= 1e-14
+
+
+def test_equal_media_degenerate_case():
+    """k1 = k2: the upper scattered field vanishes up to PML truncation, and
+    the GPU agrees with the oracle on the boundary data."""
+    import oracle
+    wl = workloads.tiny().with_(k2=workloads.tiny().k1, S=4.0)
+    g = oracle.geometry(wl)
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    ref = oracle.solve(g, modes, b1, b2)
+    s = _solver(wl)
+    out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes([("point", 0.3, 1.0)])]
+    assert np.max(_boundary_err(out, ref[:4])) <= BOUNDARY_TOL
+    assert np.linalg.norm(out[0][0]) / np.linalg.norm(b1[0]) < 1e-4
+
+
+# ------------------------------------------------- small workload (cfg of the paper's small case)
+
+def test_small_boundary_data_against_stored_oracle():
+    ref = np.load(os.path.join(HERE, "golden", "boundary_small.npz"))
+    wl = workloads.small()
+    s = _solver(wl)
+    out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(list(wl.incidences))]
+    errs = _boundary_err(out, (ref["u1"], ref["p1"], ref["u2"], ref["p2"]))
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+    # the on-axis source only drives mode 0
+    assert np.max(np.abs(out[0][1:])) <= 1e-12 * np.max(np.abs(out[0][0]))
+
+
+def test_small_operator_rows_against_oracle():
+    import oracle
+    from paper_2412_11162_amd._binding import PMLBIE_KEEP_OPERATORS
+    wl = workloads.small()
+    g = oracle.geometry(wl)
+    rows = [0, 37, 130, 200, 255]
+    modes = [0, 7, 16]
+    S, K = oracle.core.operator_rows(g, rows, [wl.k1, wl.k2], modes)
+    s = _solver(wl, flags=PMLBIE_KEEP_OPERATORS)
+    N = g.n
+    for j, n in enumerate(modes):
+        G = s.get_operator(n).cpu().numpy()
+        I = np.eye(N)[rows]
+        for (blkG, ref) in ((G[rows, :N], K[0, j] + I), (G[rows, N:], -S[0, j]),
+                            (G[[N + r for r in rows], :N], K[1, j] - I), (G[[N + r for r in rows], N:], -S[1, j])):
+            assert _normwise(blkG, ref) <= KERNEL_TOL, n
+
+
+# ------------------------------------------------ paper-scale workload (the benchmark configuration)
+
+@pytest.fixture(scope="module")
+def paper_solver():
+    from paper_2412_11162_amd._binding import PMLBIE_KEEP_OPERATORS
+    wl = workloads.paper_scale()
+    return wl, _solver(wl, flags=PMLBIE_KEEP_OPERATORS)
+
+
+def test_paper_scale_modal_kernels_sampled(paper_solver):
+    """Sampled node pairs of every class (far FFT, split, direct) at the
+    benchmark size, against the oracle's adaptive quadrature."""
+    import oracle
+    wl, s = paper_solver
+    g = oracle.geometry(wl)
+    pairs = workloads.seeded_pairs(g.n, 96, seed=3)
+    # add near-in-index but off-panel pairs and deep-PML pairs
+    extra = [(1600, 1640), (1990, 1950), (2040, 1900), (700, 760), (1400, 1350), (10, 60)]
+    pairs = np.concatenate([pairs, np.array(extra)])
+    geom = []
+    for i, l in pairs:
+        geom.append([g.rho[i], g.I[i], g.rho[l], g.I[l], g.rho[i] - g.rho[l], g.I[i] - g.I[l],
+                     g.z[i] - g.z[l], 0.0, g.nrho[l].real, g.nrho[l].imag, g.nz[l].real, g.nz[l].imag])
+    out = s.modal_kernels(np.array(geom)).cpu().numpy()  # [pair, (S1, K1, S2, K2), mode]
+    modes = list(range(wl.m_max + 1))
+    ref = oracle.modal_kernels_nodes(g, pairs, [wl.k1, wl.k2], modes)  # [pair, k, (S, K), mode]
+    refr = np.stack([ref[:, 0, 0], ref[:, 0, 1], ref[:, 1, 0], ref[:, 1, 1]], axis=1)
+    for sidx in range(4):
+        for n in modes:
+            assert _normwise(out[:, sidx, n], refr[:, sidx, n]) <= KERNEL_TOL, (sidx, n)
+
+
+def test_paper_scale_operator_rows(paper_solver):
+    """Rows of the assembled matrices (far, split, direct and near-panel
+    entries) at the benchmark size for three modes."""
+    import oracle
+    wl, s = paper_solver
+    g = oracle.geometry(wl)
+    rows = [5, 1100, 1700]
+    modes = [0, 64, 128]
+    S, K = oracle.core.operator_rows(g, rows, [wl.k1, wl.k2], modes)
+    N = g.n
+    for j, n in enumerate(modes):
+        G = s.get_operator(n).cpu().numpy()
+        I = np.eye(N)[rows]
+        for (blkG, ref) in ((G[rows, :N], K[0, j] + I), (G[rows, N:], -S[0, j]),
+                            (G[[N + r for r in rows], :N], K[1, j] - I), (G[[N + r for r in rows], N:], -S[1, j])):
+            assert _normwise(blkG, ref) <= KERNEL_TOL, n
+
+
+def test_paper_scale_boundary_data_against_stored_oracle(paper_solver):
+    wl, s = paper_solver
+    ref = np.load(os.path.join(HERE, "golden", "boundary_paper_scale.npz"))
+    out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(list(wl.incidences))]
+    modes = list(ref["modes"])
+    sel = [o[modes] for o in out]
+    errs = _boundary_err(sel, (ref["u1"], ref["p1"], ref["u2"], ref["p2"]))
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+
+
+# ----------------------------------------------------------------- edge cases
+
+def test_call_order_and_argument_errors():
+    from paper_2412_11162_amd.solver import Solver, PmlbieError
+    wl = workloads.tiny()
+    s = Solver(0)
+    with pytest.raises(PmlbieError) as e:
+        s.build_modal_operators(32, 8)
+    assert e.value.code == -2
+    s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
+    with pytest.raises(PmlbieError) as e:
+        s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T + 0.5, wl.S, wl.a2, wl.T2, wl.S2)
+    assert e.value.code == -1
+    s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2)
+    for nt, mm in ((48, 8), (32, 17), (8, 2)):
+        with pytest.raises(PmlbieError) as e:
+            s.build_modal_operators(nt, mm)
+        assert e.value.code == -1
+    with pytest.raises(PmlbieError) as e:
+        s.solve_modes([("point", 0.3, 1.0)])
+    assert e.value.code == -2
+    s.build_modal_operators(32, 8)
+    with pytest.raises(PmlbieError):
+        s.solve_modes([("point", 0.3, -2.0)])  # source below the interface
+    s.solve_modes([("point", 0.3, 1.0)])
+    assert s.evaluate_field(np.zeros((0, 3)), 1).shape == (1, 0)
+
+
+def test_field_matches_oracle_representation():
+    """Field synthesis off the curve against the oracle's representation
+    formula on the same (oracle) boundary data and kernels."""
+    import oracle
+    wl = workloads.tiny()
+    g = oracle.geometry(wl)
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    sol = oracle.solve(g, modes, b1, b2)
+    pts = np.array([[0.5, 1.4], [1.2, -0.9], [0.2, 0.9]])
+    theta = np.array([0.0, 0.7, 2.0])
+    ref = np.zeros(len(pts), dtype=complex)
+    for q in range(len(pts)):
+        z0 = float(np.interp(pts[q, 0], g.rho, g.z))
+        med = 1 if pts[q, 1] > z0 else 2
+        fm = oracle.field_modes(g, modes, sol, pts[q:q + 1], med)[:, 0]
+        ref[q] = (fm[0] + 2 * np.sum(fm[1:] * np.cos(np.arange(1, len(modes)) * theta[q]))) / (2 * np.pi)
+    s = _solver(wl)
+    s.solve_modes([("point", 0.3, 1.0)])
+    rtz = np.stack([pts[:, 0], theta, pts[:, 1]], axis=1)
+    out = s.evaluate_field(rtz, 1)[0]
+    assert np.max(np.abs(out - ref)) <= 1e-8 * np.max(np.abs(ref))

@@ -44,12 +44,13 @@ class Workload:
     p: int
     nodes_per_segment: int
     n_theta: int
+    m_max_: int
     # incidences: ("point", rho*, z*) or ("plane", phi_inc)
     incidences: Tuple[Tuple, ...] = field(default_factory=tuple)
 
     @property
     def m_max(self) -> int:
-        return self.n_theta // 4
+        return self.m_max_
 
     @property
     def n_sub(self) -> int:
@@ -78,7 +79,7 @@ def small() -> Workload:
         k1=2 * math.pi, k2=3 * math.pi,
         bumps=((0.3, 0.0, 1.0),), cos_freq=0.0,
         a1=2.0, T=1.0, S=2.0, a2=2.0, T2=1.0, S2=2.0, p=6,
-        nodes_per_segment=64, n_theta=64,
+        nodes_per_segment=64, n_theta=64, m_max_=16,
         incidences=(("point", 0.0, 1.0),),
     )
 
@@ -87,13 +88,13 @@ def paper_scale() -> Workload:
     """Plain FP64 at paper scale: k1 = 10, k2 = 15,
     h = 0.5 exp(-rho^2/2) cos(2 rho), PML rho in [4, 5.5], sigma0 = 3,
     512 nodes per segment (2048 nodes, 4096 unknowns per mode), 256 theta
-    samples (modes -128..128), point source at (0.3, 0, 1.2)."""
+    samples with modes -128..128 kept, point source at (0.3, 0, 1.2)."""
     return Workload(
         name="paper_scale",
         k1=10.0, k2=15.0,
         bumps=((0.5, 0.0, math.sqrt(2.0)),), cos_freq=2.0,
         a1=4.0, T=1.5, S=3.0, a2=3.0, T2=1.5, S2=3.0, p=6,
-        nodes_per_segment=512, n_theta=256,
+        nodes_per_segment=512, n_theta=256, m_max_=128,
         incidences=(("point", 0.3, 1.2),),
     )
 
@@ -113,14 +114,15 @@ def largest(seed: int = 11162) -> Workload:
         name="largest",
         k1=20.0, k2=30.0, bumps=bumps, cos_freq=0.0,
         a1=5.0, T=2.0, S=3.0, a2=4.0, T2=2.0, S2=3.0, p=6,
-        nodes_per_segment=1024, n_theta=512, incidences=incs,
+        nodes_per_segment=1024, n_theta=512, m_max_=256, incidences=incs,
     )
 
 
 def tiny(nodes_per_segment: int = 16, n_theta: int = 32, **kw) -> Workload:
     """A reduced version of the small workload (used for oracle-vs-kernel
     parity on the CPU side and for fast end-to-end checks)."""
-    w = small().with_(name="tiny", nodes_per_segment=nodes_per_segment, n_theta=n_theta)
+    w = small().with_(name="tiny", nodes_per_segment=nodes_per_segment, n_theta=n_theta,
+                      m_max_=n_theta // 4)
     return w.with_(**kw) if kw else w
 
 
