@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="paper_scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the per-mode systems would shard "
@@ -79,10 +80,10 @@ def main():
     wl = workloads.ALL[args.workload]()
     s = Solver(0)
 
-    def step():
+    def step(precision=0):
         s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
         s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
-        s.build_modal_operators(wl.n_theta, wl.m_max)
+        s.build_modal_operators(wl.n_theta, wl.m_max, precision)
         return s.solve_modes(list(wl.incidences))
 
     for _ in range(args.warmup):
@@ -138,6 +139,39 @@ def main():
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
     }
+    if not args.no_mixed:
+        # complex64 LU on FP32 MFMA + FP64 refinement, same workload; its error
+        # is measured against this run's FP64 result (which the parity tests
+        # hold to the FP64 oracle)
+        ref = [o.cpu().numpy() for o in step(0)]
+        step(1)
+        torch.cuda.synchronize()
+        tm = []
+        for k in range(args.steps):
+            t0 = time.time()
+            sol = step(1)
+            torch.cuda.synchronize()
+            tm.append(time.time() - t0)
+            print("mixed step %d: %.1f ms" % (k, 1e3 * tm[-1]), file=sys.stderr, flush=True)
+        got = [o.cpu().numpy() for o in sol]
+        xg = np.concatenate(got, axis=2)[:, 0]
+        xr = np.concatenate(ref, axis=2)[:, 0]
+        big = np.max(np.linalg.norm(xr, axis=1))
+        errs = []
+        for j in range(xr.shape[0]):
+            nr = np.linalg.norm(xr[j])
+            d = np.linalg.norm(xg[j] - xr[j])
+            errs.append(d / nr if nr > 1e-9 * big else d / big)
+        stm, cnt = s.stats()
+        ms_mixed = 1e3 * float(np.mean(tm))
+        out["mixed_precision"] = {
+            "ms_per_step": ms_mixed, "value": units / (ms_mixed * 1e-3), "unit": "pairs*modes/s",
+            "speedup_vs_fp64": ms_step / ms_mixed, "dtype": "c64 LU + f64 refinement",
+            "max_rel_err_vs_fp64": float(np.max(errs)), "refinement_iterations": int(cnt[0]),
+            "final_rel_residual": float(cnt[1]),
+            "stage_ms": {"lu": stm[5], "lu_trailing_update": stm[6], "solve": stm[7], "refinement": stm[9]},
+            "lu_trailing_update_tflops": lu_gemm_flops(2 * N, M + 1) / (stm[6] * 1e-3) / 1e12 if stm[6] > 0 else None,
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))

@@ -74,6 +74,9 @@ struct pmlbie_ctx {
   DBuf<zd> tw_far, tw_int;
   DBuf<double> glx, glw;
   DBuf<zd> A, Alow, Akeep;
+  DBuf<zf> A32;               // complex64 factors (mixed precision)
+  DBuf<zd> rbuf, xs;          // refinement: residual / correction, iterate
+  DBuf<double> rsq, rnorm;
   DBuf<int> ipiv, info;
   DBuf<PairGeom> lgeom;
   DBuf<int2> ldest;
@@ -304,8 +307,8 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       return fail(c, PMLBIE_EINVAL, "build: n_theta must be a power of two >= 16");
     if (m_max < 0 || m_max > n_theta / 2)
       return fail(c, PMLBIE_EINVAL, "build: need 0 <= m_max <= n_theta / 2");
-    if (precision != PMLBIE_FP64)
-      return fail(c, PMLBIE_EINVAL, "build: only PMLBIE_FP64 is available in this library");
+    if (precision != PMLBIE_FP64 && precision != PMLBIE_MIXED)
+      return fail(c, PMLBIE_EINVAL, "build: precision must be PMLBIE_FP64 or PMLBIE_MIXED");
     auto t_all = std::chrono::steady_clock::now();
     c->stage = 2;
     c->n_theta = n_theta;
@@ -431,12 +434,20 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     // the near-panel pairs of the grid were not counted as far
     c->cnt_far -= 16LL * (long long)ajobs.size();
 
-    // keep what the solve needs: the lower block row [K2 - D2, -S2]
-    c->Alow.alloc((size_t)(M + 1) * N * n2);
-    for (int n = 0; n <= M; ++n)
-      HIPCHK(hipMemcpyAsync(c->Alow.p + (size_t)n * N * n2, c->A.p + (size_t)n * ms + (size_t)N * n2,
-                            (size_t)N * n2 * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
-    if (flags & PMLBIE_KEEP_OPERATORS) {
+    // keep what the solve needs: the unfactored operator (FP64) -- the lower
+    // block row [K2 - D2, -S2] for the right-hand sides, and in mixed
+    // precision the whole matrix for the residuals of the refinement
+    const bool mixed = precision == PMLBIE_MIXED;
+    if (mixed) {
+      c->Alow.release();
+    } else {
+      c->A32.release();
+      c->Alow.alloc((size_t)(M + 1) * N * n2);
+      for (int n = 0; n <= M; ++n)
+        HIPCHK(hipMemcpyAsync(c->Alow.p + (size_t)n * N * n2, c->A.p + (size_t)n * ms + (size_t)N * n2,
+                              (size_t)N * n2 * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+    }
+    if ((flags & PMLBIE_KEEP_OPERATORS) && !mixed) {
       c->Akeep.alloc((size_t)(M + 1) * ms);
       HIPCHK(hipMemcpyAsync(c->Akeep.p, c->A.p, (size_t)(M + 1) * ms * sizeof(zd),
                             hipMemcpyDeviceToDevice, c->stream));
@@ -444,7 +455,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       c->Akeep.release();
     }
 
-    // per-mode LU
+    // per-mode LU (complex128, or complex64 on FP32 MFMA in mixed precision)
     Timer t_lu(c->stream);
     const int npan = (int)((n2 + LU_NB - 1) / LU_NB);
     std::vector<hipEvent_t> gb(npan), ge(npan);
@@ -455,7 +466,14 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     LuTimers tm;
     tm.gemm_begin = gb.data();
     tm.gemm_end = ge.data();
-    lu_factor_batched<double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->stream, &tm);
+    if (mixed) {
+      c->A32.alloc((size_t)(M + 1) * ms);
+      launch_to_c64(c->A.p, c->A32.p, (long)(M + 1) * ms, c->stream);
+      HIPCHK(hipGetLastError());
+      lu_factor_batched<float>(c->A32.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->stream, &tm);
+    } else {
+      lu_factor_batched<double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->stream, &tm);
+    }
     HIPCHK(hipGetLastError());
     c->stage_ms[5] = t_lu.stop();
     double gsum = 0;
@@ -529,12 +547,66 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     c->b2.alloc(vec);
     c->x.alloc(2 * vec);
     launch_rhs_gather_point(c->raw.p, N, M, n_rhs, c->b1.p, c->b2.p, c->stream);
-    launch_lower_rhs(c->Alow.p, (long)N * n2, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+    const bool mixed = c->precision == PMLBIE_MIXED;
+    if (mixed)
+      launch_lower_rhs(c->A.p + (size_t)N * n2, ms, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+    else
+      launch_lower_rhs(c->Alow.p, (long)N * n2, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[8] = t_rhs.stop();
     Timer t_sol(c->stream);
-    lu_solve_batched<double, double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->x.p, n_rhs, c->stream);
-    HIPCHK(hipGetLastError());
+    double t_ref = 0.0;
+    c->counters[0] = 0;
+    c->counters[1] = 0;
+    if (!mixed) {
+      lu_solve_batched<double, double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->x.p, n_rhs, c->stream);
+      HIPCHK(hipGetLastError());
+    } else {
+      // FP64 iterative refinement with the complex64 factors:
+      //   d = LU32 \ r (FP64 arithmetic), x += d, r = rhs - A64 x,
+      // until ||r|| <= tol ||rhs|| for every mode and right-hand side.
+      const long nv = (long)(M + 1) * n_rhs;
+      const long len = nv * n2;
+      c->rbuf.alloc(len);
+      c->xs.alloc(len);
+      c->rsq.alloc(len);
+      c->rnorm.alloc(2 * nv);
+      const double tol = 1e-10;
+      const int maxit = 30;
+      HIPCHK(hipMemsetAsync(c->xs.p, 0, len * sizeof(zd), c->stream));
+      HIPCHK(hipMemcpyAsync(c->rbuf.p, c->x.p, len * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+      launch_sq(c->x.p, len, c->rsq.p, c->stream);
+      launch_sumsq(c->rsq.p, (int)n2, (int)nv, c->rnorm.p + nv, c->stream);  // ||rhs||^2
+      std::vector<double> hn(2 * nv);
+      Timer t_r(c->stream);
+      int it = 0;
+      double worst = 0.0;
+      for (; it < maxit; ++it) {
+        lu_solve_batched<float, double>(c->A32.p, ms, (int)n2, M + 1, c->ipiv.p, c->rbuf.p, n_rhs, c->stream);
+        launch_axpy(c->xs.p, c->rbuf.p, len, c->stream);
+        launch_residual(c->A.p, ms, (int)n2, M + 1, n_rhs, c->xs.p, c->x.p, c->rbuf.p, c->rsq.p, c->stream);
+        launch_sumsq(c->rsq.p, (int)n2, (int)nv, c->rnorm.p, c->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(hn.data(), c->rnorm.p, 2 * nv * sizeof(double), hipMemcpyDeviceToHost));
+        worst = 0.0;
+        for (long v = 0; v < nv; ++v) {
+          const double rr = sqrt(hn[v]), bb = sqrt(hn[nv + v]);
+          const double rel = bb > 0 ? rr / bb : (rr > 0 ? 1.0 : 0.0);
+          worst = std::max(worst, rel);
+        }
+        if (worst <= tol) {
+          ++it;
+          break;
+        }
+      }
+      t_ref = t_r.stop();
+      c->counters[0] = it;
+      c->counters[1] = worst;
+      HIPCHK(hipMemcpyAsync(c->x.p, c->xs.p, len * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+      if (worst > tol)
+        return fail(c, PMLBIE_ENOCONV, "solve: refinement stopped at relative residual " +
+                                           std::to_string(worst) + " after " + std::to_string(it) + " iterations");
+    }
     c->u1.alloc(vec);
     c->p1.alloc(vec);
     c->u2.alloc(vec);
@@ -546,7 +618,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     if (d_phi1) HIPCHK(hipMemcpyAsync(d_phi1, c->p1.p, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (d_u2) HIPCHK(hipMemcpyAsync(d_u2, c->u2.p, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (d_phi2) HIPCHK(hipMemcpyAsync(d_phi2, c->p2.p, bytes, hipMemcpyDeviceToDevice, c->stream));
-    c->stage_ms[9] = 0.0;
+    c->stage_ms[9] = t_ref;
     c->stage_ms[7] = t_sol.stop() + c->stage_ms[8];
     (void)t0;
     c->stage = 4;
@@ -649,10 +721,12 @@ int pmlbie_modal_kernels(pmlbie_ctx* c, int n_pairs, const double* geom, void* d
 int pmlbie_get_operator(pmlbie_ctx* c, int mode, void* d_out) {
   return guarded(c, [&]() -> int {
     if (c->stage < 3) return fail(c, PMLBIE_ESTATE, "get_operator: build first");
-    if (!c->Akeep.p) return fail(c, PMLBIE_ESTATE, "get_operator: build with PMLBIE_KEEP_OPERATORS");
+    // in mixed precision the FP64 operator is kept unfactored anyway
+    const zd* src = c->precision == PMLBIE_MIXED ? c->A.p : c->Akeep.p;
+    if (!src) return fail(c, PMLBIE_ESTATE, "get_operator: build with PMLBIE_KEEP_OPERATORS");
     if (mode < 0 || mode > c->M || !d_out) return fail(c, PMLBIE_EINVAL, "get_operator: bad mode");
     const size_t ms = (size_t)4 * c->N * c->N;
-    HIPCHK(hipMemcpyAsync(d_out, c->Akeep.p + (size_t)mode * ms, ms * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(d_out, src + (size_t)mode * ms, ms * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;
   });

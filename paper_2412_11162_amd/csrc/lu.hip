@@ -386,34 +386,36 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
 }
 
 // ---------------------------------------------------------------------------
-// Solves with the factors, one workgroup per matrix, nrhs right-hand sides
-// stored as b[mat][rhs][n] (overwritten by the solution).
+// Solves with the factors, panel by panel; nrhs right-hand sides stored as
+// b[mat][rhs][n] (overwritten by the solution).
+//   forward, panel [k0, k0+nb): (1) one workgroup per matrix applies the
+//   panel's row interchanges to b and solves the unit lower diagonal block;
+//   (2) many workgroups update the rows below, one wavefront per row.
+//   backward: (3) the upper diagonal block, (4) the rows above.
 template <typename T, typename TB>
-__global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long ms, int n,
-                                               const int* __restrict__ ipiv, cx<TB>* __restrict__ B,
-                                               int nrhs) {
+__global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A, long ms, int n,
+                                                    int k0, int nb, const int* __restrict__ ipiv,
+                                                    cx<TB>* __restrict__ B, int nrhs, int upper) {
   const cx<T>* a = A + (long)blockIdx.x * ms;
   const int* piv = ipiv + (long)blockIdx.x * n;
   cx<TB>* b = B + (long)blockIdx.x * nrhs * n;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x;
   __shared__ cx<TB> yb[LU_NB][LU_MAX_RHS];
-  // forward: panel by panel
-  for (int k0 = 0; k0 < n; k0 += LU_NB) {
-    const int nb = min(LU_NB, n - k0);
-    if (tid < nrhs) {
-      cx<TB>* v = b + (long)tid * n;
-      for (int j = 0; j < nb; ++j) {
-        const int p = piv[k0 + j];
-        if (p != k0 + j) {
-          cx<TB> t0 = v[k0 + j];
-          v[k0 + j] = v[p];
-          v[p] = t0;
-        }
+  if (!upper && tid < nrhs) {
+    cx<TB>* v = b + (long)tid * n;
+    for (int j = 0; j < nb; ++j) {
+      const int p = piv[k0 + j];
+      if (p != k0 + j) {
+        const cx<TB> t0 = v[k0 + j];
+        v[k0 + j] = v[p];
+        v[p] = t0;
       }
     }
-    __syncthreads();
-    for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  if (!upper) {
     for (int j = 0; j < nb; ++j) {
       for (int e = tid; e < nb * nrhs; e += 256) {
         const int r = e % nb, s = e / nb;
@@ -424,31 +426,7 @@ __global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long
       }
       __syncthreads();
     }
-    for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
-    __syncthreads();
-    // rows below: one wavefront per row, lanes over the panel columns
-    for (int r = k0 + nb + wid; r < n; r += 4) {
-      const cx<T>* row = a + (long)r * n + k0;
-      for (int s = 0; s < nrhs; ++s) {
-        cx<TB> acc{TB(0), TB(0)};
-        for (int j = lane; j < nb; j += 64) {
-          const cx<T> l = row[j];
-          acc = acc + cx<TB>{(TB)l.re, (TB)l.im} * yb[j][s];
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-          acc.re += __shfl_xor(acc.re, off);
-          acc.im += __shfl_xor(acc.im, off);
-        }
-        if (lane == 0) b[(long)s * n + r] = b[(long)s * n + r] - acc;
-      }
-    }
-    __syncthreads();
-  }
-  // backward
-  for (int k0 = ((n - 1) / LU_NB) * LU_NB; k0 >= 0; k0 -= LU_NB) {
-    const int nb = min(LU_NB, n - k0);
-    for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
-    __syncthreads();
+  } else {
     for (int j = nb - 1; j >= 0; --j) {
       if (tid < nrhs) {
         const cx<T> u = a[(long)(k0 + j) * n + k0 + j];
@@ -464,24 +442,46 @@ __global__ __launch_bounds__(256) void k_solve(const cx<T>* __restrict__ A, long
       }
       __syncthreads();
     }
-    for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
-    __syncthreads();
-    for (int r = wid; r < k0; r += 4) {
-      const cx<T>* row = a + (long)r * n + k0;
-      for (int s = 0; s < nrhs; ++s) {
-        cx<TB> acc{TB(0), TB(0)};
-        for (int j = lane; j < nb; j += 64) {
-          const cx<T> u = row[j];
-          acc = acc + cx<TB>{(TB)u.re, (TB)u.im} * yb[j][s];
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-          acc.re += __shfl_xor(acc.re, off);
-          acc.im += __shfl_xor(acc.im, off);
-        }
-        if (lane == 0) b[(long)s * n + r] = b[(long)s * n + r] - acc;
-      }
+  }
+  for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
+}
+
+// rows [r0, r1) of b -= A[rows][k0 .. k0+nb) * b[k0 .. k0+nb); one wavefront
+// per row, lanes over the panel columns; grid (row blocks of 16, matrices).
+template <typename T, typename TB>
+__global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ A, long ms, int n,
+                                                      int k0, int nb, cx<TB>* __restrict__ B,
+                                                      int nrhs, int r0, int r1) {
+  const cx<T>* a = A + (long)blockIdx.y * ms;
+  cx<TB>* b = B + (long)blockIdx.y * nrhs * n;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ cx<TB> yb[LU_MAX_RHS][LU_NB];
+  for (int e = tid; e < nb * nrhs; e += 256) yb[e / nb][e % nb] = b[(long)(e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  for (int rr = 0; rr < 4; ++rr) {
+    const int r = r0 + blockIdx.x * 16 + wid * 4 + rr;
+    if (r >= r1) break;
+    const cx<T>* row = a + (long)r * n + k0;
+    cx<T> lv[LU_NB / 64];
+#pragma unroll
+    for (int t = 0; t < LU_NB / 64; ++t) {
+      const int j = lane + 64 * t;
+      lv[t] = j < nb ? row[j] : cx<T>{T(0), T(0)};
     }
-    __syncthreads();
+    for (int s = 0; s < nrhs; ++s) {
+      cx<TB> acc{TB(0), TB(0)};
+#pragma unroll
+      for (int t = 0; t < LU_NB / 64; ++t) {
+        const int j = lane + 64 * t;
+        if (j < nb) acc = acc + cx<TB>{(TB)lv[t].re, (TB)lv[t].im} * yb[s][j];
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        acc.re += __shfl_xor(acc.re, off);
+        acc.im += __shfl_xor(acc.im, off);
+      }
+      if (lane == 0) b[(long)s * n + r] = b[(long)s * n + r] - acc;
+    }
   }
 }
 
@@ -517,7 +517,23 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
 template <typename T, typename TB>
 void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv, cx<TB>* B,
                       int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_solve<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, ipiv, B, nrhs);
+  for (int k0 = 0; k0 < n; k0 += LU_NB) {
+    const int nb = std::min(LU_NB, n - k0);
+    hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
+                       B, nrhs, 0);
+    const int r0 = k0 + nb, r1 = n;
+    if (r1 > r0)
+      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((r1 - r0 + 15) / 16, batch), dim3(256), 0, st,
+                         A, ms, n, k0, nb, B, nrhs, r0, r1);
+  }
+  for (int k0 = ((n - 1) / LU_NB) * LU_NB; k0 >= 0; k0 -= LU_NB) {
+    const int nb = std::min(LU_NB, n - k0);
+    hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
+                       B, nrhs, 1);
+    if (k0 > 0)
+      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((k0 + 15) / 16, batch), dim3(256), 0, st, A, ms,
+                         n, k0, nb, B, nrhs, 0, k0);
+  }
 }
 
 template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, hipStream_t, LuTimers*);

@@ -99,6 +99,87 @@ __global__ void k_field(const zd* __restrict__ raw, const double* __restrict__ W
   out[e] = tot;
 }
 
+// FP64 -> FP32 copy of the operators (complex128 -> complex64).
+__global__ void k_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, long count) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
+    const zd v = src[e];
+    dst[e] = zf{(float)v.re, (float)v.im};
+  }
+}
+
+// Residual of the FP64 systems: r = rhs - A x for all modes and right-hand
+// sides (A row-major 2N x 2N per mode), one wavefront per row; rs2 receives
+// |r_i|^2 for the convergence test.
+__global__ __launch_bounds__(256) void k_residual(const zd* __restrict__ A, long ms, int n,
+                                                  int nrhs, const zd* __restrict__ x,
+                                                  const zd* __restrict__ rhs, zd* __restrict__ r,
+                                                  double* __restrict__ rs2) {
+  const int md = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const zd* row = A + (long)md * ms + (long)i * n;
+  for (int s = 0; s < nrhs; ++s) {
+    const zd* xv = x + ((long)md * nrhs + s) * n;
+    zd acc{0.0, 0.0};
+    for (int c = lane; c < n; c += 64) acc = cfma(row[c], xv[c], acc);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      acc.re += __shfl_xor(acc.re, off);
+      acc.im += __shfl_xor(acc.im, off);
+    }
+    if (lane == 0) {
+      const long e = ((long)md * nrhs + s) * n + i;
+      const zd v = rhs[e] - acc;
+      r[e] = v;
+      rs2[e] = abs2(v);
+    }
+  }
+}
+
+// Per (mode, rhs) sums of squares of vectors of length n: out[v] = sum |.|^2.
+__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ sq, int n, double* __restrict__ out) {
+  const double* p = sq + (long)blockIdx.x * n;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += p[i];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ void k_sq(const zd* __restrict__ v, long count, double* __restrict__ sq) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) sq[e] = abs2(v[e]);
+}
+
+__global__ void k_axpy(zd* __restrict__ x, const zd* __restrict__ d, long count) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) x[e] = x[e] + d[e];
+}
+
+void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_c64, dim3(256 * 32), dim3(256), 0, st, src, dst, count);
+}
+void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd* x, const zd* rhs,
+                     zd* r, double* rs2, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3((n + 3) / 4, modes), dim3(256), 0, st, A, ms, n, nrhs, x, rhs, r,
+                     rs2);
+}
+void launch_sumsq(const double* sq, int n, int nvec, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nvec), dim3(256), 0, st, sq, n, out);
+}
+void launch_sq(const zd* v, long count, double* sq, hipStream_t st) {
+  hipLaunchKernelGGL(k_sq, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v, count, sq);
+}
+void launch_axpy(zd* x, const zd* d, long count, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, d, count);
+}
+
 void launch_rhs_gather_point(const zd* raw, int N, int M, int nrhs, zd* b1, zd* b2, hipStream_t st) {
   const long tot = (long)(M + 1) * nrhs * N;
   hipLaunchKernelGGL(k_rhs_gather_point, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, raw,

@@ -201,6 +201,34 @@ def test_paper_scale_boundary_data_against_stored_oracle(paper_solver):
     assert np.max(errs) <= BOUNDARY_TOL, errs
 
 
+# ---------------------------------------------- mixed precision (complex64 LU + FP64 refinement)
+
+MIXED_TOL = 1e-6
+
+
+def test_mixed_small_boundary_data():
+    from paper_2412_11162_amd._binding import PMLBIE_MIXED
+    ref = np.load(os.path.join(HERE, "golden", "boundary_small.npz"))
+    wl = workloads.small()
+    s = _solver(wl, precision=PMLBIE_MIXED)
+    out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(list(wl.incidences))]
+    errs = _boundary_err(out, (ref["u1"], ref["p1"], ref["u2"], ref["p2"]))
+    assert np.max(errs) <= MIXED_TOL, errs
+    st, cnt = s.stats()
+    assert 1 <= cnt[0] <= 30 and cnt[1] <= 1e-10
+
+
+def test_mixed_paper_scale_boundary_data():
+    from paper_2412_11162_amd._binding import PMLBIE_MIXED
+    ref = np.load(os.path.join(HERE, "golden", "boundary_paper_scale.npz"))
+    wl = workloads.paper_scale()
+    s = _solver(wl, precision=PMLBIE_MIXED)
+    out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(list(wl.incidences))]
+    modes = list(ref["modes"])
+    errs = _boundary_err([o[modes] for o in out], (ref["u1"], ref["p1"], ref["u2"], ref["p2"]))
+    assert np.max(errs) <= MIXED_TOL, errs
+
+
 # ----------------------------------------------------------------- edge cases
 
 def test_call_order_and_argument_errors():
