@@ -84,7 +84,6 @@ struct pmlbie_ctx {
   DBuf<zd> zhat, phat, qscr;
   DBuf<zd> raw;
   DBuf<PairGeom> xgeom;
-  DBuf<int2> xdest;
   DBuf<double> coef;
   DBuf<NearJob> jobs;
   // solution of the last solve
@@ -141,18 +140,6 @@ struct Timer {
   }
 };
 
-int classify_host(const PairGeom& g, const ClassParams& cp, bool allow_far) {
-  PairInv v = pair_invariants(g);
-  double delta, re0;
-  singularity(v, delta, re0);
-  const double sc = sqrt(cabs_(g.rt * g.rs));
-  const double bw = cp.bw * cp.kmax * sc;
-  if (allow_far && (cp.nt_far - cp.M - bw) * delta >= cp.c_far) return CLASS_FAR;
-  zd Rpi = csqrt_(v.d2 + v.c4);
-  double grow = cp.kmax * fabs(Rpi.im) + cp.kmax_im * fabs(Rpi.re);
-  return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
-}
-
 // Split-path work on a device list [first, first+count): phase 1 (singular
 // modes) in chunks, phase 2 (smooth FFTs + convolution).
 void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count, zd* A, long n2,
@@ -171,38 +158,35 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
   }
 }
 
-// Explicit pair list (host) -> raw modal values raw[dest.x][s][n].
+// Explicit pair list (host) -> raw modal values raw[q][s][n]: upload, classify
+// on the device into far / split / direct lists, run the three paths.
 void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long long* counts) {
-  std::vector<PairGeom> gs[3];
-  std::vector<int2> ds[3];
-  for (size_t q = 0; q < g.size(); ++q) {
-    int cls = classify_host(g[q], c->cp, true);
-    gs[cls].push_back(g[q]);
-    ds[cls].push_back(make_int2((int)q, -1));
-  }
-  size_t tot = g.size();
-  c->xgeom.alloc(std::max<size_t>(tot, 1));
-  c->xdest.alloc(std::max<size_t>(tot, 1));
-  size_t off[3] = {0, gs[0].size(), gs[0].size() + gs[1].size()};
-  for (int k = 0; k < 3; ++k) {
-    if (gs[k].empty()) continue;
-    HIPCHK(hipMemcpyAsync(c->xgeom.p + off[k], gs[k].data(), gs[k].size() * sizeof(PairGeom),
-                          hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->xdest.p + off[k], ds[k].data(), ds[k].size() * sizeof(int2),
-                          hipMemcpyHostToDevice, c->stream));
-  }
-  if (counts) {
-    counts[0] += gs[0].size();
-    counts[1] += gs[1].size();
-    counts[2] += gs[2].size();
-  }
-  launch_list_far(c->nt_far, c->xgeom.p, c->xdest.p, (long)off[0], (long)gs[0].size(), c->M, c->k1,
-                  c->k2, c->tw_far.p, nullptr, 0, 0, nullptr, raw, c->stream);
+  const size_t tot = g.size();
+  if (tot == 0) return;
+  c->xgeom.alloc(tot);
+  HIPCHK(hipMemcpyAsync(c->xgeom.p, g.data(), tot * sizeof(PairGeom), hipMemcpyHostToDevice, c->stream));
+  c->lgeom.alloc(3 * tot > c->lgeom.n ? 3 * tot : c->lgeom.n);
+  c->ldest.alloc(3 * tot > c->ldest.n ? 3 * tot : c->ldest.n);
+  c->lcount.alloc(3);
+  HIPCHK(hipMemsetAsync(c->lcount.p, 0, 3 * sizeof(unsigned), c->stream));
+  WorkList wf{c->lgeom.p, c->ldest.p, c->lcount.p, (unsigned)tot};
+  WorkList ws{c->lgeom.p + tot, c->ldest.p + tot, c->lcount.p + 1, (unsigned)tot};
+  WorkList wd{c->lgeom.p + 2 * tot, c->ldest.p + 2 * tot, c->lcount.p + 2, (unsigned)tot};
+  launch_classify_list(c->xgeom.p, (long)tot, c->cp, wf, ws, wd, c->stream);
   HIPCHK(hipGetLastError());
-  run_split(c, c->xgeom.p + off[1], c->xdest.p + off[1], (long)gs[1].size(), nullptr, 0, 0, nullptr,
-            raw);
-  launch_direct(c->xgeom.p + off[2], c->xdest.p + off[2], 0, (long)gs[2].size(), c->M, c->k1,
-                c->k2, c->glx.p, c->glw.p, nullptr, 0, 0, nullptr, raw, kOmegaPiece, c->stream);
+  unsigned cnt[3];
+  HIPCHK(hipMemcpy(cnt, c->lcount.p, sizeof(cnt), hipMemcpyDeviceToHost));
+  if (counts) {
+    counts[0] += cnt[0];
+    counts[1] += cnt[1];
+    counts[2] += cnt[2];
+  }
+  launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, c->k1, c->k2, c->tw_far.p, nullptr, 0,
+                  0, nullptr, raw, c->stream);
+  HIPCHK(hipGetLastError());
+  run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw);
+  launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
+                nullptr, raw, kOmegaPiece, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
 }

@@ -49,6 +49,8 @@ void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, z
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                      zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
                      zd* raw, hipStream_t st);
+void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
+                          WorkList split, WorkList direct, hipStream_t st);
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
                            zd* phat, zd* qscr, hipStream_t st);
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,

@@ -47,6 +47,23 @@ __device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, z
   }
 }
 
+// Modes 0..M of one sequence s in {S1, K1, S2, K2} held in LDS, scaled.
+__device__ __forceinline__ void emit_one(const OutSpec& o, int2 dst, int s, double scale,
+                                         const zd* buf) {
+  if (dst.y >= 0) {
+    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
+    const double w2 = 2.0 * o.W[l] * scale;
+    // S blocks carry the minus sign of [[K1 + I, -S1], [K2 - I, -S2]]
+    const double f = (s & 1) ? w2 : -w2;
+    const long row = (s < 2 ? i : N + i), col = ((s & 1) ? l : N + l);
+    zd* p = o.A + row * o.n2 + col;
+    for (int n = threadIdx.x; n <= o.M; n += 64) p[(long)n * o.mstride] = f * buf[n];
+  } else {
+    zd* r = o.raw + (long)dst.x * 4 * (o.M + 1) + (long)s * (o.M + 1);
+    for (int n = threadIdx.x; n <= o.M; n += 64) r[n] = scale * buf[n];
+  }
+}
+
 __device__ __forceinline__ PairGeom node_pair(const NodesDev& nd, int i, int l) {
   PairGeom g;
   g.rt = zd{nd.rho[i], nd.I[i]};
@@ -99,37 +116,52 @@ __device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, con
   return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
 }
 
-// Raw-kernel FFT of one pair (one wavefront): samples on the half circle,
+// Raw-kernel FFT of one pair (one wavefront): samples on the half circle
+// held in registers (both media share R), then one sequence at a time is
 // mirrored to the full circle (the kernels are even in D), bit-reversed into
-// LDS, FFT, modes 0..M emitted.
+// a single LDS buffer, transformed, and its modes 0..M emitted.
 template <int NT>
 __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const zd* __restrict__ tw,
                                          zd* buf, const OutSpec& o, int2 dst) {
+  constexpr int SPL = (NT / 2) / 64 + 1;  // samples per lane
   const double scale = 2.0 * PMLBIE_PI / NT;
-  for (int j = threadIdx.x; j <= NT / 2; j += 64) {
-    const double sh = sin(PMLBIE_PI * j / NT);
-    zd S1, K1, S2, K2;
-    kernel_sample(v, sh * sh, k1, S1, K1);
-    kernel_sample(v, sh * sh, k2, S2, K2);
-    const int a = bitrev<NT>(j);
-    buf[a] = S1;
-    buf[NT + a] = K1;
-    buf[2 * NT + a] = S2;
-    buf[3 * NT + a] = K2;
-    if (j > 0 && j < NT / 2) {
-      const int b = bitrev<NT>(NT - j);
-      buf[b] = S1;
-      buf[NT + b] = K1;
-      buf[2 * NT + b] = S2;
-      buf[3 * NT + b] = K2;
+  zd smp[4][SPL];
+#pragma unroll
+  for (int t = 0; t < SPL; ++t) {
+    const int j = threadIdx.x + 64 * t;
+    if (j <= NT / 2) {
+      const double sh = sin(PMLBIE_PI * j / NT);
+      const double s2 = sh * sh;
+      const zd R2 = v.d2 + s2 * v.c4;
+      const zd R = csqrt_(R2);
+      const zd inv4piR = inv(R) * (0.25 / PMLBIE_PI);
+      const zd iR2 = inv(R2);
+      const zd N = v.N0 + s2 * v.N1;
+      const zd kk[2] = {k1, k2};
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const zd ikR = zd{0.0, 1.0} * (kk[m] * R);
+        const zd e = cexp_(ikR) * inv4piR;
+        smp[2 * m][t] = e;
+        smp[2 * m + 1][t] = N * e * (ikR - 1.0) * iR2;
+      }
     }
   }
-  __syncthreads();
-  fft_lds<NT, 4>(buf, tw);
-  for (int n = threadIdx.x; n <= o.M; n += 64)
-    emit(o, dst, n, scale * buf[n], scale * buf[NT + n], scale * buf[2 * NT + n],
-         scale * buf[3 * NT + n]);
-  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) {
+      const int j = threadIdx.x + 64 * t;
+      if (j <= NT / 2) {
+        buf[bitrev<NT>(j)] = smp[s][t];
+        if (j > 0 && j < NT / 2) buf[bitrev<NT>(NT - j)] = smp[s][t];
+      }
+    }
+    __syncthreads();
+    fft_lds<NT, 1>(buf, tw);
+    emit_one(o, dst, s, scale, buf);
+    __syncthreads();
+  }
 }
 
 // Main grid: every (target i, source l) pair off the near panels.  Far pairs
@@ -139,7 +171,7 @@ template <int NT>
 __global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
                                                  WorkList split, WorkList direct) {
-  __shared__ zd buf[4 * NT];
+  __shared__ zd buf[NT];
   const int N = nd.N;
   const long total = (long)N * N;
   for (long p = blockIdx.x; p < total; p += gridDim.x) {
@@ -164,13 +196,30 @@ __global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd
   }
 }
 
+// Classification of an explicit pair list into far / split / direct work
+// lists (destination = raw row q).
+__global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, ClassParams cp,
+                                WorkList far, WorkList split, WorkList direct) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const PairGeom g = geom[q];
+  const PairInv v = pair_invariants(g);
+  const int cls = classify(g, v, cp);
+  WorkList& wl = cls == CLASS_FAR ? far : (cls == CLASS_SPLIT ? split : direct);
+  const unsigned slot = atomicAdd(wl.count, 1u);
+  if (slot < wl.cap) {
+    wl.geom[slot] = g;
+    wl.dest[slot] = make_int2((int)q, -1);
+  }
+}
+
 // Explicit list of far pairs (right-hand sides, field points).
 template <int NT>
 __global__ __launch_bounds__(64) void k_list_far(const PairGeom* __restrict__ geom,
                                                  const int2* __restrict__ dest, long first,
                                                  long count, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o) {
-  __shared__ zd buf[4 * NT];
+  __shared__ zd buf[NT];
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
     const PairGeom g = geom[first + t];
     const PairInv v = pair_invariants(g);
@@ -494,7 +543,7 @@ template <int NT>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
                          const OutSpec& o, WorkList split, WorkList direct, hipStream_t st) {
   long total = (long)nd.N * nd.N;
-  int grid = (int)std::min<long>(total, 256L * 40);
+  int grid = (int)std::min<long>(total, 256L * 128);
   hipLaunchKernelGGL(k_grid_far<NT>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
                      direct);
 }
@@ -517,7 +566,7 @@ void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, z
 template <int NT>
 static void launch_list_far_t(const PairGeom* geom, const int2* dest, long first, long count,
                               zd k1, zd k2, const zd* tw, const OutSpec& o, hipStream_t st) {
-  int grid = (int)std::min<long>(count, 256L * 40);
+  int grid = (int)std::min<long>(count, 256L * 128);
   hipLaunchKernelGGL(k_list_far<NT>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2,
                      tw, o);
 }
@@ -536,6 +585,13 @@ void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first,
     case 2048: launch_list_far_t<2048>(geom, dest, first, count, k1, k2, tw, o, st); break;
     default: break;
   }
+}
+
+void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
+                          WorkList split, WorkList direct, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_classify_list, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, geom,
+                     count, cp, far, split, direct);
 }
 
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
