@@ -67,7 +67,20 @@ def main():
     ap.add_argument("--workload", default="paper_scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (calibrates "
+                         "the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the per-mode systems would shard "
               "across GPUs by mode); --gpus %d is not supported" % args.gpus, file=sys.stderr)

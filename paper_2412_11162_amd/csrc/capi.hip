@@ -69,7 +69,10 @@ struct pmlbie_ctx {
   ClassParams cp{};
   long long cnt_far = 0, cnt_split = 0, cnt_direct = 0, cnt_aux = 0;
   // device data
-  DBuf<double> nodes;  // 8 N doubles: rho, I, z, W, nr_re, nr_im, nz_re, nz_im
+  DBuf<double> nodes;  // 10 N doubles: rho, I, z, W, nr_re, nr_im, nz_re, nz_im, nu_rho, nu_z
+  DBuf<PlaneWave> dpw;
+  DBuf<zd> tw_pw;
+  DBuf<int> rmap;
   DBuf<int> dpanel;
   DBuf<zd> tw_far, tw_int;
   DBuf<double> glx, glw;
@@ -323,7 +326,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
 
     Timer t_setup(c->stream);
     // node tables
-    std::vector<double> nt(8L * N);
+    std::vector<double> nt(10L * N);
     for (int i = 0; i < N; ++i) {
       nt[i] = c->geo.rho[i];
       nt[N + i] = c->geo.I[i];
@@ -333,6 +336,8 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       nt[5L * N + i] = c->geo.nr_im[i];
       nt[6L * N + i] = c->geo.nz_re[i];
       nt[7L * N + i] = c->geo.nz_im[i];
+      nt[8L * N + i] = c->geo.nur[i];
+      nt[9L * N + i] = c->geo.nuz[i];
     }
     c->nodes.alloc(nt.size());
     HIPCHK(hipMemcpyAsync(c->nodes.p, nt.data(), nt.size() * 8, hipMemcpyHostToDevice, c->stream));
@@ -488,20 +493,45 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     if (c->stage < 3) return fail(c, PMLBIE_ESTATE, "solve: build the operators first");
     if (n_rhs < 1 || n_rhs > LU_MAX_RHS || !inc) return fail(c, PMLBIE_EINVAL, "solve: 1 <= n_rhs <= 16");
     for (int r = 0; r < n_rhs; ++r) {
-      if (inc[r].kind != 0) return fail(c, PMLBIE_EINVAL, "solve: only point sources (kind 0) are available");
-      if (!(inc[r].p[0] >= 0)) return fail(c, PMLBIE_EINVAL, "solve: source radius must be >= 0");
-      if (inc[r].p[1] <= c->geo.h(inc[r].p[0]))
-        return fail(c, PMLBIE_EINVAL, "solve: the point source must lie in the upper medium");
+      if (inc[r].kind == 0) {
+        if (!(inc[r].p[0] >= 0)) return fail(c, PMLBIE_EINVAL, "solve: source radius must be >= 0");
+        if (!(inc[r].p[0] < c->geo.pml.a1)) return fail(c, PMLBIE_EINVAL, "solve: the point source must lie in the physical region rho < a1");
+        if (inc[r].p[1] <= c->geo.h(inc[r].p[0]))
+          return fail(c, PMLBIE_EINVAL, "solve: the point source must lie in the upper medium");
+      } else if (inc[r].kind == 1) {
+        if (!(inc[r].p[0] >= 0 && inc[r].p[0] < 0.5 * PMLBIE_PI))
+          return fail(c, PMLBIE_EINVAL, "solve: plane-wave polar angle must lie in [0, pi/2)");
+        if (c->k1.im != 0.0 || c->k2.im != 0.0)
+          return fail(c, PMLBIE_EINVAL, "solve: plane waves need real wavenumbers");
+      } else {
+        return fail(c, PMLBIE_EINVAL, "solve: incidence kind must be 0 (point source) or 1 (plane wave)");
+      }
     }
     auto t0 = std::chrono::steady_clock::now();
     const int N = c->N, M = c->M;
     const long n2 = 2L * N, ms = n2 * n2;
     c->nrhs = n_rhs;
     Timer t_rhs(c->stream);
-    // pairs (node i, source) and (source, node i) per incidence
+    // point sources: pairs (node i, source) and (source, node i)
     std::vector<PairGeom> g;
-    g.reserve((size_t)n_rhs * 2 * N);
+    std::vector<int> rmap;
+    std::vector<PlaneWave> pws;
     for (int r = 0; r < n_rhs; ++r) {
+      if (inc[r].kind == 1) {
+        const double phi = inc[r].p[0], k1 = c->k1.re, k2 = c->k2.re;
+        PlaneWave P;
+        P.k1 = k1;
+        P.c = cos(phi);
+        P.s = sin(phi);
+        // transmitted wavenumber and reflection coefficient of the flat interface (Sec. 2)
+        if (k2 > fabs(k1 * P.s)) P.kst = zd{sqrt(k2 * k2 - k1 * k1 * P.s * P.s), 0.0};
+        else P.kst = zd{0.0, sqrt(k1 * k1 * P.s * P.s - k2 * k2)};
+        P.R = 2.0 * inv(zd{1.0, 0.0} + P.kst * (1.0 / (k1 * P.c))) - 1.0;
+        P.rhs = r;
+        pws.push_back(P);
+        continue;
+      }
+      rmap.push_back(r);
       const double rs = inc[r].p[0], zs = inc[r].p[1];
       for (int i = 0; i < N; ++i) {
         PairGeom p;
@@ -524,13 +554,34 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
         g.push_back(p);
       }
     }
-    c->raw.alloc(g.size() * 4 * (M + 1));
-    run_pair_list(c, g, c->raw.p, nullptr);
     const size_t vec = (size_t)(M + 1) * n_rhs * N;
     c->b1.alloc(vec);
     c->b2.alloc(vec);
     c->x.alloc(2 * vec);
-    launch_rhs_gather_point(c->raw.p, N, M, n_rhs, c->b1.p, c->b2.p, c->stream);
+    if (!g.empty()) {
+      c->raw.alloc(g.size() * 4 * (M + 1));
+      run_pair_list(c, g, c->raw.p, nullptr);
+      c->rmap.alloc(rmap.size());
+      HIPCHK(hipMemcpyAsync(c->rmap.p, rmap.data(), rmap.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      launch_rhs_gather_point(c->raw.p, c->rmap.p, (int)rmap.size(), N, M, n_rhs, c->b1.p, c->b2.p, c->stream);
+      HIPCHK(hipGetLastError());
+    }
+    if (!pws.empty()) {
+      // FFT length: the modes of exp(-i a cos theta) die out beyond |n| ~ a
+      double amax = 0.0;
+      for (const PlaneWave& P : pws) amax = std::max(amax, P.k1 * P.s * c->geo.breaks[4]);
+      const int ntp = std::max(256, pow2_at_least(2.0 * (std::max<double>(M, amax) + 40.0)));
+      if (ntp > 2048) return fail(c, PMLBIE_EINVAL, "solve: plane-wave data need more than 2048 azimuthal samples");
+      auto twp = twiddles(ntp);
+      c->tw_pw.alloc(twp.size());
+      HIPCHK(hipMemcpyAsync(c->tw_pw.p, twp.data(), twp.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));
+      c->dpw.alloc(pws.size());
+      HIPCHK(hipMemcpyAsync(c->dpw.p, pws.data(), pws.size() * sizeof(PlaneWave), hipMemcpyHostToDevice, c->stream));
+      launch_rhs_plane(ntp, c->nodes.p, c->nodes.p + 2L * N, c->nodes.p + 8L * N, c->nodes.p + 9L * N, N,
+                       c->dpw.p, (int)pws.size(), c->tw_pw.p, M, n_rhs, c->b1.p, c->b2.p, c->stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
     const bool mixed = c->precision == PMLBIE_MIXED;
     if (mixed)
       launch_lower_rhs(c->A.p + (size_t)N * n2, ms, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);

@@ -37,6 +37,15 @@ struct WorkList {
   unsigned cap;
 };
 
+// One plane-wave incidence (theta_inc = 0): k1, cos and sin of the polar
+// angle, the transmitted wavenumber k* and the flat-interface reflection
+// coefficient Rc, and the right-hand-side slot.
+struct PlaneWave {
+  double k1, c, s;
+  zd kst, R;
+  int rhs;
+};
+
 // One near-panel product-integration job: target node, source panel, and its
 // auxiliary points q0..q1-1.
 struct NearJob {
@@ -59,6 +68,9 @@ void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, lo
 void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, zd k1,
                    zd k2, const double* glx, const double* glw, zd* A, long n2, long mstride,
                    const double* W, zd* raw, double omega_piece, hipStream_t st);
+void launch_rhs_plane(int nt, const double* rho, const double* z, const double* nur,
+                      const double* nuz, int N, const PlaneWave* pw, int npw, const zd* tw, int M,
+                      int nrhs, zd* b1, zd* b2, hipStream_t st);
 void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, zd* A,
                  long n2, long mstride, hipStream_t st);
 

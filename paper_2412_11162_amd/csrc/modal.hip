@@ -538,6 +538,62 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
 }
 
 // ------------------------------------------------------------------------
+// Plane-wave right-hand sides (Sec. 2): the jump of the reference field
+//   [u_tot0] = e^{-i k1 rho sin(phi) cos(theta)} g(z),
+//   g(z) = e^{-i k1 z cos(phi)} + Rc e^{i k1 z cos(phi)} - (1 + Rc) e^{-i k* z},
+// vanishes on the flat part z = 0 (where the PML acts), so it is evaluated at
+// the physical node coordinates; its normal derivative is
+// nu_rho d/drho + nu_z d/dz.  Modes by an azimuthal FFT of the samples (the
+// data are even in theta).  One wavefront per (node, incidence);
+// b1 = -[u_tot0]_n, b2 = -[du_tot0/dnu]_n at b[(n * nrhs + r) * N + i].
+template <int NT>
+__global__ __launch_bounds__(64) void k_rhs_plane(const double* __restrict__ rho,
+                                                  const double* __restrict__ z,
+                                                  const double* __restrict__ nur,
+                                                  const double* __restrict__ nuz, int N,
+                                                  const PlaneWave* __restrict__ pw, int npw,
+                                                  const zd* __restrict__ tw, int M, int nrhs,
+                                                  zd* __restrict__ b1, zd* __restrict__ b2) {
+  __shared__ zd buf[2 * NT];
+  const double scale = 2.0 * PMLBIE_PI / NT;
+  for (long t = blockIdx.x; t < (long)N * npw; t += gridDim.x) {
+    const int i = (int)(t % N), w = (int)(t / N);
+    const PlaneWave P = pw[w];
+    const double r = rho[i], zz = z[i];
+    const zd I{0.0, 1.0};
+    const zd e1 = cexp_(zd{0.0, -P.k1 * zz * P.c}), e2 = cexp_(zd{0.0, P.k1 * zz * P.c});
+    const zd e3 = cexp_((-1.0 * zz) * (I * P.kst));
+    const zd g = e1 + P.R * e2 - (P.R + 1.0) * e3;
+    const zd gp = (-P.k1 * P.c) * (I * e1) + (P.k1 * P.c) * (I * (P.R * e2)) +
+                  I * P.kst * (P.R + 1.0) * e3;
+    const double a = P.k1 * r * P.s;
+    for (int j = threadIdx.x; j <= NT / 2; j += 64) {
+      const double ct = cos(2.0 * PMLBIE_PI * j / NT);
+      const zd ph = cexp_(zd{0.0, -a * ct});
+      const zd f = ph * g;
+      // d/drho of the phase: -i k1 sin(phi) cos(theta)
+      const zd df = nur[i] * ((-P.k1 * P.s * ct) * (I * f)) + nuz[i] * (ph * gp);
+      const int ja = bitrev<NT>(j);
+      buf[ja] = f;
+      buf[NT + ja] = df;
+      if (j > 0 && j < NT / 2) {
+        const int jb = bitrev<NT>(NT - j);
+        buf[jb] = f;
+        buf[NT + jb] = df;
+      }
+    }
+    __syncthreads();
+    fft_lds<NT, 2>(buf, tw);
+    for (int n = threadIdx.x; n <= M; n += 64) {
+      const long e = ((long)n * nrhs + P.rhs) * N + i;
+      b1[e] = (-scale) * buf[n];
+      b2[e] = (-scale) * buf[NT + n];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
 // Host launchers.
 template <int NT>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
@@ -634,6 +690,20 @@ void launch_direct(const PairGeom* geom, const int2* dest, long first, long coun
   int grid = (int)std::min<long>(count, 256L * 24);
   hipLaunchKernelGGL(k_direct, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, k1, k2,
                      glx, glw, o, omega_piece);
+}
+
+void launch_rhs_plane(int nt, const double* rho, const double* z, const double* nur,
+                      const double* nuz, int N, const PlaneWave* pw, int npw, const zd* tw, int M,
+                      int nrhs, zd* b1, zd* b2, hipStream_t st) {
+  if (npw <= 0) return;
+  const int grid = std::min(N * npw, 256 * 32);
+  switch (nt) {
+    case 256: hipLaunchKernelGGL(k_rhs_plane<256>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
+    case 512: hipLaunchKernelGGL(k_rhs_plane<512>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
+    case 1024: hipLaunchKernelGGL(k_rhs_plane<1024>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
+    case 2048: hipLaunchKernelGGL(k_rhs_plane<2048>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
+    default: break;
+  }
 }
 
 void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, zd* A,

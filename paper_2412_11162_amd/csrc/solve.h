@@ -6,7 +6,8 @@
 
 namespace pmlbie {
 
-void launch_rhs_gather_point(const zd* raw, int N, int M, int nrhs, zd* b1, zd* b2, hipStream_t st);
+void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int nrhs, zd* b1,
+                             zd* b2, hipStream_t st);
 void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st);
 void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,

@@ -8,17 +8,19 @@ namespace pmlbie {
 // (node i, source) and s = K1 for the swapped pairs (source, node i) whose
 // source-side conormal is the node's (the conormal derivative at the target
 // of G~(r, r*) by the symmetry of G~).
-__global__ void k_rhs_gather_point(const zd* __restrict__ raw, int N, int M, int nrhs,
-                                   zd* __restrict__ b1, zd* __restrict__ b2) {
+__global__ void k_rhs_gather_point(const zd* __restrict__ raw, const int* __restrict__ rmap,
+                                   int npt, int N, int M, int nrhs, zd* __restrict__ b1,
+                                   zd* __restrict__ b2) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long tot = (long)(M + 1) * nrhs * N;
+  const long tot = (long)(M + 1) * npt * N;
   if (e >= tot) return;
   const int i = (int)(e % N);
-  const int r = (int)((e / N) % nrhs);
-  const int n = (int)(e / ((long)N * nrhs));
-  const long q1 = (long)r * 2 * N + i, q2 = q1 + N;
-  b1[e] = -raw[q1 * 4 * (M + 1) + n];
-  b2[e] = -raw[q2 * 4 * (M + 1) + (M + 1) + n];
+  const int pidx = (int)((e / N) % npt);
+  const int n = (int)(e / ((long)N * npt));
+  const long q1 = (long)pidx * 2 * N + i, q2 = q1 + N;
+  const long o = ((long)n * nrhs + rmap[pidx]) * N + i;
+  b1[o] = -raw[q1 * 4 * (M + 1) + n];
+  b2[o] = -raw[q2 * 4 * (M + 1) + (M + 1) + n];
 }
 
 // rhs[n][r] = [0 ; Alow_n [b1; b2]], Alow_n = [K2 - D2, -S2] (N x 2N, row-major):
@@ -180,10 +182,11 @@ void launch_axpy(zd* x, const zd* d, long count, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, d, count);
 }
 
-void launch_rhs_gather_point(const zd* raw, int N, int M, int nrhs, zd* b1, zd* b2, hipStream_t st) {
-  const long tot = (long)(M + 1) * nrhs * N;
+void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int nrhs, zd* b1,
+                             zd* b2, hipStream_t st) {
+  const long tot = (long)(M + 1) * npt * N;
   hipLaunchKernelGGL(k_rhs_gather_point, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, raw,
-                     N, M, nrhs, b1, b2);
+                     rmap, npt, N, M, nrhs, b1, b2);
 }
 void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st) {

@@ -110,6 +110,27 @@ def test_equal_media_degenerate_case():
     assert np.linalg.norm(out[0][0]) / np.linalg.norm(b1[0]) < 1e-4
 
 
+def test_tiny_multiple_incidences_point_and_plane(tiny_ref):
+    """Several right-hand sides of both kinds in one solve: a point source and
+    two plane waves (GPU: azimuthal FFT of the jump data; oracle:
+    Jacobi-Anger with library Bessel functions)."""
+    import oracle
+    wl, g, A, _ = tiny_ref
+    modes = list(range(wl.m_max + 1))
+    incs = [("plane", 0.4), ("point", 0.3, 1.0), ("plane", 1.2)]
+    s = _solver(wl)
+    out = s.solve_modes(incs)
+    for r, inc in enumerate(incs):
+        if inc[0] == "plane":
+            b1, b2 = oracle.rhs_plane_wave(g, modes, inc[1])
+        else:
+            b1, b2 = oracle.rhs_point_source(g, modes, inc[1], inc[2])
+        ref = oracle.solve(g, modes, b1, b2, A=A)[:4]
+        got = [o[:, r, :].cpu().numpy() for o in out]
+        errs = _boundary_err(got, ref)
+        assert np.max(errs) <= BOUNDARY_TOL, (inc, errs)
+
+
 # ------------------------------------------------- small workload (cfg of the paper's small case)
 
 def test_small_boundary_data_against_stored_oracle():
