@@ -7,6 +7,7 @@
 namespace pmlbie {
 
 constexpr int LU_NB = 128;      // panel width
+constexpr int LU_LEAF = 32;     // leaf width inside a panel
 constexpr int LU_MAX_RHS = 16;  // right-hand sides per solve call
 
 // Optional per-panel event markers (timing of the trailing-update kernel).

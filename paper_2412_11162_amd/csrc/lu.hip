@@ -43,7 +43,7 @@ __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
 // local rows t, t + PNL_T, ... (local row = row - k0); RPT rows per thread.
 template <typename T, int RPT>
 __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                                 int nb, int* __restrict__ ipiv,
+                                                 int nb, int cs0, int* __restrict__ ipiv,
                                                  int* __restrict__ info) {
   cx<T>* a = A + (long)blockIdx.x * ms;
   int* piv = ipiv + (long)blockIdx.x * n;
@@ -117,9 +117,10 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
             if (q == qp)
 #pragma unroll
               for (int j2 = 0; j2 < SUB; ++j2) sx[1][j2] = x[q][j2];
-        // the rest of the two rows in memory: the other panel columns and the
+        // the rest of the two rows in memory, from column cs0 (the start of the
+        // enclosing LU_NB panel) to the end: the other panel columns and the
         // trailing columns (the interchange of the trailing matrix happens here)
-        for (int c = tid; c < m; c += PNL_T)
+        for (int c = cs0 - k0 + tid; c < m; c += PNL_T)
           if (c < s0 || c >= s0 + SUB) {
             cx<T>* r1 = a + (long)(k0 + cl) * n + k0 + c;
             cx<T>* r2 = a + (long)(k0 + p) * n + k0 + c;
@@ -220,16 +221,16 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
 }
 
 // ---------------------------------------------------------------------------
-// U12 = L11^{-1} A12 for a tile of 64 trailing columns.  Thread
+// U12 = L11^{-1} A12 for a tile of 64 trailing columns (columns below cend).  Thread
 // (col = tid % 64, rg = tid / 64) holds panel rows rg, rg + 4, ... of its
 // column; L11 is staged through LDS in blocks of 32 columns.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                              int nb) {
+                                              int nb, int cend) {
   cx<T>* a = A + (long)blockIdx.y * ms;
   const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
   const int c = k0 + nb + blockIdx.x * 64 + cl;
-  const bool act = c < n;
+  const bool act = c < cend;
   constexpr int JB = 32;
   __shared__ cx<T> xs[64];
   __shared__ cx<T> Lb[LU_NB][JB + 1];
@@ -275,7 +276,8 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update C -= L21 U12 on MFMA.  Workgroup tile 64 x 64 (complex),
+// Trailing update C -= L21 U12 on MFMA (rows below k0 + nb, columns
+// k0 + nb .. cend - 1).  Workgroup tile 64 x 64 (complex),
 // four waves of 32 x 32, K staged through LDS in chunks of 16.
 template <typename T> struct mfma_t;
 template <> struct mfma_t<double> {
@@ -296,7 +298,7 @@ template <> struct mfma_t<float> {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
-                                                     int k0, int nb) {
+                                                     int k0, int nb, int cend) {
   typedef typename mfma_t<T>::acc acc_t;
   cx<T>* a = A + (long)blockIdx.z * ms;
   const int m0 = k0 + nb;
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
       pl[t] = (gr < n && gk < nb) ? a[(long)gr * n + k0 + gk] : cx<T>{T(0), T(0)};
       const int cc = e & 63, ku = e >> 6;  // row-major U12: columns contiguous
       const int gc = c0 + cc, gku = kk + ku;
-      pu[t] = (gc < n && gku < nb) ? a[(long)(k0 + gku) * n + gc] : cx<T>{T(0), T(0)};
+      pu[t] = (gc < cend && gku < nb) ? a[(long)(k0 + gku) * n + gc] : cx<T>{T(0), T(0)};
     }
   };
   gload(0);
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
       for (int j = 0; j < 4; ++j) {
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
-        if (gc < n && gr < n) {
+        if (gc < cend && gr < n) {
           cx<T>* p = a + (long)gr * n + gc;
           cx<T> v = *p;
           v.re -= cr[x][y][j];
@@ -487,29 +489,53 @@ __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ 
 
 // ---------------------------------------------------------------------------
 template <typename T, int RPT>
-static void launch_panel(cx<T>* A, long ms, int n, int k0, int nb, int batch, int* ipiv, int* info,
-                         hipStream_t st) {
-  hipLaunchKernelGGL((k_panel<T, RPT>), dim3(batch), dim3(PNL_T), 0, st, A, ms, n, k0, nb, ipiv, info);
+static void launch_panel(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int batch, int* ipiv,
+                         int* info, hipStream_t st) {
+  hipLaunchKernelGGL((k_panel<T, RPT>), dim3(batch), dim3(PNL_T), 0, st, A, ms, n, k0, nb, cs0, ipiv,
+                     info);
 }
 
+template <typename T>
+static void panel_any(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int batch, int* ipiv,
+                      int* info, hipStream_t st) {
+  const int m = n - k0;
+  if (m <= 1 * PNL_T) launch_panel<T, 1>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
+  else if (m <= 2 * PNL_T) launch_panel<T, 2>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
+  else if (m <= 4 * PNL_T) launch_panel<T, 4>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
+  else launch_panel<T, 8>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
+}
+
+template <typename T>
+static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch, hipStream_t st,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  const int cols = cend - k0 - nb, rows = n - k0 - nb;
+  if (cols <= 0) return;
+  hipLaunchKernelGGL(k_trsm<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb, cend);
+  if (rows > 0) {
+    if (ev0) hipEventRecord(ev0, st);
+    hipLaunchKernelGGL(k_gemm_update<T>, dim3((cols + 63) / 64, (rows + 63) / 64, batch), dim3(256), 0,
+                       st, A, ms, n, k0, nb, cend);
+    if (ev1) hipEventRecord(ev1, st);
+  }
+}
+
+// Each LU_NB panel is factored as leaves of LU_LEAF columns (register kernel),
+// the columns of the panel right of a leaf updated by a TRSM + MFMA update of
+// width LU_LEAF; then the trailing matrix gets the full-width update.
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, hipStream_t st,
                        LuTimers* tm) {
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
-    const int m = n - k0;
-    if (m <= 1 * PNL_T) launch_panel<T, 1>(A, ms, n, k0, nb, batch, ipiv, info, st);
-    else if (m <= 2 * PNL_T) launch_panel<T, 2>(A, ms, n, k0, nb, batch, ipiv, info, st);
-    else if (m <= 4 * PNL_T) launch_panel<T, 4>(A, ms, n, k0, nb, batch, ipiv, info, st);
-    else launch_panel<T, 8>(A, ms, n, k0, nb, batch, ipiv, info, st);
-    const int rest = n - k0 - nb;
-    if (rest > 0) {
-      dim3 g1((rest + 63) / 64, batch);
-      hipLaunchKernelGGL(k_trsm<T>, g1, dim3(256), 0, st, A, ms, n, k0, nb);
-      if (tm && tm->gemm_begin) hipEventRecord(tm->gemm_begin[k0 / LU_NB], st);
-      dim3 g2((rest + 63) / 64, (rest + 63) / 64, batch);
-      hipLaunchKernelGGL(k_gemm_update<T>, g2, dim3(256), 0, st, A, ms, n, k0, nb);
-      if (tm && tm->gemm_end) hipEventRecord(tm->gemm_end[k0 / LU_NB], st);
+    for (int j0 = 0; j0 < nb; j0 += LU_LEAF) {
+      const int lb = std::min(LU_LEAF, nb - j0);
+      panel_any<T>(A, ms, n, k0 + j0, lb, k0, batch, ipiv, info, st);
+      update<T>(A, ms, n, k0 + j0, lb, k0 + nb, batch, st);
+    }
+    if (n - k0 - nb > 0) {
+      const bool t = tm && tm->gemm_begin && tm->gemm_end;
+      update<T>(A, ms, n, k0, nb, n, batch, st, t ? tm->gemm_begin[k0 / LU_NB] : nullptr,
+                t ? tm->gemm_end[k0 / LU_NB] : nullptr);
     }
   }
 }
