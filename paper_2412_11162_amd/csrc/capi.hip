@@ -155,8 +155,8 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
     c->qscr.alloc((size_t)CH * (c->MQ + 1));
     launch_split_singular(geom, f, cn, c->MQ, c->zhat.p, c->phat.p, c->qscr.p, c->stream);
     HIPCHK(hipGetLastError());
-    launch_split(c->nt_int, geom, dest, f, cn, c->M, c->B, c->MQ, c->k1, c->k2, c->tw_int.p,
-                 c->zhat.p, c->phat.p, A, n2, ms, W, raw, c->stream);
+    launch_split(c->nt_int, geom, dest, f, cn, c->M, c->MQ, c->k1, c->k2, c->tw_int.p, c->zhat.p,
+                 c->phat.p, A, n2, ms, W, raw, c->stream);
     HIPCHK(hipGetLastError());
   }
 }
@@ -194,9 +194,9 @@ void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long 
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
-std::vector<zd> twiddles(int nt) {
-  std::vector<zd> t(nt / 2);
-  for (int k = 0; k < nt / 2; ++k) {
+std::vector<zd> twiddles(int nt, bool full = false) {
+  std::vector<zd> t(full ? nt : nt / 2);
+  for (int k = 0; k < (int)t.size(); ++k) {
     double a = -2.0 * PMLBIE_PI * k / nt;
     t[k] = zd{cos(a), sin(a)};
   }
@@ -305,17 +305,19 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     const int N = c->N, M = c->M;
     const long n2 = 2L * N;
     const long ms = n2 * n2;
-    // FFT lengths: the smooth parts need 2B points for the convolution
-    // window and M + B for the kept modes (B ~ |k| |rho~|max, the bandwidth
-    // of cos kR in theta); the raw-kernel path uses twice that.
+    // Angle grid L (one length for every FFT path): the smooth parts of the
+    // split carry modes up to B ~ 1.15 |k| |rho~|max + 16 (the bandwidth of
+    // cos kR in theta), the singular factors are kept to MQ = L/2 - 1, and
+    // the products are exact for the kept modes 0..M when MQ - M >= B.
     const double kmax = std::max(cabs_(c->k1), cabs_(c->k2));
     const double rmax = cabs_(zd{c->geo.breaks[4], c->geo.Iint(c->geo.breaks[4])});
     const double bneed = ceil(1.15 * kmax * rmax + 16.0);
-    c->nt_int = pow2_at_least(std::max<double>(n_theta, std::max(2.0 * bneed, M + bneed + 8.0)));
-    if (c->nt_int > 1024) return fail(c, PMLBIE_EINVAL, "build: wavenumber too large for the split FFT");
-    c->B = std::min(c->nt_int / 2, c->nt_int - M - 8);
-    c->MQ = M + c->B;
-    c->nt_far = std::min(2 * c->nt_int, 2048);
+    const int L = std::max(512, pow2_at_least(std::max<double>(n_theta, 2.0 * (M + bneed) + 2.0)));
+    if (L > 1024) return fail(c, PMLBIE_EINVAL, "build: wavenumber or m_max too large for the azimuthal FFT");
+    c->nt_int = L;
+    c->MQ = L / 2 - 1;
+    c->B = c->MQ - M;
+    c->nt_far = L;
     c->cp.M = M;
     c->cp.nt_far = c->nt_far;
     c->cp.bw = 1.1;
@@ -344,7 +346,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     c->dpanel.alloc(N);
     HIPCHK(hipMemcpyAsync(c->dpanel.p, c->geo.panel.data(), N * sizeof(int), hipMemcpyHostToDevice,
                           c->stream));
-    auto twf = twiddles(c->nt_far), twi = twiddles(c->nt_int);
+    auto twf = twiddles(c->nt_far, true), twi = twiddles(c->nt_int, true);
     c->tw_far.alloc(twf.size());
     c->tw_int.alloc(twi.size());
     HIPCHK(hipMemcpyAsync(c->tw_far.p, twf.data(), twf.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));

@@ -296,14 +296,30 @@ template <> struct mfma_t<float> {
   __device__ __forceinline__ static int rowof(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
 
+// Tile order: workgroups are dealt to the 8 XCDs round-robin, so XCD x
+// receives the contiguous range x*ceil(T/8) .. of the logical tile sequence;
+// inside a matrix the sequence walks groups of 8 tile rows column by column,
+// so the tiles in flight on one XCD share L21 rows and U12 columns in its L2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
-                                                     int k0, int nb, int cend) {
+                                                     int k0, int nb, int cend, int tx, int ty,
+                                                     int batch) {
   typedef typename mfma_t<T>::acc acc_t;
-  cx<T>* a = A + (long)blockIdx.z * ms;
+  const long tiles = (long)tx * ty * batch;
+  const long per_xcd = (tiles + 7) / 8;
+  const long lt = (long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lt >= tiles) return;
+  const long per_mat = (long)tx * ty;
+  const int bz = (int)(lt / per_mat);
+  const int t = (int)(lt % per_mat);
+  constexpr int GM = 8;
+  const int grp = t / (GM * tx), in = t % (GM * tx);
+  const int rows_in_grp = min(GM, ty - grp * GM);
+  const int by = grp * GM + in % rows_in_grp, bx = in / rows_in_grp;
+  cx<T>* a = A + (long)bz * ms;
   const int m0 = k0 + nb;
-  const int r0 = m0 + blockIdx.y * 64;  // tile rows of C
-  const int c0 = m0 + blockIdx.x * 64;  // tile columns of C
+  const int r0 = m0 + by * 64;  // tile rows of C
+  const int c0 = m0 + bx * 64;  // tile columns of C
   constexpr int KC = 16;
   __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4];  // L21 chunk: [k][row]
   __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4];  // U12 chunk: [k][col]
@@ -513,8 +529,11 @@ static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch
   hipLaunchKernelGGL(k_trsm<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb, cend);
   if (rows > 0) {
     if (ev0) hipEventRecord(ev0, st);
-    hipLaunchKernelGGL(k_gemm_update<T>, dim3((cols + 63) / 64, (rows + 63) / 64, batch), dim3(256), 0,
-                       st, A, ms, n, k0, nb, cend);
+    const int tx = (cols + 63) / 64, ty = (rows + 63) / 64;
+    const long tiles = (long)tx * ty * batch;
+    const long grid = ((tiles + 7) / 8) * 8;
+    hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)grid), dim3(256), 0, st, A, ms, n, k0, nb, cend,
+                       tx, ty, batch);
     if (ev1) hipEventRecord(ev1, st);
   }
 }

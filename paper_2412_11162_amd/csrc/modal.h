@@ -63,8 +63,8 @@ void launch_classify_list(const PairGeom* geom, long count, const ClassParams& c
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
                            zd* phat, zd* qscr, hipStream_t st);
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
-                  int B, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
-                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st);
+                  int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat, zd* A,
+                  long n2, long mstride, const double* W, zd* raw, hipStream_t st);
 void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, zd k1,
                    zd k2, const double* glx, const double* glw, zd* A, long n2, long mstride,
                    const double* W, zd* raw, double omega_piece, hipStream_t st);

@@ -8,6 +8,7 @@
 //
 // Natural modes: F_n = int_{-pi}^{pi} e^{-i n D} F(D) dD.  Every kernel is
 // even in D, so F_{-n} = F_n and only n = 0..M are formed.
+#include "fft_wave.h"
 #include "modal.h"
 
 namespace pmlbie {
@@ -44,23 +45,6 @@ __device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, z
     r[(o.M + 1) + n] = K1;
     r[2 * (o.M + 1) + n] = S2;
     r[3 * (o.M + 1) + n] = K2;
-  }
-}
-
-// Modes 0..M of one sequence s in {S1, K1, S2, K2} held in LDS, scaled.
-__device__ __forceinline__ void emit_one(const OutSpec& o, int2 dst, int s, double scale,
-                                         const zd* buf) {
-  if (dst.y >= 0) {
-    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
-    const double w2 = 2.0 * o.W[l] * scale;
-    // S blocks carry the minus sign of [[K1 + I, -S1], [K2 - I, -S2]]
-    const double f = (s & 1) ? w2 : -w2;
-    const long row = (s < 2 ? i : N + i), col = ((s & 1) ? l : N + l);
-    zd* p = o.A + row * o.n2 + col;
-    for (int n = threadIdx.x; n <= o.M; n += 64) p[(long)n * o.mstride] = f * buf[n];
-  } else {
-    zd* r = o.raw + (long)dst.x * 4 * (o.M + 1) + (long)s * (o.M + 1);
-    for (int n = threadIdx.x; n <= o.M; n += 64) r[n] = scale * buf[n];
   }
 }
 
@@ -116,62 +100,113 @@ __device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, con
   return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
 }
 
-// Raw-kernel FFT of one pair (one wavefront): samples on the half circle
-// held in registers (both media share R), then one sequence at a time is
-// mirrored to the full circle (the kernels are even in D), bit-reversed into
-// a single LDS buffer, transformed, and its modes 0..M emitted.
-template <int NT>
+// One mode value of sequence s in {S1, K1, S2, K2}, scaled.
+__device__ __forceinline__ void emit_val(const OutSpec& o, int2 dst, int s, int n, double scale,
+                                         zd val) {
+  if (dst.y >= 0) {
+    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
+    const double w2 = 2.0 * o.W[l] * scale;
+    // S blocks carry the minus sign of [[K1 + I, -S1], [K2 - I, -S2]]
+    const double f = (s & 1) ? w2 : -w2;
+    const long row = (s < 2 ? i : N + i), col = ((s & 1) ? l : N + l);
+    o.A[(long)n * o.mstride + row * o.n2 + col] = f * val;
+  } else {
+    o.raw[(long)dst.x * 4 * (o.M + 1) + (long)s * (o.M + 1) + n] = scale * val;
+  }
+}
+
+// Modes 0..M of the two sequences (s0, s0 + 1) held in the output layout of
+// fft_wave.
+template <int R>
+__device__ __forceinline__ void emit_pair(const OutSpec& o, int2 dst, int s0, double scale,
+                                          const zd (&x)[2][R]) {
+  const int b = threadIdx.x & 63;
+#pragma unroll
+  for (int sl = 0; sl < R; ++sl) {
+    const int n = fft_wave_out_index<R>(b, sl);
+    if (n <= o.M) {
+      emit_val(o, dst, s0, n, scale, x[0][sl]);
+      emit_val(o, dst, s0 + 1, n, scale, x[1][sl]);
+    }
+  }
+}
+
+// LDS of one pair (entries): the fft_wave exchange area E of two sequences,
+// preceded by a staging area P2 of two half-circle sequences; the first two
+// staged sequences (P1) sit at the start of E and are read into registers
+// before E is used by the transform.
+template <int R>
+constexpr int pair_lds() {
+  return (32 * R + 1) * 2 + 2 * fft_wave_lds<R>();
+}
+
+// Load two staged half-circle sequences (j = 0..L/2 at st[j], st[H + j]) into
+// the input layout of fft_wave, extended evenly: x[L - j] = x[j].
+template <int R>
+__device__ __forceinline__ void load_even(const zd* st, zd (&x)[2][R]) {
+  constexpr int L = 64 * R, H = L / 2 + 1;
+  const int b = threadIdx.x & 63;
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    const int j = b + 64 * a;
+    const int jj = j <= L / 2 ? j : L - j;
+    x[0][a] = st[jj];
+    x[1][a] = st[H + jj];
+  }
+}
+
+// Transform the staged sequences (s0, s0 + 1) and emit their modes.
+template <int R>
+__device__ __forceinline__ void transform_emit(const zd* st, zd* E, const zd* __restrict__ tw,
+                                               const OutSpec& o, int2 dst, int s0) {
+  const double scale = 2.0 * PMLBIE_PI / (64 * R);
+  zd x[2][R];
+  load_even<R>(st, x);
+  __syncthreads();
+  fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[0]), E, tw);
+  fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[1]), E, tw);
+  emit_pair<R>(o, dst, s0, scale, x);
+}
+
+// Raw-kernel FFT of one pair (one wavefront): the samples of S = G~ and
+// K = dG~/dnu' for both wavenumbers on the half circle D_j = 2 pi j / L,
+// j <= L/2 (R and the conormal factor are shared), staged in LDS, extended
+// to the full circle (the kernels are even in D), transformed by fft_wave;
+// modes 0..M are emitted.
+template <int R>
 __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const zd* __restrict__ tw,
-                                         zd* buf, const OutSpec& o, int2 dst) {
-  constexpr int SPL = (NT / 2) / 64 + 1;  // samples per lane
-  const double scale = 2.0 * PMLBIE_PI / NT;
-  zd smp[4][SPL];
-#pragma unroll
-  for (int t = 0; t < SPL; ++t) {
-    const int j = threadIdx.x + 64 * t;
-    if (j <= NT / 2) {
-      const double sh = sin(PMLBIE_PI * j / NT);
-      const double s2 = sh * sh;
-      const zd R2 = v.d2 + s2 * v.c4;
-      const zd R = csqrt_(R2);
-      const zd inv4piR = inv(R) * (0.25 / PMLBIE_PI);
-      const zd iR2 = inv(R2);
-      const zd N = v.N0 + s2 * v.N1;
-      const zd kk[2] = {k1, k2};
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const zd ikR = zd{0.0, 1.0} * (kk[m] * R);
-        const zd e = cexp_(ikR) * inv4piR;
-        smp[2 * m][t] = e;
-        smp[2 * m + 1][t] = N * e * (ikR - 1.0) * iR2;
-      }
-    }
+                                         zd* lds, const OutSpec& o, int2 dst) {
+  constexpr int L = 64 * R, H = L / 2 + 1;
+  zd* P2 = lds;
+  zd* E = lds + 2 * H;
+  for (int j = threadIdx.x; j <= L / 2; j += 64) {
+    const double sh = sin(PMLBIE_PI * j / L);
+    const double s2 = sh * sh;
+    const zd R2 = v.d2 + s2 * v.c4;
+    const zd Rd = csqrt_(R2);
+    const zd inv4piR = inv(Rd) * (0.25 / PMLBIE_PI);
+    const zd iR2 = inv(R2);
+    const zd N = v.N0 + s2 * v.N1;
+    const zd ikR1 = zd{0.0, 1.0} * (k1 * Rd), ikR2 = zd{0.0, 1.0} * (k2 * Rd);
+    const zd e1 = cexp_(ikR1) * inv4piR, e2 = cexp_(ikR2) * inv4piR;
+    E[j] = e1;
+    E[H + j] = N * e1 * (ikR1 - 1.0) * iR2;
+    P2[j] = e2;
+    P2[H + j] = N * e2 * (ikR2 - 1.0) * iR2;
   }
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-#pragma unroll
-    for (int t = 0; t < SPL; ++t) {
-      const int j = threadIdx.x + 64 * t;
-      if (j <= NT / 2) {
-        buf[bitrev<NT>(j)] = smp[s][t];
-        if (j > 0 && j < NT / 2) buf[bitrev<NT>(NT - j)] = smp[s][t];
-      }
-    }
-    __syncthreads();
-    fft_lds<NT, 1>(buf, tw);
-    emit_one(o, dst, s, scale, buf);
-    __syncthreads();
-  }
+  __syncthreads();
+  transform_emit<R>(E, E, tw, o, dst, 0);
+  transform_emit<R>(P2, E, tw, o, dst, 2);
 }
 
 // Main grid: every (target i, source l) pair off the near panels.  Far pairs
 // are finished here (raw-kernel FFT over theta); the others are appended to
 // the split / direct work lists.  One wavefront per pair.
-template <int NT>
-__global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
+template <int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
                                                  WorkList split, WorkList direct) {
-  __shared__ zd buf[NT];
+  __shared__ zd lds[pair_lds<R>()];
   const int N = nd.N;
   const long total = (long)N * N;
   for (long p = blockIdx.x; p < total; p += gridDim.x) {
@@ -192,7 +227,7 @@ __global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd
       }
       continue;
     }
-    far_pair<NT>(v, k1, k2, tw, buf, o, make_int2(i, l));
+    far_pair<R>(v, k1, k2, tw, lds, o, make_int2(i, l));
   }
 }
 
@@ -214,16 +249,16 @@ __global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, C
 }
 
 // Explicit list of far pairs (right-hand sides, field points).
-template <int NT>
-__global__ __launch_bounds__(64) void k_list_far(const PairGeom* __restrict__ geom,
+template <int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_list_far(const PairGeom* __restrict__ geom,
                                                  const int2* __restrict__ dest, long first,
                                                  long count, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o) {
-  __shared__ zd buf[NT];
+  __shared__ zd lds[pair_lds<R>()];
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
     const PairGeom g = geom[first + t];
     const PairInv v = pair_invariants(g);
-    far_pair<NT>(v, k1, k2, tw, buf, o, dest[first + t]);
+    far_pair<R>(v, k1, k2, tw, lds, o, dest[first + t]);
   }
 }
 
@@ -271,67 +306,79 @@ __global__ __launch_bounds__(64) void k_split_singular(const PairGeom* __restric
   }
 }
 
-// Split pairs, phase 2 (one wavefront per pair): FFT of the smooth parts
-// H1 = cos kR, ZH2 = sin(kR)/(4 pi R), H3 = cos kR + kR sin kR, DH4 = D H4 for
-// both wavenumbers, then
-//   S_n = (1/2pi) sum_j Zhat_{n-j} H1hat_j + i ZH2hat_n,
-//   K_n = (1/2pi) sum_j Dhat_{n-j} H3hat_j + i DH4hat_n,
-//   Dhat_m = -(e0 Phat_m + 4 pi e1 Zhat_m)/(4 pi).
-template <int NT>
-__global__ __launch_bounds__(64) void k_split(const PairGeom* __restrict__ geom,
+// Split pairs, phase 2 (one wavefront per pair).  With Zs and Ds the singular
+// factors restricted to their modes |m| <= MQ (Dhat_m = -(e0 Phat_m +
+// 4 pi e1 Zhat_m)/(4 pi)), the convolutions of the split become products on
+// the angle grid D_j = 2 pi j / L:
+//   S_n = modes of [Zs H1 + i ZH2],  K_n = modes of [Ds H3 + i DH4],
+// which equal (1/2pi) sum_j Zhat_{n-j} H1hat_j + i ZH2hat_n (and the same for
+// K) exactly for n <= M when L >= 2 MQ + 1 and the smooth parts carry no
+// modes beyond MQ - M.  Zs, Ds come from one transform of the even mode
+// sequences; the four products from one transform per wavenumber.
+template <int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_split(const PairGeom* __restrict__ geom,
                                               const int2* __restrict__ dest, long first,
-                                              long count, int M, int B, int MQ, zd k1, zd k2,
+                                              long count, int M, int MQ, zd k1, zd k2,
                                               const zd* __restrict__ tw,
                                               const zd* __restrict__ zhat,
                                               const zd* __restrict__ phat, OutSpec o) {
-  __shared__ zd buf[8 * NT];
-  const double scale = 2.0 * PMLBIE_PI / NT;
+  constexpr int L = 64 * R, H = L / 2 + 1;
+  __shared__ zd lds[pair_lds<R>()];
+  zd* P2 = lds;
+  zd* E = lds + 2 * H;
   const double inv2pi = 0.5 / PMLBIE_PI;
+  const int b = threadIdx.x & 63;
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
     const PairGeom g = geom[first + t];
     const int2 dst = dest[first + t];
     const PairInv v = pair_invariants(g);
     const SplitCoef sc = split_coef(g, v);
-    for (int j = threadIdx.x; j <= NT / 2; j += 64) {
-      const double sh = sin(PMLBIE_PI * j / NT);
-      zd h[8];
-      split_sample(v, sc, sh * sh, k1, h[0], h[1], h[2], h[3]);
-      split_sample(v, sc, sh * sh, k2, h[4], h[5], h[6], h[7]);
-      const int a = bitrev<NT>(j);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) buf[s * NT + a] = h[s];
-      if (j > 0 && j < NT / 2) {
-        const int b = bitrev<NT>(NT - j);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) buf[s * NT + b] = h[s];
-      }
-    }
-    __syncthreads();
-    fft_lds<NT, 8>(buf, tw);
     const zd* zz = zhat + t * (MQ + 1);
     const zd* pp = phat + t * (MQ + 1);
     const zd e0f = (-0.25 / PMLBIE_PI) * sc.e0;
     const zd e1f = -1.0 * sc.e1;
-    for (int n = threadIdx.x; n <= M; n += 64) {
-      zd zs1{0, 0}, zs2{0, 0}, dk1{0, 0}, dk2{0, 0};
-      for (int j = -B; j <= B; ++j) {
-        const int m = n - j < 0 ? j - n : n - j;
-        const int aj = j < 0 ? -j : j;
-        const zd zm = zz[m];
-        const zd dm = e0f * pp[m] + e1f * zm;
-        zs1 = cfma(zm, buf[aj], zs1);
-        dk1 = cfma(dm, buf[2 * NT + aj], dk1);
-        zs2 = cfma(zm, buf[4 * NT + aj], zs2);
-        dk2 = cfma(dm, buf[6 * NT + aj], dk2);
+    {
+      // Zs, Ds on the grid from their even mode sequences, staged in P2
+      zd sg[2][R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const int m = b + 64 * a;
+        const int mm = m <= L / 2 ? m : L - m;
+        zd zm{0.0, 0.0}, dm{0.0, 0.0};
+        if (mm <= MQ) {
+          zm = zz[mm];
+          dm = e0f * pp[mm] + e1f * zm;
+        }
+        sg[0][a] = zm;
+        sg[1][a] = dm;
       }
-      const zd I{0.0, 1.0};
-      const zd S1 = (scale * inv2pi) * zs1 + I * (scale * buf[NT + n]);
-      const zd K1 = (scale * inv2pi) * dk1 + I * (scale * buf[3 * NT + n]);
-      const zd S2 = (scale * inv2pi) * zs2 + I * (scale * buf[5 * NT + n]);
-      const zd K2 = (scale * inv2pi) * dk2 + I * (scale * buf[7 * NT + n]);
-      emit(o, dst, n, S1, K1, S2, K2);
+      fft_wave<R, 2>(sg, E, tw);
+#pragma unroll
+      for (int sl = 0; sl < R; ++sl) {
+        const int j = fft_wave_out_index<R>(b, sl);
+        if (j <= L / 2) {
+          P2[j] = inv2pi * sg[0][sl];
+          P2[H + j] = inv2pi * sg[1][sl];
+        }
+      }
     }
     __syncthreads();
+    // products for both wavenumbers: medium 1 into E, medium 2 over Zs, Ds
+    for (int j = b; j <= L / 2; j += 64) {
+      const double sh = sin(PMLBIE_PI * j / L);
+      const zd Rd = csqrt_(v.d2 + (sh * sh) * v.c4);
+      const zd zs = P2[j], ds = P2[H + j];
+      zd H1, ZH2, H3, DH4;
+      split_smooth(sc, Rd, k1, H1, ZH2, H3, DH4);
+      E[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
+      E[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
+      split_smooth(sc, Rd, k2, H1, ZH2, H3, DH4);
+      P2[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
+      P2[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
+    }
+    __syncthreads();
+    transform_emit<R>(E, E, tw, o, dst, 0);
+    transform_emit<R>(P2, E, tw, o, dst, 2);
   }
 }
 
@@ -595,12 +642,12 @@ __global__ __launch_bounds__(64) void k_rhs_plane(const double* __restrict__ rho
 
 // ------------------------------------------------------------------------
 // Host launchers.
-template <int NT>
+template <int R>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
                          const OutSpec& o, WorkList split, WorkList direct, hipStream_t st) {
   long total = (long)nd.N * nd.N;
   int grid = (int)std::min<long>(total, 256L * 128);
-  hipLaunchKernelGGL(k_grid_far<NT>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
+  hipLaunchKernelGGL(k_grid_far<R>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
                      direct);
 }
 
@@ -609,21 +656,17 @@ void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, z
                      WorkList direct, hipStream_t st) {
   OutSpec o{A, 2L * nd.N, mstride, W, nullptr, cp.M};
   switch (nt) {
-    case 64: launch_far_t<64>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 128: launch_far_t<128>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 256: launch_far_t<256>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 512: launch_far_t<512>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 1024: launch_far_t<1024>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 2048: launch_far_t<2048>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, st); break;
     default: break;
   }
 }
 
-template <int NT>
+template <int R>
 static void launch_list_far_t(const PairGeom* geom, const int2* dest, long first, long count,
                               zd k1, zd k2, const zd* tw, const OutSpec& o, hipStream_t st) {
   int grid = (int)std::min<long>(count, 256L * 128);
-  hipLaunchKernelGGL(k_list_far<NT>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2,
+  hipLaunchKernelGGL(k_list_far<R>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2,
                      tw, o);
 }
 
@@ -633,12 +676,8 @@ void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first,
   if (count <= 0) return;
   OutSpec o{A, n2, mstride, W, raw, M};
   switch (nt) {
-    case 64: launch_list_far_t<64>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 128: launch_list_far_t<128>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 256: launch_list_far_t<256>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 512: launch_list_far_t<512>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 1024: launch_list_far_t<1024>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 2048: launch_list_far_t<2048>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 512: launch_list_far_t<8>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 1024: launch_list_far_t<16>(geom, dest, first, count, k1, k2, tw, o, st); break;
     default: break;
   }
 }
@@ -658,26 +697,23 @@ void launch_split_singular(const PairGeom* geom, long first, long count, int MQ,
                      zhat, phat, qscr);
 }
 
-template <int NT>
+template <int R>
 static void launch_split_t(const PairGeom* geom, const int2* dest, long first, long count, int M,
-                           int B, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat,
-                           const zd* phat, const OutSpec& o, hipStream_t st) {
-  int grid = (int)std::min<long>(count, 256L * 24);
-  hipLaunchKernelGGL(k_split<NT>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, B,
-                     MQ, k1, k2, tw, zhat, phat, o);
+                           int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
+                           const OutSpec& o, hipStream_t st) {
+  int grid = (int)std::min<long>(count, 256L * 32);
+  hipLaunchKernelGGL(k_split<R>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, MQ, k1,
+                     k2, tw, zhat, phat, o);
 }
 
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
-                  int B, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
-                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st) {
+                  int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat, zd* A,
+                  long n2, long mstride, const double* W, zd* raw, hipStream_t st) {
   if (count <= 0) return;
   OutSpec o{A, n2, mstride, W, raw, M};
   switch (nt) {
-    case 64: launch_split_t<64>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
-    case 128: launch_split_t<128>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
-    case 256: launch_split_t<256>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
-    case 512: launch_split_t<512>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
-    case 1024: launch_split_t<1024>(geom, dest, first, count, M, B, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 512: launch_split_t<8>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 1024: launch_split_t<16>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
     default: break;
   }
 }

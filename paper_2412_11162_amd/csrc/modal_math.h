@@ -46,35 +46,6 @@ HD void kernel_sample(const PairInv& v, double s2, zd k, zd& S, zd& K) {
   K = N * e * (ikR - 1.0) * inv4piR * inv(R2);
 }
 
-// sin(q)/q, entire in q^2
-HD zd sinc_(zd q) {
-  if (cabs1(q) < 0.5) {
-    zd q2 = q * q, t = zd{1.0, 0.0}, s = zd{1.0, 0.0};
-    for (int j = 1; j <= 9; ++j) {
-      t = t * q2 * (-1.0 / ((2.0 * j) * (2.0 * j + 1.0)));
-      s = s + t;
-    }
-    return s;
-  }
-  return csin_(q) / q;
-}
-// (sin q - q cos q)/q^3, entire in q^2
-HD zd s3_(zd q) {
-  if (cabs1(q) < 1.0) {
-    // sum_j (-1)^{j+1} 2j / (2j+1)! q^{2j-2}, j >= 1
-    zd q2 = q * q, pw = zd{1.0, 0.0}, s = zd{0.0, 0.0};
-    double fact = 6.0;  // (2j+1)! for j = 1
-    for (int j = 1; j <= 11; ++j) {
-      double c = ((j & 1) ? 1.0 : -1.0) * (2.0 * j) / fact;
-      s = s + c * pw;
-      pw = pw * q2;
-      fact *= (2.0 * j + 2.0) * (2.0 * j + 3.0);
-    }
-    return s;
-  }
-  return (csin_(q) - q * ccos_(q)) / (q * q * q);
-}
-
 // Split coefficients of the double-layer singular factor:
 // D = -(e0/R^3 + e1/R)/(4 pi), with e0 = N0 - n_rho' d2/(2 rho~'), e1 = n_rho'/(2 rho~').
 struct SplitCoef {
@@ -88,22 +59,53 @@ HD SplitCoef split_coef(const PairGeom& g, const PairInv& v) {
   return c;
 }
 
-// Smooth parts of the split at one sample for wavenumber k:
-// H1 = cos kR, ZH2 = sin(kR)/(4 pi R), H3 = cos kR + kR sin kR,
-// DH4 = D (sin kR - kR cos kR).
-HD void split_sample(const PairInv& v, const SplitCoef& sc, double s2, zd k, zd& H1, zd& ZH2,
-                     zd& H3, zd& DH4) {
-  zd R2 = v.d2 + s2 * v.c4;
-  zd R = csqrt_(R2);
-  zd q = k * R;
-  zd cq = ccos_(q), sq = csin_(q);
+// cos q and sin q of a complex argument from one sine/cosine pair of Re q
+// and one expm1 of Im q (cosh and sinh without cancellation).
+HD void ccossin_(zd q, zd& c, zd& s) {
+  const double sx = sin(q.re), cx = cos(q.re);
+  const double em = expm1(q.im), ep = em + 1.0;
+  const double h = 0.5 / ep;
+  const double ch = 1.0 + em * em * h, sh = em * (em + 2.0) * h;
+  c = zd{cx * ch, -sx * sh};
+  s = zd{sx * ch, cx * sh};
+}
+
+// Smooth parts of the split at one sample (complex distance R) for
+// wavenumber k, q = k R:
+//   H1 = cos q, ZH2 = sin(q)/(4 pi R) = k sinc(q)/(4 pi), H3 = cos q + q sin q,
+//   DH4 = D (sin q - q cos q) = -(1/4pi)(e0 k^3 + e1 k q^2) s3(q),
+// with sinc(q) = sin(q)/q and s3(q) = (sin q - q cos q)/q^3, both entire in
+// q^2 and summed from their Taylor series for |q| < 1.
+HD void split_smooth(const SplitCoef& sc, zd R, zd k, zd& H1, zd& ZH2, zd& H3, zd& DH4) {
+  const zd q = k * R;
+  zd cq, sq;
+  ccossin_(q, cq, sq);
   H1 = cq;
   H3 = cq + q * sq;
-  ZH2 = k * sinc_(q) * (0.25 / PMLBIE_PI);
-  zd s3 = s3_(q);
-  zd k3 = k * k * k;
-  // D (sin q - q cos q) = -(1/4pi) (e0 k^3 s3 + e1 k q^2 s3)
-  DH4 = (sc.e0 * k3 + sc.e1 * k * (q * q)) * s3 * (-0.25 / PMLBIE_PI);
+  const zd q2 = q * q;
+  zd sn, s3;
+  if (cabs1(q) < 1.0) {
+    // sinc = sum_i (-1)^i q^{2i}/(2i+1)!, s3 = sum_i (-1)^i 2(i+1) q^{2i}/(2i+3)!
+    zd pw{1.0, 0.0};
+    sn = zd{0.0, 0.0};
+    s3 = zd{0.0, 0.0};
+    double f1 = 1.0;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const double sg = (i & 1) ? -1.0 : 1.0;
+      const double f3 = f1 * (2.0 * i + 2.0) * (2.0 * i + 3.0);
+      sn = sn + (sg / f1) * pw;
+      s3 = s3 + (sg * (2.0 * i + 2.0) / f3) * pw;
+      pw = pw * q2;
+      f1 = f3;
+    }
+  } else {
+    const zd iq = inv(q);
+    sn = sq * iq;
+    s3 = (sq - q * cq) * (iq * iq * iq);
+  }
+  ZH2 = (0.25 / PMLBIE_PI) * (k * sn);
+  DH4 = (sc.e0 * (k * k * k) + sc.e1 * k * q2) * s3 * (-0.25 / PMLBIE_PI);
 }
 
 // ---------------------------------------------------------------------------
