@@ -81,6 +81,7 @@ struct pmlbie_ctx {
   DBuf<zd> rbuf, xs;          // refinement: residual / correction, iterate
   DBuf<double> rsq, rnorm;
   DBuf<int> ipiv, info;
+  DBuf<zd> luw;  // inverses of the LU diagonal blocks
   DBuf<PairGeom> lgeom;
   DBuf<int2> ldest;
   DBuf<unsigned> lcount;
@@ -358,6 +359,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     // operators
     c->A.alloc((size_t)(M + 1) * ms);
     c->ipiv.alloc((size_t)(M + 1) * n2);
+    c->luw.alloc((size_t)(M + 1) * LU_NB * LU_NB);
     c->info.alloc(M + 1);
     HIPCHK(hipMemsetAsync(c->info.p, 0, (M + 1) * sizeof(int), c->stream));
     // work lists of the grid (split and direct share one allocation)
@@ -461,9 +463,11 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       c->A32.alloc((size_t)(M + 1) * ms);
       launch_to_c64(c->A.p, c->A32.p, (long)(M + 1) * ms, c->stream);
       HIPCHK(hipGetLastError());
-      lu_factor_batched<float>(c->A32.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->stream, &tm);
+      lu_factor_batched<float>(c->A32.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p,
+                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm);
     } else {
-      lu_factor_batched<double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->stream, &tm);
+      lu_factor_batched<double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->luw.p,
+                                c->stream, &tm);
     }
     HIPCHK(hipGetLastError());
     c->stage_ms[5] = t_lu.stop();

@@ -20,9 +20,10 @@ struct LuTimers {
 // Factor `batch` row-major n x n matrices A + b * ms in place (n <= 8192).
 // ipiv[b * n + j] = row interchanged with row j (0-based);
 // info[b] = first zero pivot (1-based), untouched otherwise.
+// work: batch * LU_NB * LU_NB elements (the inverses of the diagonal blocks).
 template <typename T>
-void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, hipStream_t st,
-                       LuTimers* tm = nullptr);
+void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
+                       hipStream_t st, LuTimers* tm = nullptr);
 
 // Solve A x = b for nrhs right-hand sides per matrix, B[b][rhs][n] in place.
 template <typename T, typename TB>

@@ -205,15 +205,32 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
       for (int jj = 0; jj < SUB; ++jj) Ls[tid][jj] = x[q][jj];
       __syncthreads();
       const int rlo = max(base, s0 + SUB), rhi = min(base + PNL_T, m);
-      const int nr = rhi - rlo;
-      for (int e = tid; e < nr * wr; e += PNL_T) {
-        const int rr = e / wr, c = e % wr;
-        const int rl = rlo + rr;
-        cx<T>* dst = a + (long)(k0 + rl) * n + k0 + s0 + SUB + c;
-        cx<T> acc = *dst;
+      // thread -> (column c, first row rs), rows strided by PNL_T / wr; four
+      // independent row segments in flight per step
+      const int c = tid % wr, rs = tid / wr, stride = PNL_T / wr;
+      if (rs < stride) {
+        cx<T> u[SUB];
 #pragma unroll
-        for (int j = 0; j < SUB; ++j) acc = acc - Ls[rl - base][j] * Ur[j][c];
-        *dst = acc;
+        for (int j = 0; j < SUB; ++j) u[j] = Ur[j][c];
+        cx<T>* col = a + (long)k0 * n + k0 + s0 + SUB + c;
+        for (int r1 = rlo + rs; r1 < rhi; r1 += 4 * stride) {
+          cx<T> v[4];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int rl = r1 + h * stride;
+            if (rl < rhi) v[h] = col[(long)rl * n];
+          }
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int rl = r1 + h * stride;
+            if (rl < rhi) {
+              cx<T> acc = v[h];
+#pragma unroll
+              for (int j = 0; j < SUB; ++j) acc = acc - Ls[rl - base][j] * u[j];
+              col[(long)rl * n] = acc;
+            }
+          }
+        }
       }
       __syncthreads();
     }
@@ -221,16 +238,19 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
 }
 
 // ---------------------------------------------------------------------------
-// U12 = L11^{-1} A12 for a tile of 64 trailing columns (columns below cend).  Thread
-// (col = tid % 64, rg = tid / 64) holds panel rows rg, rg + 4, ... of its
-// column; L11 is staged through LDS in blocks of 32 columns.
+// X = L11^{-1} B for a tile of 64 columns.  Thread (col = tid % 64,
+// rg = tid / 64) holds rows rg, rg + 4, ... of its column; L11 is staged
+// through LDS in blocks of 32 columns.  With W == nullptr, B = A12 (columns
+// k0 + nb .. cend - 1 of the panel rows) is overwritten by U12; otherwise B is
+// the identity and X = L11^{-1} is written to W + b * LU_NB^2 (row-major,
+// leading dimension LU_NB).
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                              int nb, int cend) {
+                                              int nb, int cend, cx<T>* __restrict__ W) {
   cx<T>* a = A + (long)blockIdx.y * ms;
   const int tid = threadIdx.x, cl = tid & 63, rg = tid >> 6;
-  const int c = k0 + nb + blockIdx.x * 64 + cl;
-  const bool act = c < cend;
+  const int c = (W ? 0 : k0 + nb) + blockIdx.x * 64 + cl;
+  const bool act = c < (W ? nb : cend);
   constexpr int JB = 32;
   __shared__ cx<T> xs[64];
   __shared__ cx<T> Lb[LU_NB][JB + 1];
@@ -239,7 +259,10 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int r = rg + 4 * t;
-    x[t] = (act && r < nb) ? a[(long)(k0 + r) * n + c] : cx<T>{T(0), T(0)};
+    if (W)
+      x[t] = cx<T>{(act && r == c) ? T(1) : T(0), T(0)};
+    else
+      x[t] = (act && r < nb) ? a[(long)(k0 + r) * n + c] : cx<T>{T(0), T(0)};
   }
   for (int j0 = 0; j0 < nb; j0 += JB) {
     __syncthreads();
@@ -267,10 +290,12 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
     }
   }
   if (act) {
+    cx<T>* out = W ? W + (long)blockIdx.y * LU_NB * LU_NB + c : a + (long)k0 * n + c;
+    const long ld = W ? LU_NB : n;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       const int r = rg + 4 * t;
-      if (r < nb) a[(long)(k0 + r) * n + c] = x[t];
+      if (r < nb) out[(long)r * ld] = x[t];
     }
   }
 }
@@ -295,6 +320,90 @@ template <> struct mfma_t<float> {
   }
   __device__ __forceinline__ static int rowof(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
+
+// U12 = L11^{-1} A12 on MFMA, in place: one workgroup per strip of 64
+// trailing columns of the panel rows (it reads the whole strip before writing
+// it), W = L11^{-1} from k_trsm.  Four waves of 32 rows x 64 columns; the
+// K chunks above a wave's rows are skipped (W is lower triangular).
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_mfma(cx<T>* __restrict__ A, long ms, int n, int k0,
+                                                   int nb, int cend,
+                                                   const cx<T>* __restrict__ W) {
+  typedef typename mfma_t<T>::acc acc_t;
+  cx<T>* a = A + (long)blockIdx.y * ms;
+  const cx<T>* w = W + (long)blockIdx.y * LU_NB * LU_NB;
+  const int c0 = k0 + nb + blockIdx.x * 64;
+  constexpr int KC = 16;
+  __shared__ T Lre[KC][LU_NB + 4], Lim[KC][LU_NB + 4];  // W chunk: [k][row]
+  __shared__ T Bre[KC][64 + 4], Bim[KC][64 + 4];        // A12 chunk: [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid * 32;
+  acc_t cr[2][4], ci[2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      cr[x][y] = acc_t{0, 0, 0, 0};
+      ci[x][y] = acc_t{0, 0, 0, 0};
+    }
+  for (int kk = 0; kk < nb; kk += KC) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + 256 * t;
+      const int k = e % KC, r = e / KC;
+      const cx<T> v = (r < nb && kk + k < nb) ? w[(long)r * LU_NB + kk + k] : cx<T>{T(0), T(0)};
+      Lre[k][r] = v.re;
+      Lim[k][r] = v.im;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int cc = e & 63, k = e >> 6;
+      const int gc = c0 + cc, gk = kk + k;
+      const cx<T> v = (gc < cend && gk < nb) ? a[(long)(k0 + gk) * n + gc] : cx<T>{T(0), T(0)};
+      Bre[k][cc] = v.re;
+      Bim[k][cc] = v.im;
+    }
+    __syncthreads();
+    if (kk < wr + 32) {
+#pragma unroll
+      for (int k4 = 0; k4 < KC; k4 += 4) {
+        const int kx = k4 + (lane >> 4), lx = lane & 15;
+        T lr[2], li[2], br[4], bi[4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          lr[t] = Lre[kx][wr + 16 * t + lx];
+          li[t] = Lim[kx][wr + 16 * t + lx];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          br[t] = Bre[kx][16 * t + lx];
+          bi[t] = Bim[kx][16 * t + lx];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            cr[x][y] = mfma_t<T>::op(lr[x], br[y], cr[x][y]);
+            cr[x][y] = mfma_t<T>::op(-li[x], bi[y], cr[x][y]);
+            ci[x][y] = mfma_t<T>::op(lr[x], bi[y], ci[x][y]);
+            ci[x][y] = mfma_t<T>::op(li[x], br[y], ci[x][y]);
+          }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = wr + 16 * x + mfma_t<T>::rowof(lane, j);
+        const int gc = c0 + 16 * y + (lane & 15);
+        if (r < nb && gc < cend) a[(long)(k0 + r) * n + gc] = cx<T>{cr[x][y][j], ci[x][y][j]};
+      }
+}
 
 // Tile order: workgroups are dealt to the 8 XCDs round-robin, so XCD x
 // receives the contiguous range x*ceil(T/8) .. of the logical tile sequence;
@@ -523,10 +632,19 @@ static void panel_any(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int bat
 
 template <typename T>
 static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch, hipStream_t st,
-                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                   cx<T>* W = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const int cols = cend - k0 - nb, rows = n - k0 - nb;
   if (cols <= 0) return;
-  hipLaunchKernelGGL(k_trsm<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb, cend);
+  if (W) {
+    // U12 = (L11^{-1}) A12: the inverse by the column solver, the product on MFMA
+    hipLaunchKernelGGL(k_trsm<T>, dim3((nb + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb,
+                       cend, W);
+    hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0,
+                       nb, cend, (const cx<T>*)W);
+  } else {
+    hipLaunchKernelGGL(k_trsm<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb,
+                       cend, (cx<T>*)nullptr);
+  }
   if (rows > 0) {
     if (ev0) hipEventRecord(ev0, st);
     const int tx = (cols + 63) / 64, ty = (rows + 63) / 64;
@@ -542,8 +660,8 @@ static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch
 // the columns of the panel right of a leaf updated by a TRSM + MFMA update of
 // width LU_LEAF; then the trailing matrix gets the full-width update.
 template <typename T>
-void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, hipStream_t st,
-                       LuTimers* tm) {
+void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
+                       hipStream_t st, LuTimers* tm) {
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
     for (int j0 = 0; j0 < nb; j0 += LU_LEAF) {
@@ -553,7 +671,7 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
     }
     if (n - k0 - nb > 0) {
       const bool t = tm && tm->gemm_begin && tm->gemm_end;
-      update<T>(A, ms, n, k0, nb, n, batch, st, t ? tm->gemm_begin[k0 / LU_NB] : nullptr,
+      update<T>(A, ms, n, k0, nb, n, batch, st, work, t ? tm->gemm_begin[k0 / LU_NB] : nullptr,
                 t ? tm->gemm_end[k0 / LU_NB] : nullptr);
     }
   }
@@ -581,8 +699,8 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
   }
 }
 
-template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, hipStream_t, LuTimers*);
-template void lu_factor_batched<float>(zf*, long, int, int, int*, int*, hipStream_t, LuTimers*);
+template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, zd*, hipStream_t, LuTimers*);
+template void lu_factor_batched<float>(zf*, long, int, int, int*, int*, zf*, hipStream_t, LuTimers*);
 template void lu_solve_batched<double, double>(const zd*, long, int, int, const int*, zd*, int,
                                                hipStream_t);
 template void lu_solve_batched<float, double>(const zf*, long, int, int, const int*, zd*, int,
