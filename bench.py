@@ -23,19 +23,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def lu_gemm_flops(n2: int, modes: int, nb: int = 64) -> float:
-    """Algorithmic real flops of all trailing updates: 8 m^2 nb per panel
-    (complex multiply-add = 8 real flops) for each mode."""
-    tot = 0.0
-    k0 = 0
-    while k0 < n2:
-        b = min(nb, n2 - k0)
-        m = n2 - k0 - b
-        tot += 8.0 * m * m * b
-        k0 += nb
-    return tot * modes
-
-
 def cpu_baseline(wl, seconds: float = 15.0):
     """The FP64 oracle's modal-kernel stage timed on this host on a bounded
     sample of (target, source) node pairs of the same workload."""
@@ -105,13 +92,16 @@ def main():
     torch.cuda.synchronize()
     times = []
     stages = []
+    counts = []
     t_all = time.time()
     for k in range(args.steps):
         t0 = time.time()
         step()
         torch.cuda.synchronize()
         times.append(time.time() - t0)
-        stages.append(s.stats()[0].copy())
+        sk, ck = s.stats()
+        stages.append(sk.copy())
+        counts.append(ck.copy())
         print("step %d: %.1f ms" % (k, 1e3 * times[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.time() - t_all
@@ -121,8 +111,12 @@ def main():
     units = 2.0 * N * N * (M + 1)
     st = np.mean(np.array(stages), axis=0)
     kernel_ms = st[1] + st[2] + st[3] + st[4]
+    # trailing-update kernel: algorithmic flops of all its launches (counted by
+    # the library, 8 real flops per complex multiply-add) over the summed
+    # durations of those launches (HIP events on the streams they run on)
     gemm_ms = st[6]
-    flops = lu_gemm_flops(2 * N, M + 1)
+    flops = float(counts[-1][2])
+    launches = int(counts[-1][3])
     achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     peak = 78.6
     out = {
@@ -150,7 +144,8 @@ def main():
                          "aux_near_points": int(info[7])},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_update<double> (LU trailing update)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None},
+                     "traffic": None, "launches": launches, "flop_per_launch": flops / max(launches, 1),
+                     "avg_launch_ms": gemm_ms / max(launches, 1)},
     }
     if not args.no_mixed:
         # complex64 LU on FP32 MFMA + FP64 refinement, same workload; its error
@@ -183,7 +178,7 @@ def main():
             "max_rel_err_vs_fp64": float(np.max(errs)), "refinement_iterations": int(cnt[0]),
             "final_rel_residual": float(cnt[1]),
             "stage_ms": {"lu": stm[5], "lu_trailing_update": stm[6], "solve": stm[7], "refinement": stm[9]},
-            "lu_trailing_update_tflops": lu_gemm_flops(2 * N, M + 1) / (stm[6] * 1e-3) / 1e12 if stm[6] > 0 else None,
+            "lu_trailing_update_tflops": float(cnt[2]) / (stm[6] * 1e-3) / 1e12 if stm[6] > 0 else None,
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -156,7 +156,9 @@ int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
  * [0] setup, [1] far kernels, [2] split, [3] direct, [4] near panels,
  * [5] LU total, [6] LU trailing updates, [7] solve total, [8] right-hand
  * sides, [9] refinement, [10] build total; and counters (host, 16 doubles):
- * [0] refinement iterations, [1] final relative residual. */
+ * [0] refinement iterations, [1] final relative residual, [2] real flops of
+ * all LU trailing updates (8 per complex multiply-add), [3] number of
+ * trailing-update launches (stage [6] is the sum of their durations). */
 int pmlbie_get_stats(const pmlbie_ctx* ctx, double* stage_ms, double* counters);
 
 #ifdef __cplusplus

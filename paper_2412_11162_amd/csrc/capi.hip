@@ -471,6 +471,17 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     }
     HIPCHK(hipGetLastError());
     c->stage_ms[5] = t_lu.stop();
+    // algorithmic flops of the trailing updates (8 real flops per complex
+    // multiply-add) and the number of their launches
+    double gflop = 0;
+    for (int p = 0; p < npan; ++p) {
+      const double nbp = std::min<long>(LU_NB, n2 - (long)p * LU_NB);
+      const double mr = (double)n2 - (double)p * LU_NB - nbp;
+      gflop += 8.0 * mr * mr * nbp * (M + 1);
+    }
+    c->counters[2] = gflop;
+    c->counters[3] = (double)(npan - 1);
+    // summed durations of the trailing-update launches
     double gsum = 0;
     for (int k = 0; k + 1 < npan; ++k) {
       float ms1 = 0;
