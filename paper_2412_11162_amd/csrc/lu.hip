@@ -302,8 +302,9 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
 
 // ---------------------------------------------------------------------------
 // Trailing update C -= L21 U12 on MFMA (rows below k0 + nb, columns
-// k0 + nb .. cend - 1).  Workgroup tile 64 x 64 (complex),
-// four waves of 32 x 32, K staged through LDS in chunks of 16.
+// k0 + nb .. cend - 1).  Workgroup tile 64 x 64 (complex), four waves of
+// 32 x 32, K staged through LDS in chunks of 8; registers held to four waves
+// per SIMD, whose interleaving hides the global and LDS latencies.
 template <typename T> struct mfma_t;
 template <> struct mfma_t<double> {
   typedef v4d acc;
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(cx<T>* __restrict__ A, long m
 // inside a matrix the sequence walks groups of 8 tile rows column by column,
 // so the tiles in flight on one XCD share L21 rows and U12 columns in its L2.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
                                                      int k0, int nb, int cend, int tx, int ty,
                                                      int batch) {
   typedef typename mfma_t<T>::acc acc_t;
@@ -429,25 +430,32 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
   const int m0 = k0 + nb;
   const int r0 = m0 + by * 64;  // tile rows of C
   const int c0 = m0 + bx * 64;  // tile columns of C
-  constexpr int KC = 16;
+  constexpr int KC = 8;
   __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4];  // L21 chunk: [k][row]
   __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4];  // U12 chunk: [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = (wid & 1) * 32, wc = (wid >> 1) * 32;
+  // the accumulators start from C (loaded before the K loop, so its latency
+  // overlaps the first chunk) and the products are subtracted
   acc_t cr[2][2], ci[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      cr[x][y] = acc_t{0, 0, 0, 0};
-      ci[x][y] = acc_t{0, 0, 0, 0};
-    }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
+        const int gc = c0 + wc + 16 * y + (lane & 15);
+        const cx<T> v = (gc < cend && gr < n) ? a[(long)gr * n + gc] : cx<T>{T(0), T(0)};
+        cr[x][y][j] = v.re;
+        ci[x][y][j] = v.im;
+      }
   // global -> register prefetch of the next K chunk overlaps the MFMA work
-  // on the current one; each thread moves 4 elements of L21 and of U12
-  cx<T> pl[4], pu[4];
+  // on the current one; each thread moves 2 elements of L21 and of U12
+  cx<T> pl[2], pu[2];
   auto gload = [&](int kk) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 2; ++t) {
       const int e = tid + 256 * t;
       const int k = e % KC, rr = e / KC;  // row-major L21: k contiguous
       const int gr = r0 + rr, gk = kk + k;
@@ -460,7 +468,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
   gload(0);
   for (int kk = 0; kk < nb; kk += KC) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 2; ++t) {
       const int e = tid + 256 * t;
       const int k = e % KC, rr = e / KC;
       Lre[k][rr] = pl[t].re;
@@ -471,7 +479,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
     }
     __syncthreads();
     if (kk + KC < nb) gload(kk + KC);
-#pragma unroll
+#pragma unroll 1
     for (int k4 = 0; k4 < KC; k4 += 4) {
       const int kx = k4 + (lane >> 4), lx = lane & 15;
       T lr[2], li[2], ur[2], ui[2];
@@ -486,10 +494,11 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
       for (int x = 0; x < 2; ++x)      // row sub-tile
 #pragma unroll
         for (int y = 0; y < 2; ++y) {  // column sub-tile
-          cr[x][y] = mfma_t<T>::op(lr[x], ur[y], cr[x][y]);
-          cr[x][y] = mfma_t<T>::op(-li[x], ui[y], cr[x][y]);
-          ci[x][y] = mfma_t<T>::op(lr[x], ui[y], ci[x][y]);
-          ci[x][y] = mfma_t<T>::op(li[x], ur[y], ci[x][y]);
+          // C -= L U: re -= lr ur - li ui, im -= lr ui + li ur
+          cr[x][y] = mfma_t<T>::op(-lr[x], ur[y], cr[x][y]);
+          ci[x][y] = mfma_t<T>::op(-lr[x], ui[y], ci[x][y]);
+          cr[x][y] = mfma_t<T>::op(li[x], ui[y], cr[x][y]);
+          ci[x][y] = mfma_t<T>::op(-li[x], ur[y], ci[x][y]);
         }
     }
     __syncthreads();
@@ -502,13 +511,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(cx<T>* __restrict__ A, long
       for (int j = 0; j < 4; ++j) {
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
-        if (gc < cend && gr < n) {
-          cx<T>* p = a + (long)gr * n + gc;
-          cx<T> v = *p;
-          v.re -= cr[x][y][j];
-          v.im -= ci[x][y][j];
-          *p = v;
-        }
+        if (gc < cend && gr < n) a[(long)gr * n + gc] = cx<T>{cr[x][y][j], ci[x][y][j]};
       }
 }
 
