@@ -11,6 +11,7 @@ solves.  Prints one JSON line.
 """
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -21,6 +22,24 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+
+def gemm_traffic_record():
+    """HBM bytes per launch of the trailing-update kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken (the record carries a digest of it)."""
+    src = open(os.path.join(ROOT, "paper_2412_11162_amd", "csrc", "lu.hip")).read()
+    a = src.index("void k_gemm_update(")
+    digest = hashlib.sha256(src[a:src.index("\n}\n", a)].encode()).hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "k_gemm_update_paper_scale.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.strip().startswith("traffic-record"):
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("source_sha256_16") == digest:
+                return float(kv["hbm_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(wl, seconds: float = 15.0):
@@ -144,7 +163,8 @@ def main():
                          "aux_near_points": int(info[7])},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_update<double> (LU trailing update)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "launches": launches, "flop_per_launch": flops / max(launches, 1),
+                     "traffic": gemm_traffic_record() if wl.name == "paper_scale" else None,
+                     "traffic_unit": "bytes per launch", "launches": launches, "flop_per_launch": flops / max(launches, 1),
                      "avg_launch_ms": gemm_ms / max(launches, 1)},
     }
     if not args.no_mixed:
