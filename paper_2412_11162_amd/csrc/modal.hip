@@ -209,7 +209,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ zd lds[pair_lds<R>()];
   const int N = nd.N;
   const long total = (long)N * N;
-  for (long p = blockIdx.x; p < total; p += gridDim.x) {
+  // workgroups are dealt to the 8 XCDs round-robin; each XCD takes a
+  // contiguous run of pairs so that the partial cache lines its neighbouring
+  // sources write meet in one L2
+  const long lb = (long)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  for (long p = lb; p < total; p += gridDim.x) {
     const int l = (int)(p % N), i = (int)(p / N);  // neighbouring sources write neighbouring columns
     const int dp = nd.panel[i] - nd.panel[l];
     if (dp >= -1 && dp <= 1) continue;  // near panels: product integration
@@ -236,15 +240,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 __global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, ClassParams cp,
                                 WorkList far, WorkList split, WorkList direct) {
   const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= count) return;
-  const PairGeom g = geom[q];
-  const PairInv v = pair_invariants(g);
-  const int cls = classify(g, v, cp);
-  WorkList& wl = cls == CLASS_FAR ? far : (cls == CLASS_SPLIT ? split : direct);
-  const unsigned slot = atomicAdd(wl.count, 1u);
-  if (slot < wl.cap) {
-    wl.geom[slot] = g;
-    wl.dest[slot] = make_int2((int)q, -1);
+  int cls = -1;
+  PairGeom g;
+  if (q < count) {
+    g = geom[q];
+    cls = classify(g, pair_invariants(g), cp);
+  }
+  // one counter update per wavefront and class
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const unsigned long long mask = __ballot(cls == c);
+    if (mask == 0) continue;
+    const int leader = __ffsll((long long)mask) - 1;
+    WorkList& wl = c == CLASS_FAR ? far : (c == CLASS_SPLIT ? split : direct);
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(wl.count, (unsigned)__popcll(mask));
+    base = __shfl(base, leader);
+    if (cls == c) {
+      const unsigned slot = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+      if (slot < wl.cap) {
+        wl.geom[slot] = g;
+        wl.dest[slot] = make_int2((int)q, -1);
+      }
+    }
   }
 }
 
@@ -558,29 +577,32 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
   if (jb >= njobs) return;
   const NearJob J = jobs[jb];
   const long N = o.n2 >> 1;
-  const int tot = 16 * (M + 1);
+  const int tot = 4 * (M + 1);
+  // thread -> (sequence s, mode n): each raw value is read once per job and
+  // weighted by the 16 Lagrange coefficients of its auxiliary point
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int l = e / (M + 1), n = e % (M + 1);
-    zd a0{0, 0}, a1{0, 0}, a2{0, 0}, a3{0, 0};
+    const int sq = e / (M + 1), n = e % (M + 1);
+    zd acc[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) acc[l] = zd{0.0, 0.0};
     for (int q = J.q0; q < J.q1; ++q) {
-      const double c = coef[(long)q * 16 + l];
-      const zd* r = raw + (long)q * 4 * (M + 1);
-      a0 = a0 + c * r[n];
-      a1 = a1 + c * r[(M + 1) + n];
-      a2 = a2 + c * r[2 * (M + 1) + n];
-      a3 = a3 + c * r[3 * (M + 1) + n];
+      const zd r = raw[(long)q * 4 * (M + 1) + e];
+      const double* c = coef + (long)q * 16;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) acc[l] = acc[l] + c[l] * r;
     }
-    const long i = J.target, col = (long)J.panel * 16 + l;
-    zd* An = o.A + (long)n * o.mstride;
-    zd k1v = a1, k2v = a3;
-    if (col == i) {
-      k1v = k1v + 1.0;
-      k2v = k2v - 1.0;
+    const long i = J.target;
+    const long row = sq < 2 ? i : N + i;
+    const long col0 = (sq & 1) ? 0 : N;
+    zd* dst = o.A + (long)n * o.mstride + row * o.n2 + col0 + (long)J.panel * 16;
+    // K blocks carry the identity term, S blocks the minus sign
+    const double diag = sq == 1 ? 1.0 : (sq == 3 ? -1.0 : 0.0);
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+      zd v = (sq & 1) ? acc[l] : -1.0 * acc[l];
+      if ((long)J.panel * 16 + l == i) v.re += diag;
+      dst[l] = v;
     }
-    An[i * o.n2 + col] = k1v;
-    An[i * o.n2 + N + col] = -a0;
-    An[(N + i) * o.n2 + col] = k2v;
-    An[(N + i) * o.n2 + N + col] = -a2;
   }
 }
 
@@ -646,7 +668,7 @@ template <int R>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
                          const OutSpec& o, WorkList split, WorkList direct, hipStream_t st) {
   long total = (long)nd.N * nd.N;
-  int grid = (int)std::min<long>(total, 256L * 128);
+  int grid = (int)std::min<long>((total + 7) / 8 * 8, 256L * 128);  // a multiple of 8
   hipLaunchKernelGGL(k_grid_far<R>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
                      direct);
 }
