@@ -56,7 +56,7 @@ enum {
 };
 
 enum { PMLBIE_FP64 = 0, PMLBIE_MIXED = 1 };
-enum { PMLBIE_KEEP_OPERATORS = 1 };
+enum { PMLBIE_KEEP_OPERATORS = 1, PMLBIE_USE_SURROGATE = 2 };
 
 /* Create a context on HIP device `device`, ordering work on `stream`
  * (a hipStream_t; NULL = the default stream).  *out receives the context. */
@@ -96,7 +96,12 @@ int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_
  * precision: PMLBIE_FP64 (complex128 throughout) or PMLBIE_MIXED
  * (complex64 LU with FP64 iterative refinement in solve_modes).
  * flags: PMLBIE_KEEP_OPERATORS keeps a copy of the assembled matrices for
- * pmlbie_get_operator.
+ * pmlbie_get_operator; PMLBIE_USE_SURROGATE offers the well-separated
+ * ("far") pairs to the learned surrogate first (needs a network for this PML
+ * geometry, real wavenumbers and m_max <= 64): its modes are kept where its
+ * modal synthesis at four angles matches direct kernel samples to the
+ * tolerance of pmlbie_surrogate_set_tolerance, the raw-kernel FFT takes the
+ * rest.
  * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOMEM, PMLBIE_EDEVICE,
  * PMLBIE_ESINGULAR (a zero pivot; pmlbie_last_error names the mode). */
 int pmlbie_build_modal_operators(pmlbie_ctx* ctx, int n_theta, int m_max, int precision,
@@ -129,10 +134,11 @@ int pmlbie_evaluate_field(pmlbie_ctx* ctx, int n_pts, const double* rtz, double*
 
 /* ---- inspection ---------------------------------------------------------- */
 
-/* Sizes of the current build: info[0] = N, [1] = m_max, [2] = internal FFT
- * length of the split, [3] = FFT length of the far path, [4] = far pairs,
- * [5] = split pairs, [6] = direct pairs, [7] = auxiliary near-panel points,
- * [8] = convolution half-width. */
+/* Sizes of the current build: info[0] = N, [1] = m_max, [2] = angle grid L
+ * of the split, [3] = angle grid of the far path (the same L), [4] = far
+ * pairs, [5] = split pairs, [6] = direct pairs, [7] = auxiliary near-panel
+ * points, [8] = modes of the smooth parts the split resolves beyond m_max
+ * (L/2 - 1 - m_max). */
 int pmlbie_get_info(const pmlbie_ctx* ctx, long long* info /* host, 9 */);
 
 /* Node table (host output, N x 13 doubles per node): rho, Im rho~, z,
@@ -158,8 +164,69 @@ int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
  * sides, [9] refinement, [10] build total; and counters (host, 16 doubles):
  * [0] refinement iterations, [1] final relative residual, [2] real flops of
  * all LU trailing updates (8 per complex multiply-add), [3] number of
- * trailing-update launches (stage [6] is the sum of their durations). */
+ * trailing-update launches (stage [6] is the sum of their durations),
+ * [4] far pairs offered to the surrogate, [5] pairs whose surrogate modes
+ * were accepted. */
 int pmlbie_get_stats(const pmlbie_ctx* ctx, double* stage_ms, double* counters);
+
+/* ---- Learned surrogate of the far-pair modes ------------------------------
+ * A multilayer perceptron (inputs rho, rho', dz, k, S; four hidden layers of
+ * 256 with the erf GELU; 390 outputs) trained on modal kernels that the
+ * raw-kernel FFT of the build generates.  It predicts modes 0..64 of
+ *   S = G~, P = (-(rho~ - rho~') + 2 rho~ sin^2(D/2)) f, Q = -(z - z') f,
+ *   f = e^{ikR}(ikR - 1)/(4 pi R^3)  (K = n'_rho P + n'_z Q, Sec. 3.1),
+ * each normalised by the phase e^{ik Re R0} and an amplitude scale that
+ * includes the largest PML decay factor |e^{ikR}| over the angle
+ * (R0 = R at D = 0).
+ * Weights: FP32 master copy and Adam moments on the device, BF16 copies for
+ * the MFMA products (FP32 accumulation).  One network serves one PML
+ * geometry (a1, T, p, fixed at init or load); S enters as an input.
+ * Every call returns a status; PMLBIE_ESTATE when no network exists. */
+
+/* Number of FP32 parameters of the network (weights and biases, padded
+ * layouts: layer l is (out x in) row-major, in padded to 32 / 256). */
+long pmlbie_surrogate_nparams(void);
+
+/* Fresh network (Glorot-uniform weights from a splitmix64 stream seeded
+ * with `seed`, zero biases) for the PML geometry of the current media. */
+int pmlbie_surrogate_init(pmlbie_ctx* ctx, unsigned long long seed);
+
+/* Sample set `which` (0 training, 1 held out) of n pairs: random interfaces
+ * a exp(-(rho / w)^2), a ~ U[0, 0.6], w ~ U[0.5, 2], at 512 nodes per
+ * segment; node pairs farther apart than twice the longer sub-panel;
+ * S ~ U[1, 4]; k = k1 ~ U[5, 15] or k1 * U[1.2, 2] with equal odds.  Labels
+ * by the raw-kernel FFT on the device (512 angles).  n <= 2^24. */
+int pmlbie_surrogate_make_samples(pmlbie_ctx* ctx, int which, long n, unsigned long long seed);
+
+/* `steps` Adam steps on consecutive batches of the training set (step size
+ * decaying from lr to lr / 20 along a cosine); loss_out (host, steps
+ * doubles, may be NULL) receives the mean squared error of each batch. */
+int pmlbie_surrogate_train(pmlbie_ctx* ctx, int steps, int batch, double lr, double* loss_out);
+
+/* Mean squared error of the network over sample set `which`. */
+int pmlbie_surrogate_eval(pmlbie_ctx* ctx, int which, double* mse);
+
+/* Acceptance tolerance of the build: a pair's surrogate modes are kept when
+ * 4 pi W_l max |synthesis - direct sample| <= tol over four angles and both
+ * media (W_l the quadrature weight of the source node).  0 rejects all. */
+int pmlbie_surrogate_set_tolerance(pmlbie_ctx* ctx, double tol);
+
+/* Serialise / restore the network (header + FP32 parameters).  save with
+ * blob = NULL stores the size in *bytes. */
+int pmlbie_surrogate_save(pmlbie_ctx* ctx, void* blob, size_t* bytes);
+int pmlbie_surrogate_load(pmlbie_ctx* ctx, const void* blob, size_t bytes);
+
+/* Test hooks (host arrays).  params: get (1) or set (0) the FP32 parameters
+ * (nparams doubles).  forward: x n x 5 raw features -> y n x 390 outputs.
+ * grad: loss and gradient of the mean squared error against targets t
+ * (n x 390) for the current parameters (no update).  label: normalised
+ * FFT targets (n x 390) of samples s (n x 6: Re, Im rho~, Re, Im rho~',
+ * z - z', k). */
+int pmlbie_surrogate_params(pmlbie_ctx* ctx, double* p, int get);
+int pmlbie_surrogate_forward(pmlbie_ctx* ctx, int n, const double* x, double* y);
+int pmlbie_surrogate_grad(pmlbie_ctx* ctx, int n, const double* x, const double* t, double* loss,
+                          double* grad);
+int pmlbie_surrogate_label(pmlbie_ctx* ctx, int n, const double* s, double* y);
 
 #ifdef __cplusplus
 }

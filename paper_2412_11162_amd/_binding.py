@@ -19,12 +19,17 @@ PMLBIE_ENOCONV = -6
 PMLBIE_FP64 = 0
 PMLBIE_MIXED = 1
 PMLBIE_KEEP_OPERATORS = 1
+PMLBIE_USE_SURROGATE = 2
 
 EXPORTS = (
     "pmlbie_create", "pmlbie_destroy", "pmlbie_last_error", "pmlbie_set_geometry",
     "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_solve_modes",
     "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
     "pmlbie_get_operator", "pmlbie_get_stats",
+    "pmlbie_surrogate_nparams", "pmlbie_surrogate_init", "pmlbie_surrogate_make_samples",
+    "pmlbie_surrogate_train", "pmlbie_surrogate_eval", "pmlbie_surrogate_set_tolerance",
+    "pmlbie_surrogate_save", "pmlbie_surrogate_load", "pmlbie_surrogate_params",
+    "pmlbie_surrogate_forward", "pmlbie_surrogate_grad", "pmlbie_surrogate_label",
 )
 
 
@@ -60,8 +65,22 @@ def load():
     L.pmlbie_modal_kernels.argtypes = [P, i, P, P]
     L.pmlbie_get_operator.argtypes = [P, i, P]
     L.pmlbie_get_stats.argtypes = [P, P, P]
+    ul, l, sz = ctypes.c_ulonglong, ctypes.c_long, ctypes.c_size_t
+    L.pmlbie_surrogate_nparams.argtypes = []
+    L.pmlbie_surrogate_init.argtypes = [P, ul]
+    L.pmlbie_surrogate_make_samples.argtypes = [P, i, l, ul]
+    L.pmlbie_surrogate_train.argtypes = [P, i, i, d, P]
+    L.pmlbie_surrogate_eval.argtypes = [P, i, P]
+    L.pmlbie_surrogate_set_tolerance.argtypes = [P, d]
+    L.pmlbie_surrogate_save.argtypes = [P, P, ctypes.POINTER(sz)]
+    L.pmlbie_surrogate_load.argtypes = [P, P, sz]
+    L.pmlbie_surrogate_params.argtypes = [P, P, i]
+    L.pmlbie_surrogate_forward.argtypes = [P, i, P, P]
+    L.pmlbie_surrogate_grad.argtypes = [P, i, P, P, P, P]
+    L.pmlbie_surrogate_label.argtypes = [P, i, P, P]
     for name in EXPORTS:
-        if name not in ("pmlbie_destroy", "pmlbie_last_error"):
+        if name not in ("pmlbie_destroy", "pmlbie_last_error", "pmlbie_surrogate_nparams"):
             getattr(L, name).restype = ctypes.c_int
+    L.pmlbie_surrogate_nparams.restype = ctypes.c_long
     _lib = L
     return L

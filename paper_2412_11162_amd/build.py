@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpmlbie.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["modal.hip", "lu.hip", "solve.hip", "capi.hip", "host_geom.cpp"]
+SOURCES = ["modal.hip", "lu.hip", "solve.hip", "surrogate.hip", "capi.hip", "host_geom.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

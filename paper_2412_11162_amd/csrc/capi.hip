@@ -16,6 +16,7 @@
 #include "lu.h"
 #include "modal.h"
 #include "solve.h"
+#include "surrogate.h"
 
 using namespace pmlbie;
 
@@ -95,6 +96,24 @@ struct pmlbie_ctx {
   DBuf<zd> b1, b2, x, u1, p1, u2, p2;
   double stage_ms[16] = {0};
   double counters[16] = {0};
+  // learned surrogate of the far-pair modes
+  SgNet sg;
+  SgWork sgw;
+  bool sg_ready = false;
+  double sg_a1 = 0, sg_T = 0, sg_tol = 1e-10;
+  int sg_p = 0;
+  DBuf<double> sgx[2];     // features (rho, rho', dz, k, S) of the sample sets
+  DBuf<float> sgT[2];      // their normalised modal targets
+  long sgn[2] = {0, 0};
+  DBuf<zd> sgtw;           // twiddles of the labelling FFT
+  DBuf<double> sgfx;       // features of the far pairs of one chunk
+  DBuf<unsigned> sgcnt;    // accepted pairs, fallback count
+  DBuf<PairGeom> sgfb_geom;  // far pairs the network's modes were not accepted for
+  DBuf<int2> sgfb_dest;
+  ~pmlbie_ctx() {
+    sg_free(sg);
+    sg_work_free(sgw);
+  }
 };
 
 namespace {
@@ -160,6 +179,38 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
                  c->phat.p, A, n2, ms, W, raw, c->stream);
     HIPCHK(hipGetLastError());
   }
+}
+
+// Far pairs of the grid through the surrogate: features, network forward,
+// acceptance against direct kernel samples (accepted modes go into A), and
+// the raw-kernel FFT for the rest.
+void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count, long n2, long ms,
+                   const double* W) {
+  const long CH = 1L << 16;
+  HIPCHK(sg_work_alloc(c->sgw, (int)(2 * CH)));
+  c->sgfx.alloc((size_t)2 * CH * SG_IN);
+  c->sgcnt.alloc(2);
+  c->sgfb_geom.alloc(std::max<long>(count, 1));
+  c->sgfb_dest.alloc(std::max<long>(count, 1));
+  HIPCHK(hipMemsetAsync(c->sgcnt.p, 0, 2 * sizeof(unsigned), c->stream));
+  WorkList fb{c->sgfb_geom.p, c->sgfb_dest.p, c->sgcnt.p + 1, (unsigned)std::max<long>(count, 1)};
+  SgFeat f{c->sg_a1 + c->sg_T};
+  for (long s = 0; s < count; s += CH) {
+    const long cn = std::min(CH, count - s);
+    sg_pair_features(geom + s, cn, c->k1.re, c->k2.re, c->geo.pml.S, c->sgfx.p, c->stream);
+    sg_features(c->sgfx.p, (int)(2 * cn), f, c->sgw, c->stream);
+    sg_forward(c->sg, c->sgw, (int)(2 * cn), c->stream);
+    sg_accept(geom + s, dest + s, cn, c->sgw.z[SG_NL - 1], c->M, c->k1, c->k2, c->sg_tol, c->A.p, n2, ms,
+              W, fb, c->sgcnt.p, c->stream);
+    HIPCHK(hipGetLastError());
+  }
+  unsigned h[2];
+  HIPCHK(hipMemcpy(h, c->sgcnt.p, sizeof(h), hipMemcpyDeviceToHost));
+  c->counters[4] = (double)count;
+  c->counters[5] = (double)h[0];
+  launch_list_far(c->nt_far, c->sgfb_geom.p, c->sgfb_dest.p, 0, h[1], c->M, c->k1, c->k2, c->tw_far.p, c->A.p,
+                  n2, ms, W, nullptr, c->stream);
+  HIPCHK(hipGetLastError());
 }
 
 // Explicit pair list (host) -> raw modal values raw[q][s][n]: upload, classify
@@ -297,6 +348,17 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       return fail(c, PMLBIE_EINVAL, "build: need 0 <= m_max <= n_theta / 2");
     if (precision != PMLBIE_FP64 && precision != PMLBIE_MIXED)
       return fail(c, PMLBIE_EINVAL, "build: precision must be PMLBIE_FP64 or PMLBIE_MIXED");
+    const bool use_sg = (flags & PMLBIE_USE_SURROGATE) != 0;
+    if (use_sg) {
+      if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "build: no surrogate network (init, train or load one)");
+      if (m_max > SG_MODES - 1)
+        return fail(c, PMLBIE_EINVAL, "build: the surrogate covers modes 0..64 only");
+      if (c->k1.im != 0.0 || c->k2.im != 0.0)
+        return fail(c, PMLBIE_EINVAL, "build: the surrogate takes real wavenumbers");
+      if (fabs(c->geo.pml.a1 - c->sg_a1) > 1e-12 || fabs(c->geo.pml.T - c->sg_T) > 1e-12 ||
+          c->geo.pml.p != c->sg_p)
+        return fail(c, PMLBIE_EINVAL, "build: the surrogate was trained for another PML geometry");
+    }
     auto t_all = std::chrono::steady_clock::now();
     c->stage = 2;
     c->n_theta = n_theta;
@@ -362,12 +424,12 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     c->luw.alloc((size_t)(M + 1) * LU_NB * LU_NB);
     c->info.alloc(M + 1);
     HIPCHK(hipMemsetAsync(c->info.p, 0, (M + 1) * sizeof(int), c->stream));
-    // work lists of the grid (split and direct share one allocation)
+    // work lists of the grid (split, direct and far share one allocation)
     const size_t cap = (size_t)N * N;
-    c->lgeom.alloc(2 * cap);
-    c->ldest.alloc(2 * cap);
-    c->lcount.alloc(2);
-    HIPCHK(hipMemsetAsync(c->lcount.p, 0, 2 * sizeof(unsigned), c->stream));
+    c->lgeom.alloc(3 * cap);
+    c->ldest.alloc(3 * cap);
+    c->lcount.alloc(3);
+    HIPCHK(hipMemsetAsync(c->lcount.p, 0, 3 * sizeof(unsigned), c->stream));
     // auxiliary near-panel points
     std::vector<PairGeom> ageom;
     std::vector<double> acoef;
@@ -395,14 +457,22 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     WorkList ws{c->lgeom.p, c->ldest.p, c->lcount.p, (unsigned)cap};
     WorkList wd{c->lgeom.p + cap, c->ldest.p + cap, c->lcount.p + 1, (unsigned)cap};
 
+    // far pairs: raw-kernel FFT in the grid, or listed for the surrogate
+    WorkList wf{c->lgeom.p + 2 * cap, c->ldest.p + 2 * cap, c->lcount.p + 2, (unsigned)cap};
     Timer t_far(c->stream);
-    launch_grid_far(c->nt_far, nd, c->cp, c->k1, c->k2, c->tw_far.p, c->A.p, ms, nd.W, ws, wd,
-                    c->stream);
+    if (use_sg)
+      launch_grid_classify(nd, c->cp, wf, ws, wd, c->stream);
+    else
+      launch_grid_far(c->nt_far, nd, c->cp, c->k1, c->k2, c->tw_far.p, c->A.p, ms, nd.W, ws, wd, c->stream);
     HIPCHK(hipGetLastError());
+    unsigned counts[3] = {0, 0, 0};
+    HIPCHK(hipMemcpy(counts, c->lcount.p, 3 * sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (counts[0] > cap || counts[1] > cap || counts[2] > cap)
+      return fail(c, PMLBIE_EDEVICE, "build: work list overflow");
+    c->counters[4] = 0;
+    c->counters[5] = 0;
+    if (use_sg) run_surrogate(c, wf.geom, wf.dest, counts[2], n2, ms, nd.W);
     c->stage_ms[1] = t_far.stop();
-    unsigned counts[2];
-    HIPCHK(hipMemcpy(counts, c->lcount.p, sizeof(counts), hipMemcpyDeviceToHost));
-    if (counts[0] > cap || counts[1] > cap) return fail(c, PMLBIE_EDEVICE, "build: work list overflow");
     c->cnt_split = counts[0];
     c->cnt_direct = counts[1];
     c->cnt_far = (long long)N * N - counts[0] - counts[1];
@@ -789,6 +859,335 @@ int pmlbie_get_stats(const pmlbie_ctx* c, double* stage_ms, double* counters) {
   if (stage_ms) memcpy(stage_ms, c->stage_ms, sizeof(c->stage_ms));
   if (counters) memcpy(counters, c->counters, sizeof(c->counters));
   return PMLBIE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned surrogate (training, persistence, test hooks).
+namespace {
+
+// splitmix64 (Steele, Lea and Flood 2014): seeded uniform draws for the
+// surrogate's initial weights and training geometries.
+struct Rng {
+  uint64_t s;
+  explicit Rng(uint64_t seed) : s(seed) {}
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double u() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+struct SgHeader {
+  char magic[8];
+  int version, p;
+  double a1, T;
+  long nparams;
+};
+
+}  // namespace
+
+extern "C" {
+
+long pmlbie_surrogate_nparams(void) { return SgLayout().total; }
+
+int pmlbie_surrogate_init(pmlbie_ctx* c, unsigned long long seed) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 2) return fail(c, PMLBIE_ESTATE, "surrogate_init: set geometry and media first");
+    sg_free(c->sg);
+    c->sg_ready = false;
+    HIPCHK(sg_alloc(c->sg));
+    SgLayout L;
+    std::vector<float> p(L.total, 0.0f);
+    Rng r(seed);
+    for (int l = 0; l < SG_NL; ++l) {
+      const int fin = l == 0 ? SG_IN : SG_D[l], fout = l == SG_NL - 1 ? SG_OUT : SG_D[l + 1];
+      const double a = sqrt(6.0 / (fin + fout));
+      for (int o = 0; o < fout; ++o)
+        for (int i = 0; i < fin; ++i) p[L.w[l] + (long)o * SG_D[l] + i] = (float)(a * (2.0 * r.u() - 1.0));
+    }
+    HIPCHK(hipMemcpy(c->sg.p, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice));
+    sg_refresh_bf16(c->sg, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->sg_a1 = c->geo.pml.a1;
+    c->sg_T = c->geo.pml.T;
+    c->sg_p = c->geo.pml.p;
+    c->sg_ready = true;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_make_samples(pmlbie_ctx* c, int which, long n, unsigned long long seed) {
+  return guarded(c, [&]() -> int {
+    if (which != 0 && which != 1) return fail(c, PMLBIE_EINVAL, "surrogate_make_samples: which is 0 or 1");
+    if (n <= 0 || n > (1L << 24)) return fail(c, PMLBIE_EINVAL, "surrogate_make_samples: 0 < n <= 2^24");
+    if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_make_samples: no network");
+    Rng r(seed);
+    std::vector<SgSample> smp(n);
+    std::vector<double> x(5 * n);
+    const double a1 = c->sg_a1, T = c->sg_T;
+    long q = 0;
+    while (q < n) {
+      // one interface z = a exp(-(rho / w)^2) at the paper-scale resolution
+      Geometry g;
+      g.itf.amp = {0.6 * r.u()};
+      g.itf.cen = {0.0};
+      g.itf.wid = {0.5 + 1.5 * r.u()};
+      g.itf.cos_freq = 0.0;
+      g.itf.rho_c = a1;
+      g.pml.a1 = a1;
+      g.pml.T = T;
+      g.pml.S = 1.0;  // Im rho~ is linear in S
+      g.pml.p = c->sg_p;
+      g.breaks = {0.0, 0.5 * a1, a1, a1 + 0.5 * T, a1 + T};
+      g.nodes_per_segment = 512;
+      g.build();
+      const int N = g.n();
+      for (long t = 0; t < 16384 && q < n;) {
+        const int i = std::min(N - 1, (int)(r.u() * N)), l = std::min(N - 1, (int)(r.u() * N));
+        const double h = 1.2 * std::max(g.pl[g.panel[i]], g.pl[g.panel[l]]);
+        const double dr = g.rho[i] - g.rho[l], dz = g.z[i] - g.z[l];
+        if (dr * dr + dz * dz <= 4.0 * h * h) continue;  // separation > 2 h
+        const double S = 1.0 + 3.0 * r.u();
+        const double k1 = 5.0 + 10.0 * r.u();
+        const double k = r.u() < 0.5 ? k1 : k1 * (1.2 + 0.8 * r.u());
+        smp[q] = SgSample{g.rho[i], S * g.I[i], g.rho[l], S * g.I[l], dz, k};
+        const double xs[5] = {g.rho[i], g.rho[l], dz, k, S};
+        for (int j = 0; j < 5; ++j) x[5 * q + j] = xs[j];
+        ++q;
+        ++t;
+      }
+    }
+    for (long a = n - 1; a > 0; --a) {  // shuffle the geometries together
+      const long b = std::min(a, (long)(r.u() * (a + 1)));
+      std::swap(smp[a], smp[b]);
+      for (int j = 0; j < 5; ++j) std::swap(x[5 * a + j], x[5 * b + j]);
+    }
+    DBuf<SgSample> ds;
+    ds.alloc(n);
+    HIPCHK(hipMemcpy(ds.p, smp.data(), n * sizeof(SgSample), hipMemcpyHostToDevice));
+    const int L = 512;
+    auto tw = twiddles(L, true);
+    c->sgtw.alloc(tw.size());
+    HIPCHK(hipMemcpy(c->sgtw.p, tw.data(), tw.size() * sizeof(zd), hipMemcpyHostToDevice));
+    c->sgT[which].alloc((size_t)n * SG_OUT);
+    c->sgx[which].alloc((size_t)n * 5);
+    HIPCHK(hipMemcpy(c->sgx[which].p, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice));
+    sg_label(ds.p, n, L, c->sgtw.p, c->sgT[which].p, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->sgn[which] = n;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_train(pmlbie_ctx* c, int steps, int batch, double lr, double* loss_out) {
+  return guarded(c, [&]() -> int {
+    if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_train: no network");
+    if (steps < 0 || batch < 64 || batch > 65536 || !(lr > 0))
+      return fail(c, PMLBIE_EINVAL, "surrogate_train: steps >= 0, 64 <= batch <= 65536, lr > 0");
+    const long n = c->sgn[0];
+    if (n < batch) return fail(c, PMLBIE_ESTATE, "surrogate_train: fewer training samples than a batch");
+    HIPCHK(sg_work_alloc(c->sgw, batch));
+    DBuf<double> lsum;
+    lsum.alloc(std::max(steps, 1));
+    SgFeat f{c->sg_a1 + c->sg_T};
+    for (int s = 0; s < steps; ++s) {
+      long off = ((long)s * batch) % n;
+      if (off + batch > n) off = 0;
+      // cosine decay of the step size from lr to lr / 20
+      const double lr_s = lr * (0.05 + 0.475 * (1.0 + cos(PMLBIE_PI * s / std::max(steps, 1))));
+      sg_features(c->sgx[0].p + 5 * off, batch, f, c->sgw, c->stream);
+      sg_forward(c->sg, c->sgw, batch, c->stream);
+      sg_backward(c->sg, c->sgw, batch, c->sgT[0].p + (long)SG_OUT * off, c->stream);
+      sg_adam(c->sg, lr_s, c->stream);
+      HIPCHK(hipMemcpyAsync(lsum.p + s, c->sgw.loss, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipGetLastError());
+    }
+    std::vector<double> h(std::max(steps, 1));
+    HIPCHK(hipMemcpy(h.data(), lsum.p, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (loss_out)
+      for (int s = 0; s < steps; ++s) loss_out[s] = h[s] / ((double)batch * SG_OUT);
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_eval(pmlbie_ctx* c, int which, double* mse) {
+  return guarded(c, [&]() -> int {
+    if (which != 0 && which != 1) return fail(c, PMLBIE_EINVAL, "surrogate_eval: which is 0 or 1");
+    if (!c->sg_ready || c->sgn[which] <= 0) return fail(c, PMLBIE_ESTATE, "surrogate_eval: no network or samples");
+    const long n = c->sgn[which], CH = 1L << 15;
+    HIPCHK(sg_work_alloc(c->sgw, (int)CH));
+    SgFeat f{c->sg_a1 + c->sg_T};
+    double tot = 0.0;
+    for (long off = 0; off < n; off += CH) {
+      const int cn = (int)std::min(CH, n - off);
+      sg_features(c->sgx[which].p + 5 * off, cn, f, c->sgw, c->stream);
+      sg_forward(c->sg, c->sgw, cn, c->stream);
+      sg_loss(c->sgw, cn, c->sgT[which].p + (long)SG_OUT * off, c->stream);
+      double l = 0;
+      HIPCHK(hipMemcpy(&l, c->sgw.loss, sizeof(double), hipMemcpyDeviceToHost));
+      tot += l;
+    }
+    if (mse) *mse = tot / ((double)n * SG_OUT);
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_set_tolerance(pmlbie_ctx* c, double tol) {
+  if (!c) return PMLBIE_EINVAL;
+  if (!(tol >= 0)) return fail(c, PMLBIE_EINVAL, "surrogate_set_tolerance: tol >= 0");
+  c->sg_tol = tol;
+  return PMLBIE_OK;
+}
+
+int pmlbie_surrogate_save(pmlbie_ctx* c, void* blob, size_t* bytes) {
+  return guarded(c, [&]() -> int {
+    if (!bytes) return fail(c, PMLBIE_EINVAL, "surrogate_save: bytes is null");
+    if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_save: no network");
+    SgLayout L;
+    const size_t need = sizeof(SgHeader) + (size_t)L.total * sizeof(float);
+    if (!blob) {
+      *bytes = need;
+      return PMLBIE_OK;
+    }
+    if (*bytes < need) return fail(c, PMLBIE_EINVAL, "surrogate_save: buffer too small");
+    SgHeader hd{};
+    memcpy(hd.magic, "PMLBIESG", 8);
+    hd.version = 1;
+    hd.p = c->sg_p;
+    hd.a1 = c->sg_a1;
+    hd.T = c->sg_T;
+    hd.nparams = L.total;
+    memcpy(blob, &hd, sizeof(hd));
+    HIPCHK(hipMemcpy((char*)blob + sizeof(hd), c->sg.p, (size_t)L.total * sizeof(float), hipMemcpyDeviceToHost));
+    *bytes = need;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_load(pmlbie_ctx* c, const void* blob, size_t bytes) {
+  return guarded(c, [&]() -> int {
+    SgLayout L;
+    SgHeader hd{};
+    if (!blob || bytes < sizeof(hd)) return fail(c, PMLBIE_EINVAL, "surrogate_load: short blob");
+    memcpy(&hd, blob, sizeof(hd));
+    if (memcmp(hd.magic, "PMLBIESG", 8) != 0 || hd.version != 1 || hd.nparams != L.total ||
+        bytes < sizeof(hd) + (size_t)L.total * sizeof(float))
+      return fail(c, PMLBIE_EINVAL, "surrogate_load: not a surrogate blob of this layout");
+    sg_free(c->sg);
+    c->sg_ready = false;
+    HIPCHK(sg_alloc(c->sg));
+    HIPCHK(hipMemcpy(c->sg.p, (const char*)blob + sizeof(hd), (size_t)L.total * sizeof(float),
+                     hipMemcpyHostToDevice));
+    sg_refresh_bf16(c->sg, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->sg_a1 = hd.a1;
+    c->sg_T = hd.T;
+    c->sg_p = hd.p;
+    c->sg_ready = true;
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_params(pmlbie_ctx* c, double* p, int get) {
+  return guarded(c, [&]() -> int {
+    if (!p) return fail(c, PMLBIE_EINVAL, "surrogate_params: null buffer");
+    if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_params: no network");
+    SgLayout L;
+    std::vector<float> f(L.total);
+    if (get) {
+      HIPCHK(hipMemcpy(f.data(), c->sg.p, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+      for (long i = 0; i < L.total; ++i) p[i] = f[i];
+    } else {
+      for (long i = 0; i < L.total; ++i) f[i] = (float)p[i];
+      HIPCHK(hipMemcpy(c->sg.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+      sg_refresh_bf16(c->sg, c->stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_forward(pmlbie_ctx* c, int n, const double* x, double* y) {
+  return guarded(c, [&]() -> int {
+    if (n <= 0 || n > 65536 || !x || !y) return fail(c, PMLBIE_EINVAL, "surrogate_forward: 0 < n <= 65536");
+    if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_forward: no network");
+    HIPCHK(sg_work_alloc(c->sgw, n));
+    DBuf<double> dx;
+    dx.alloc((size_t)n * 5);
+    HIPCHK(hipMemcpy(dx.p, x, (size_t)n * 5 * sizeof(double), hipMemcpyHostToDevice));
+    SgFeat f{c->sg_a1 + c->sg_T};
+    sg_features(dx.p, n, f, c->sgw, c->stream);
+    sg_forward(c->sg, c->sgw, n, c->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<float> h((size_t)n * SG_D[SG_NL]);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(h.data(), c->sgw.z[SG_NL - 1], h.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (long r = 0; r < n; ++r)
+      for (int j = 0; j < SG_OUT; ++j) y[r * SG_OUT + j] = h[r * SG_D[SG_NL] + j];
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_grad(pmlbie_ctx* c, int n, const double* x, const double* t, double* loss,
+                          double* grad) {
+  return guarded(c, [&]() -> int {
+    if (n <= 0 || n > 65536 || !x || !t || !grad) return fail(c, PMLBIE_EINVAL, "surrogate_grad: 0 < n <= 65536");
+    if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_grad: no network");
+    SgLayout L;
+    HIPCHK(sg_work_alloc(c->sgw, n));
+    DBuf<double> dx;
+    dx.alloc((size_t)n * 5);
+    DBuf<float> dt;
+    dt.alloc((size_t)n * SG_OUT);
+    std::vector<float> tf((size_t)n * SG_OUT);
+    for (size_t i = 0; i < tf.size(); ++i) tf[i] = (float)t[i];
+    HIPCHK(hipMemcpy(dx.p, x, (size_t)n * 5 * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dt.p, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice));
+    SgFeat f{c->sg_a1 + c->sg_T};
+    sg_features(dx.p, n, f, c->sgw, c->stream);
+    sg_forward(c->sg, c->sgw, n, c->stream);
+    sg_backward(c->sg, c->sgw, n, dt.p, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<float> g(L.total);
+    HIPCHK(hipMemcpy(g.data(), c->sg.g, g.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (long i = 0; i < L.total; ++i) grad[i] = g[i];
+    double l = 0;
+    HIPCHK(hipMemcpy(&l, c->sgw.loss, sizeof(double), hipMemcpyDeviceToHost));
+    if (loss) *loss = l / ((double)n * SG_OUT);
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_label(pmlbie_ctx* c, int n, const double* s, double* y) {
+  return guarded(c, [&]() -> int {
+    if (n <= 0 || n > (1 << 20) || !s || !y) return fail(c, PMLBIE_EINVAL, "surrogate_label: 0 < n <= 2^20");
+    std::vector<SgSample> smp(n);
+    for (int q = 0; q < n; ++q) smp[q] = SgSample{s[6 * q], s[6 * q + 1], s[6 * q + 2], s[6 * q + 3], s[6 * q + 4], s[6 * q + 5]};
+    DBuf<SgSample> ds;
+    ds.alloc(n);
+    HIPCHK(hipMemcpy(ds.p, smp.data(), n * sizeof(SgSample), hipMemcpyHostToDevice));
+    auto tw = twiddles(512, true);
+    c->sgtw.alloc(tw.size());
+    HIPCHK(hipMemcpy(c->sgtw.p, tw.data(), tw.size() * sizeof(zd), hipMemcpyHostToDevice));
+    DBuf<float> dt;
+    dt.alloc((size_t)n * SG_OUT);
+    sg_label(ds.p, n, 512, c->sgtw.p, dt.p, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<float> h((size_t)n * SG_OUT);
+    HIPCHK(hipMemcpy(h.data(), dt.p, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < h.size(); ++i) y[i] = h[i];
+    return PMLBIE_OK;
+  });
 }
 
 }  // extern "C"

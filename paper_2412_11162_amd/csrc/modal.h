@@ -52,9 +52,15 @@ struct NearJob {
   int target, panel, q0, q1;
 };
 
+// The main grid over all node pairs off the near panels: far pairs are
+// transformed in place, split and direct pairs appended to their lists.
 void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
                      const zd* tw, zd* A, long mstride, const double* W, WorkList split,
                      WorkList direct, hipStream_t st);
+// Classification only (surrogate path): far / split / direct lists with
+// destinations (i, l).
+void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,
+                          WorkList direct, hipStream_t st);
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                      zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
                      zd* raw, hipStream_t st);

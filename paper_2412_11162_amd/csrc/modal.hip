@@ -10,95 +10,9 @@
 // even in D, so F_{-n} = F_n and only n = 0..M are formed.
 #include "fft_wave.h"
 #include "modal.h"
+#include "modal_out.h"
 
 namespace pmlbie {
-
-// ------------------------------------------------------------------------
-// Output: either the per-mode system matrices or a raw modal buffer.
-//
-// System matrix of mode n, row-major 2N x 2N at A + n * mstride:
-//   [[K1 - D1, -S1], [K2 - D2, -S2]],  K_il = 2 W_l K_n(r_i, r_l),
-//   S_il = 2 W_l S_n(r_i, r_l) for l off the near panels of i.
-// Raw modal buffer: out[q][s][n], s in {S1, K1, S2, K2}.
-struct OutSpec {
-  zd* A;
-  long n2;       // 2N
-  long mstride;  // elements per mode matrix
-  const double* W;
-  zd* raw;
-  int M;
-};
-
-__device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, zd K1, zd S2,
-                                     zd K2) {
-  if (dst.y >= 0) {
-    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
-    const double w2 = 2.0 * o.W[l];
-    zd* An = o.A + (long)n * o.mstride;
-    An[i * o.n2 + l] = w2 * K1;
-    An[i * o.n2 + N + l] = (-w2) * S1;
-    An[(N + i) * o.n2 + l] = w2 * K2;
-    An[(N + i) * o.n2 + N + l] = (-w2) * S2;
-  } else {
-    zd* r = o.raw + (long)dst.x * 4 * (o.M + 1);
-    r[n] = S1;
-    r[(o.M + 1) + n] = K1;
-    r[2 * (o.M + 1) + n] = S2;
-    r[3 * (o.M + 1) + n] = K2;
-  }
-}
-
-__device__ __forceinline__ PairGeom node_pair(const NodesDev& nd, int i, int l) {
-  PairGeom g;
-  g.rt = zd{nd.rho[i], nd.I[i]};
-  g.rs = zd{nd.rho[l], nd.I[l]};
-  g.drho = zd{nd.rho[i] - nd.rho[l], nd.I[i] - nd.I[l]};
-  g.dz = zd{nd.z[i] - nd.z[l], 0.0};
-  g.nr = zd{nd.nr_re[l], nd.nr_im[l]};
-  g.nz = zd{nd.nz_re[l], nd.nz_im[l]};
-  return g;
-}
-
-// In-place radix-2 FFT (decimation in time, bit-reversed input) of NSEQ
-// sequences of length NT held in LDS, one wavefront.  tw[k] = e^{-2 pi i k/NT}.
-template <int NT, int NSEQ>
-__device__ __forceinline__ void fft_lds(zd* buf, const zd* __restrict__ tw) {
-#pragma unroll 1
-  for (int len = 2; len <= NT; len <<= 1) {
-    const int half = len >> 1, step = NT / len;
-    for (int b = threadIdx.x; b < NSEQ * (NT / 2); b += 64) {
-      const int s = b / (NT / 2), bb = b % (NT / 2);
-      const int grp = bb / half, pos = bb % half;
-      const int i0 = s * NT + grp * len + pos, i1 = i0 + half;
-      const zd w = tw[pos * step];
-      const zd u = buf[i0], v = buf[i1] * w;
-      buf[i0] = u + v;
-      buf[i1] = u - v;
-    }
-    __syncthreads();
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ int bitrev(int j) {
-  constexpr int LOG = __builtin_ctz(NT);
-  return (int)(__brev((unsigned)j) >> (32 - LOG));
-}
-
-// ------------------------------------------------------------------------
-// Classification of a pair (Sec. 4.1: well-separated pairs by FFT of the raw
-// kernel; close pairs by the split; close pairs deep in the PML by graded
-// direct quadrature, where cos(kR) grows like exp(max |Im kR|)).
-__device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, const ClassParams& cp) {
-  double delta, re0;
-  singularity(v, delta, re0);
-  const double sc = sqrt(cabs_(g.rt * g.rs));
-  const double bw = cp.bw * cp.kmax * sc;
-  if ((cp.nt_far - cp.M - bw) * delta >= cp.c_far) return CLASS_FAR;
-  zd Rpi = csqrt_(v.d2 + v.c4);
-  double grow = cp.kmax * fabs(Rpi.im) + cp.kmax_im * fabs(Rpi.re);
-  return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
-}
 
 // One mode value of sequence s in {S1, K1, S2, K2}, scaled.
 __device__ __forceinline__ void emit_val(const OutSpec& o, int2 dst, int s, int n, double scale,
@@ -179,6 +93,7 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
   constexpr int L = 64 * R, H = L / 2 + 1;
   zd* P2 = lds;
   zd* E = lds + 2 * H;
+#pragma unroll 1
   for (int j = threadIdx.x; j <= L / 2; j += 64) {
     const double sh = sin(PMLBIE_PI * j / L);
     const double s2 = sh * sh;
@@ -235,18 +150,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
-// Classification of an explicit pair list into far / split / direct work
-// lists (destination = raw row q).
-__global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, ClassParams cp,
-                                WorkList far, WorkList split, WorkList direct) {
-  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  int cls = -1;
-  PairGeom g;
-  if (q < count) {
-    g = geom[q];
-    cls = classify(g, pair_invariants(g), cp);
-  }
-  // one counter update per wavefront and class
+// Wave-aggregated append of this lane's pair to the work list of its class
+// (one counter update per wavefront and class).
+__device__ __forceinline__ void append_by_class(int cls, const PairGeom& g, int2 dst, WorkList far,
+                                                WorkList split, WorkList direct) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -261,10 +168,45 @@ __global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, C
       const unsigned slot = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
       if (slot < wl.cap) {
         wl.geom[slot] = g;
-        wl.dest[slot] = make_int2((int)q, -1);
+        wl.dest[slot] = dst;
       }
     }
   }
+}
+
+// Classification only (the surrogate path): every (target i, source l) pair
+// off the near panels goes to the far / split / direct work list of its class
+// with destination (i, l); one thread per pair.
+__global__ __launch_bounds__(256) void k_grid_classify(NodesDev nd, ClassParams cp, WorkList far,
+                                                       WorkList split, WorkList direct) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = nd.N;
+  int cls = -1, i = 0, l = 0;
+  PairGeom g;
+  if (p < (long)N * N) {
+    l = (int)(p % N);
+    i = (int)(p / N);
+    const int dp = nd.panel[i] - nd.panel[l];
+    if (dp < -1 || dp > 1) {  // near panels: product integration
+      g = node_pair(nd, i, l);
+      cls = classify(g, pair_invariants(g), cp);
+    }
+  }
+  append_by_class(cls, g, make_int2(i, l), far, split, direct);
+}
+
+// Classification of an explicit pair list into far / split / direct work
+// lists (destination = raw row q).
+__global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, ClassParams cp,
+                                WorkList far, WorkList split, WorkList direct) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int cls = -1;
+  PairGeom g;
+  if (q < count) {
+    g = geom[q];
+    cls = classify(g, pair_invariants(g), cp);
+  }
+  append_by_class(cls, g, make_int2((int)q, -1), far, split, direct);
 }
 
 // Explicit list of far pairs (right-hand sides, field points).
@@ -383,6 +325,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     __syncthreads();
     // products for both wavenumbers: medium 1 into E, medium 2 over Zs, Ds
+#pragma unroll 1
     for (int j = b; j <= L / 2; j += 64) {
       const double sh = sin(PMLBIE_PI * j / L);
       const zd Rd = csqrt_(v.d2 + (sh * sh) * v.c4);
@@ -682,6 +625,13 @@ void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, z
     case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, st); break;
     default: break;
   }
+}
+
+void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,
+                          WorkList direct, hipStream_t st) {
+  const long total = (long)nd.N * nd.N;
+  hipLaunchKernelGGL(k_grid_classify, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, nd, cp, far,
+                     split, direct);
 }
 
 template <int R>

@@ -120,6 +120,70 @@ class Solver:
         self._chk(self.L.pmlbie_get_operator(self.h, int(mode), ctypes.c_void_p(out.data_ptr())))
         return out  # row-major storage
 
+    # -- learned surrogate of the far-pair modes ---------------------------
+    def surrogate_nparams(self) -> int:
+        return int(self.L.pmlbie_surrogate_nparams())
+
+    def surrogate_init(self, seed: int):
+        self._chk(self.L.pmlbie_surrogate_init(self.h, int(seed)))
+
+    def surrogate_make_samples(self, which: int, n: int, seed: int):
+        self._chk(self.L.pmlbie_surrogate_make_samples(self.h, int(which), int(n), int(seed)))
+
+    def surrogate_train(self, steps: int, batch: int, lr: float) -> np.ndarray:
+        loss = np.zeros(max(int(steps), 1))
+        self._chk(self.L.pmlbie_surrogate_train(self.h, int(steps), int(batch), float(lr), _p(loss)))
+        return loss[:int(steps)]
+
+    def surrogate_eval(self, which: int) -> float:
+        m = np.zeros(1)
+        self._chk(self.L.pmlbie_surrogate_eval(self.h, int(which), _p(m)))
+        return float(m[0])
+
+    def surrogate_set_tolerance(self, tol: float):
+        self._chk(self.L.pmlbie_surrogate_set_tolerance(self.h, float(tol)))
+
+    def surrogate_save(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        self._chk(self.L.pmlbie_surrogate_save(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._chk(self.L.pmlbie_surrogate_save(self.h, buf, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def surrogate_load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._chk(self.L.pmlbie_surrogate_load(self.h, buf, len(blob)))
+
+    def surrogate_params(self, p: np.ndarray = None) -> np.ndarray:
+        """Get the FP32 parameters (as float64), or set them when p is given."""
+        if p is None:
+            out = np.zeros(self.surrogate_nparams())
+            self._chk(self.L.pmlbie_surrogate_params(self.h, _p(out), 1))
+            return out
+        q = np.ascontiguousarray(p, dtype=np.float64)
+        self._chk(self.L.pmlbie_surrogate_params(self.h, _p(q), 0))
+        return q
+
+    def surrogate_forward(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros((x.shape[0], 390))
+        self._chk(self.L.pmlbie_surrogate_forward(self.h, x.shape[0], _p(x), _p(y)))
+        return y
+
+    def surrogate_grad(self, x: np.ndarray, t: np.ndarray):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        g = np.zeros(self.surrogate_nparams())
+        loss = np.zeros(1)
+        self._chk(self.L.pmlbie_surrogate_grad(self.h, x.shape[0], _p(x), _p(t), _p(loss), _p(g)))
+        return float(loss[0]), g
+
+    def surrogate_label(self, s: np.ndarray) -> np.ndarray:
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        y = np.zeros((s.shape[0], 390))
+        self._chk(self.L.pmlbie_surrogate_label(self.h, s.shape[0], _p(s), _p(y)))
+        return y
+
     def stats(self):
         s = np.zeros(16)
         c = np.zeros(16)
