@@ -42,6 +42,52 @@ def gemm_traffic_record():
     return None
 
 
+def surrogate_leg(s, wl, step, m_max: int = 64, tol: float = 1e-11):
+    """The learned surrogate on this geometry: training on 2^22 labelled
+    samples (timed apart, it is amortised over builds), then the step at
+    m_max = 64 (the modes the network covers) with and without it; the
+    surrogate step's error is measured against the plain FP64 step."""
+    import torch
+    from paper_2412_11162_amd import _binding as B
+
+    t0 = time.time()
+    s.surrogate_init(2412)
+    s.surrogate_make_samples(0, 1 << 22, 2412_11162)
+    s.surrogate_make_samples(1, 1 << 18, 2412_11163)
+    t_samples = time.time() - t0
+    t0 = time.time()
+    loss = s.surrogate_train(4096, 1024, 1e-3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    mse = s.surrogate_eval(1)
+
+    def run(flags):
+        s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
+        s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
+        t = time.time()
+        s.build_modal_operators(wl.n_theta, m_max, 0, flags)
+        sol = s.solve_modes(list(wl.incidences))
+        torch.cuda.synchronize()
+        return time.time() - t, [o.cpu().numpy() for o in sol], s.stats()
+
+    s.surrogate_set_tolerance(tol)
+    run(0)
+    t_plain, ref, _ = run(0)
+    t_sg, got, (st, cnt) = run(B.PMLBIE_USE_SURROGATE)
+    xg = np.concatenate(got, axis=2)[:, 0]
+    xr = np.concatenate(ref, axis=2)[:, 0]
+    big = np.max(np.linalg.norm(xr, axis=1))
+    err = max(float(np.linalg.norm(xg[j] - xr[j]) / max(np.linalg.norm(xr[j]), 1e-9 * big))
+              for j in range(xr.shape[0]))
+    return {"samples": {"train": 1 << 22, "held_out": 1 << 18, "seconds": t_samples},
+            "training": {"steps": 4096, "batch": 1024, "seconds": t_train, "loss_first": float(loss[:64].mean()),
+                         "loss_last": float(loss[-64:].mean()), "held_out_mse": mse},
+            "m_max": m_max, "tolerance": tol, "far_pairs": int(cnt[4]), "accepted": int(cnt[5]),
+            "acceptance": float(cnt[5]) / max(float(cnt[4]), 1.0),
+            "ms_plain": 1e3 * t_plain, "ms_surrogate": 1e3 * t_sg, "speedup": t_plain / t_sg,
+            "far_stage_ms": float(st[1]), "max_rel_err_vs_fp64": err}
+
+
 def cpu_baseline(wl, seconds: float = 15.0):
     """The FP64 oracle's modal-kernel stage timed on this host on a bounded
     sample of (target, source) node pairs of the same workload."""
@@ -73,6 +119,8 @@ def main():
     ap.add_argument("--workload", default="paper_scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-surrogate leg (training + builds at m_max = 64)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (calibrates "
                          "the HBM byte counters) and exit")
@@ -200,6 +248,8 @@ def main():
             "stage_ms": {"lu": stm[5], "lu_trailing_update": stm[6], "solve": stm[7], "refinement": stm[9]},
             "lu_trailing_update_tflops": float(cnt[2]) / (stm[6] * 1e-3) / 1e12 if stm[6] > 0 else None,
         }
+    if not args.no_surrogate and wl.name == "paper_scale":
+        out["surrogate"] = surrogate_leg(s, wl, step)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))
