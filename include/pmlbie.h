@@ -107,6 +107,17 @@ int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_
 int pmlbie_build_modal_operators(pmlbie_ctx* ctx, int n_theta, int m_max, int precision,
                                  int flags);
 
+/* The same for the modes m_min..m_max only (0 <= m_min <= m_max), for mode
+ * batches when the operators of all modes do not fit in device memory
+ * (Sec. 4.2: the modes are independent systems).  Every pair is sampled and
+ * transformed as in the full build (the FFT yields all modes at once); only
+ * the kept modes are assembled and factored.  solve_modes then returns the
+ * boundary data of modes m_min..m_max ([mode - m_min][rhs][node]),
+ * evaluate_field sums those modes only, get_operator takes modes in the
+ * range.  The surrogate needs m_min = 0. */
+int pmlbie_build_modal_operators_range(pmlbie_ctx* ctx, int n_theta, int m_min, int m_max,
+                                       int precision, int flags);
+
 /* One incidence: kind 0 = point source at (rho, 0, z) = (p[0], p[1]) in the
  * upper medium (p[0] >= 0); kind 1 = plane wave with polar angle p[0]
  * (theta_inc = 0) (Sec. 2). */

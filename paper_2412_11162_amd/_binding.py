@@ -23,7 +23,8 @@ PMLBIE_USE_SURROGATE = 2
 
 EXPORTS = (
     "pmlbie_create", "pmlbie_destroy", "pmlbie_last_error", "pmlbie_set_geometry",
-    "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_solve_modes",
+    "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_build_modal_operators_range",
+    "pmlbie_solve_modes",
     "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
     "pmlbie_get_operator", "pmlbie_get_stats",
     "pmlbie_surrogate_nparams", "pmlbie_surrogate_init", "pmlbie_surrogate_make_samples",
@@ -58,6 +59,7 @@ def load():
     L.pmlbie_set_geometry.argtypes = [P, i, P, d, d, P, i]
     L.pmlbie_set_media_pml.argtypes = [P, d, d, d, d, d, d, d, d, d, d, i]
     L.pmlbie_build_modal_operators.argtypes = [P, i, i, i, i]
+    L.pmlbie_build_modal_operators_range.argtypes = [P, i, i, i, i, i]
     L.pmlbie_solve_modes.argtypes = [P, i, ctypes.POINTER(pmlbie_incidence), P, P, P, P]
     L.pmlbie_evaluate_field.argtypes = [P, i, P, P]
     L.pmlbie_get_info.argtypes = [P, P]

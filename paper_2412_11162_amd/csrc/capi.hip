@@ -65,7 +65,7 @@ struct pmlbie_ctx {
   zd k1{0, 0}, k2{0, 0};
   double a2 = 0, T2 = 0, S2 = 0;
   // build parameters
-  int n_theta = 0, M = 0, nt_int = 0, nt_far = 0, B = 0, MQ = 0, precision = 0, flags = 0;
+  int n_theta = 0, M = 0, m0 = 0, nt_int = 0, nt_far = 0, B = 0, MQ = 0, precision = 0, flags = 0;
   int N = 0;
   ClassParams cp{};
   long long cnt_far = 0, cnt_split = 0, cnt_direct = 0, cnt_aux = 0;
@@ -175,7 +175,7 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
     c->qscr.alloc((size_t)CH * (c->MQ + 1));
     launch_split_singular(geom, f, cn, c->MQ, c->zhat.p, c->phat.p, c->qscr.p, c->stream);
     HIPCHK(hipGetLastError());
-    launch_split(c->nt_int, geom, dest, f, cn, c->M, c->MQ, c->k1, c->k2, c->tw_int.p, c->zhat.p,
+    launch_split(c->nt_int, geom, dest, f, cn, c->M, c->m0, c->MQ, c->k1, c->k2, c->tw_int.p, c->zhat.p,
                  c->phat.p, A, n2, ms, W, raw, c->stream);
     HIPCHK(hipGetLastError());
   }
@@ -208,8 +208,8 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
   HIPCHK(hipMemcpy(h, c->sgcnt.p, sizeof(h), hipMemcpyDeviceToHost));
   c->counters[4] = (double)count;
   c->counters[5] = (double)h[0];
-  launch_list_far(c->nt_far, c->sgfb_geom.p, c->sgfb_dest.p, 0, h[1], c->M, c->k1, c->k2, c->tw_far.p, c->A.p,
-                  n2, ms, W, nullptr, c->stream);
+  launch_list_far(c->nt_far, c->sgfb_geom.p, c->sgfb_dest.p, 0, h[1], c->M, 0, c->k1, c->k2, c->tw_far.p,
+                  c->A.p, n2, ms, W, nullptr, c->stream);
   HIPCHK(hipGetLastError());
 }
 
@@ -236,11 +236,11 @@ void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long 
     counts[1] += cnt[1];
     counts[2] += cnt[2];
   }
-  launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, c->k1, c->k2, c->tw_far.p, nullptr, 0,
+  launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, 0, c->k1, c->k2, c->tw_far.p, nullptr, 0,
                   0, nullptr, raw, c->stream);
   HIPCHK(hipGetLastError());
   run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw);
-  launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
+  launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
                 nullptr, raw, kOmegaPiece, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -340,19 +340,25 @@ int pmlbie_set_media_pml(pmlbie_ctx* c, double k1_re, double k1_im, double k2_re
 }
 
 int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int precision, int flags) {
+  return pmlbie_build_modal_operators_range(c, n_theta, 0, m_max, precision, flags);
+}
+
+int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, int m_max, int precision,
+                                       int flags) {
   return guarded(c, [&]() -> int {
     if (c->stage < 2) return fail(c, PMLBIE_ESTATE, "build: set geometry and media first");
     if (n_theta < 16 || (n_theta & (n_theta - 1)))
       return fail(c, PMLBIE_EINVAL, "build: n_theta must be a power of two >= 16");
     if (m_max < 0 || m_max > n_theta / 2)
       return fail(c, PMLBIE_EINVAL, "build: need 0 <= m_max <= n_theta / 2");
+    if (m_min < 0 || m_min > m_max) return fail(c, PMLBIE_EINVAL, "build: need 0 <= m_min <= m_max");
     if (precision != PMLBIE_FP64 && precision != PMLBIE_MIXED)
       return fail(c, PMLBIE_EINVAL, "build: precision must be PMLBIE_FP64 or PMLBIE_MIXED");
     const bool use_sg = (flags & PMLBIE_USE_SURROGATE) != 0;
     if (use_sg) {
       if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "build: no surrogate network (init, train or load one)");
-      if (m_max > SG_MODES - 1)
-        return fail(c, PMLBIE_EINVAL, "build: the surrogate covers modes 0..64 only");
+      if (m_max > SG_MODES - 1 || m_min != 0)
+        return fail(c, PMLBIE_EINVAL, "build: the surrogate covers modes 0..64 only (from mode 0)");
       if (c->k1.im != 0.0 || c->k2.im != 0.0)
         return fail(c, PMLBIE_EINVAL, "build: the surrogate takes real wavenumbers");
       if (fabs(c->geo.pml.a1 - c->sg_a1) > 1e-12 || fabs(c->geo.pml.T - c->sg_T) > 1e-12 ||
@@ -363,9 +369,10 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     c->stage = 2;
     c->n_theta = n_theta;
     c->M = m_max;
+    c->m0 = m_min;
     c->precision = precision;
     c->flags = flags;
-    const int N = c->N, M = c->M;
+    const int N = c->N, M = c->M, m0 = c->m0, nm = M - m0 + 1;
     const long n2 = 2L * N;
     const long ms = n2 * n2;
     // Angle grid L (one length for every FFT path): the smooth parts of the
@@ -419,11 +426,11 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     HIPCHK(hipMemcpyAsync(c->glx.p, c->geo.glx, 16 * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->glw.p, c->geo.glw, 16 * 8, hipMemcpyHostToDevice, c->stream));
     // operators
-    c->A.alloc((size_t)(M + 1) * ms);
-    c->ipiv.alloc((size_t)(M + 1) * n2);
-    c->luw.alloc((size_t)(M + 1) * LU_NB * LU_NB);
-    c->info.alloc(M + 1);
-    HIPCHK(hipMemsetAsync(c->info.p, 0, (M + 1) * sizeof(int), c->stream));
+    c->A.alloc((size_t)nm * ms);
+    c->ipiv.alloc((size_t)nm * n2);
+    c->luw.alloc((size_t)nm * LU_NB * LU_NB);
+    c->info.alloc(nm);
+    HIPCHK(hipMemsetAsync(c->info.p, 0, nm * sizeof(int), c->stream));
     // work lists of the grid (split, direct and far share one allocation)
     const size_t cap = (size_t)N * N;
     c->lgeom.alloc(3 * cap);
@@ -463,7 +470,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     if (use_sg)
       launch_grid_classify(nd, c->cp, wf, ws, wd, c->stream);
     else
-      launch_grid_far(c->nt_far, nd, c->cp, c->k1, c->k2, c->tw_far.p, c->A.p, ms, nd.W, ws, wd, c->stream);
+      launch_grid_far(c->nt_far, nd, c->cp, c->k1, c->k2, c->tw_far.p, c->A.p, ms, m0, nd.W, ws, wd, c->stream);
     HIPCHK(hipGetLastError());
     unsigned counts[3] = {0, 0, 0};
     HIPCHK(hipMemcpy(counts, c->lcount.p, 3 * sizeof(unsigned), hipMemcpyDeviceToHost));
@@ -481,7 +488,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     run_split(c, c->lgeom.p, c->ldest.p, counts[0], c->A.p, n2, ms, nd.W, nullptr);
     c->stage_ms[2] = t_split.stop();
     Timer t_direct(c->stream);
-    launch_direct(c->lgeom.p + cap, c->ldest.p + cap, 0, counts[1], M, c->k1, c->k2, c->glx.p,
+    launch_direct(c->lgeom.p + cap, c->ldest.p + cap, 0, counts[1], M, m0, c->k1, c->k2, c->glx.p,
                   c->glw.p, c->A.p, n2, ms, nd.W, nullptr, kOmegaPiece, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[3] = t_direct.stop();
@@ -491,7 +498,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     c->raw.alloc(std::max<size_t>(ageom.size(), 1) * 4 * (M + 1));
     long long dummy[3] = {0, 0, 0};
     run_pair_list(c, ageom, c->raw.p, dummy);
-    launch_near(c->jobs.p, (int)ajobs.size(), c->coef.p, c->raw.p, M, c->A.p, n2, ms, c->stream);
+    launch_near(c->jobs.p, (int)ajobs.size(), c->coef.p, c->raw.p, M, m0, c->A.p, n2, ms, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[4] = t_near.stop();
     // the near-panel pairs of the grid were not counted as far
@@ -505,14 +512,14 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       c->Alow.release();
     } else {
       c->A32.release();
-      c->Alow.alloc((size_t)(M + 1) * N * n2);
-      for (int n = 0; n <= M; ++n)
+      c->Alow.alloc((size_t)nm * N * n2);
+      for (int n = 0; n < nm; ++n)
         HIPCHK(hipMemcpyAsync(c->Alow.p + (size_t)n * N * n2, c->A.p + (size_t)n * ms + (size_t)N * n2,
                               (size_t)N * n2 * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
     }
     if ((flags & PMLBIE_KEEP_OPERATORS) && !mixed) {
-      c->Akeep.alloc((size_t)(M + 1) * ms);
-      HIPCHK(hipMemcpyAsync(c->Akeep.p, c->A.p, (size_t)(M + 1) * ms * sizeof(zd),
+      c->Akeep.alloc((size_t)nm * ms);
+      HIPCHK(hipMemcpyAsync(c->Akeep.p, c->A.p, (size_t)nm * ms * sizeof(zd),
                             hipMemcpyDeviceToDevice, c->stream));
     } else {
       c->Akeep.release();
@@ -530,13 +537,13 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     tm.gemm_begin = gb.data();
     tm.gemm_end = ge.data();
     if (mixed) {
-      c->A32.alloc((size_t)(M + 1) * ms);
-      launch_to_c64(c->A.p, c->A32.p, (long)(M + 1) * ms, c->stream);
+      c->A32.alloc((size_t)nm * ms);
+      launch_to_c64(c->A.p, c->A32.p, (long)nm * ms, c->stream);
       HIPCHK(hipGetLastError());
-      lu_factor_batched<float>(c->A32.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p,
+      lu_factor_batched<float>(c->A32.p, ms, (int)n2, nm, c->ipiv.p, c->info.p,
                                reinterpret_cast<zf*>(c->luw.p), c->stream, &tm);
     } else {
-      lu_factor_batched<double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->info.p, c->luw.p,
+      lu_factor_batched<double>(c->A.p, ms, (int)n2, nm, c->ipiv.p, c->info.p, c->luw.p,
                                 c->stream, &tm);
     }
     HIPCHK(hipGetLastError());
@@ -547,7 +554,7 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
     for (int p = 0; p < npan; ++p) {
       const double nbp = std::min<long>(LU_NB, n2 - (long)p * LU_NB);
       const double mr = (double)n2 - (double)p * LU_NB - nbp;
-      gflop += 8.0 * mr * mr * nbp * (M + 1);
+      gflop += 8.0 * mr * mr * nbp * nm;
     }
     c->counters[2] = gflop;
     c->counters[3] = (double)(npan - 1);
@@ -562,12 +569,12 @@ int pmlbie_build_modal_operators(pmlbie_ctx* c, int n_theta, int m_max, int prec
       (void)hipEventDestroy(ge[k]);
     }
     c->stage_ms[6] = gsum;
-    std::vector<int> info(M + 1);
-    HIPCHK(hipMemcpy(info.data(), c->info.p, (M + 1) * sizeof(int), hipMemcpyDeviceToHost));
-    for (int n = 0; n <= M; ++n)
+    std::vector<int> info(nm);
+    HIPCHK(hipMemcpy(info.data(), c->info.p, nm * sizeof(int), hipMemcpyDeviceToHost));
+    for (int n = 0; n < nm; ++n)
       if (info[n])
         return fail(c, PMLBIE_ESINGULAR,
-                    "build: mode " + std::to_string(n) + " has a zero pivot at column " + std::to_string(info[n] - 1));
+                    "build: mode " + std::to_string(m0 + n) + " has a zero pivot at column " + std::to_string(info[n] - 1));
     c->stage_ms[10] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_all).count();
     c->stage = 3;
     return PMLBIE_OK;
@@ -595,7 +602,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       }
     }
     auto t0 = std::chrono::steady_clock::now();
-    const int N = c->N, M = c->M;
+    const int N = c->N, M = c->M, m0 = c->m0, nm = M - m0 + 1;
     const long n2 = 2L * N, ms = n2 * n2;
     c->nrhs = n_rhs;
     Timer t_rhs(c->stream);
@@ -641,7 +648,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
         g.push_back(p);
       }
     }
-    const size_t vec = (size_t)(M + 1) * n_rhs * N;
+    const size_t vec = (size_t)nm * n_rhs * N;
     c->b1.alloc(vec);
     c->b2.alloc(vec);
     c->x.alloc(2 * vec);
@@ -650,7 +657,8 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       run_pair_list(c, g, c->raw.p, nullptr);
       c->rmap.alloc(rmap.size());
       HIPCHK(hipMemcpyAsync(c->rmap.p, rmap.data(), rmap.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-      launch_rhs_gather_point(c->raw.p, c->rmap.p, (int)rmap.size(), N, M, n_rhs, c->b1.p, c->b2.p, c->stream);
+      launch_rhs_gather_point(c->raw.p, c->rmap.p, (int)rmap.size(), N, M, m0, n_rhs, c->b1.p, c->b2.p,
+                              c->stream);
       HIPCHK(hipGetLastError());
     }
     if (!pws.empty()) {
@@ -665,15 +673,15 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       c->dpw.alloc(pws.size());
       HIPCHK(hipMemcpyAsync(c->dpw.p, pws.data(), pws.size() * sizeof(PlaneWave), hipMemcpyHostToDevice, c->stream));
       launch_rhs_plane(ntp, c->nodes.p, c->nodes.p + 2L * N, c->nodes.p + 8L * N, c->nodes.p + 9L * N, N,
-                       c->dpw.p, (int)pws.size(), c->tw_pw.p, M, n_rhs, c->b1.p, c->b2.p, c->stream);
+                       c->dpw.p, (int)pws.size(), c->tw_pw.p, M, m0, n_rhs, c->b1.p, c->b2.p, c->stream);
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(c->stream));
     }
     const bool mixed = c->precision == PMLBIE_MIXED;
     if (mixed)
-      launch_lower_rhs(c->A.p + (size_t)N * n2, ms, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+      launch_lower_rhs(c->A.p + (size_t)N * n2, ms, N, nm, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
     else
-      launch_lower_rhs(c->Alow.p, (long)N * n2, N, M + 1, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+      launch_lower_rhs(c->Alow.p, (long)N * n2, N, nm, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[8] = t_rhs.stop();
     Timer t_sol(c->stream);
@@ -681,13 +689,13 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     c->counters[0] = 0;
     c->counters[1] = 0;
     if (!mixed) {
-      lu_solve_batched<double, double>(c->A.p, ms, (int)n2, M + 1, c->ipiv.p, c->x.p, n_rhs, c->stream);
+      lu_solve_batched<double, double>(c->A.p, ms, (int)n2, nm, c->ipiv.p, c->x.p, n_rhs, c->stream);
       HIPCHK(hipGetLastError());
     } else {
       // FP64 iterative refinement with the complex64 factors:
       //   d = LU32 \ r (FP64 arithmetic), x += d, r = rhs - A64 x,
       // until ||r|| <= tol ||rhs|| for every mode and right-hand side.
-      const long nv = (long)(M + 1) * n_rhs;
+      const long nv = (long)nm * n_rhs;
       const long len = nv * n2;
       c->rbuf.alloc(len);
       c->xs.alloc(len);
@@ -704,9 +712,9 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       int it = 0;
       double worst = 0.0;
       for (; it < maxit; ++it) {
-        lu_solve_batched<float, double>(c->A32.p, ms, (int)n2, M + 1, c->ipiv.p, c->rbuf.p, n_rhs, c->stream);
+        lu_solve_batched<float, double>(c->A32.p, ms, (int)n2, nm, c->ipiv.p, c->rbuf.p, n_rhs, c->stream);
         launch_axpy(c->xs.p, c->rbuf.p, len, c->stream);
-        launch_residual(c->A.p, ms, (int)n2, M + 1, n_rhs, c->xs.p, c->x.p, c->rbuf.p, c->rsq.p, c->stream);
+        launch_residual(c->A.p, ms, (int)n2, nm, n_rhs, c->xs.p, c->x.p, c->rbuf.p, c->rsq.p, c->stream);
         launch_sumsq(c->rsq.p, (int)n2, (int)nv, c->rnorm.p, c->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpy(hn.data(), c->rnorm.p, 2 * nv * sizeof(double), hipMemcpyDeviceToHost));
@@ -733,7 +741,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     c->p1.alloc(vec);
     c->u2.alloc(vec);
     c->p2.alloc(vec);
-    launch_outputs(c->x.p, c->b1.p, c->b2.p, N, M, n_rhs, c->u1.p, c->p1.p, c->u2.p, c->p2.p, c->stream);
+    launch_outputs(c->x.p, c->b1.p, c->b2.p, N, nm - 1, n_rhs, c->u1.p, c->p1.p, c->u2.p, c->p2.p, c->stream);
     HIPCHK(hipGetLastError());
     const size_t bytes = vec * sizeof(zd);
     if (d_u1) HIPCHK(hipMemcpyAsync(d_u1, c->u1.p, bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -784,8 +792,8 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
     dout.alloc((size_t)n_pts * c->nrhs);
     HIPCHK(hipMemcpyAsync(dmed.p, med.data(), n_pts * sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(dth.p, th.data(), n_pts * 8, hipMemcpyHostToDevice, c->stream));
-    launch_field(c->raw.p, c->nodes.p + 3L * N, N, M, c->nrhs, n_pts, dmed.p, dth.p, c->u1.p, c->p1.p,
-                 c->u2.p, c->p2.p, dout.p, c->stream);
+    launch_field(c->raw.p, c->nodes.p + 3L * N, N, M, c->m0, c->nrhs, n_pts, dmed.p, dth.p, c->u1.p,
+                 c->p1.p, c->u2.p, c->p2.p, dout.p, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, dout.p, (size_t)n_pts * c->nrhs * sizeof(zd), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -846,9 +854,10 @@ int pmlbie_get_operator(pmlbie_ctx* c, int mode, void* d_out) {
     // in mixed precision the FP64 operator is kept unfactored anyway
     const zd* src = c->precision == PMLBIE_MIXED ? c->A.p : c->Akeep.p;
     if (!src) return fail(c, PMLBIE_ESTATE, "get_operator: build with PMLBIE_KEEP_OPERATORS");
-    if (mode < 0 || mode > c->M || !d_out) return fail(c, PMLBIE_EINVAL, "get_operator: bad mode");
+    if (mode < c->m0 || mode > c->M || !d_out) return fail(c, PMLBIE_EINVAL, "get_operator: mode outside the build");
     const size_t ms = (size_t)4 * c->N * c->N;
-    HIPCHK(hipMemcpyAsync(d_out, src + (size_t)mode * ms, ms * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(d_out, src + (size_t)(mode - c->m0) * ms, ms * sizeof(zd), hipMemcpyDeviceToDevice,
+                          c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;
   });

@@ -55,29 +55,30 @@ struct NearJob {
 // The main grid over all node pairs off the near panels: far pairs are
 // transformed in place, split and direct pairs appended to their lists.
 void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
-                     const zd* tw, zd* A, long mstride, const double* W, WorkList split,
+                     const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
                      WorkList direct, hipStream_t st);
 // Classification only (surrogate path): far / split / direct lists with
 // destinations (i, l).
 void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,
                           WorkList direct, hipStream_t st);
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
-                     zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
-                     zd* raw, hipStream_t st);
+                     int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride,
+                     const double* W, zd* raw, hipStream_t st);
 void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
                           WorkList split, WorkList direct, hipStream_t st);
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
                            zd* phat, zd* qscr, hipStream_t st);
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
-                  int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat, zd* A,
-                  long n2, long mstride, const double* W, zd* raw, hipStream_t st);
-void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, zd k1,
-                   zd k2, const double* glx, const double* glw, zd* A, long n2, long mstride,
-                   const double* W, zd* raw, double omega_piece, hipStream_t st);
+                  int m0, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
+                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st);
+void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, int m0,
+                   zd k1, zd k2, const double* glx, const double* glw, zd* A, long n2,
+                   long mstride, const double* W, zd* raw, double omega_piece, hipStream_t st);
+// Plane-wave right-hand sides of modes m0..M (b[(n - m0) * nrhs + r][node]).
 void launch_rhs_plane(int nt, const double* rho, const double* z, const double* nur,
                       const double* nuz, int N, const PlaneWave* pw, int npw, const zd* tw, int M,
-                      int nrhs, zd* b1, zd* b2, hipStream_t st);
-void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, zd* A,
-                 long n2, long mstride, hipStream_t st);
+                      int m0, int nrhs, zd* b1, zd* b2, hipStream_t st);
+void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, int m0,
+                 zd* A, long n2, long mstride, hipStream_t st);
 
 }  // namespace pmlbie

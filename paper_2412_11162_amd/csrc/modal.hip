@@ -18,12 +18,13 @@ namespace pmlbie {
 __device__ __forceinline__ void emit_val(const OutSpec& o, int2 dst, int s, int n, double scale,
                                          zd val) {
   if (dst.y >= 0) {
+    if (n < o.m0) return;
     const long i = dst.x, l = dst.y, N = o.n2 >> 1;
     const double w2 = 2.0 * o.W[l] * scale;
     // S blocks carry the minus sign of [[K1 + I, -S1], [K2 - I, -S2]]
     const double f = (s & 1) ? w2 : -w2;
     const long row = (s < 2 ? i : N + i), col = ((s & 1) ? l : N + l);
-    o.A[(long)n * o.mstride + row * o.n2 + col] = f * val;
+    o.A[(long)(n - o.m0) * o.mstride + row * o.n2 + col] = f * val;
   } else {
     o.raw[(long)dst.x * 4 * (o.M + 1) + (long)s * (o.M + 1) + n] = scale * val;
   }
@@ -534,10 +535,11 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
 #pragma unroll
       for (int l = 0; l < 16; ++l) acc[l] = acc[l] + c[l] * r;
     }
+    if (n < o.m0) continue;
     const long i = J.target;
     const long row = sq < 2 ? i : N + i;
     const long col0 = (sq & 1) ? 0 : N;
-    zd* dst = o.A + (long)n * o.mstride + row * o.n2 + col0 + (long)J.panel * 16;
+    zd* dst = o.A + (long)(n - o.m0) * o.mstride + row * o.n2 + col0 + (long)J.panel * 16;
     // K blocks carry the identity term, S blocks the minus sign
     const double diag = sq == 1 ? 1.0 : (sq == 3 ? -1.0 : 0.0);
 #pragma unroll
@@ -564,7 +566,7 @@ __global__ __launch_bounds__(64) void k_rhs_plane(const double* __restrict__ rho
                                                   const double* __restrict__ nur,
                                                   const double* __restrict__ nuz, int N,
                                                   const PlaneWave* __restrict__ pw, int npw,
-                                                  const zd* __restrict__ tw, int M, int nrhs,
+                                                  const zd* __restrict__ tw, int M, int m0, int nrhs,
                                                   zd* __restrict__ b1, zd* __restrict__ b2) {
   __shared__ zd buf[2 * NT];
   const double scale = 2.0 * PMLBIE_PI / NT;
@@ -596,8 +598,8 @@ __global__ __launch_bounds__(64) void k_rhs_plane(const double* __restrict__ rho
     }
     __syncthreads();
     fft_lds<NT, 2>(buf, tw);
-    for (int n = threadIdx.x; n <= M; n += 64) {
-      const long e = ((long)n * nrhs + P.rhs) * N + i;
+    for (int n = m0 + threadIdx.x; n <= M; n += 64) {
+      const long e = ((long)(n - m0) * nrhs + P.rhs) * N + i;
       b1[e] = (-scale) * buf[n];
       b2[e] = (-scale) * buf[NT + n];
     }
@@ -617,9 +619,9 @@ static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2
 }
 
 void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
-                     const zd* tw, zd* A, long mstride, const double* W, WorkList split,
+                     const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
                      WorkList direct, hipStream_t st) {
-  OutSpec o{A, 2L * nd.N, mstride, W, nullptr, cp.M};
+  OutSpec o{A, 2L * nd.N, mstride, W, nullptr, cp.M, m0};
   switch (nt) {
     case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, st); break;
     case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, st); break;
@@ -643,10 +645,10 @@ static void launch_list_far_t(const PairGeom* geom, const int2* dest, long first
 }
 
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
-                     zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
-                     zd* raw, hipStream_t st) {
+                     int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride,
+                     const double* W, zd* raw, hipStream_t st) {
   if (count <= 0) return;
-  OutSpec o{A, n2, mstride, W, raw, M};
+  OutSpec o{A, n2, mstride, W, raw, M, m0};
   switch (nt) {
     case 512: launch_list_far_t<8>(geom, dest, first, count, k1, k2, tw, o, st); break;
     case 1024: launch_list_far_t<16>(geom, dest, first, count, k1, k2, tw, o, st); break;
@@ -679,10 +681,10 @@ static void launch_split_t(const PairGeom* geom, const int2* dest, long first, l
 }
 
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
-                  int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat, zd* A,
-                  long n2, long mstride, const double* W, zd* raw, hipStream_t st) {
+                  int m0, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
+                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st) {
   if (count <= 0) return;
-  OutSpec o{A, n2, mstride, W, raw, M};
+  OutSpec o{A, n2, mstride, W, raw, M, m0};
   switch (nt) {
     case 512: launch_split_t<8>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
     case 1024: launch_split_t<16>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
@@ -690,11 +692,11 @@ void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, lo
   }
 }
 
-void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, zd k1,
-                   zd k2, const double* glx, const double* glw, zd* A, long n2, long mstride,
-                   const double* W, zd* raw, double omega_piece, hipStream_t st) {
+void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, int m0,
+                   zd k1, zd k2, const double* glx, const double* glw, zd* A, long n2,
+                   long mstride, const double* W, zd* raw, double omega_piece, hipStream_t st) {
   if (count <= 0) return;
-  OutSpec o{A, n2, mstride, W, raw, M};
+  OutSpec o{A, n2, mstride, W, raw, M, m0};
   int grid = (int)std::min<long>(count, 256L * 24);
   hipLaunchKernelGGL(k_direct, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, k1, k2,
                      glx, glw, o, omega_piece);
@@ -702,22 +704,22 @@ void launch_direct(const PairGeom* geom, const int2* dest, long first, long coun
 
 void launch_rhs_plane(int nt, const double* rho, const double* z, const double* nur,
                       const double* nuz, int N, const PlaneWave* pw, int npw, const zd* tw, int M,
-                      int nrhs, zd* b1, zd* b2, hipStream_t st) {
+                      int m0, int nrhs, zd* b1, zd* b2, hipStream_t st) {
   if (npw <= 0) return;
   const int grid = std::min(N * npw, 256 * 32);
   switch (nt) {
-    case 256: hipLaunchKernelGGL(k_rhs_plane<256>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
-    case 512: hipLaunchKernelGGL(k_rhs_plane<512>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
-    case 1024: hipLaunchKernelGGL(k_rhs_plane<1024>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
-    case 2048: hipLaunchKernelGGL(k_rhs_plane<2048>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, nrhs, b1, b2); break;
+    case 256: hipLaunchKernelGGL(k_rhs_plane<256>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, m0, nrhs, b1, b2); break;
+    case 512: hipLaunchKernelGGL(k_rhs_plane<512>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, m0, nrhs, b1, b2); break;
+    case 1024: hipLaunchKernelGGL(k_rhs_plane<1024>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, m0, nrhs, b1, b2); break;
+    case 2048: hipLaunchKernelGGL(k_rhs_plane<2048>, dim3(grid), dim3(64), 0, st, rho, z, nur, nuz, N, pw, npw, tw, M, m0, nrhs, b1, b2); break;
     default: break;
   }
 }
 
-void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, zd* A,
-                 long n2, long mstride, hipStream_t st) {
+void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, int m0,
+                 zd* A, long n2, long mstride, hipStream_t st) {
   if (njobs <= 0) return;
-  OutSpec o{A, n2, mstride, nullptr, nullptr, M};
+  OutSpec o{A, n2, mstride, nullptr, nullptr, M, m0};
   hipLaunchKernelGGL(k_near, dim3(njobs), dim3(256), 0, st, jobs, njobs, coef, raw, M, o);
 }
 

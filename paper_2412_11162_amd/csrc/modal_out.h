@@ -7,7 +7,7 @@ namespace pmlbie {
 
 // Output: either the per-mode system matrices or a raw modal buffer.
 //
-// System matrix of mode n, row-major 2N x 2N at A + n * mstride:
+// System matrix of mode n, row-major 2N x 2N at A + (n - m0) * mstride:
 //   [[K1 - D1, -S1], [K2 - D2, -S2]],  K_il = 2 W_l K_n(r_i, r_l),
 //   S_il = 2 W_l S_n(r_i, r_l) for l off the near panels of i.
 // Raw modal buffer: out[q][s][n], s in {S1, K1, S2, K2}.
@@ -17,15 +17,17 @@ struct OutSpec {
   long mstride;  // elements per mode matrix
   const double* W;
   zd* raw;
-  int M;
+  int M;         // highest mode formed
+  int m0;        // first mode kept in A (A + (n - m0) * mstride holds mode n)
 };
 
 __device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, zd K1, zd S2,
                                      zd K2) {
   if (dst.y >= 0) {
+    if (n < o.m0) return;
     const long i = dst.x, l = dst.y, N = o.n2 >> 1;
     const double w2 = 2.0 * o.W[l];
-    zd* An = o.A + (long)n * o.mstride;
+    zd* An = o.A + (long)(n - o.m0) * o.mstride;
     An[i * o.n2 + l] = w2 * K1;
     An[i * o.n2 + N + l] = (-w2) * S1;
     An[(N + i) * o.n2 + l] = w2 * K2;

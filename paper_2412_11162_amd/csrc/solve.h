@@ -6,8 +6,8 @@
 
 namespace pmlbie {
 
-void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int nrhs, zd* b1,
-                             zd* b2, hipStream_t st);
+void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int m0, int nrhs,
+                             zd* b1, zd* b2, hipStream_t st);
 void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st);
 void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,
@@ -18,8 +18,8 @@ void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd*
 void launch_sumsq(const double* sq, int n, int nvec, double* out, hipStream_t st);
 void launch_sq(const zd* v, long count, double* sq, hipStream_t st);
 void launch_axpy(zd* x, const zd* d, long count, hipStream_t st);
-void launch_field(const zd* raw, const double* W, int N, int M, int nrhs, int npts, const int* medium,
-                  const double* theta, const zd* u1, const zd* p1, const zd* u2, const zd* p2,
-                  zd* out, hipStream_t st);
+void launch_field(const zd* raw, const double* W, int N, int M, int m0, int nrhs, int npts,
+                  const int* medium, const double* theta, const zd* u1, const zd* p1, const zd* u2,
+                  const zd* p2, zd* out, hipStream_t st);
 
 }  // namespace pmlbie

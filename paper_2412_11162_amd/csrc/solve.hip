@@ -3,22 +3,24 @@
 
 namespace pmlbie {
 
-// b1 = -[u_tot0]_n, b2 = -[du_tot0/dnu_c]_n from the raw modal values of the
-// point-source pairs: raw[(inc * 2N + i)][s][n] with s = S1 for the pairs
+// b1 = -[u_tot0]_n, b2 = -[du_tot0/dnu_c]_n (modes n = m0..M, stored from
+// index 0) from the raw modal values (modes 0..M) of the point-source pairs:
+// raw[(inc * 2N + i)][s][n] with s = S1 for the pairs
 // (node i, source) and s = K1 for the swapped pairs (source, node i) whose
 // source-side conormal is the node's (the conormal derivative at the target
 // of G~(r, r*) by the symmetry of G~).
 __global__ void k_rhs_gather_point(const zd* __restrict__ raw, const int* __restrict__ rmap,
-                                   int npt, int N, int M, int nrhs, zd* __restrict__ b1,
+                                   int npt, int N, int M, int m0, int nrhs, zd* __restrict__ b1,
                                    zd* __restrict__ b2) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long tot = (long)(M + 1) * npt * N;
+  const long tot = (long)(M + 1 - m0) * npt * N;
   if (e >= tot) return;
   const int i = (int)(e % N);
   const int pidx = (int)((e / N) % npt);
-  const int n = (int)(e / ((long)N * npt));
+  const int nk = (int)(e / ((long)N * npt));  // kept mode index, mode m0 + nk
+  const int n = m0 + nk;
   const long q1 = (long)pidx * 2 * N + i, q2 = q1 + N;
-  const long o = ((long)n * nrhs + rmap[pidx]) * N + i;
+  const long o = ((long)nk * nrhs + rmap[pidx]) * N + i;
   b1[o] = -raw[q1 * 4 * (M + 1) + n];
   b2[o] = -raw[q2 * 4 * (M + 1) + (M + 1) + n];
 }
@@ -71,11 +73,12 @@ __global__ void k_outputs(const zd* __restrict__ x, const zd* __restrict__ b1,
 }
 
 // Field modes by the Green representation (Sec. 4.2, eq. eqfujs) and the
-// synthesis u = (1/2pi) sum_n u_n e^{i n theta} with u_{-n} = u_n:
+// synthesis u = (1/2pi) sum_n u_n e^{i n theta} with u_{-n} = u_n over the
+// built modes n = m0..M (boundary data stored from index 0):
 //   u_n(x) = sgn sum_l W_l [S_n(x, r_l) phi_n(r_l) - K_n(x, r_l) u_n(r_l)],
 // sgn = +1 in the upper medium, -1 in the lower one.  raw[(p * N + l)][s][n].
 __global__ void k_field(const zd* __restrict__ raw, const double* __restrict__ W, int N, int M,
-                        int nrhs, int npts, const int* __restrict__ medium,
+                        int m0, int nrhs, int npts, const int* __restrict__ medium,
                         const double* __restrict__ theta, const zd* __restrict__ u1,
                         const zd* __restrict__ p1, const zd* __restrict__ u2,
                         const zd* __restrict__ p2, zd* __restrict__ out) {
@@ -88,11 +91,11 @@ __global__ void k_field(const zd* __restrict__ raw, const double* __restrict__ W
   const zd* U = md == 1 ? u1 : u2;
   const zd* P = md == 1 ? p1 : p2;
   zd tot{0.0, 0.0};
-  for (int n = 0; n <= M; ++n) {
+  for (int n = m0; n <= M; ++n) {
     zd un{0.0, 0.0};
     for (int l = 0; l < N; ++l) {
       const zd* rw = raw + ((long)p * N + l) * 4 * (M + 1);
-      const long idx = ((long)n * nrhs + r) * N + l;
+      const long idx = ((long)(n - m0) * nrhs + r) * N + l;
       un = un + W[l] * (rw[sS * (M + 1) + n] * P[idx] - rw[sK * (M + 1) + n] * U[idx]);
     }
     const double f = (n == 0 ? 1.0 : 2.0) * cos(n * theta[p]) * sgn * (0.5 / PMLBIE_PI);
@@ -182,11 +185,11 @@ void launch_axpy(zd* x, const zd* d, long count, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, d, count);
 }
 
-void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int nrhs, zd* b1,
-                             zd* b2, hipStream_t st) {
-  const long tot = (long)(M + 1) * npt * N;
+void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int m0, int nrhs,
+                             zd* b1, zd* b2, hipStream_t st) {
+  const long tot = (long)(M + 1 - m0) * npt * N;
   hipLaunchKernelGGL(k_rhs_gather_point, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, raw,
-                     rmap, npt, N, M, nrhs, b1, b2);
+                     rmap, npt, N, M, m0, nrhs, b1, b2);
 }
 void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st) {
@@ -199,12 +202,12 @@ void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int n
   hipLaunchKernelGGL(k_outputs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, x, b1, b2, N,
                      M, nrhs, u1, p1, u2, p2);
 }
-void launch_field(const zd* raw, const double* W, int N, int M, int nrhs, int npts, const int* medium,
-                  const double* theta, const zd* u1, const zd* p1, const zd* u2, const zd* p2,
-                  zd* out, hipStream_t st) {
+void launch_field(const zd* raw, const double* W, int N, int M, int m0, int nrhs, int npts,
+                  const int* medium, const double* theta, const zd* u1, const zd* p1, const zd* u2,
+                  const zd* p2, zd* out, hipStream_t st) {
   const int tot = npts * nrhs;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_field, dim3((tot + 63) / 64), dim3(64), 0, st, raw, W, N, M, nrhs, npts,
+  hipLaunchKernelGGL(k_field, dim3((tot + 63) / 64), dim3(64), 0, st, raw, W, N, M, m0, nrhs, npts,
                      medium, theta, u1, p1, u2, p2, out);
 }
 

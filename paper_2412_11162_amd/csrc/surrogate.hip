@@ -529,7 +529,7 @@ void sg_accept(const PairGeom* g, const int2* dest, long n, const float* Y, int 
                double tol, zd* A, long n2, long mstride, const double* W, WorkList fallback,
                unsigned* accepted, hipStream_t st) {
   if (n <= 0) return;
-  OutSpec o{A, n2, mstride, W, nullptr, M};
+  OutSpec o{A, n2, mstride, W, nullptr, M, 0};
   const int grid = (int)std::min<long>(n, 256L * 32);
   hipLaunchKernelGGL(k_sg_accept, dim3(grid), dim3(64), 0, st, g, dest, n, Y, M, k1, k2, tol, o, fallback,
                      accepted);

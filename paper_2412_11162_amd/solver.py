@@ -36,6 +36,7 @@ class Solver:
         self.h = h
         self.N = 0
         self.M = 0
+        self.m0 = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -68,10 +69,12 @@ class Solver:
         self.N = self.nodes().shape[0]
 
     def build_modal_operators(self, n_theta: int, m_max: int, precision: int = B.PMLBIE_FP64,
-                              flags: int = 0):
-        self._chk(self.L.pmlbie_build_modal_operators(self.h, int(n_theta), int(m_max), int(precision),
-                                                      int(flags)))
+                              flags: int = 0, m_min: int = 0):
+        """Modes m_min..m_max (m_min > 0: one batch of a mode-batched solve)."""
+        self._chk(self.L.pmlbie_build_modal_operators_range(self.h, int(n_theta), int(m_min), int(m_max),
+                                                            int(precision), int(flags)))
         self.M = int(self.info()[1])
+        self.m0 = int(m_min)
 
     def solve_modes(self, incidences):
         n = len(incidences)
@@ -83,7 +86,7 @@ class Solver:
             else:
                 arr[r].kind = 1
                 arr[r].p[0] = float(inc[1])
-        shape = (self.M + 1, n, self.N)
+        shape = (self.M - self.m0 + 1, n, self.N)
         dev = torch.device("cuda", self.device)
         outs = [torch.empty(shape, dtype=torch.complex128, device=dev) for _ in range(4)]
         self._chk(self.L.pmlbie_solve_modes(self.h, n, arr, *[ctypes.c_void_p(o.data_ptr()) for o in outs]))

@@ -300,3 +300,30 @@ def test_field_matches_oracle_representation():
     rtz = np.stack([pts[:, 0], theta, pts[:, 1]], axis=1)
     out = s.evaluate_field(rtz, 1)[0]
     assert np.max(np.abs(out - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_mode_batches_reproduce_the_full_build():
+    """Modes built in two batches (the path for problems whose operators do
+    not fit at once) match the full build: the pair classification uses the
+    batch's highest mode, so a few pairs may take another (equally accurate)
+    path, and agreement is to the kernel tolerance, not bit for bit; the
+    batch fields add up to the full field."""
+    from paper_2412_11162_amd import _binding as B
+    wl = workloads.tiny()
+    incs = [("point", 0.3, 1.0), ("plane", 0.4)]
+    full = _solver(wl, device=0, flags=B.PMLBIE_KEEP_OPERATORS)
+    ref = [o.cpu().numpy() for o in full.solve_modes(incs)]
+    pts = np.array([[0.3, 0.2, 0.9], [0.8, 1.1, -0.7]])
+    f_full = full.evaluate_field(pts, len(incs))
+    s = _solver(wl, device=0, build=False)
+    f_sum = np.zeros_like(f_full)
+    for lo, hi in ((0, 3), (4, wl.m_max)):
+        s.build_modal_operators(wl.n_theta, hi, B.PMLBIE_FP64, B.PMLBIE_KEEP_OPERATORS, m_min=lo)
+        got = [o.cpu().numpy() for o in s.solve_modes(incs)]
+        for g, r in zip(got, ref):
+            assert g.shape[0] == hi - lo + 1
+            assert _normwise(g, r[lo:hi + 1]) <= KERNEL_TOL
+        for n in range(lo, hi + 1):
+            assert _normwise(s.get_operator(n).cpu().numpy(), full.get_operator(n).cpu().numpy()) <= KERNEL_TOL
+        f_sum += s.evaluate_field(pts, len(incs))
+    assert np.max(np.abs(f_sum - f_full)) <= 1e-10 * np.max(np.abs(f_full))
