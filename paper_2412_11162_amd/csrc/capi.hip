@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -437,17 +438,14 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->ldest.alloc(3 * cap);
     c->lcount.alloc(3);
     HIPCHK(hipMemsetAsync(c->lcount.p, 0, 3 * sizeof(unsigned), c->stream));
-    // auxiliary near-panel points
+    // auxiliary near-panel points: built on the host while the device runs
+    // the far, split and direct stages (the future is declared after the
+    // vectors it fills, so it is joined before they go away)
     std::vector<PairGeom> ageom;
     std::vector<double> acoef;
     std::vector<NearJob> ajobs;
-    c->geo.build_near(ageom, acoef, ajobs, 6);
-    c->cnt_aux = (long long)ageom.size();
-    c->coef.alloc(acoef.size());
-    HIPCHK(hipMemcpyAsync(c->coef.p, acoef.data(), acoef.size() * 8, hipMemcpyHostToDevice, c->stream));
-    c->jobs.alloc(ajobs.size());
-    HIPCHK(hipMemcpyAsync(c->jobs.p, ajobs.data(), ajobs.size() * sizeof(NearJob),
-                          hipMemcpyHostToDevice, c->stream));
+    std::future<void> near_tables =
+        std::async(std::launch::async, [&]() { c->geo.build_near(ageom, acoef, ajobs, 6); });
     c->stage_ms[0] = t_setup.stop();
 
     NodesDev nd;
@@ -495,6 +493,13 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
 
     // near panels: modal kernels at the auxiliary points, then product integration
     Timer t_near(c->stream);
+    near_tables.get();
+    c->cnt_aux = (long long)ageom.size();
+    c->coef.alloc(acoef.size());
+    HIPCHK(hipMemcpyAsync(c->coef.p, acoef.data(), acoef.size() * 8, hipMemcpyHostToDevice, c->stream));
+    c->jobs.alloc(ajobs.size());
+    HIPCHK(hipMemcpyAsync(c->jobs.p, ajobs.data(), ajobs.size() * sizeof(NearJob),
+                          hipMemcpyHostToDevice, c->stream));
     c->raw.alloc(std::max<size_t>(ageom.size(), 1) * 4 * (M + 1));
     long long dummy[3] = {0, 0, 0};
     run_pair_list(c, ageom, c->raw.p, dummy);
