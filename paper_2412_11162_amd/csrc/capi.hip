@@ -384,7 +384,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     const double rmax = cabs_(zd{c->geo.breaks[4], c->geo.Iint(c->geo.breaks[4])});
     const double bneed = ceil(1.15 * kmax * rmax + 16.0);
     const int L = std::max(512, pow2_at_least(std::max<double>(n_theta, 2.0 * (M + bneed) + 2.0)));
-    if (L > 1024) return fail(c, PMLBIE_EINVAL, "build: wavenumber or m_max too large for the azimuthal FFT");
+    if (L > 2048) return fail(c, PMLBIE_EINVAL, "build: wavenumber or m_max too large for the azimuthal FFT");
     c->nt_int = L;
     c->MQ = L / 2 - 1;
     c->B = c->MQ - M;

@@ -1,4 +1,4 @@
-// One-wavefront FFT of length L = 64 R (R = 8 or 16) with the data held in
+// One-wavefront FFT of length L = 64 R (R = 8, 16 or 32) with the data held in
 // registers: an R-point DFT per lane, then the 64-point DFTs across lanes as
 // two radix-8 passes, with two transposes through LDS (rows padded to 65
 // entries so that eight consecutive lanes touch distinct banks).
@@ -38,33 +38,42 @@ __device__ __forceinline__ void dft8(zd* u) {
   u[7] = e3 - t3;
 }
 
-// In-place forward R-point DFT (R = 8, or 16 as two 8-point DFTs of the even
-// and odd samples joined by the twiddles e^{-i pi k / 8}).
+// In-place forward R-point DFT (R = 8; R = 16 and 32 as two half-length DFTs
+// of the even and odd samples joined by the twiddles e^{-2 pi i k / R}).
 template <int R>
 __device__ __forceinline__ void dft_r(zd* v) {
   if constexpr (R == 8) {
     dft8(v);
   } else {
-    static_assert(R == 16, "fft_wave supports L = 512 and L = 1024");
-    zd e[8], o[8];
+    static_assert(R == 16 || R == 32, "fft_wave supports L = 512, 1024 and 2048");
+    constexpr int H = R / 2;
+    zd e[H], o[H];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
+    for (int a = 0; a < H; ++a) {
       e[a] = v[2 * a];
       o[a] = v[2 * a + 1];
     }
-    dft8(e);
-    dft8(o);
-    constexpr double c[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
-                             0.38268343236508977173, 0.0, -0.38268343236508977173,
-                             -0.70710678118654752440, -0.92387953251128675613};
-    constexpr double s[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
-                             0.92387953251128675613, 1.0, 0.92387953251128675613,
-                             0.70710678118654752440, 0.38268343236508977173};
+    dft_r<H>(e);
+    dft_r<H>(o);
+    // cos and sin of pi k / 16, k = 0..16 (W_R^k = e^{-2 pi i k / R})
+    constexpr double c16[17] = {1.0, 0.98078528040323044913, 0.92387953251128675613,
+                                0.83146961230254523708, 0.70710678118654752440, 0.55557023301960222474,
+                                0.38268343236508977173, 0.19509032201612826785, 0.0,
+                                -0.19509032201612826785, -0.38268343236508977173, -0.55557023301960222474,
+                                -0.70710678118654752440, -0.83146961230254523708, -0.92387953251128675613,
+                                -0.98078528040323044913, -1.0};
+    constexpr double s16[17] = {0.0, 0.19509032201612826785, 0.38268343236508977173,
+                                0.55557023301960222474, 0.70710678118654752440, 0.83146961230254523708,
+                                0.92387953251128675613, 0.98078528040323044913, 1.0,
+                                0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,
+                                0.70710678118654752440, 0.55557023301960222474, 0.38268343236508977173,
+                                0.19509032201612826785, 0.0};
+    constexpr int st = 32 / R;  // angle 2 pi k / R = pi (st k) / 16
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const zd t = o[k] * zd{c[k], -s[k]};
+    for (int k = 0; k < H; ++k) {
+      const zd t = o[k] * zd{c16[st * k], -s16[st * k]};
       v[k] = e[k] + t;
-      v[k + 8] = e[k] - t;
+      v[k + H] = e[k] - t;
     }
   }
 }

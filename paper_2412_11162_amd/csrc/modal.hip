@@ -46,27 +46,48 @@ __device__ __forceinline__ void emit_pair(const OutSpec& o, int2 dst, int s0, do
   }
 }
 
-// LDS of one pair (entries): the fft_wave exchange area E of two sequences,
-// preceded by a staging area P2 of two half-circle sequences; the first two
-// staged sequences (P1) sit at the start of E and are read into registers
-// before E is used by the transform.
+// LDS of one pair (entries): two staging areas P1, P2 of two half-circle
+// sequences each and the fft_wave exchange area E.  For R <= 16, E holds two
+// sequences and P1 sits at its start (P1 is read into registers before the
+// transform uses E); for R = 32 the sequences are transformed one at a time
+// and P1, P2 and E are disjoint.
 template <int R>
 constexpr int pair_lds() {
-  return (32 * R + 1) * 2 + 2 * fft_wave_lds<R>();
+  return R <= 16 ? (32 * R + 1) * 2 + 2 * fft_wave_lds<R>() : 4 * (32 * R + 1) + fft_wave_lds<R>();
+}
+template <int R>
+__device__ __forceinline__ zd* pair_p1(zd* lds) {
+  return lds + 2 * (32 * R + 1);
+}
+template <int R>
+__device__ __forceinline__ zd* pair_e(zd* lds) {
+  return R <= 16 ? lds + 2 * (32 * R + 1) : lds + 4 * (32 * R + 1);
 }
 
-// Load two staged half-circle sequences (j = 0..L/2 at st[j], st[H + j]) into
-// the input layout of fft_wave, extended evenly: x[L - j] = x[j].
-template <int R>
-__device__ __forceinline__ void load_even(const zd* st, zd (&x)[2][R]) {
+// Load staged half-circle sequence(s) (j = 0..L/2 at st[j], st[H + j], ...)
+// into the input layout of fft_wave, extended evenly: x[L - j] = x[j].
+template <int R, int NS>
+__device__ __forceinline__ void load_even(const zd* st, zd (&x)[NS][R]) {
   constexpr int L = 64 * R, H = L / 2 + 1;
   const int b = threadIdx.x & 63;
 #pragma unroll
   for (int a = 0; a < R; ++a) {
     const int j = b + 64 * a;
     const int jj = j <= L / 2 ? j : L - j;
-    x[0][a] = st[jj];
-    x[1][a] = st[H + jj];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) x[q][a] = st[q * H + jj];
+  }
+}
+
+// Modes 0..M of one sequence s held in the output layout of fft_wave.
+template <int R>
+__device__ __forceinline__ void emit_seq(const OutSpec& o, int2 dst, int s, double scale,
+                                         const zd (&x)[R]) {
+  const int b = threadIdx.x & 63;
+#pragma unroll
+  for (int sl = 0; sl < R; ++sl) {
+    const int n = fft_wave_out_index<R>(b, sl);
+    if (n <= o.M) emit_val(o, dst, s, n, scale, x[sl]);
   }
 }
 
@@ -74,13 +95,25 @@ __device__ __forceinline__ void load_even(const zd* st, zd (&x)[2][R]) {
 template <int R>
 __device__ __forceinline__ void transform_emit(const zd* st, zd* E, const zd* __restrict__ tw,
                                                const OutSpec& o, int2 dst, int s0) {
+  constexpr int H = 32 * R + 1;
   const double scale = 2.0 * PMLBIE_PI / (64 * R);
-  zd x[2][R];
-  load_even<R>(st, x);
-  __syncthreads();
-  fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[0]), E, tw);
-  fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[1]), E, tw);
-  emit_pair<R>(o, dst, s0, scale, x);
+  if constexpr (R <= 16) {
+    zd x[2][R];
+    load_even<R, 2>(st, x);
+    __syncthreads();
+    fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[0]), E, tw);
+    fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[1]), E, tw);
+    emit_pair<R>(o, dst, s0, scale, x);
+  } else {
+#pragma unroll 1
+    for (int q = 0; q < 2; ++q) {
+      zd x[1][R];
+      load_even<R, 1>(st + q * H, x);
+      __syncthreads();
+      fft_wave<R, 1>(x, E, tw);
+      emit_seq<R>(o, dst, s0 + q, scale, x[0]);
+    }
+  }
 }
 
 // Raw-kernel FFT of one pair (one wavefront): the samples of S = G~ and
@@ -93,7 +126,8 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
                                          zd* lds, const OutSpec& o, int2 dst) {
   constexpr int L = 64 * R, H = L / 2 + 1;
   zd* P2 = lds;
-  zd* E = lds + 2 * H;
+  zd* P1 = pair_p1<R>(lds);
+  zd* E = pair_e<R>(lds);
 #pragma unroll 1
   for (int j = threadIdx.x; j <= L / 2; j += 64) {
     const double sh = sin(PMLBIE_PI * j / L);
@@ -105,13 +139,13 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
     const zd N = v.N0 + s2 * v.N1;
     const zd ikR1 = zd{0.0, 1.0} * (k1 * Rd), ikR2 = zd{0.0, 1.0} * (k2 * Rd);
     const zd e1 = cexp_(ikR1) * inv4piR, e2 = cexp_(ikR2) * inv4piR;
-    E[j] = e1;
-    E[H + j] = N * e1 * (ikR1 - 1.0) * iR2;
+    P1[j] = e1;
+    P1[H + j] = N * e1 * (ikR1 - 1.0) * iR2;
     P2[j] = e2;
     P2[H + j] = N * e2 * (ikR2 - 1.0) * iR2;
   }
   __syncthreads();
-  transform_emit<R>(E, E, tw, o, dst, 0);
+  transform_emit<R>(P1, E, tw, o, dst, 0);
   transform_emit<R>(P2, E, tw, o, dst, 2);
 }
 
@@ -287,7 +321,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   constexpr int L = 64 * R, H = L / 2 + 1;
   __shared__ zd lds[pair_lds<R>()];
   zd* P2 = lds;
-  zd* E = lds + 2 * H;
+  zd* P1 = pair_p1<R>(lds);
+  zd* E = pair_e<R>(lds);
   const double inv2pi = 0.5 / PMLBIE_PI;
   const int b = threadIdx.x & 63;
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
@@ -301,31 +336,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const zd e1f = -1.0 * sc.e1;
     {
       // Zs, Ds on the grid from their even mode sequences, staged in P2
-      zd sg[2][R];
+      constexpr int NQ = R <= 16 ? 2 : 1;  // sequences per transform
+#pragma unroll 1
+      for (int q0 = 0; q0 < 2; q0 += NQ) {
+        zd sg[NQ][R];
 #pragma unroll
-      for (int a = 0; a < R; ++a) {
-        const int m = b + 64 * a;
-        const int mm = m <= L / 2 ? m : L - m;
-        zd zm{0.0, 0.0}, dm{0.0, 0.0};
-        if (mm <= MQ) {
-          zm = zz[mm];
-          dm = e0f * pp[mm] + e1f * zm;
+        for (int a = 0; a < R; ++a) {
+          const int m = b + 64 * a;
+          const int mm = m <= L / 2 ? m : L - m;
+          zd zm{0.0, 0.0}, dm{0.0, 0.0};
+          if (mm <= MQ) {
+            zm = zz[mm];
+            dm = e0f * pp[mm] + e1f * zm;
+          }
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) sg[q][a] = (q0 + q) == 0 ? zm : dm;
         }
-        sg[0][a] = zm;
-        sg[1][a] = dm;
-      }
-      fft_wave<R, 2>(sg, E, tw);
+        fft_wave<R, NQ>(sg, E, tw);
 #pragma unroll
-      for (int sl = 0; sl < R; ++sl) {
-        const int j = fft_wave_out_index<R>(b, sl);
-        if (j <= L / 2) {
-          P2[j] = inv2pi * sg[0][sl];
-          P2[H + j] = inv2pi * sg[1][sl];
+        for (int sl = 0; sl < R; ++sl) {
+          const int j = fft_wave_out_index<R>(b, sl);
+          if (j <= L / 2) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) P2[(q0 + q) * H + j] = inv2pi * sg[q][sl];
+          }
         }
       }
     }
     __syncthreads();
-    // products for both wavenumbers: medium 1 into E, medium 2 over Zs, Ds
+    // products for both wavenumbers: medium 1 into P1, medium 2 over Zs, Ds
 #pragma unroll 1
     for (int j = b; j <= L / 2; j += 64) {
       const double sh = sin(PMLBIE_PI * j / L);
@@ -333,14 +372,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const zd zs = P2[j], ds = P2[H + j];
       zd H1, ZH2, H3, DH4;
       split_smooth(sc, Rd, k1, H1, ZH2, H3, DH4);
-      E[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
-      E[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
+      P1[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
+      P1[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
       split_smooth(sc, Rd, k2, H1, ZH2, H3, DH4);
       P2[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
       P2[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
     }
     __syncthreads();
-    transform_emit<R>(E, E, tw, o, dst, 0);
+    transform_emit<R>(P1, E, tw, o, dst, 0);
     transform_emit<R>(P2, E, tw, o, dst, 2);
   }
 }
@@ -625,6 +664,7 @@ void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, z
   switch (nt) {
     case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, st); break;
     case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 2048: launch_far_t<32>(nd, cp, k1, k2, tw, o, split, direct, st); break;
     default: break;
   }
 }
@@ -652,6 +692,7 @@ void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first,
   switch (nt) {
     case 512: launch_list_far_t<8>(geom, dest, first, count, k1, k2, tw, o, st); break;
     case 1024: launch_list_far_t<16>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 2048: launch_list_far_t<32>(geom, dest, first, count, k1, k2, tw, o, st); break;
     default: break;
   }
 }
@@ -688,6 +729,7 @@ void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, lo
   switch (nt) {
     case 512: launch_split_t<8>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
     case 1024: launch_split_t<16>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 2048: launch_split_t<32>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
     default: break;
   }
 }

@@ -327,3 +327,15 @@ def test_mode_batches_reproduce_the_full_build():
             assert _normwise(s.get_operator(n).cpu().numpy(), full.get_operator(n).cpu().numpy()) <= KERNEL_TOL
         f_sum += s.evaluate_field(pts, len(incs))
     assert np.max(np.abs(f_sum - f_full)) <= 1e-10 * np.max(np.abs(f_full))
+
+
+def test_modes_on_the_2048_grid_against_oracle(tiny_ref):
+    """m_max = 500 needs the 2048-point angle grid (R = 32 register FFTs, one
+    sequence at a time, for the far and split pairs); every mode comes out of
+    the same transforms, so the modes the oracle has (0..8) check them."""
+    from paper_2412_11162_amd._binding import PMLBIE_KEEP_OPERATORS
+    wl, g, A, _ = tiny_ref
+    s = _solver(wl, flags=PMLBIE_KEEP_OPERATORS, n_theta=1024, m_max=500)
+    assert int(s.info()[2]) == 2048
+    for n in range(wl.m_max + 1):
+        assert _normwise(s.get_operator(n).cpu().numpy(), A[n]) <= KERNEL_TOL, n
