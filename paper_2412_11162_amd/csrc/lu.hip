@@ -324,12 +324,12 @@ template <> struct mfma_t<float> {
 
 // U12 = L11^{-1} A12 on MFMA, in place: one workgroup per strip of 64
 // trailing columns of the panel rows (it reads the whole strip before writing
-// it), W = L11^{-1} from k_trsm.  Four waves of 32 rows x 64 columns; the
-// K chunks above a wave's rows are skipped (W is lower triangular).
+// it), W = L11^{-1} from k_trsm.  Eight waves of 32 x 32 (four row blocks x
+// two column blocks); the K chunks above a wave's rows are skipped (W is
+// lower triangular).
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm_mfma(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                                   int nb, int cend,
-                                                   const cx<T>* __restrict__ W) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_trsm_mfma(
+    cx<T>* __restrict__ A, long ms, int n, int k0, int nb, int cend, const cx<T>* __restrict__ W) {
   typedef typename mfma_t<T>::acc acc_t;
   cx<T>* a = A + (long)blockIdx.y * ms;
   const cx<T>* w = W + (long)blockIdx.y * LU_NB * LU_NB;
@@ -338,27 +338,27 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(cx<T>* __restrict__ A, long m
   __shared__ T Lre[KC][LU_NB + 4], Lim[KC][LU_NB + 4];  // W chunk: [k][row]
   __shared__ T Bre[KC][64 + 4], Bim[KC][64 + 4];        // A12 chunk: [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = wid * 32;
-  acc_t cr[2][4], ci[2][4];
+  const int wr = (wid & 3) * 32, wc = (wid >> 2) * 32;
+  acc_t cr[2][2], ci[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
+    for (int y = 0; y < 2; ++y) {
       cr[x][y] = acc_t{0, 0, 0, 0};
       ci[x][y] = acc_t{0, 0, 0, 0};
     }
   for (int kk = 0; kk < nb; kk += KC) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + 256 * t;
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 512 * t;
       const int k = e % KC, r = e / KC;
       const cx<T> v = (r < nb && kk + k < nb) ? w[(long)r * LU_NB + kk + k] : cx<T>{T(0), T(0)};
       Lre[k][r] = v.re;
       Lim[k][r] = v.im;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = tid + 256 * t;
+    for (int t = 0; t < 2; ++t) {
+      const int e = tid + 512 * t;
       const int cc = e & 63, k = e >> 6;
       const int gc = c0 + cc, gk = kk + k;
       const cx<T> v = (gc < cend && gk < nb) ? a[(long)(k0 + gk) * n + gc] : cx<T>{T(0), T(0)};
@@ -367,24 +367,21 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(cx<T>* __restrict__ A, long m
     }
     __syncthreads();
     if (kk < wr + 32) {
-#pragma unroll
+#pragma unroll 1
       for (int k4 = 0; k4 < KC; k4 += 4) {
         const int kx = k4 + (lane >> 4), lx = lane & 15;
-        T lr[2], li[2], br[4], bi[4];
+        T lr[2], li[2], br[2], bi[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           lr[t] = Lre[kx][wr + 16 * t + lx];
           li[t] = Lim[kx][wr + 16 * t + lx];
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          br[t] = Bre[kx][16 * t + lx];
-          bi[t] = Bim[kx][16 * t + lx];
+          br[t] = Bre[kx][wc + 16 * t + lx];
+          bi[t] = Bim[kx][wc + 16 * t + lx];
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) {
+          for (int y = 0; y < 2; ++y) {
             cr[x][y] = mfma_t<T>::op(lr[x], br[y], cr[x][y]);
             cr[x][y] = mfma_t<T>::op(-li[x], bi[y], cr[x][y]);
             ci[x][y] = mfma_t<T>::op(lr[x], bi[y], ci[x][y]);
@@ -397,11 +394,11 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(cx<T>* __restrict__ A, long m
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int r = wr + 16 * x + mfma_t<T>::rowof(lane, j);
-        const int gc = c0 + 16 * y + (lane & 15);
+        const int gc = c0 + wc + 16 * y + (lane & 15);
         if (r < nb && gc < cend) a[(long)(k0 + r) * n + gc] = cx<T>{cr[x][y][j], ci[x][y][j]};
       }
 }
@@ -530,47 +527,73 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
   const int* piv = ipiv + (long)blockIdx.x * n;
   cx<TB>* b = B + (long)blockIdx.x * nrhs * n;
   const int tid = threadIdx.x;
+  constexpr int JB = 32;
   __shared__ cx<TB> yb[LU_NB][LU_MAX_RHS];
-  if (!upper && tid < nrhs) {
-    cx<TB>* v = b + (long)tid * n;
-    for (int j = 0; j < nb; ++j) {
-      const int p = piv[k0 + j];
-      if (p != k0 + j) {
-        const cx<TB> t0 = v[k0 + j];
-        v[k0 + j] = v[p];
-        v[p] = t0;
-      }
-    }
-  }
-  __syncthreads();
+  __shared__ cx<T> Lb[LU_NB][JB + 1];  // a block of JB columns of the diagonal block
   for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
   __syncthreads();
   if (!upper) {
-    for (int j = 0; j < nb; ++j) {
-      for (int e = tid; e < nb * nrhs; e += 256) {
-        const int r = e % nb, s = e / nb;
-        if (r > j) {
-          const cx<T> l = a[(long)(k0 + r) * n + k0 + j];
-          yb[r][s] = yb[r][s] - cx<TB>{(TB)l.re, (TB)l.im} * yb[j][s];
+    // the panel's row interchanges, in order; rows inside the panel are
+    // exchanged in LDS, a pivot row below the panel in memory
+    if (tid < nrhs) {
+      cx<TB>* v = b + (long)tid * n;
+      for (int j = 0; j < nb; ++j) {
+        const int p = piv[k0 + j] - k0;
+        if (p == j) continue;
+        const cx<TB> t0 = yb[j][tid];
+        if (p < nb) {
+          yb[j][tid] = yb[p][tid];
+          yb[p][tid] = t0;
+        } else {
+          yb[j][tid] = v[k0 + p];
+          v[k0 + p] = t0;
         }
       }
+    }
+    __syncthreads();
+    for (int j0 = 0; j0 < nb; j0 += JB) {
+      const int jn = min(JB, nb - j0);
+      for (int e = tid; e < nb * JB; e += 256) {
+        const int r = e / JB, jj = e % JB;
+        Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
+      }
       __syncthreads();
+      for (int jj = 0; jj < jn; ++jj) {
+        const int j = j0 + jj;
+        for (int e = tid; e < nb * nrhs; e += 256) {
+          const int r = e % nb, s = e / nb;
+          if (r > j) {
+            const cx<T> l = Lb[r][jj];
+            yb[r][s] = yb[r][s] - cx<TB>{(TB)l.re, (TB)l.im} * yb[j][s];
+          }
+        }
+        __syncthreads();
+      }
     }
   } else {
-    for (int j = nb - 1; j >= 0; --j) {
-      if (tid < nrhs) {
-        const cx<T> u = a[(long)(k0 + j) * n + k0 + j];
-        yb[j][tid] = yb[j][tid] / cx<TB>{(TB)u.re, (TB)u.im};
+    for (int j1 = nb; j1 > 0; j1 -= JB) {  // columns [j0, j1), last block first
+      const int j0 = max(0, j1 - JB), jn = j1 - j0;
+      for (int e = tid; e < nb * JB; e += 256) {
+        const int r = e / JB, jj = e % JB;
+        Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
       }
       __syncthreads();
-      for (int e = tid; e < nb * nrhs; e += 256) {
-        const int r = e % nb, s = e / nb;
-        if (r < j) {
-          const cx<T> u = a[(long)(k0 + r) * n + k0 + j];
-          yb[r][s] = yb[r][s] - cx<TB>{(TB)u.re, (TB)u.im} * yb[j][s];
+      for (int jj = jn - 1; jj >= 0; --jj) {
+        const int j = j0 + jj;
+        if (tid < nrhs) {
+          const cx<T> u = Lb[j][jj];
+          yb[j][tid] = yb[j][tid] / cx<TB>{(TB)u.re, (TB)u.im};
         }
+        __syncthreads();
+        for (int e = tid; e < nb * nrhs; e += 256) {
+          const int r = e % nb, s = e / nb;
+          if (r < j) {
+            const cx<T> u = Lb[r][jj];
+            yb[r][s] = yb[r][s] - cx<TB>{(TB)u.re, (TB)u.im} * yb[j][s];
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
@@ -642,7 +665,7 @@ static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch
     // U12 = (L11^{-1}) A12: the inverse by the column solver, the product on MFMA
     hipLaunchKernelGGL(k_trsm<T>, dim3((nb + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb,
                        cend, W);
-    hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0,
+    hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(512), 0, st, A, ms, n, k0,
                        nb, cend, (const cx<T>*)W);
   } else {
     hipLaunchKernelGGL(k_trsm<T>, dim3((cols + 63) / 64, batch), dim3(256), 0, st, A, ms, n, k0, nb,

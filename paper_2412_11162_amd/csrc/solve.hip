@@ -113,8 +113,9 @@ __global__ void k_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, long 
 }
 
 // Residual of the FP64 systems: r = rhs - A x for all modes and right-hand
-// sides (A row-major 2N x 2N per mode), one wavefront per row; rs2 receives
-// |r_i|^2 for the convergence test.
+// sides (A row-major 2N x 2N per mode), one wavefront per row; the row is read
+// once and multiplied into every right-hand side; rs2 receives |r_i|^2 for
+// the convergence test.
 __global__ __launch_bounds__(256) void k_residual(const zd* __restrict__ A, long ms, int n,
                                                   int nrhs, const zd* __restrict__ x,
                                                   const zd* __restrict__ rhs, zd* __restrict__ r,
@@ -124,20 +125,30 @@ __global__ __launch_bounds__(256) void k_residual(const zd* __restrict__ A, long
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   const zd* row = A + (long)md * ms + (long)i * n;
-  for (int s = 0; s < nrhs; ++s) {
-    const zd* xv = x + ((long)md * nrhs + s) * n;
-    zd acc{0.0, 0.0};
-    for (int c = lane; c < n; c += 64) acc = cfma(row[c], xv[c], acc);
+  const zd* xm = x + (long)md * nrhs * n;
+  zd acc[LU_MAX_RHS];
+#pragma unroll
+  for (int s = 0; s < LU_MAX_RHS; ++s) acc[s] = zd{0.0, 0.0};
+  for (int c = lane; c < n; c += 64) {
+    const zd a = row[c];
+#pragma unroll
+    for (int s = 0; s < LU_MAX_RHS; ++s)
+      if (s < nrhs) acc[s] = cfma(a, xm[(long)s * n + c], acc[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < LU_MAX_RHS; ++s) {
+    if (s >= nrhs) continue;
+    zd v = acc[s];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-      acc.re += __shfl_xor(acc.re, off);
-      acc.im += __shfl_xor(acc.im, off);
+      v.re += __shfl_xor(v.re, off);
+      v.im += __shfl_xor(v.im, off);
     }
     if (lane == 0) {
       const long e = ((long)md * nrhs + s) * n + i;
-      const zd v = rhs[e] - acc;
-      r[e] = v;
-      rs2[e] = abs2(v);
+      const zd d = rhs[e] - v;
+      r[e] = d;
+      rs2[e] = abs2(d);
     }
   }
 }
