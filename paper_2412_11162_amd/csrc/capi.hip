@@ -60,6 +60,8 @@ struct DBuf {
 struct pmlbie_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t up_stream = nullptr;  // uploads of the near-panel tables
+  hipEvent_t up_done = nullptr;
   std::string err;
   int stage = 0;  // 0 created, 1 geometry, 2 media, 3 built, 4 solved
   Geometry geo;
@@ -216,11 +218,19 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
 
 // Explicit pair list (host) -> raw modal values raw[q][s][n]: upload, classify
 // on the device into far / split / direct lists, run the three paths.
+void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts);
+
 void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long long* counts) {
   const size_t tot = g.size();
   if (tot == 0) return;
   c->xgeom.alloc(tot);
   HIPCHK(hipMemcpyAsync(c->xgeom.p, g.data(), tot * sizeof(PairGeom), hipMemcpyHostToDevice, c->stream));
+  run_pair_list_dev(c, tot, raw, counts);
+}
+
+// The same with the pair geometry already in c->xgeom.
+void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts) {
+  if (tot == 0) return;
   c->lgeom.alloc(3 * tot > c->lgeom.n ? 3 * tot : c->lgeom.n);
   c->ldest.alloc(3 * tot > c->ldest.n ? 3 * tot : c->ldest.n);
   c->lcount.alloc(3);
@@ -283,6 +293,11 @@ int pmlbie_create(pmlbie_ctx** out, int device, void* stream) {
 void pmlbie_destroy(pmlbie_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  if (c->up_stream) {
+    (void)hipStreamSynchronize(c->up_stream);
+    (void)hipStreamDestroy(c->up_stream);
+  }
+  if (c->up_done) (void)hipEventDestroy(c->up_done);
   delete c;
 }
 
@@ -444,8 +459,22 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     std::vector<PairGeom> ageom;
     std::vector<double> acoef;
     std::vector<NearJob> ajobs;
-    std::future<void> near_tables =
-        std::async(std::launch::async, [&]() { c->geo.build_near(ageom, acoef, ajobs, 6); });
+    if (!c->up_stream) HIPCHK(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking));
+    if (!c->up_done) HIPCHK(hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming));
+    std::future<void> near_tables = std::async(std::launch::async, [&]() {
+      HIPCHK(hipSetDevice(c->device));
+      c->geo.build_near(ageom, acoef, ajobs, 6);
+      // uploaded on their own stream while the far/split/direct stages run
+      c->coef.alloc(acoef.size());
+      c->jobs.alloc(ajobs.size());
+      c->xgeom.alloc(std::max<size_t>(ageom.size(), 1));
+      HIPCHK(hipMemcpyAsync(c->coef.p, acoef.data(), acoef.size() * 8, hipMemcpyHostToDevice, c->up_stream));
+      HIPCHK(hipMemcpyAsync(c->jobs.p, ajobs.data(), ajobs.size() * sizeof(NearJob), hipMemcpyHostToDevice,
+                            c->up_stream));
+      HIPCHK(hipMemcpyAsync(c->xgeom.p, ageom.data(), ageom.size() * sizeof(PairGeom),
+                            hipMemcpyHostToDevice, c->up_stream));
+      HIPCHK(hipEventRecord(c->up_done, c->up_stream));
+    });
     c->stage_ms[0] = t_setup.stop();
 
     NodesDev nd;
@@ -494,15 +523,11 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     // near panels: modal kernels at the auxiliary points, then product integration
     Timer t_near(c->stream);
     near_tables.get();
+    HIPCHK(hipStreamWaitEvent(c->stream, c->up_done, 0));
     c->cnt_aux = (long long)ageom.size();
-    c->coef.alloc(acoef.size());
-    HIPCHK(hipMemcpyAsync(c->coef.p, acoef.data(), acoef.size() * 8, hipMemcpyHostToDevice, c->stream));
-    c->jobs.alloc(ajobs.size());
-    HIPCHK(hipMemcpyAsync(c->jobs.p, ajobs.data(), ajobs.size() * sizeof(NearJob),
-                          hipMemcpyHostToDevice, c->stream));
     c->raw.alloc(std::max<size_t>(ageom.size(), 1) * 4 * (M + 1));
     long long dummy[3] = {0, 0, 0};
-    run_pair_list(c, ageom, c->raw.p, dummy);
+    run_pair_list_dev(c, ageom.size(), c->raw.p, dummy);
     launch_near(c->jobs.p, (int)ajobs.size(), c->coef.p, c->raw.p, M, m0, c->A.p, n2, ms, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[4] = t_near.stop();
