@@ -170,7 +170,10 @@ struct Timer {
 // modes) in chunks, phase 2 (smooth FFTs + convolution).
 void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count, zd* A, long n2,
                long ms, const double* W, zd* raw) {
-  const long CH = 1L << 15;
+  // chunks of pairs sized to about 1 GiB per singular-part table: the
+  // Legendre recurrences run one pair per lane and are latency bound, so the
+  // chunk must hold several wavefronts per SIMD
+  const long CH = std::max(1L << 15, std::min(1L << 18, (1L << 30) / (16L * (c->MQ + 1))));
   for (long f = 0; f < count; f += CH) {
     const long cn = std::min(CH, count - f);
     c->zhat.alloc((size_t)CH * (c->MQ + 1));
