@@ -61,13 +61,20 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
   const cx<T> zero{T(0), T(0)};
   cx<T> x[RPT][SUB];
   for (int s0 = 0; s0 < nb; s0 += SUB) {
+    // unconditional loads (rows past the end re-read the last row) so that
+    // they are all in flight together; those rows are then zeroed
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int rl = tid + PNL_T * q;
-      const cx<T>* src = a + (long)(k0 + rl) * n + k0 + s0;
+      const cx<T>* src = a + (long)(k0 + min(rl, m - 1)) * n + k0 + s0;
 #pragma unroll
-      for (int jj = 0; jj < SUB; ++jj) x[q][jj] = rl < m ? src[jj] : zero;
+      for (int jj = 0; jj < SUB; ++jj) x[q][jj] = src[jj];
     }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int jj = 0; jj < SUB; ++jj)
+        if (tid + PNL_T * q >= m) x[q][jj] = zero;
 #pragma unroll
     for (int jj = 0; jj < SUB; ++jj) {
       const int cl = s0 + jj;
@@ -196,7 +203,8 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
       a[(long)(k0 + s0 + r) * n + k0 + s0 + SUB + c] = Ur[r][c];
     }
     // rows below: A[r][right] -= L[r][0..SUB-1] Ur, one block of PNL_T rows at
-    // a time with L staged in LDS so that the row segments are read coalesced
+    // a time with L staged in LDS so that the row segments are read coalesced;
+    // UNR independent row segments in flight per step
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int base = PNL_T * q;
@@ -205,23 +213,22 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
       for (int jj = 0; jj < SUB; ++jj) Ls[tid][jj] = x[q][jj];
       __syncthreads();
       const int rlo = max(base, s0 + SUB), rhi = min(base + PNL_T, m);
-      // thread -> (column c, first row rs), rows strided by PNL_T / wr; four
-      // independent row segments in flight per step
+      // thread -> (column c, first row rs), rows strided by PNL_T / wr
       const int c = tid % wr, rs = tid / wr, stride = PNL_T / wr;
       if (rs < stride) {
         cx<T> u[SUB];
 #pragma unroll
         for (int j = 0; j < SUB; ++j) u[j] = Ur[j][c];
         cx<T>* col = a + (long)k0 * n + k0 + s0 + SUB + c;
-        for (int r1 = rlo + rs; r1 < rhi; r1 += 4 * stride) {
-          cx<T> v[4];
+        constexpr int UNR = 4;
+        for (int r1 = rlo + rs; r1 < rhi; r1 += UNR * stride) {
+          cx<T> v[UNR];
+          // unconditional loads (rows past the end re-read the last row), so
+          // that all UNR of them are in flight together
 #pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const int rl = r1 + h * stride;
-            if (rl < rhi) v[h] = col[(long)rl * n];
-          }
+          for (int h = 0; h < UNR; ++h) v[h] = col[(long)min(r1 + h * stride, rhi - 1) * n];
 #pragma unroll
-          for (int h = 0; h < 4; ++h) {
+          for (int h = 0; h < UNR; ++h) {
             const int rl = r1 + h * stride;
             if (rl < rhi) {
               cx<T> acc = v[h];
