@@ -526,6 +526,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 //   panel's row interchanges to b and solves the unit lower diagonal block;
 //   (2) many workgroups update the rows below, one wavefront per row.
 //   backward: (3) the upper diagonal block, (4) the rows above.
+// Columns [j0, j0 + jn) of the diagonal block, rows [r_lo, r_hi), into Lb.
+template <typename T>
+__device__ __forceinline__ void stage_cols(const cx<T>* __restrict__ a, int n, int k0, int r_lo, int r_hi,
+                                           int j0, int jn, cx<T> (*Lb)[33]) {
+  for (int e = r_lo * 32 + threadIdx.x; e < r_hi * 32; e += blockDim.x) {
+    const int r = e >> 5, jj = e & 31;
+    Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
+  }
+}
+
+// Triangle of a 32-column block of the diagonal block, solved by one
+// wavefront without barriers: lane l holds the entries (row j0 + (l & 31),
+// rhs 2 t + (l >> 5)) in slot t, so the entry (row j0 + jj, same rhs) of
+// slot t sits in lane (l & 32) + jj, slot t.  Lower: unit diagonal, forward;
+// upper: divided by the diagonal, backward.
+template <typename T, typename TB, bool UPPER>
+__device__ __forceinline__ void tri_wave(cx<T> (*Lb)[33], cx<TB> (*yb)[LU_MAX_RHS], int j0, int jn,
+                                         int nrhs) {
+  constexpr int NT = LU_MAX_RHS / 2;
+  const int lane = threadIdx.x & 63, rr = lane & 31, hs = lane >> 5;
+  const int nt = (nrhs + 1) >> 1;
+  cx<TB> y[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int s2 = 2 * t + hs;
+    y[t] = (t < nt && rr < jn && s2 < nrhs) ? yb[j0 + rr][s2] : cx<TB>{TB(0), TB(0)};
+  }
+  for (int q = 0; q < jn; ++q) {
+    const int jj = UPPER ? jn - 1 - q : q;
+    const cx<T> lj = Lb[j0 + rr][jj];
+    if (UPPER) {
+      const cx<T> d = Lb[j0 + jj][jj];
+      const cx<TB> dd{(TB)d.re, (TB)d.im};
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        if (t < nt && rr == jj) y[t] = y[t] / dd;
+    }
+    const int src = (lane & 32) + jj;
+    const bool below = UPPER ? rr < jj : (rr > jj && rr < jn);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < nt) {
+        const cx<TB> yj{__shfl(y[t].re, src), __shfl(y[t].im, src)};
+        if (below) y[t] = y[t] - cx<TB>{(TB)lj.re, (TB)lj.im} * yj;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int s2 = 2 * t + hs;
+    if (t < nt && rr < jn && s2 < nrhs) yb[j0 + rr][s2] = y[t];
+  }
+}
+
 template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A, long ms, int n,
                                                     int k0, int nb, const int* __restrict__ ipiv,
@@ -537,6 +591,7 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
   constexpr int JB = 32;
   __shared__ cx<TB> yb[LU_NB][LU_MAX_RHS];
   __shared__ cx<T> Lb[LU_NB][JB + 1];  // a block of JB columns of the diagonal block
+  static_assert(JB == 32, "tri_wave holds 32 rows per half wavefront");
   for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
   __syncthreads();
   if (!upper) {
@@ -560,54 +615,49 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
     __syncthreads();
     for (int j0 = 0; j0 < nb; j0 += JB) {
       const int jn = min(JB, nb - j0);
-      for (int e = tid; e < nb * JB; e += 256) {
-        const int r = e / JB, jj = e % JB;
-        Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
+      stage_cols(a, n, k0, j0, nb, j0, jn, Lb);
+      __syncthreads();
+      // the triangle of the block: one wavefront, register-held entries
+      if (tid < 64) tri_wave<T, TB, false>(Lb, yb, j0, jn, nrhs);
+      __syncthreads();
+      // rows below the block inside the panel: a rank-jn update
+      for (int e = tid; e < (nb - j0 - jn) * nrhs; e += 256) {
+        const int r = j0 + jn + e % (nb - j0 - jn), s2 = e / (nb - j0 - jn);
+        cx<TB> acc = yb[r][s2];
+        for (int jj = 0; jj < jn; ++jj) {
+          const cx<T> l = Lb[r][jj];
+          acc = acc - cx<TB>{(TB)l.re, (TB)l.im} * yb[j0 + jj][s2];
+        }
+        yb[r][s2] = acc;
       }
       __syncthreads();
-      for (int jj = 0; jj < jn; ++jj) {
-        const int j = j0 + jj;
-        for (int e = tid; e < nb * nrhs; e += 256) {
-          const int r = e % nb, s = e / nb;
-          if (r > j) {
-            const cx<T> l = Lb[r][jj];
-            yb[r][s] = yb[r][s] - cx<TB>{(TB)l.re, (TB)l.im} * yb[j][s];
-          }
-        }
-        __syncthreads();
-      }
     }
   } else {
     for (int j1 = nb; j1 > 0; j1 -= JB) {  // columns [j0, j1), last block first
       const int j0 = max(0, j1 - JB), jn = j1 - j0;
-      for (int e = tid; e < nb * JB; e += 256) {
-        const int r = e / JB, jj = e % JB;
-        Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
+      stage_cols(a, n, k0, 0, j1, j0, jn, Lb);
+      __syncthreads();
+      if (tid < 64) tri_wave<T, TB, true>(Lb, yb, j0, jn, nrhs);
+      __syncthreads();
+      // rows above the block: a rank-jn update
+      for (int e = tid; e < j0 * nrhs; e += 256) {
+        const int r = e % j0, s2 = e / j0;
+        cx<TB> acc = yb[r][s2];
+        for (int jj = 0; jj < jn; ++jj) {
+          const cx<T> u = Lb[r][jj];
+          acc = acc - cx<TB>{(TB)u.re, (TB)u.im} * yb[j0 + jj][s2];
+        }
+        yb[r][s2] = acc;
       }
       __syncthreads();
-      for (int jj = jn - 1; jj >= 0; --jj) {
-        const int j = j0 + jj;
-        if (tid < nrhs) {
-          const cx<T> u = Lb[j][jj];
-          yb[j][tid] = yb[j][tid] / cx<TB>{(TB)u.re, (TB)u.im};
-        }
-        __syncthreads();
-        for (int e = tid; e < nb * nrhs; e += 256) {
-          const int r = e % nb, s = e / nb;
-          if (r < j) {
-            const cx<T> u = Lb[r][jj];
-            yb[r][s] = yb[r][s] - cx<TB>{(TB)u.re, (TB)u.im} * yb[j][s];
-          }
-        }
-        __syncthreads();
-      }
     }
   }
   for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
 }
 
-// rows [r0, r1) of b -= A[rows][k0 .. k0+nb) * b[k0 .. k0+nb); one wavefront
-// per row, lanes over the panel columns; grid (row blocks of 16, matrices).
+// rows [r0, r1) of b -= A[rows][k0 .. k0+nb) * b[k0 .. k0+nb); a wavefront
+// per 4 rows (all four rows' loads in flight together), lanes over the panel
+// columns; grid (row blocks of 16, matrices).
 template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ A, long ms, int n,
                                                       int k0, int nb, cx<TB>* __restrict__ B,
@@ -618,30 +668,42 @@ __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ 
   __shared__ cx<TB> yb[LU_MAX_RHS][LU_NB];
   for (int e = tid; e < nb * nrhs; e += 256) yb[e / nb][e % nb] = b[(long)(e / nb) * n + k0 + e % nb];
   __syncthreads();
-  for (int rr = 0; rr < 4; ++rr) {
-    const int r = r0 + blockIdx.x * 16 + wid * 4 + rr;
-    if (r >= r1) break;
-    const cx<T>* row = a + (long)r * n + k0;
-    cx<T> lv[LU_NB / 64];
+  constexpr int RW = 4, NC = LU_NB / 64;
+  const int rb = r0 + blockIdx.x * 16 + wid * RW;
+  if (rb >= r1) return;
+  // unconditional loads: rows past r1 re-read row r1 - 1, columns past nb
+  // re-read column nb - 1 (their products are dropped below)
+  cx<T> lv[RW][NC];
 #pragma unroll
-    for (int t = 0; t < LU_NB / 64; ++t) {
+  for (int q = 0; q < RW; ++q) {
+    const cx<T>* row = a + (long)min(rb + q, r1 - 1) * n + k0;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) lv[q][t] = row[min(lane + 64 * t, nb - 1)];
+  }
+  for (int s = 0; s < nrhs; ++s) {
+    cx<TB> acc[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) acc[q] = cx<TB>{TB(0), TB(0)};
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
       const int j = lane + 64 * t;
-      lv[t] = j < nb ? row[j] : cx<T>{T(0), T(0)};
-    }
-    for (int s = 0; s < nrhs; ++s) {
-      cx<TB> acc{TB(0), TB(0)};
+      if (j < nb) {
+        const cx<TB> y = yb[s][j];
 #pragma unroll
-      for (int t = 0; t < LU_NB / 64; ++t) {
-        const int j = lane + 64 * t;
-        if (j < nb) acc = acc + cx<TB>{(TB)lv[t].re, (TB)lv[t].im} * yb[s][j];
+        for (int q = 0; q < RW; ++q) acc[q] = acc[q] + cx<TB>{(TB)lv[q][t].re, (TB)lv[q][t].im} * y;
       }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        acc.re += __shfl_xor(acc.re, off);
-        acc.im += __shfl_xor(acc.im, off);
-      }
-      if (lane == 0) b[(long)s * n + r] = b[(long)s * n + r] - acc;
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+        acc[q].re += __shfl_xor(acc[q].re, off);
+        acc[q].im += __shfl_xor(acc[q].im, off);
+      }
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < RW; ++q)
+        if (rb + q < r1) b[(long)s * n + rb + q] = b[(long)s * n + rb + q] - acc[q];
   }
 }
 
