@@ -215,7 +215,7 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
   c->counters[4] = (double)count;
   c->counters[5] = (double)h[0];
   launch_list_far(c->nt_far, c->sgfb_geom.p, c->sgfb_dest.p, 0, h[1], c->M, 0, c->k1, c->k2, c->tw_far.p,
-                  c->A.p, n2, ms, W, nullptr, c->stream);
+                  c->A.p, n2, ms, W, nullptr, &c->cp, c->stream);
   HIPCHK(hipGetLastError());
 }
 
@@ -251,7 +251,7 @@ void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts) {
     counts[2] += cnt[2];
   }
   launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, 0, c->k1, c->k2, c->tw_far.p, nullptr, 0,
-                  0, nullptr, raw, c->stream);
+                  0, nullptr, raw, nullptr, c->stream);
   HIPCHK(hipGetLastError());
   run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw);
   launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,

@@ -61,9 +61,11 @@ void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, z
 // destinations (i, l).
 void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,
                           WorkList direct, hipStream_t st);
+// Far pairs of an explicit list; with cp, the pairs the classification marks
+// coarse are sampled on the half-length grid, as in the main grid.
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                      int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride,
-                     const double* W, zd* raw, hipStream_t st);
+                     const double* W, zd* raw, const ClassParams* cp, hipStream_t st);
 void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
                           WorkList split, WorkList direct, hipStream_t st);
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,

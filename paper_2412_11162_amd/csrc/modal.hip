@@ -120,22 +120,30 @@ __device__ __forceinline__ void transform_emit(const zd* st, zd* E, const zd* __
 // K = dG~/dnu' for both wavenumbers on the half circle D_j = 2 pi j / L,
 // j <= L/2 (R and the conormal factor are shared), staged in LDS, extended
 // to the full circle (the kernels are even in D), transformed by fft_wave;
-// modes 0..M are emitted.
+// modes 0..M are emitted.  A coarse pair is sampled at the odd j only (the
+// L/2-point grid shifted by half a step) with doubled weights and zeros at
+// the even j, so the same transform returns that grid's trapezoidal modes.
+// sin^2(D_j / 2) comes from the twiddle table: (1 - cos D) / 2, written as
+// sin^2 D / (2 (1 + cos D)) where cos D >= 0 to keep its relative accuracy.
 template <int R>
 __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const zd* __restrict__ tw,
-                                         zd* lds, const OutSpec& o, int2 dst) {
+                                         zd* lds, const OutSpec& o, int2 dst, bool coarse) {
   constexpr int L = 64 * R, H = L / 2 + 1;
   zd* P2 = lds;
   zd* P1 = pair_p1<R>(lds);
   zd* E = pair_e<R>(lds);
+  const int ns = coarse ? L / 4 : L / 2 + 1;
+  const double w4pi = (coarse ? 2.0 : 1.0) * (0.25 / PMLBIE_PI);
 #pragma unroll 1
-  for (int j = threadIdx.x; j <= L / 2; j += 64) {
-    const double sh = sin(PMLBIE_PI * j / L);
-    const double s2 = sh * sh;
+  for (int q = threadIdx.x; q < ns; q += 64) {
+    const int j = coarse ? 2 * q + 1 : q;
+    const zd t = tw[j];
+    const double s2 = t.re >= 0.0 ? t.im * t.im / (2.0 + 2.0 * t.re) : 0.5 - 0.5 * t.re;
     const zd R2 = v.d2 + s2 * v.c4;
     const zd Rd = csqrt_(R2);
-    const zd inv4piR = inv(Rd) * (0.25 / PMLBIE_PI);
-    const zd iR2 = inv(R2);
+    const zd iR = inv(Rd);
+    const zd inv4piR = iR * w4pi;
+    const zd iR2 = iR * iR;
     const zd N = v.N0 + s2 * v.N1;
     const zd ikR1 = zd{0.0, 1.0} * (k1 * Rd), ikR2 = zd{0.0, 1.0} * (k2 * Rd);
     const zd e1 = cexp_(ikR1) * inv4piR, e2 = cexp_(ikR2) * inv4piR;
@@ -143,6 +151,20 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
     P1[H + j] = N * e1 * (ikR1 - 1.0) * iR2;
     P2[j] = e2;
     P2[H + j] = N * e2 * (ikR2 - 1.0) * iR2;
+    if (coarse) {
+      const zd z0{0.0, 0.0};
+      P1[j - 1] = z0;
+      P1[H + j - 1] = z0;
+      P2[j - 1] = z0;
+      P2[H + j - 1] = z0;
+    }
+  }
+  if (coarse && threadIdx.x == 0) {
+    const zd z0{0.0, 0.0};
+    P1[L / 2] = z0;
+    P1[H + L / 2] = z0;
+    P2[L / 2] = z0;
+    P2[H + L / 2] = z0;
   }
   __syncthreads();
   transform_emit<R>(P1, E, tw, o, dst, 0);
@@ -169,7 +191,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (dp >= -1 && dp <= 1) continue;  // near panels: product integration
     const PairGeom g = node_pair(nd, i, l);
     const PairInv v = pair_invariants(g);
-    const int cls = classify(g, v, cp);
+    bool coarse = false;
+    const int cls = classify(g, v, cp, &coarse);
     if (cls != CLASS_FAR) {
       if (threadIdx.x == 0) {
         WorkList& wl = cls == CLASS_SPLIT ? split : direct;
@@ -181,7 +204,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       }
       continue;
     }
-    far_pair<R>(v, k1, k2, tw, lds, o, make_int2(i, l));
+    far_pair<R>(v, k1, k2, tw, lds, o, make_int2(i, l), coarse);
   }
 }
 
@@ -249,12 +272,15 @@ template <int R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_list_far(const PairGeom* __restrict__ geom,
                                                  const int2* __restrict__ dest, long first,
                                                  long count, zd k1, zd k2,
-                                                 const zd* __restrict__ tw, OutSpec o) {
+                                                 const zd* __restrict__ tw, OutSpec o,
+                                                 ClassParams cp, int use_coarse) {
   __shared__ zd lds[pair_lds<R>()];
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
     const PairGeom g = geom[first + t];
     const PairInv v = pair_invariants(g);
-    far_pair<R>(v, k1, k2, tw, lds, o, dest[first + t]);
+    bool coarse = false;
+    if (use_coarse) (void)classify(g, v, cp, &coarse);
+    far_pair<R>(v, k1, k2, tw, lds, o, dest[first + t], coarse);
   }
 }
 
@@ -678,21 +704,22 @@ void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList fa
 
 template <int R>
 static void launch_list_far_t(const PairGeom* geom, const int2* dest, long first, long count,
-                              zd k1, zd k2, const zd* tw, const OutSpec& o, hipStream_t st) {
+                              zd k1, zd k2, const zd* tw, const OutSpec& o, const ClassParams* cp,
+                              hipStream_t st) {
   int grid = (int)std::min<long>(count, 256L * 128);
   hipLaunchKernelGGL(k_list_far<R>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2,
-                     tw, o);
+                     tw, o, cp ? *cp : ClassParams{}, cp ? 1 : 0);
 }
 
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                      int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride,
-                     const double* W, zd* raw, hipStream_t st) {
+                     const double* W, zd* raw, const ClassParams* cp, hipStream_t st) {
   if (count <= 0) return;
   OutSpec o{A, n2, mstride, W, raw, M, m0};
   switch (nt) {
-    case 512: launch_list_far_t<8>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 1024: launch_list_far_t<16>(geom, dest, first, count, k1, k2, tw, o, st); break;
-    case 2048: launch_list_far_t<32>(geom, dest, first, count, k1, k2, tw, o, st); break;
+    case 512: launch_list_far_t<8>(geom, dest, first, count, k1, k2, tw, o, cp, st); break;
+    case 1024: launch_list_far_t<16>(geom, dest, first, count, k1, k2, tw, o, cp, st); break;
+    case 2048: launch_list_far_t<32>(geom, dest, first, count, k1, k2, tw, o, cp, st); break;
     default: break;
   }
 }

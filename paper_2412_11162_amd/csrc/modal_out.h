@@ -82,12 +82,18 @@ __device__ __forceinline__ int bitrev(int j) {
 // Classification of a pair (Sec. 4.1: well-separated pairs by FFT of the raw
 // kernel; close pairs by the split; close pairs deep in the PML by graded
 // direct quadrature, where cos(kR) grows like exp(max |Im kR|)).
-__device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, const ClassParams& cp) {
+// A far pair is also marked coarse when the same aliasing bound holds on the
+// grid of half the length (its modes beyond L/2 - M are as negligible).
+__device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, const ClassParams& cp,
+                                        bool* coarse = nullptr) {
   double delta, re0;
   singularity(v, delta, re0);
   const double sc = sqrt(cabs_(g.rt * g.rs));
   const double bw = cp.bw * cp.kmax * sc;
-  if ((cp.nt_far - cp.M - bw) * delta >= cp.c_far) return CLASS_FAR;
+  if ((cp.nt_far - cp.M - bw) * delta >= cp.c_far) {
+    if (coarse) *coarse = (cp.nt_far / 2 - cp.M - bw) * delta >= cp.c_far;
+    return CLASS_FAR;
+  }
   zd Rpi = csqrt_(v.d2 + v.c4);
   double grow = cp.kmax * fabs(Rpi.im) + cp.kmax_im * fabs(Rpi.re);
   return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
