@@ -204,15 +204,27 @@ def test_paper_scale_modal_kernels_sampled(paper_solver):
             assert _normwise(out[:, sidx, n], refr[:, sidx, n]) <= KERNEL_TOL, (sidx, n)
 
 
-def test_paper_scale_operator_rows(paper_solver):
-    """Rows of the assembled matrices (far, split, direct and near-panel
-    entries) at the benchmark size for three modes."""
+@pytest.fixture(scope="module")
+def paper_rows():
+    """Oracle operator rows and point-source data at the benchmark size for
+    three rows (a physical node, a node of the bump, a PML node) and five
+    modes."""
     import oracle
-    wl, s = paper_solver
+    wl = workloads.paper_scale()
     g = oracle.geometry(wl)
     rows = [5, 1100, 1700]
-    modes = [0, 64, 128]
+    modes = [0, 2, 8, 64, 128]
     S, K = oracle.core.operator_rows(g, rows, [wl.k1, wl.k2], modes)
+    inc = wl.incidences[0]
+    b1, b2 = oracle.rhs_point_source(g, modes, inc[1], inc[2])
+    return g, rows, modes, S, K, b1, b2
+
+
+def test_paper_scale_operator_rows(paper_solver, paper_rows):
+    """Rows of the assembled matrices (far, split, direct and near-panel
+    entries) at the benchmark size for three modes."""
+    wl, s = paper_solver
+    g, rows, modes, S, K, _, _ = paper_rows
     N = g.n
     for j, n in enumerate(modes):
         G = s.get_operator(n).cpu().numpy()
@@ -220,6 +232,51 @@ def test_paper_scale_operator_rows(paper_solver):
         for (blkG, ref) in ((G[rows, :N], K[0, j] + I), (G[rows, N:], -S[0, j]),
                             (G[[N + r for r in rows], :N], K[1, j] - I), (G[[N + r for r in rows], N:], -S[1, j])):
             assert _normwise(blkG, ref) <= KERNEL_TOL, n
+
+
+def _row_backward_errors(out, rows_data):
+    """Componentwise relative residuals of the oracle's rows of
+    [[K1 + I, -S1], [K2 - I, -S2]] x = [0; (K2 - I) b1 - S2 b2] at the GPU
+    solution x = [u1; phi1].  Modes whose data vanish (the source's modes
+    decay fast with n) hold only the rounding noise of their right-hand side
+    (~1e-16 of the largest mode), so every residual is measured against at
+    least 1e-6 of the largest scale."""
+    g, rows, modes, S, K, b1, b2 = rows_data
+    u1 = out[0][:, 0, :].cpu().numpy()
+    p1 = out[1][:, 0, :].cpu().numpy()
+    res, den = [], []
+    for j, n in enumerate(modes):
+        x1, x2 = u1[n], p1[n]
+        for q, i in enumerate(rows):
+            res.append(abs(K[0, j][q] @ x1 + x1[i] - S[0, j][q] @ x2))
+            den.append(np.abs(K[0, j][q]) @ np.abs(x1) + abs(x1[i]) + np.abs(S[0, j][q]) @ np.abs(x2))
+            lo = K[1, j][q] @ x1 - x1[i] - S[1, j][q] @ x2
+            rhs = K[1, j][q] @ b1[j] - b1[j][i] - S[1, j][q] @ b2[j]
+            res.append(abs(lo - rhs))
+            den.append(np.abs(K[1, j][q]) @ (np.abs(x1) + np.abs(b1[j])) + abs(x1[i]) + abs(b1[j][i])
+                       + np.abs(S[1, j][q]) @ (np.abs(x2) + np.abs(b2[j])))
+    res, den = np.array(res), np.array(den)
+    return res / np.maximum(den, 1e-6 * den.max())
+
+
+def test_paper_scale_solution_satisfies_oracle_rows(paper_solver, paper_rows):
+    """The solve at the benchmark size, pinned without a full oracle solve:
+    the GPU solution satisfies the oracle's own equations (rows and
+    right-hand side) to a componentwise backward error within the
+    boundary-data bar (a wrong pivot, interchange or substitution gives
+    O(1); a relative change of 1e-6 in u1 gives ~4e-7)."""
+    wl, s = paper_solver
+    errs = _row_backward_errors(s.solve_modes(list(wl.incidences)), paper_rows)
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+
+
+def test_mixed_paper_scale_solution_satisfies_oracle_rows(paper_rows):
+    """Same check for the complex64 LU with FP64 refinement."""
+    from paper_2412_11162_amd._binding import PMLBIE_MIXED
+    wl = workloads.paper_scale()
+    s = _solver(wl, precision=PMLBIE_MIXED)
+    errs = _row_backward_errors(s.solve_modes(list(wl.incidences)), paper_rows)
+    assert np.max(errs) <= BOUNDARY_TOL, errs
 
 
 def test_paper_scale_boundary_data_against_stored_oracle(paper_solver):
