@@ -295,16 +295,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 __global__ __launch_bounds__(64) void k_split_singular(const PairGeom* __restrict__ geom,
                                                        long first, long count, int MQ,
                                                        zd* __restrict__ zhat,
-                                                       zd* __restrict__ phat,
-                                                       zd* __restrict__ qscr) {
+                                                       zd* __restrict__ phat) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   const PairGeom g = geom[first + t];
   const PairInv v = pair_invariants(g);
   const zd c = 2.0 * (g.rt * g.rs);
   const zd chim1 = v.d2 / c;
-  zd* Q = qscr + t * (MQ + 1);
-  legendre_q_half(chim1, MQ, Q);
+  // tables are [m][pair] (consecutive lanes write consecutive pairs); Q is
+  // formed in the Zhat table and scaled in place below
+  zd* zo = zhat + t;
+  zd* po = phat + t;
+  legendre_q_half(chim1, MQ, zo, count);
   const zd sc = csqrt_(c);
   const zd Rpi = csqrt_(v.d2 + v.c4);
   const zd Rsp = sc * csqrt_(chim1 + 2.0);
@@ -315,16 +317,16 @@ __global__ __launch_bounds__(64) void k_split_singular(const PairGeom* __restric
   const zd fp = (sgn * (-4.0) * rt2) * isc * isc * isc;            // Phat_m = fp Q'_m
   const zd chi2m1 = chim1 * (chim1 + 2.0);
   const zd ichi2 = inv(chi2m1);
-  zd* zo = zhat + t * (MQ + 1);
-  zd* po = phat + t * (MQ + 1);
+  zd qprev = zo[(long)(1 < MQ ? 1 : MQ) * count];  // Q_{-3/2} = Q_{1/2}
   for (int m = 0; m <= MQ; ++m) {
-    const zd qm = Q[m];
-    const zd qm1 = m == 0 ? Q[1 < MQ ? 1 : MQ] : Q[m - 1];
+    const zd qm = zo[(long)m * count];
+    const zd qm1 = qprev;
+    qprev = qm;
     // Q'_{m-1/2} = (m - 1/2)(chi Q_{m-1/2} - Q_{m-3/2})/(chi^2 - 1)
     const zd num = chim1 * qm + (qm - qm1);
     const zd dq = (m - 0.5) * num * ichi2;
-    zo[m] = fz * qm;
-    po[m] = fp * dq;
+    zo[(long)m * count] = fz * qm;
+    po[(long)m * count] = fp * dq;
   }
 }
 
@@ -356,8 +358,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int2 dst = dest[first + t];
     const PairInv v = pair_invariants(g);
     const SplitCoef sc = split_coef(g, v);
-    const zd* zz = zhat + t * (MQ + 1);
-    const zd* pp = phat + t * (MQ + 1);
+    const zd* zz = zhat + t;  // [m][pair] tables
+    const zd* pp = phat + t;
     const zd e0f = (-0.25 / PMLBIE_PI) * sc.e0;
     const zd e1f = -1.0 * sc.e1;
     {
@@ -372,8 +374,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           const int mm = m <= L / 2 ? m : L - m;
           zd zm{0.0, 0.0}, dm{0.0, 0.0};
           if (mm <= MQ) {
-            zm = zz[mm];
-            dm = e0f * pp[mm] + e1f * zm;
+            zm = zz[(long)mm * count];
+            dm = e0f * pp[(long)mm * count] + e1f * zm;
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) sg[q][a] = (q0 + q) == 0 ? zm : dm;
@@ -732,11 +734,11 @@ void launch_classify_list(const PairGeom* geom, long count, const ClassParams& c
 }
 
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
-                           zd* phat, zd* qscr, hipStream_t st) {
+                           zd* phat, hipStream_t st) {
   if (count <= 0) return;
   int blocks = (int)((count + 63) / 64);
   hipLaunchKernelGGL(k_split_singular, dim3(blocks), dim3(64), 0, st, geom, first, count, MQ,
-                     zhat, phat, qscr);
+                     zhat, phat);
 }
 
 template <int R>

@@ -162,11 +162,11 @@ HD zd carlson_rd(zd x, zd y, zd z) {
   return p4 * ser * iA * inv(csqrt_(Am)) + 3.0 * sum;
 }
 
-// Q[m] = Q_{m-1/2}(chi) for m = 0..mq, chi = 1 + chim1 (chim1 passed exactly).
+// Q[m qs] = Q_{m-1/2}(chi) for m = 0..mq, chi = 1 + chim1 (chim1 passed exactly).
 // Q_{-1/2} = sqrt2 RF(0, chi-1, chi+1); Q_{1/2} from RF and RD; higher
 // degrees by forward recurrence when it is stable over the range, else by the
 // backward (Miller) ratio recurrence normalised by Q_{-1/2}.
-HD void legendre_q_half(zd chim1, int mq, zd* Q) {
+HD void legendre_q_half(zd chim1, int mq, zd* Q, long qs = 1) {
   const double rt2 = 1.4142135623730950488;
   zd chi = chim1 + 1.0;
   zd zero = zd{0.0, 0.0};
@@ -177,22 +177,22 @@ HD void legendre_q_half(zd chim1, int mq, zd* Q) {
   double La = log(fmax(cabs_(chi + s), cabs_(chi - s)));  // -log of the decay ratio
   if (2.0 * mq * La <= 6.0) {
     zd rd = carlson_rd(zero, chim1, chim1 + 2.0);
-    Q[1] = rt2 * (-rf + (2.0 / 3.0) * (chim1 + 2.0) * rd);
+    Q[qs] = rt2 * (-rf + (2.0 / 3.0) * (chim1 + 2.0) * rd);
     for (int m = 1; m < mq; ++m) {
       // (m + 1/2) Q_{m+1/2} = 2 m chi Q_{m-1/2} - (m - 1/2) Q_{m-3/2}
-      Q[m + 1] = ((2.0 * m) * chi * Q[m] - (m - 0.5) * Q[m - 1]) * (1.0 / (m + 0.5));
+      Q[(m + 1) * qs] = ((2.0 * m) * chi * Q[m * qs] - (m - 0.5) * Q[(m - 1) * qs]) * (1.0 / (m + 0.5));
     }
   } else {
     int ns = mq + (int)ceil(19.0 / La) + 8;
     if (ns > mq + 6000) ns = mq + 6000;
     zd r = zero;  // r_{m} = Q_{m-1/2} / Q_{m-3/2}
     for (int m = ns; m > mq; --m) r = (m - 0.5) * inv((2.0 * m) * chi - (m + 0.5) * r);
-    // keep the ratios for m = mq..1 in Q[m] temporarily
+    // keep the ratios for m = mq..1 in Q temporarily
     for (int m = mq; m >= 1; --m) {
       r = (m - 0.5) * inv((2.0 * m) * chi - (m + 0.5) * r);
-      Q[m] = r;
+      Q[m * qs] = r;
     }
-    for (int m = 1; m <= mq; ++m) Q[m] = Q[m] * Q[m - 1];
+    for (int m = 1; m <= mq; ++m) Q[m * qs] = Q[m * qs] * Q[(m - 1) * qs];
   }
 }
 
