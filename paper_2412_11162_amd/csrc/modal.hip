@@ -55,6 +55,13 @@ template <int R>
 constexpr int pair_lds() {
   return R <= 16 ? (32 * R + 1) * 2 + 2 * fft_wave_lds<R>() : 4 * (32 * R + 1) + fft_wave_lds<R>();
 }
+// The far-pair path transforms one sequence at a time, so for R <= 16 its E
+// needs only one exchange area (which also covers P1).
+template <int R>
+constexpr int far_lds() {
+  return R <= 16 ? 2 * (32 * R + 1) + (fft_wave_lds<R>() > 2 * (32 * R + 1) ? fft_wave_lds<R>() : 2 * (32 * R + 1))
+                 : pair_lds<R>();
+}
 template <int R>
 __device__ __forceinline__ zd* pair_p1(zd* lds) {
   return lds + 2 * (32 * R + 1);
@@ -178,7 +185,7 @@ template <int R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
                                                  WorkList split, WorkList direct) {
-  __shared__ zd lds[pair_lds<R>()];
+  __shared__ zd lds[far_lds<R>()];
   const int N = nd.N;
   const long total = (long)N * N;
   // workgroups are dealt to the 8 XCDs round-robin; each XCD takes a
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                  long count, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
                                                  ClassParams cp, int use_coarse) {
-  __shared__ zd lds[pair_lds<R>()];
+  __shared__ zd lds[far_lds<R>()];
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
     const PairGeom g = geom[first + t];
     const PairInv v = pair_invariants(g);
