@@ -89,7 +89,7 @@ struct pmlbie_ctx {
   DBuf<PairGeom> lgeom;
   DBuf<int2> ldest;
   DBuf<unsigned> lcount;
-  DBuf<zd> zhat, phat;
+  DBuf<zd> zhat, phat, qtab, qcoef;
   DBuf<zd> raw;
   DBuf<PairGeom> xgeom;
   DBuf<double> coef;
@@ -178,7 +178,9 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
     const long cn = std::min(CH, count - f);
     c->zhat.alloc((size_t)CH * (c->MQ + 1));
     c->phat.alloc((size_t)CH * (c->MQ + 1));
-    launch_split_singular(geom, f, cn, c->MQ, c->zhat.p, c->phat.p, c->stream);
+    c->qtab.alloc((size_t)CH * (c->MQ + 1));
+    c->qcoef.alloc((size_t)CH * 4);
+    launch_split_singular(geom, f, cn, c->MQ, c->qtab.p, c->qcoef.p, c->zhat.p, c->phat.p, c->stream);
     HIPCHK(hipGetLastError());
     launch_split(c->nt_int, geom, dest, f, cn, c->M, c->m0, c->MQ, c->k1, c->k2, c->tw_int.p, c->zhat.p,
                  c->phat.p, A, n2, ms, W, raw, c->stream);

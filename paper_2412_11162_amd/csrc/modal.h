@@ -68,10 +68,11 @@ void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first,
                      const double* W, zd* raw, const ClassParams* cp, hipStream_t st);
 void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
                           WorkList split, WorkList direct, hipStream_t st);
-// Singular-part modes of split pairs: zhat, phat hold [MQ + 1][count]
-// entries (mode-major, consecutive pairs adjacent), read by launch_split.
-void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
-                           zd* phat, hipStream_t st);
+// Singular-part modes of split pairs: qtab ([MQ + 1][count], mode-major)
+// and coef (4 per pair) are work space; zhat, phat receive [count][MQ + 1]
+// (pair-major), read by launch_split.
+void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* qtab, zd* coef,
+                           zd* zhat, zd* phat, hipStream_t st);
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                   int m0, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
                   zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st);

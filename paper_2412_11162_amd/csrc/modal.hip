@@ -292,48 +292,68 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 }
 
 // ------------------------------------------------------------------------
-// Split pairs, phase 1 (one lane per pair): the semi-analytic modes of the
-// singular factors, Zhat_m = modes of 1/(4 pi R) and Phat_m = modes of 1/R^3,
-// m = 0..MQ, from Q_{m-1/2}(chi), chi = 1 + d2/(2 rho~ rho~').
+// Split pairs, phase 1 (one lane per pair): Q_{m-1/2}(chi), m = 0..MQ,
+// chi = 1 + d2/(2 rho~ rho~'), and the factors that turn it into the
+// semi-analytic modes of the singular factors, Zhat_m = modes of 1/(4 pi R)
+// and Phat_m = modes of 1/R^3 (formed in phase 1b):
 //   modes of (chi - cos D)^{-1/2} = 2 sqrt2 Q_{m-1/2}(chi)          (Heine)
 //   modes of (chi - cos D)^{-3/2} = -4 sqrt2 Q'_{m-1/2}(chi)
 // and R = sgn sqrt(c) sqrt(chi - cos D), c = 2 rho~ rho~', with the sign
 // fixed by continuity against the principal R at D = pi.
 __global__ __launch_bounds__(64) void k_split_singular(const PairGeom* __restrict__ geom,
                                                        long first, long count, int MQ,
-                                                       zd* __restrict__ zhat,
-                                                       zd* __restrict__ phat) {
+                                                       zd* __restrict__ qtab,
+                                                       zd* __restrict__ coef) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   const PairGeom g = geom[first + t];
   const PairInv v = pair_invariants(g);
   const zd c = 2.0 * (g.rt * g.rs);
   const zd chim1 = v.d2 / c;
-  // tables are [m][pair] (consecutive lanes write consecutive pairs); Q is
-  // formed in the Zhat table and scaled in place below
-  zd* zo = zhat + t;
-  zd* po = phat + t;
-  legendre_q_half(chim1, MQ, zo, count);
+  // Q is [m][pair], so that consecutive lanes write consecutive pairs
+  legendre_q_half(chim1, MQ, qtab + t, count);
   const zd sc = csqrt_(c);
   const zd Rpi = csqrt_(v.d2 + v.c4);
   const zd Rsp = sc * csqrt_(chim1 + 2.0);
   const double sgn = cabs_(Rpi - Rsp) <= cabs_(Rpi + Rsp) ? 1.0 : -1.0;
   const double rt2 = 1.4142135623730950488;
   const zd isc = inv(sc);
-  const zd fz = (sgn * 2.0 * rt2 * (0.25 / PMLBIE_PI)) * isc;     // Zhat_m = fz Q_m
-  const zd fp = (sgn * (-4.0) * rt2) * isc * isc * isc;            // Phat_m = fp Q'_m
-  const zd chi2m1 = chim1 * (chim1 + 2.0);
-  const zd ichi2 = inv(chi2m1);
-  zd qprev = zo[(long)(1 < MQ ? 1 : MQ) * count];  // Q_{-3/2} = Q_{1/2}
-  for (int m = 0; m <= MQ; ++m) {
-    const zd qm = zo[(long)m * count];
-    const zd qm1 = qprev;
-    qprev = qm;
-    // Q'_{m-1/2} = (m - 1/2)(chi Q_{m-1/2} - Q_{m-3/2})/(chi^2 - 1)
-    const zd num = chim1 * qm + (qm - qm1);
-    const zd dq = (m - 0.5) * num * ichi2;
-    zo[(long)m * count] = fz * qm;
-    po[(long)m * count] = fp * dq;
+  zd* cf = coef + 4 * t;
+  cf[0] = (sgn * 2.0 * rt2 * (0.25 / PMLBIE_PI)) * isc;  // Zhat_m = cf0 Q_m
+  cf[1] = (sgn * (-4.0) * rt2) * isc * isc * isc;        // Phat_m = cf1 Q'_m
+  cf[2] = chim1;
+  cf[3] = inv(chim1 * (chim1 + 2.0));                    // 1 / (chi^2 - 1)
+}
+
+// Split pairs, phase 1b: Zhat and Phat in pair-major tables (the layout the
+// split kernel reads) from the mode-major Q table, through an LDS tile of 64
+// pairs x 64 modes (plus the mode below the tile):
+//   Q'_{m-1/2} = (m - 1/2)(chi Q_{m-1/2} - Q_{m-3/2}) / (chi^2 - 1),
+// with Q_{-3/2} = Q_{1/2}.
+__global__ __launch_bounds__(256) void k_split_tables(const zd* __restrict__ qtab,
+                                                      const zd* __restrict__ coef, long count,
+                                                      int MQ, zd* __restrict__ zhat,
+                                                      zd* __restrict__ phat) {
+  __shared__ zd Qs[65][65];  // [mode - m0 + 1][pair - p0]
+  const long p0 = (long)blockIdx.x * 64;
+  const int m0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 65 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int m = (m0 == 0 && r == 0) ? (MQ >= 1 ? 1 : 0) : m0 - 1 + r;
+    const long p = p0 + c;
+    Qs[r][c] = (p < count && m <= MQ) ? qtab[(long)m * count + p] : zd{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int c = e >> 6, r = e & 63;  // a wavefront per pair, lanes over modes
+    const long p = p0 + c;
+    const int m = m0 + r;
+    if (p >= count || m > MQ) continue;
+    const zd* cf = coef + 4 * p;
+    const zd qm = Qs[r + 1][c], qm1 = Qs[r][c];
+    const zd num = cf[2] * qm + (qm - qm1);
+    zhat[p * (MQ + 1) + m] = cf[0] * qm;
+    phat[p * (MQ + 1) + m] = cf[1] * ((m - 0.5) * num * cf[3]);
   }
 }
 
@@ -365,8 +385,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int2 dst = dest[first + t];
     const PairInv v = pair_invariants(g);
     const SplitCoef sc = split_coef(g, v);
-    const zd* zz = zhat + t;  // [m][pair] tables
-    const zd* pp = phat + t;
+    const zd* zz = zhat + t * (MQ + 1);
+    const zd* pp = phat + t * (MQ + 1);
     const zd e0f = (-0.25 / PMLBIE_PI) * sc.e0;
     const zd e1f = -1.0 * sc.e1;
     {
@@ -381,8 +401,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           const int mm = m <= L / 2 ? m : L - m;
           zd zm{0.0, 0.0}, dm{0.0, 0.0};
           if (mm <= MQ) {
-            zm = zz[(long)mm * count];
-            dm = e0f * pp[(long)mm * count] + e1f * zm;
+            zm = zz[mm];
+            dm = e0f * pp[mm] + e1f * zm;
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) sg[q][a] = (q0 + q) == 0 ? zm : dm;
@@ -740,12 +760,14 @@ void launch_classify_list(const PairGeom* geom, long count, const ClassParams& c
                      count, cp, far, split, direct);
 }
 
-void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* zhat,
-                           zd* phat, hipStream_t st) {
+void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* qtab, zd* coef,
+                           zd* zhat, zd* phat, hipStream_t st) {
   if (count <= 0) return;
   int blocks = (int)((count + 63) / 64);
-  hipLaunchKernelGGL(k_split_singular, dim3(blocks), dim3(64), 0, st, geom, first, count, MQ,
-                     zhat, phat);
+  hipLaunchKernelGGL(k_split_singular, dim3(blocks), dim3(64), 0, st, geom, first, count, MQ, qtab,
+                     coef);
+  hipLaunchKernelGGL(k_split_tables, dim3((unsigned)((count + 63) / 64), (unsigned)((MQ + 64) / 64)),
+                     dim3(256), 0, st, qtab, coef, count, MQ, zhat, phat);
 }
 
 template <int R>
