@@ -245,46 +245,55 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
 }
 
 // ---------------------------------------------------------------------------
-// X = L11^{-1} B for a tile of 32 columns, held in LDS.  The rows are taken
-// in blocks of 32: the triangle of a block is solved by wavefronts without
-// barriers (lane = row of the block x one of two columns; the solved value of
-// row q comes by a shuffle from lane q of the same half), then the rows below
-// get the block's rank-32 update.  With W == nullptr, B = A12 (columns
-// k0 + nb .. cend - 1 of the panel rows) is overwritten by U12; otherwise B is
-// the identity and X = L11^{-1} is written to W + b * LU_NB^2 (row-major,
-// leading dimension LU_NB).
-constexpr int TRSM_C = 32;  // columns per workgroup
+// X = L11^{-1} B for a tile of trsm_cols<T>() columns, held in LDS.  The
+// rows are taken in blocks of JB = trsm_jb<T>(): the triangle of a block is
+// solved by wavefronts without barriers (lane = row of the block x one of
+// 64 / JB columns; the solved value of row q comes by a shuffle from lane q
+// of the same group), then the rows below get the block's rank-JB update.
+// With W == nullptr, B = A12 (columns k0 + nb .. cend - 1 of the panel rows)
+// is overwritten by U12; otherwise B is the identity and X = L11^{-1} is
+// written to W + b * LU_NB^2 (row-major, leading dimension LU_NB).  FP64 uses
+// 16-wide blocks and tiles so that two workgroups fit in one CU's LDS.
+template <typename T>
+constexpr int trsm_jb() {
+  return sizeof(T) == 8 ? 16 : 32;
+}
+template <typename T>
+constexpr int trsm_cols() {
+  return sizeof(T) == 8 ? 16 : 32;
+}
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, int n, int k0,
                                               int nb, int cend, cx<T>* __restrict__ W) {
+  constexpr int JB = trsm_jb<T>(), TC = trsm_cols<T>(), G = 64 / JB;
   cx<T>* a = A + (long)blockIdx.y * ms;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int cbase = (W ? 0 : k0 + nb) + blockIdx.x * TRSM_C;
+  const int cbase = (W ? 0 : k0 + nb) + blockIdx.x * TC;
   const int cmax = W ? nb : cend;
-  __shared__ cx<T> Xs[LU_NB][TRSM_C + 1];
-  __shared__ cx<T> Lb[LU_NB][33];
+  __shared__ cx<T> Xs[LU_NB][TC + 1];
+  __shared__ cx<T> Lb[LU_NB][JB + 1];
   const cx<T> zero{T(0), T(0)};
-  for (int e = tid; e < nb * TRSM_C; e += 256) {
-    const int r = e / TRSM_C, cc = e % TRSM_C, c = cbase + cc;
+  for (int e = tid; e < nb * TC; e += 256) {
+    const int r = e / TC, cc = e % TC, c = cbase + cc;
     if (W)
       Xs[r][cc] = cx<T>{(c < cmax && r == c) ? T(1) : T(0), T(0)};
     else
       Xs[r][cc] = c < cmax ? a[(long)(k0 + r) * n + c] : zero;
   }
-  for (int j0 = 0; j0 < nb; j0 += 32) {
-    const int jn = min(32, nb - j0);
-    for (int e = j0 * 32 + tid; e < nb * 32; e += 256) {
-      const int r = e >> 5, jj = e & 31;
+  for (int j0 = 0; j0 < nb; j0 += JB) {
+    const int jn = min(JB, nb - j0);
+    for (int e = j0 * JB + tid; e < nb * JB; e += 256) {
+      const int r = e / JB, jj = e % JB;
       Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : zero;
     }
     __syncthreads();
     {
-      const int rr = lane & 31, hs = lane >> 5;
-      for (int cp = wid; cp < TRSM_C / 2; cp += 4) {
-        const int cc = 2 * cp + hs;
+      const int rr = lane % JB, gs = lane / JB, base = lane - rr;
+      for (int cg = wid; cg < TC / G; cg += 4) {
+        const int cc = G * cg + gs;
         cx<T> y = rr < jn ? Xs[j0 + rr][cc] : zero;
         for (int q = 0; q < jn; ++q) {
-          const int src = (lane & 32) + q;
+          const int src = base + q;
           const cx<T> yq{__shfl(y.re, src), __shfl(y.im, src)};
           if (rr > q && rr < jn) y = y - Lb[j0 + rr][q] * yq;
         }
@@ -294,16 +303,16 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
     __syncthreads();
     // rows below the block: a rank-jn update
     const int r0 = j0 + jn;
-    for (int e = tid; e < (nb - r0) * TRSM_C; e += 256) {
-      const int r = r0 + e / TRSM_C, cc = e % TRSM_C;
+    for (int e = tid; e < (nb - r0) * TC; e += 256) {
+      const int r = r0 + e / TC, cc = e % TC;
       cx<T> acc = Xs[r][cc];
       for (int q = 0; q < jn; ++q) acc = acc - Lb[r][q] * Xs[j0 + q][cc];
       Xs[r][cc] = acc;
     }
     __syncthreads();
   }
-  for (int e = tid; e < nb * TRSM_C; e += 256) {
-    const int r = e / TRSM_C, cc = e % TRSM_C, c = cbase + cc;
+  for (int e = tid; e < nb * TC; e += 256) {
+    const int r = e / TC, cc = e % TC, c = cbase + cc;
     if (c >= cmax) continue;
     if (W)
       W[(long)blockIdx.y * LU_NB * LU_NB + (long)r * LU_NB + c] = Xs[r][cc];
@@ -737,12 +746,12 @@ static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch
   if (cols <= 0) return;
   if (W) {
     // U12 = (L11^{-1}) A12: the inverse by the column solver, the product on MFMA
-    hipLaunchKernelGGL(k_trsm<T>, dim3((nb + TRSM_C - 1) / TRSM_C, batch), dim3(256), 0, st, A, ms, n, k0, nb,
+    hipLaunchKernelGGL(k_trsm<T>, dim3((nb + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms, n, k0, nb,
                        cend, W);
     hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(512), 0, st, A, ms, n, k0,
                        nb, cend, (const cx<T>*)W);
   } else {
-    hipLaunchKernelGGL(k_trsm<T>, dim3((cols + TRSM_C - 1) / TRSM_C, batch), dim3(256), 0, st, A, ms, n, k0, nb,
+    hipLaunchKernelGGL(k_trsm<T>, dim3((cols + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms, n, k0, nb,
                        cend, (cx<T>*)nullptr);
   }
   if (rows > 0) {
