@@ -345,9 +345,9 @@ template <> struct mfma_t<float> {
 
 // U12 = L11^{-1} A12 on MFMA, in place: one workgroup per strip of 64
 // trailing columns of the panel rows (it reads the whole strip before writing
-// it), W = L11^{-1} from k_trsm.  Eight waves of 32 x 32 (four row blocks x
-// two column blocks); the K chunks above a wave's rows are skipped (W is
-// lower triangular).
+// it), W = L11^{-1} from k_trsm.  Eight waves, each with two 16-row tiles
+// (t and 7 - t) x 32 columns; the K chunks above a tile's rows are skipped (W
+// is lower triangular), which leaves every wave the same work.
 template <typename T>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_trsm_mfma(
     cx<T>* __restrict__ A, long ms, int n, int k0, int nb, int cend, const cx<T>* __restrict__ W) {
@@ -359,7 +359,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   __shared__ T Lre[KC][LU_NB + 4], Lim[KC][LU_NB + 4];  // W chunk: [k][row]
   __shared__ T Bre[KC][64 + 4], Bim[KC][64 + 4];        // A12 chunk: [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = (wid & 3) * 32, wc = (wid >> 2) * 32;
+  // wave: 16-row tiles t and 7 - t of the strip (W is lower triangular, so
+  // tile t needs the first t + 1 K chunks: every wave has the same work)
+  const int rt0 = 16 * (wid & 3), rt1 = 16 * (7 - (wid & 3)), wc = (wid >> 2) * 32;
   acc_t cr[2][2], ci[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -387,15 +389,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       Bim[k][cc] = v.im;
     }
     __syncthreads();
-    if (kk < wr + 32) {
+    if (kk < rt1 + 16) {
+      const bool both = kk < rt0 + 16;  // tile rt0 still below the diagonal
 #pragma unroll 1
       for (int k4 = 0; k4 < KC; k4 += 4) {
         const int kx = k4 + (lane >> 4), lx = lane & 15;
         T lr[2], li[2], br[2], bi[2];
+        lr[0] = Lre[kx][rt0 + lx];
+        li[0] = Lim[kx][rt0 + lx];
+        lr[1] = Lre[kx][rt1 + lx];
+        li[1] = Lim[kx][rt1 + lx];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          lr[t] = Lre[kx][wr + 16 * t + lx];
-          li[t] = Lim[kx][wr + 16 * t + lx];
           br[t] = Bre[kx][wc + 16 * t + lx];
           bi[t] = Bim[kx][wc + 16 * t + lx];
         }
@@ -403,6 +408,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
+            if (x == 0 && !both) continue;
             cr[x][y] = mfma_t<T>::op(lr[x], br[y], cr[x][y]);
             cr[x][y] = mfma_t<T>::op(-li[x], bi[y], cr[x][y]);
             ci[x][y] = mfma_t<T>::op(lr[x], bi[y], ci[x][y]);
@@ -418,7 +424,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = wr + 16 * x + mfma_t<T>::rowof(lane, j);
+        const int r = (x == 0 ? rt0 : rt1) + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
         if (r < nb && gc < cend) a[(long)(k0 + r) * n + gc] = cx<T>{cr[x][y][j], ci[x][y][j]};
       }
