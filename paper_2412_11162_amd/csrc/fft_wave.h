@@ -149,25 +149,5 @@ template <int R>
 __device__ __forceinline__ int fft_wave_out_index(int b, int s) {
   return b + 64 * (s >> 3) + 8 * R * (s & 7);
 }
-// Output slot that holds index b + 64 a.
-template <int R>
-__device__ __forceinline__ constexpr int fft_wave_slot_of(int a) {
-  return R == 8 ? a : 8 * (a % (R / 8)) + a / (R / 8);
-}
-
-// Even extension in the input layout: slots a <= R/2 hold x[b + 64 a]; fill
-// slots a > R/2 from x[L - j] = x[j]: lane 64 - b, slot R - 1 - a for b > 0,
-// and the lane's own slot R - a for b = 0.
-template <int R>
-__device__ __forceinline__ void mirror_even(zd* v) {
-  const int b = threadIdx.x & 63;
-  const int src = (64 - b) & 63;
-#pragma unroll
-  for (int a = R / 2 + 1; a < R; ++a) {
-    const zd s = v[R - 1 - a];
-    const zd m{__shfl(s.re, src), __shfl(s.im, src)};
-    v[a] = b == 0 ? v[R - a] : m;
-  }
-}
 
 }  // namespace pmlbie
