@@ -370,25 +370,42 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       cr[x][y] = acc_t{0, 0, 0, 0};
       ci[x][y] = acc_t{0, 0, 0, 0};
     }
-  for (int kk = 0; kk < nb; kk += KC) {
+  // global -> register prefetch of the next K chunk overlaps the MFMA work
+  // on the current one
+  cx<T> pw[4], pa[2];
+  auto gload = [&](int kk) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 512 * t;
       const int k = e % KC, r = e / KC;
-      const cx<T> v = (r < nb && kk + k < nb) ? w[(long)r * LU_NB + kk + k] : cx<T>{T(0), T(0)};
-      Lre[k][r] = v.re;
-      Lim[k][r] = v.im;
+      pw[t] = (r < nb && kk + k < nb) ? w[(long)r * LU_NB + kk + k] : cx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int e = tid + 512 * t;
       const int cc = e & 63, k = e >> 6;
       const int gc = c0 + cc, gk = kk + k;
-      const cx<T> v = (gc < cend && gk < nb) ? a[(long)(k0 + gk) * n + gc] : cx<T>{T(0), T(0)};
-      Bre[k][cc] = v.re;
-      Bim[k][cc] = v.im;
+      pa[t] = (gc < cend && gk < nb) ? a[(long)(k0 + gk) * n + gc] : cx<T>{T(0), T(0)};
+    }
+  };
+  gload(0);
+  for (int kk = 0; kk < nb; kk += KC) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 512 * t;
+      const int k = e % KC, r = e / KC;
+      Lre[k][r] = pw[t].re;
+      Lim[k][r] = pw[t].im;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int e = tid + 512 * t;
+      const int cc = e & 63, k = e >> 6;
+      Bre[k][cc] = pa[t].re;
+      Bim[k][cc] = pa[t].im;
     }
     __syncthreads();
+    if (kk + KC < nb) gload(kk + KC);
     if (kk < rt1 + 16) {
       const bool both = kk < rt0 + 16;  // tile rt0 still below the diagonal
 #pragma unroll 1
