@@ -4,7 +4,7 @@
 //
 // Right-looking blocked algorithm with panel width LU_NB:
 //   1. panel factorisation, one workgroup per matrix: the panel is walked in
-//      sub-panels of 4 columns held in registers (pivot search, row exchange
+//      sub-panels of 4 (8) columns held in registers (pivot search, row exchange
 //      and rank-1 updates never leave the chip), each followed by the update
 //      of the panel columns to its right;
 //   2. the triangular solve U12 = L11^{-1} A12 (the row interchanges of the
@@ -23,7 +23,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int PNL_T = 1024;  // threads of the panel kernel
-constexpr int SUB = 4;       // register sub-panel width
 
 template <typename T>
 __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
@@ -45,6 +44,9 @@ template <typename T, int RPT>
 __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms, int n, int k0,
                                                  int nb, int cs0, int* __restrict__ ipiv,
                                                  int* __restrict__ info) {
+  // register sub-panel width: 8 columns where the registers allow it (FP32 up
+  // to two rows per thread), which halves the passes of the in-leaf update
+  constexpr int SUB = (sizeof(T) == 4 && RPT <= 2) ? 8 : 4;
   cx<T>* a = A + (long)blockIdx.x * ms;
   int* piv = ipiv + (long)blockIdx.x * n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
