@@ -803,28 +803,15 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
     if (n_pts < 0 || (n_pts > 0 && (!rtz || !out))) return fail(c, PMLBIE_EINVAL, "evaluate_field: bad arguments");
     if (n_pts == 0) return PMLBIE_OK;
     const int N = c->N, M = c->M;
-    std::vector<PairGeom> g;
+    if (M - c->m0 + 1 > FIELD_MAX_MODES) return fail(c, PMLBIE_EINVAL, "evaluate_field: too many modes");
     std::vector<int> med(n_pts);
     std::vector<double> th(n_pts);
-    g.reserve((size_t)n_pts * N);
     for (int p = 0; p < n_pts; ++p) {
       const double r = rtz[3 * p], zz = rtz[3 * p + 2];
       th[p] = rtz[3 * p + 1];
       if (!(r >= 0) || r >= c->geo.pml.a1) return fail(c, PMLBIE_EINVAL, "evaluate_field: points must lie in the physical region rho < a1");
       med[p] = zz > c->geo.h(r) ? 1 : 2;
-      for (int l = 0; l < N; ++l) {
-        PairGeom q;
-        q.rt = zd{r, 0.0};
-        q.rs = zd{c->geo.rho[l], c->geo.I[l]};
-        q.drho = zd{r - c->geo.rho[l], -c->geo.I[l]};
-        q.dz = zd{zz - c->geo.z[l], 0.0};
-        q.nr = zd{c->geo.nr_re[l], c->geo.nr_im[l]};
-        q.nz = zd{c->geo.nz_re[l], c->geo.nz_im[l]};
-        g.push_back(q);
-      }
     }
-    c->raw.alloc(g.size() * 4 * (M + 1));
-    run_pair_list(c, g, c->raw.p, nullptr);
     DBuf<int> dmed;
     DBuf<double> dth;
     DBuf<zd> dout;
@@ -833,9 +820,33 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
     dout.alloc((size_t)n_pts * c->nrhs);
     HIPCHK(hipMemcpyAsync(dmed.p, med.data(), n_pts * sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(dth.p, th.data(), n_pts * 8, hipMemcpyHostToDevice, c->stream));
-    launch_field(c->raw.p, c->nodes.p + 3L * N, N, M, c->m0, c->nrhs, n_pts, dmed.p, dth.p, c->u1.p,
-                 c->p1.p, c->u2.p, c->p2.p, dout.p, c->stream);
-    HIPCHK(hipGetLastError());
+    // points in chunks whose modal kernels against every node take about 2 GiB
+    const long per_pt = (long)N * 4 * (M + 1) * (long)sizeof(zd);
+    const int chunk = (int)std::max(1L, std::min((long)n_pts, (2L << 30) / per_pt));
+    std::vector<PairGeom> g;
+    g.reserve((size_t)chunk * N);
+    for (int p0 = 0; p0 < n_pts; p0 += chunk) {
+      const int np = std::min(chunk, n_pts - p0);
+      g.clear();
+      for (int p = p0; p < p0 + np; ++p) {
+        const double r = rtz[3 * p], zz = rtz[3 * p + 2];
+        for (int l = 0; l < N; ++l) {
+          PairGeom q;
+          q.rt = zd{r, 0.0};
+          q.rs = zd{c->geo.rho[l], c->geo.I[l]};
+          q.drho = zd{r - c->geo.rho[l], -c->geo.I[l]};
+          q.dz = zd{zz - c->geo.z[l], 0.0};
+          q.nr = zd{c->geo.nr_re[l], c->geo.nr_im[l]};
+          q.nz = zd{c->geo.nz_re[l], c->geo.nz_im[l]};
+          g.push_back(q);
+        }
+      }
+      c->raw.alloc(g.size() * 4 * (M + 1));
+      run_pair_list(c, g, c->raw.p, nullptr);  // synchronous: g may be reused
+      launch_field(c->raw.p, c->nodes.p + 3L * N, N, M, c->m0, c->nrhs, np, dmed.p + p0, dth.p + p0,
+                   c->u1.p, c->p1.p, c->u2.p, c->p2.p, dout.p + p0, n_pts, c->stream);
+      HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipMemcpyAsync(out, dout.p, (size_t)n_pts * c->nrhs * sizeof(zd), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;

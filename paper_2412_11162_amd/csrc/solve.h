@@ -18,8 +18,11 @@ void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd*
 void launch_sumsq(const double* sq, int n, int nvec, double* out, hipStream_t st);
 void launch_sq(const zd* v, long count, double* sq, hipStream_t st);
 void launch_axpy(zd* x, const zd* d, long count, hipStream_t st);
+constexpr int FIELD_MAX_MODES = 1024;  // modes a field evaluation may sum
+// Field at npts points for every right-hand side into out[r * ldo + p] (raw:
+// the points' modal kernels against every node, [(p * N + l)][4][M + 1]).
 void launch_field(const zd* raw, const double* W, int N, int M, int m0, int nrhs, int npts,
                   const int* medium, const double* theta, const zd* u1, const zd* p1, const zd* u2,
-                  const zd* p2, zd* out, hipStream_t st);
+                  const zd* p2, zd* out, long ldo, hipStream_t st);
 
 }  // namespace pmlbie

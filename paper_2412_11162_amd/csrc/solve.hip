@@ -77,31 +77,43 @@ __global__ void k_outputs(const zd* __restrict__ x, const zd* __restrict__ b1,
 // built modes n = m0..M (boundary data stored from index 0):
 //   u_n(x) = sgn sum_l W_l [S_n(x, r_l) phi_n(r_l) - K_n(x, r_l) u_n(r_l)],
 // sgn = +1 in the upper medium, -1 in the lower one.  raw[(p * N + l)][s][n].
-__global__ void k_field(const zd* __restrict__ raw, const double* __restrict__ W, int N, int M,
-                        int m0, int nrhs, int npts, const int* __restrict__ medium,
-                        const double* __restrict__ theta, const zd* __restrict__ u1,
-                        const zd* __restrict__ p1, const zd* __restrict__ u2,
-                        const zd* __restrict__ p2, zd* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= npts * nrhs) return;
-  const int p = e % npts, r = e / npts;
+// One workgroup per (point, right-hand side): threads take nodes l (the
+// solution values of one mode are read coalesced), a block reduction sums
+// them; the result goes to out[r * ldo + p].
+__global__ __launch_bounds__(256) void k_field(const zd* __restrict__ raw, const double* __restrict__ W,
+                                               int N, int M, int m0, int nrhs, const int* __restrict__ medium,
+                                               const double* __restrict__ theta, const zd* __restrict__ u1,
+                                               const zd* __restrict__ p1, const zd* __restrict__ u2,
+                                               const zd* __restrict__ p2, zd* __restrict__ out, long ldo) {
+  __shared__ double fn[FIELD_MAX_MODES];
+  __shared__ zd part[4];
+  const int p = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int md = medium[p];
   const double sgn = md == 1 ? 1.0 : -1.0;
   const int sS = md == 1 ? 0 : 2, sK = md == 1 ? 1 : 3;
   const zd* U = md == 1 ? u1 : u2;
   const zd* P = md == 1 ? p1 : p2;
-  zd tot{0.0, 0.0};
-  for (int n = m0; n <= M; ++n) {
-    zd un{0.0, 0.0};
-    for (int l = 0; l < N; ++l) {
-      const zd* rw = raw + ((long)p * N + l) * 4 * (M + 1);
+  for (int n = m0 + tid; n <= M; n += 256)
+    fn[n - m0] = (n == 0 ? 1.0 : 2.0) * cos(n * theta[p]) * sgn * (0.5 / PMLBIE_PI);
+  __syncthreads();
+  zd acc{0.0, 0.0};
+  for (int l = tid; l < N; l += 256) {
+    const zd* rw = raw + ((long)p * N + l) * 4 * (M + 1);
+    zd ul{0.0, 0.0};
+    for (int n = m0; n <= M; ++n) {
       const long idx = ((long)(n - m0) * nrhs + r) * N + l;
-      un = un + W[l] * (rw[sS * (M + 1) + n] * P[idx] - rw[sK * (M + 1) + n] * U[idx]);
+      ul = ul + fn[n - m0] * (rw[sS * (M + 1) + n] * P[idx] - rw[sK * (M + 1) + n] * U[idx]);
     }
-    const double f = (n == 0 ? 1.0 : 2.0) * cos(n * theta[p]) * sgn * (0.5 / PMLBIE_PI);
-    tot = tot + f * un;
+    acc = acc + W[l] * ul;
   }
-  out[e] = tot;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    acc.re += __shfl_xor(acc.re, off);
+    acc.im += __shfl_xor(acc.im, off);
+  }
+  if ((tid & 63) == 0) part[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) out[(long)r * ldo + p] = part[0] + part[1] + part[2] + part[3];
 }
 
 // FP64 -> FP32 copy of the operators (complex128 -> complex64).
@@ -215,11 +227,10 @@ void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int n
 }
 void launch_field(const zd* raw, const double* W, int N, int M, int m0, int nrhs, int npts,
                   const int* medium, const double* theta, const zd* u1, const zd* p1, const zd* u2,
-                  const zd* p2, zd* out, hipStream_t st) {
-  const int tot = npts * nrhs;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(k_field, dim3((tot + 63) / 64), dim3(64), 0, st, raw, W, N, M, m0, nrhs, npts,
-                     medium, theta, u1, p1, u2, p2, out);
+                  const zd* p2, zd* out, long ldo, hipStream_t st) {
+  if (npts <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_field, dim3(npts, nrhs), dim3(256), 0, st, raw, W, N, M, m0, nrhs, medium, theta, u1,
+                     p1, u2, p2, out, ldo);
 }
 
 }  // namespace pmlbie

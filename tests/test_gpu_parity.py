@@ -279,6 +279,36 @@ def test_mixed_paper_scale_solution_satisfies_oracle_rows(paper_rows):
     assert np.max(errs) <= BOUNDARY_TOL, errs
 
 
+def test_paper_scale_field_in_chunks(paper_solver):
+    """Field evaluation at 300 points of the benchmark geometry, which the
+    library processes in three chunks of point x node modal kernels: two
+    sampled points against the oracle's representation formula applied to the
+    GPU boundary data, and every point bit-identical whether evaluated in one
+    call or in two."""
+    import oracle
+    wl, s = paper_solver
+    bd = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(list(wl.incidences))]
+    g = oracle.geometry(wl)
+    rng = np.random.default_rng(7)
+    npts = 300
+    rho = rng.uniform(0.05, 3.8, npts)                 # physical region rho < a1
+    zc = np.interp(rho, g.rho, g.z)                     # the curve below / above
+    side = np.where(rng.uniform(size=npts) < 0.5, 1.0, -1.0)
+    z = zc + side * rng.uniform(0.3, 2.0, npts)         # well off the curve, |z| < a2
+    theta = rng.uniform(0.0, 2.0 * np.pi, npts)
+    rtz = np.stack([rho, theta, z], axis=1)
+    out = s.evaluate_field(rtz, 1)[0]
+    assert np.all(np.isfinite(out))
+    split = np.concatenate([s.evaluate_field(rtz[:150], 1)[0], s.evaluate_field(rtz[150:], 1)[0]])
+    assert np.array_equal(out, split)
+    modes = list(range(wl.m_max + 1))
+    for q in (11, 237):
+        med = 1 if z[q] > zc[q] else 2
+        fm = oracle.field_modes(g, modes, bd, np.array([[rho[q], z[q]]]), med)[:, 0]
+        ref = (fm[0] + 2 * np.sum(fm[1:] * np.cos(np.arange(1, len(modes)) * theta[q]))) / (2 * np.pi)
+        assert abs(out[q] - ref) <= 1e-8 * abs(ref), (q, out[q], ref)
+
+
 def test_paper_scale_boundary_data_against_stored_oracle(paper_solver):
     wl, s = paper_solver
     ref = _golden("paper_scale")
