@@ -140,7 +140,10 @@ int pmlbie_solve_modes(pmlbie_ctx* ctx, int n_rhs, const pmlbie_incidence* inc, 
  * triples, physical region, at least one panel length away from the
  * curve), by the Green representation of each medium (Sec. 4.2, eq.
  * eqfujs) and the modal synthesis.  out: host array, n_rhs * n_pts
- * complex128, layout [rhs][point].  n_pts = 0 is allowed. */
+ * complex128, layout [rhs][point].  n_pts = 0 is allowed.  The points are
+ * processed in chunks whose point x node modal kernels take about 2 GiB of
+ * device memory, so any number of points fits; PMLBIE_EINVAL for a point
+ * outside rho < a1 or for more than 1024 summed modes. */
 int pmlbie_evaluate_field(pmlbie_ctx* ctx, int n_pts, const double* rtz, double* out);
 
 /* ---- inspection ---------------------------------------------------------- */
