@@ -162,6 +162,26 @@ def cpu_baseline(wl, seconds: float = 15.0):
                       "adaptive azimuthal quadrature (%.1f s)" % (done, wl.m_max, dt)}
 
 
+def field_leg(s, wl, N):
+    """Field synthesis outside the timed step: 1024 seeded points off the curve
+    in the physical region, the representation formula over every node and
+    mode, evaluated by the library in chunks of point x node modal kernels."""
+    nd = s.nodes()
+    rng = np.random.default_rng(2412)
+    npf = 1024
+    rho_f = rng.uniform(0.05, 0.95 * wl.a1, npf)
+    zc = np.interp(rho_f, nd[:, 0], nd[:, 2])
+    z_f = zc + np.where(rng.uniform(size=npf) < 0.5, 1.0, -1.0) * rng.uniform(0.3, 0.6 * wl.a2, npf)
+    rtz = np.stack([rho_f, rng.uniform(0.0, 2.0 * np.pi, npf), z_f], axis=1)
+    nrhs = len(wl.incidences)
+    s.evaluate_field(rtz[:8], nrhs)
+    t0 = time.time()
+    s.evaluate_field(rtz, nrhs)
+    t_field = time.time() - t0
+    return {"points": npf, "right_hand_sides": nrhs, "ms": 1e3 * t_field, "points_per_s": npf / t_field,
+            "node_point_pairs_per_s": npf * N / t_field}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +190,8 @@ def main():
     ap.add_argument("--workload", default="paper_scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-field", action="store_true",
+                    help="skip the field-synthesis leg (1024 points after the timed steps)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training + builds at m_max = 64)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -269,23 +291,8 @@ def main():
                      "traffic_unit": "bytes per launch", "launches": launches, "flop_per_launch": flops / max(launches, 1),
                      "avg_launch_ms": gemm_ms / max(launches, 1)},
     }
-    # field synthesis (outside the timed step): 1024 seeded points off the curve
-    # in the physical region, the representation formula over every node and
-    # mode, evaluated by the library in chunks of point x node modal kernels
-    nd = s.nodes()
-    rng = np.random.default_rng(2412)
-    npf = 1024
-    rho_f = rng.uniform(0.05, 0.95 * wl.a1, npf)
-    zc = np.interp(rho_f, nd[:, 0], nd[:, 2])
-    z_f = zc + np.where(rng.uniform(size=npf) < 0.5, 1.0, -1.0) * rng.uniform(0.3, 0.6 * wl.a2, npf)
-    rtz = np.stack([rho_f, rng.uniform(0.0, 2.0 * np.pi, npf), z_f], axis=1)
-    nrhs = len(wl.incidences)
-    s.evaluate_field(rtz[:8], nrhs)
-    t0 = time.time()
-    s.evaluate_field(rtz, nrhs)
-    t_field = time.time() - t0
-    out["field"] = {"points": npf, "right_hand_sides": nrhs, "ms": 1e3 * t_field, "points_per_s": npf / t_field,
-                    "node_point_pairs_per_s": npf * N / t_field}
+    if not args.no_field:
+        out["field"] = field_leg(s, wl, N)
     if not args.no_mixed:
         # complex64 LU on FP32 MFMA + FP64 refinement, same workload; its error
         # is measured against this run's FP64 result (which the parity tests
