@@ -19,7 +19,7 @@
  *   - Every call returns PMLBIE_OK (0) or a negative status; nothing throws
  *     or aborts across the ABI.  pmlbie_last_error() describes the last
  *     failure of a context.
- *   - Calls run in order: set_geometry -> set_media_pml ->
+ *   - Calls run in order: set_geometry (or set_polyline) -> set_media_pml ->
  *     build_modal_operators -> solve_modes -> evaluate_field; a call out of
  *     order returns PMLBIE_ESTATE.  Changing geometry or media invalidates
  *     later stages.
@@ -77,11 +77,33 @@ const char* pmlbie_last_error(const pmlbie_ctx* ctx);
 int pmlbie_set_geometry(pmlbie_ctx* ctx, int n_bumps, const double* bumps, double cos_freq,
                         double rho_c, const double* seg_breaks, int nodes_per_segment);
 
+/* Generating curve with corners (Sec. 4: piecewise smooth curves, corner
+ * singularities resolved by a graded mesh, eq. eqsxi; Sec. 5, Examples 1 and
+ * 3): the polyline through n_vert vertices (rho_j, z_j), host array
+ * verts[2 * n_vert] = rho_0, z_0, rho_1, z_1, ..., run from the axis
+ * (rho_0 = 0) outward; every later vertex has rho > 0.  Segment j (vertex j
+ * to j + 1) is cut into panels[j] equal panels of 16 Gauss-Legendre nodes;
+ * at every corner (an interior vertex where the direction changes) the panel
+ * touching it is cut again at the fractions 2^-grade, ..., 1/4, 1/2 of its
+ * length measured from the corner, which clusters the nodes geometrically
+ * toward the corner.  Node i lies on panel i / 16, panels in curve order.
+ * The unit normal (z', -rho') / |r'| points into the lower medium.  The
+ * curve must be flat (z = 0) where rho > a1, with a vertex at rho = a1, and
+ * end at rho = a1 + T (checked by pmlbie_set_media_pml).
+ * Errors: PMLBIE_EINVAL for n_vert outside [2, PMLBIE_POLY_MAX_VERTS],
+ * rho_0 != 0, a later rho <= 0, a repeated vertex, panels[j] outside
+ * [2, 4096], grade outside [0, 24], or a total panel count (after grading)
+ * that is not a multiple of 4. */
+#define PMLBIE_POLY_MAX_VERTS 64
+int pmlbie_set_polyline(pmlbie_ctx* ctx, int n_vert, const double* verts, const int* panels,
+                        int grade);
+
 /* Media and PML (Sec. 2, Sec. 3.1 eq. eqsgm1): wavenumbers k1 (upper medium),
  * k2 (lower medium), real or complex; radial PML from a1 with thickness T and
  * strength S; axial PML (a2, T2, S2), which never meets the curve; profile
  * order p >= 2.  The curve must end at the outer PML edge a1 + T.
- * Errors: PMLBIE_EINVAL (T <= 0, a1 <= 0, S < 0, p < 2, curve end != a1 + T),
+ * Errors: PMLBIE_EINVAL (T <= 0, a1 <= 0, S < 0, p < 2, curve end != a1 + T,
+ * a polyline that is not flat beyond a1 or has no vertex at a1),
  * PMLBIE_ESTATE (no geometry). */
 int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_re,
                          double k2_im, double a1, double T, double S, double a2, double T2,

@@ -60,6 +60,7 @@ def lib():
         L.or_near_panels.argtypes = [i, P, P, i, P, i, P, d, P]
         L.or_near_panels.restype = i
         L.or_set_reltol.argtypes = [d]
+        L.or_set_poly.argtypes = [i]
         L.or_num_threads.restype = i
         _lib = L
     return _lib
@@ -84,7 +85,7 @@ def gl16():
 @dataclass
 class Geometry:
     wl: object                 # the workload
-    panels: np.ndarray         # [P, 2] (rho_a, L)
+    panels: np.ndarray         # [P, 4] (rho_a, L, z_a, dz): start and extent (z: polylines)
     panel_of: np.ndarray       # [N] panel index of each node
     t: np.ndarray              # [N] panel parameter in [-1, 1]
     rho: np.ndarray
@@ -123,6 +124,7 @@ def _set_geometry(wl) -> None:
     x, _ = gl16()
     L.or_set_geometry(len(wl.bumps), _p(bumps), float(wl.cos_freq), float(wl.a1),
                       float(wl.T), float(wl.S), int(wl.p), _p(np.ascontiguousarray(x)))
+    L.or_set_poly(1 if wl.polyline else 0)
 
 
 def sigma(wl, rho: float) -> float:
@@ -130,10 +132,67 @@ def sigma(wl, rho: float) -> float:
     return lib().or_sigma(float(rho))
 
 
+def polyline_panels(wl) -> np.ndarray:
+    """Straight panels of a polyline curve (Sec. 4, graded mesh near corners):
+    each segment in equal parts, and at a corner -- an interior vertex where
+    the curve turns -- the part touching it cut again at 2^-g, ..., 1/2 of its
+    length from the corner.  Returns [P, 4] (rho_a, d rho, z_a, d z)."""
+    V = np.asarray(wl.polyline, dtype=np.float64)
+    g = int(wl.grade)
+    turns = [False] * len(V)
+    for j in range(1, len(V) - 1):
+        a, b = V[j] - V[j - 1], V[j + 1] - V[j]
+        cross = a[0] * b[1] - a[1] * b[0]
+        turns[j] = abs(cross) > 1e-12 * np.hypot(*a) * np.hypot(*b) or float(a @ b) < 0.0
+    out = []
+    for sgi in range(len(V) - 1):
+        n = int(wl.panels[sgi])
+        cuts = [k / n for k in range(n + 1)]
+        if turns[sgi]:
+            cuts = [0.0] + [2.0 ** -l / n for l in range(g, 0, -1)] + cuts[1:]
+        if turns[sgi + 1]:
+            cuts = cuts[:-1] + [1.0 - 2.0 ** -l / n for l in range(1, g + 1)] + [1.0]
+        d = V[sgi + 1] - V[sgi]
+        for u0, u1 in zip(cuts[:-1], cuts[1:]):
+            out.append((V[sgi, 0] + u0 * d[0], (u1 - u0) * d[0], V[sgi, 1] + u0 * d[1], (u1 - u0) * d[1]))
+    return np.array(out)
+
+
+def _polyline_geometry(wl) -> Geometry:
+    """Node tables on straight panels: r(t) = start + (1 + t)/2 extent, unit
+    normal (z', -rho')/|r'| into the lower medium, conormal of Sec. 3.1."""
+    L = lib()
+    x, wq = gl16()
+    panels = polyline_panels(wl)
+    cols = {k: [] for k in ("rho", "I", "z", "nu", "jac", "nr", "nz", "sg", "p", "t", "w")}
+    for p, (ra, dr, za, dz) in enumerate(panels):
+        ln = math.hypot(dr, dz)
+        nu = (dz / ln, -dr / ln)
+        for q in range(16):
+            u = 0.5 * (1.0 + x[q])
+            rho = ra + u * dr
+            Iv = L.or_I(rho)
+            sg = L.or_sigma(rho)
+            rt = rho + 1j * Iv
+            cols["rho"].append(rho); cols["I"].append(Iv); cols["z"].append(za + u * dz)
+            cols["nu"].append(nu); cols["jac"].append(0.5 * ln)
+            cols["nr"].append(nu[0] * rt / rho); cols["nz"].append(nu[1] * rt * (1 + 1j * sg) / rho)
+            cols["sg"].append(sg); cols["p"].append(p); cols["t"].append(x[q]); cols["w"].append(wq[q])
+    rho = np.array(cols["rho"]); jac = np.array(cols["jac"]); w = np.array(cols["w"])
+    return Geometry(
+        wl=wl, panels=panels, panel_of=np.array(cols["p"]), t=np.array(cols["t"]), rho=rho,
+        I=np.array(cols["I"]), z=np.array(cols["z"]), hp=np.zeros_like(rho), nu=np.array(cols["nu"]),
+        jac=jac, nrho=np.array(cols["nr"]), nz=np.array(cols["nz"]), sigma=np.array(cols["sg"]),
+        w=w, W=w * rho * jac)
+
+
 def geometry(wl) -> Geometry:
     """Gauss-Legendre node tables: four segments split into equal-rho
-    sub-panels of 16 nodes each."""
+    sub-panels of 16 nodes each (graph curves), or graded straight panels
+    (polylines)."""
     _set_geometry(wl)
+    if wl.polyline:
+        return _polyline_geometry(wl)
     L = lib()
     x, wq = gl16()
     br = wl.seg_breaks
@@ -142,12 +201,12 @@ def geometry(wl) -> Geometry:
         a, b = br[s], br[s + 1]
         h = (b - a) / wl.n_sub
         for k in range(wl.n_sub):
-            panels.append((a + k * h, h))
+            panels.append((a + k * h, h, 0.0, 0.0))
     panels = np.array(panels)
     rows = []
     pof, ts, ws = [], [], []
     buf = np.zeros(12)
-    for p, (pa, h) in enumerate(panels):
+    for p, (pa, h, _, _) in enumerate(panels):
         for q in range(16):
             rho = pa + 0.5 * (1.0 + x[q]) * h
             L.or_point(rho, h, _p(buf))
@@ -200,8 +259,10 @@ def modal_kernels_nodes(g: Geometry, pairs: np.ndarray, ks: Sequence[complex],
                         modes: Sequence[int], reltol: float = 1e-14) -> np.ndarray:
     """Modal kernels between curve nodes; pairs [P, 2] = (target i, source l)."""
     pairs = np.asarray(pairs, dtype=np.int64)
+    # graph curves: z differences from the interface formula without
+    # cancellation; polylines: plain coordinate differences
     return modal_kernels_points(g.wl, g.tgt_table(pairs[:, 0]), g.src_table(pairs[:, 1]), ks,
-                                modes, oncurve=True, reltol=reltol)
+                                modes, oncurve=not g.wl.polyline, reltol=reltol)
 
 
 def near_integrals(g: Geometry, targets: Iterable[int], ks: Sequence[complex],

@@ -154,6 +154,7 @@ typedef struct {
   double a1, T, S;
   int p;
   double gl[16]; /* Gauss-Legendre nodes on [-1, 1] for the Lagrange basis */
+  int poly;      /* 1: the curve is a polyline of straight panels (Sec. 4, graded mesh) */
 } geom_t;
 
 static geom_t G_;
@@ -166,7 +167,12 @@ void or_set_geometry(int nb, const double *bumps, double cosf, double a1,
   }
   G_.cosf = cosf; G_.a1 = a1; G_.T = T; G_.S = S; G_.p = p;
   for (int i = 0; i < 16; ++i) G_.gl[i] = gl16[i];
+  G_.poly = 0;
 }
+
+/* Switch the near-panel integrals to straight panels: a panel is then given
+   by its start (rho_a, z_a) and its extent (d rho, d z). */
+void or_set_poly(int on) { G_.poly = on; }
 
 static double gsum(double r) {
   double s = 0;
@@ -389,6 +395,7 @@ int or_modal_pairs(int npairs, const double *tgt, const double *src, int oncurve
 typedef struct {
   double rho_t, I_t, z_t;    /* target node */
   double pa, L;              /* panel: rho = pa + (1 + t) L / 2 */
+  double za, dzp;            /* straight panel: z = za + (1 + t) dzp / 2 */
   int self;                  /* 1: target lies on this panel at t_i */
   double ti;
   int nk;
@@ -410,16 +417,47 @@ static double lagr(int l, double t) {
  * Integrand at panel parameter t: F_n(r_i, r(t)) rho(t) |dr/dt| l_l(t) for the
  * 16 Lagrange functions.  Layout out[l][(2*ik+{S,K})][j].
  */
+/* Straight panel at parameter t: the same 12 values as or_point. */
+static void poly_point(const nearctx *c, double t, double *out) {
+  double u = 0.5 * (1.0 + t);
+  double rho = c->pa + u * c->L;
+  double len = hypot(c->L, c->dzp);
+  double nur = c->dzp / len, nuz = -c->L / len; /* (z', -rho') / |r'| */
+  double Iv = or_I(rho), sg = or_sigma(rho);
+  cplx rhot = rho + Iv * (cplx)_Complex_I;
+  cplx nr = nur * rhot / rho;
+  cplx nz = nuz * rhot * (1.0 + sg * (cplx)_Complex_I) / rho;
+  out[0] = rho; out[1] = Iv; out[2] = c->za + u * c->dzp; out[3] = 0.0;
+  out[4] = nur; out[5] = nuz; out[6] = 0.5 * len;
+  out[7] = creal(nr); out[8] = cimag(nr); out[9] = creal(nz); out[10] = cimag(nz);
+  out[11] = sg;
+}
+
 static void near_integrand(double t, void *vctx, cplx *out) {
   nearctx *c = (nearctx *)vctx;
-  double rho = c->pa + 0.5 * (1.0 + t) * c->L;
   double g[12];
-  or_point(rho, c->L, g);
-  /* rho_t - rho is exact in floating point for nearby points, and or_hdiff
-     uses that same difference, so the pair geometry stays consistent down to
-     the log singularity */
-  double drho = c->rho_t - rho;
-  double dz = or_hdiff(c->rho_t, rho);
+  double rho, drho, dz;
+  if (G_.poly) {
+    poly_point(c, t, g);
+    rho = g[0];
+    if (c->self) {
+      /* on the target's own straight panel the offset is (t_i - t)/2 times
+         the panel extent, exactly */
+      drho = 0.5 * (c->ti - t) * c->L;
+      dz = 0.5 * (c->ti - t) * c->dzp;
+    } else {
+      drho = c->rho_t - rho;
+      dz = c->z_t - g[2];
+    }
+  } else {
+    rho = c->pa + 0.5 * (1.0 + t) * c->L;
+    or_point(rho, c->L, g);
+    /* rho_t - rho is exact in floating point for nearby points, and or_hdiff
+       uses that same difference, so the pair geometry stays consistent down to
+       the log singularity */
+    drho = c->rho_t - rho;
+    dz = or_hdiff(c->rho_t, rho);
+  }
   double dI = or_Idiff(c->rho_t, rho);
   pairctx p;
   fill_pair(&p, c->rho_t, c->I_t, c->z_t, rho, g[1], g[2],
@@ -444,7 +482,9 @@ static void near_integrand(double t, void *vctx, cplx *out) {
 /*
  * Product integrals of nt targets against panels.  For target q:
  * tinfo[5*q] = (rho_t, I_t, z_t, t_i or 2 (not on panel), which: 0 self,
- * -1 left neighbour, +1 right neighbour), panel[2*q] = (pa, L).
+ * -1 left neighbour, +1 right neighbour), panel[4*q] = (pa, L, za, dz): the
+ * start rho and rho-extent, and (straight panels only) the start z and
+ * z-extent.
  * out[q][l][(2*ik+{S,K})][j] = int_{-1}^{1} F_n(r_q, r(t)) rho |dr/dt| l_l(t) dt.
  */
 int or_near_panels(int nt, const double *tinfo, const double *panel, int nk,
@@ -458,7 +498,8 @@ int or_near_panels(int nt, const double *tinfo, const double *panel, int nk,
     nearctx c;
     const double *ti = tinfo + 5 * q;
     c.rho_t = ti[0]; c.I_t = ti[1]; c.z_t = ti[2];
-    c.pa = panel[2 * q]; c.L = panel[2 * q + 1];
+    c.pa = panel[4 * q]; c.L = panel[4 * q + 1];
+    c.za = panel[4 * q + 2]; c.dzp = panel[4 * q + 3];
     int which = (int)ti[4];
     c.self = which == 0;
     c.ti = ti[3];

@@ -342,14 +342,48 @@ int pmlbie_set_geometry(pmlbie_ctx* c, int n_bumps, const double* bumps, double 
   });
 }
 
+int pmlbie_set_polyline(pmlbie_ctx* c, int n_vert, const double* verts, const int* panels,
+                        int grade) {
+  return guarded(c, [&]() -> int {
+    if (n_vert < 2 || n_vert > PMLBIE_POLY_MAX_VERTS || !verts || !panels)
+      return fail(c, PMLBIE_EINVAL, "set_polyline: need 2 <= n_vert <= 64 vertices and a panel count per segment");
+    if (grade < 0 || grade > 24) return fail(c, PMLBIE_EINVAL, "set_polyline: grade must lie in [0, 24]");
+    if (verts[0] != 0.0) return fail(c, PMLBIE_EINVAL, "set_polyline: the curve must start on the axis");
+    for (int j = 1; j < n_vert; ++j) {
+      if (!(verts[2 * j] > 0.0) || !std::isfinite(verts[2 * j]) || !std::isfinite(verts[2 * j + 1]))
+        return fail(c, PMLBIE_EINVAL, "set_polyline: vertices after the first must have rho > 0");
+      if (verts[2 * j] == verts[2 * j - 2] && verts[2 * j + 1] == verts[2 * j - 1])
+        return fail(c, PMLBIE_EINVAL, "set_polyline: repeated vertex");
+      if (panels[j - 1] < 2 || panels[j - 1] > 4096)
+        return fail(c, PMLBIE_EINVAL, "set_polyline: 2 <= panels per segment <= 4096");
+    }
+    Geometry g;
+    g.poly = true;
+    g.verts.assign(verts, verts + 2 * n_vert);
+    g.seg_panels.assign(panels, panels + n_vert - 1);
+    g.grade = grade;
+    // graded panels: the layout is fixed here, so the node count is known
+    Geometry probe = g;
+    probe.pml.a1 = verts[2 * n_vert - 2];
+    probe.pml.T = 1.0;
+    probe.build();
+    if (probe.npanels() % 4)
+      return fail(c, PMLBIE_EINVAL, "set_polyline: the total number of panels (after grading) must be a multiple of 4");
+    c->geo = g;
+    c->stage = 1;
+    return PMLBIE_OK;
+  });
+}
+
 int pmlbie_set_media_pml(pmlbie_ctx* c, double k1_re, double k1_im, double k2_re, double k2_im,
                          double a1, double T, double S, double a2, double T2, double S2, int p) {
   return guarded(c, [&]() -> int {
     if (c->stage < 1) return fail(c, PMLBIE_ESTATE, "set_media_pml: set the geometry first");
     if (!(a1 > 0) || !(T > 0) || !(S >= 0) || p < 2)
       return fail(c, PMLBIE_EINVAL, "set_media_pml: need a1 > 0, T > 0, S >= 0, p >= 2");
-    if (fabs(c->geo.breaks[4] - (a1 + T)) > 1e-12 * (a1 + T))
+    if (fabs(c->geo.rho_end() - (a1 + T)) > 1e-12 * (a1 + T))
       return fail(c, PMLBIE_EINVAL, "set_media_pml: the curve must end at the outer PML edge a1 + T");
+    if (const char* e = c->geo.poly_pml_error(a1)) return fail(c, PMLBIE_EINVAL, e);
     c->k1 = zd{k1_re, k1_im};
     c->k2 = zd{k2_re, k2_im};
     c->geo.pml.a1 = a1;
@@ -407,7 +441,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     // cos kR in theta), the singular factors are kept to MQ = L/2 - 1, and
     // the products are exact for the kept modes 0..M when MQ - M >= B.
     const double kmax = std::max(cabs_(c->k1), cabs_(c->k2));
-    const double rmax = cabs_(zd{c->geo.breaks[4], c->geo.Iint(c->geo.breaks[4])});
+    const double rmax = cabs_(zd{c->geo.rho_end(), c->geo.Iint(c->geo.rho_end())});
     const double bneed = ceil(1.15 * kmax * rmax + 16.0);
     const int L = std::max(512, pow2_at_least(std::max<double>(n_theta, 2.0 * (M + bneed) + 2.0)));
     if (L > 2048) return fail(c, PMLBIE_EINVAL, "build: wavenumber or m_max too large for the azimuthal FFT");
@@ -470,11 +504,15 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     std::vector<PairGeom> ageom;
     std::vector<double> acoef;
     std::vector<NearJob> ajobs;
+    // longest auxiliary interval: |k| |1 + i sigma| h <= 4 keeps the 16-point
+    // rule times a degree-15 Lagrange factor at rounding level
+    const double keff = std::max(cabs_(c->k1), cabs_(c->k2)) * sqrt(1.0 + c->geo.pml.S * c->geo.pml.S);
+    const double near_hmax = keff > 0.0 ? 4.0 / keff : 1e300;
     if (!c->up_stream) HIPCHK(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking));
     if (!c->up_done) HIPCHK(hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming));
     std::future<void> near_tables = std::async(std::launch::async, [&]() {
       HIPCHK(hipSetDevice(c->device));
-      c->geo.build_near(ageom, acoef, ajobs, 6);
+      c->geo.build_near(ageom, acoef, ajobs, 6, near_hmax);
       // uploaded on their own stream while the far/split/direct stages run
       c->coef.alloc(acoef.size());
       c->jobs.alloc(ajobs.size());
@@ -631,7 +669,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       if (inc[r].kind == 0) {
         if (!(inc[r].p[0] >= 0)) return fail(c, PMLBIE_EINVAL, "solve: source radius must be >= 0");
         if (!(inc[r].p[0] < c->geo.pml.a1)) return fail(c, PMLBIE_EINVAL, "solve: the point source must lie in the physical region rho < a1");
-        if (inc[r].p[1] <= c->geo.h(inc[r].p[0]))
+        if (!c->geo.above(inc[r].p[0], inc[r].p[1]))
           return fail(c, PMLBIE_EINVAL, "solve: the point source must lie in the upper medium");
       } else if (inc[r].kind == 1) {
         if (!(inc[r].p[0] >= 0 && inc[r].p[0] < 0.5 * PMLBIE_PI))
@@ -705,7 +743,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     if (!pws.empty()) {
       // FFT length: the modes of exp(-i a cos theta) die out beyond |n| ~ a
       double amax = 0.0;
-      for (const PlaneWave& P : pws) amax = std::max(amax, P.k1 * P.s * c->geo.breaks[4]);
+      for (const PlaneWave& P : pws) amax = std::max(amax, P.k1 * P.s * c->geo.rho_end());
       const int ntp = std::max(256, pow2_at_least(2.0 * (std::max<double>(M, amax) + 40.0)));
       if (ntp > 2048) return fail(c, PMLBIE_EINVAL, "solve: plane-wave data need more than 2048 azimuthal samples");
       auto twp = twiddles(ntp);
@@ -810,7 +848,7 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
       const double r = rtz[3 * p], zz = rtz[3 * p + 2];
       th[p] = rtz[3 * p + 1];
       if (!(r >= 0) || r >= c->geo.pml.a1) return fail(c, PMLBIE_EINVAL, "evaluate_field: points must lie in the physical region rho < a1");
-      med[p] = zz > c->geo.h(r) ? 1 : 2;
+      med[p] = c->geo.above(r, zz) ? 1 : 2;
     }
     DBuf<int> dmed;
     DBuf<double> dth;

@@ -1,5 +1,6 @@
 #include "host_geom.h"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -141,36 +142,125 @@ double Geometry::Idiff(double r, double dr) const {
 
 void Geometry::point(int pn, double tpar, double& r, double& Ir, double& zz, zd& nr, zd& nz,
                      double& jacobian) const {
-  r = pa[pn] + 0.5 * (1.0 + tpar) * pl[pn];
+  double nu_r, nu_z, sq;
+  if (poly) {
+    // straight panel: r(t) = start + (1 + t)/2 (d rho, d z); the normal
+    // (z', -rho') / |r'| points into the lower medium for a curve run from
+    // the axis outward
+    const double u = 0.5 * (1.0 + tpar);
+    r = pa[pn] + u * pl[pn];
+    zz = pz[pn] + u * pdz[pn];
+    nu_r = pdz[pn] / plen[pn];
+    nu_z = -pl[pn] / plen[pn];
+    sq = 0.0;
+  } else {
+    r = pa[pn] + 0.5 * (1.0 + tpar) * pl[pn];
+    zz = h(r);
+    double hpv = hprime(r);
+    sq = sqrt(1.0 + hpv * hpv);
+    nu_r = hpv / sq;
+    nu_z = -1.0 / sq;  // unit normal into the lower medium
+  }
   Ir = Ipanel(pn, r);
-  zz = h(r);
-  double hpv = hprime(r);
-  double sq = sqrt(1.0 + hpv * hpv);
-  double nu_r = hpv / sq, nu_z = -1.0 / sq;  // unit normal into the lower medium
   zd rt{r, Ir};
   zd ar{1.0, sigma(r)};
   // nu_c . grad_r in stretched variables: n_rho d/drho~ + n_z d/dz~,
   // n_rho = nu_rho rho~ alpha_z / rho, n_z = nu_z rho~ alpha_rho / rho (alpha_z = 1 on the curve)
   nr = (nu_r / r) * rt;
   nz = (nu_z / r) * (rt * ar);
-  jacobian = 0.5 * pl[pn] * sq;
+  jacobian = poly ? 0.5 * plen[pn] : 0.5 * pl[pn] * sq;
+}
+
+// Panels of the polyline model.  Segment s runs from vertex s to vertex s+1
+// and is cut at the fractions 0, 1/n, ..., 1 of its length (n = seg_panels[s]);
+// where a segment end is a corner (an interior vertex at which the direction
+// changes) the end panel is cut again at the fractions 2^-g, ..., 1/2 of its
+// own length measured from the corner.
+static void poly_layout(const Geometry& g, std::vector<double>& pa, std::vector<double>& pl,
+                        std::vector<double>& pz, std::vector<double>& pdz) {
+  const int nv = (int)g.verts.size() / 2, nseg = nv - 1;
+  std::vector<char> corner(nv, 0);
+  for (int j = 1; j < nv - 1; ++j) {
+    const double ax = g.verts[2 * j] - g.verts[2 * j - 2], az = g.verts[2 * j + 1] - g.verts[2 * j - 1];
+    const double bx = g.verts[2 * j + 2] - g.verts[2 * j], bz = g.verts[2 * j + 3] - g.verts[2 * j + 1];
+    const double cr = ax * bz - az * bx, dt = ax * bx + az * bz;
+    corner[j] = fabs(cr) > 1e-12 * hypot(ax, az) * hypot(bx, bz) || dt < 0.0;
+  }
+  pa.clear(); pl.clear(); pz.clear(); pdz.clear();
+  for (int s = 0; s < nseg; ++s) {
+    const double r0 = g.verts[2 * s], z0 = g.verts[2 * s + 1];
+    const double dr = g.verts[2 * s + 2] - r0, dz = g.verts[2 * s + 3] - z0;
+    const int n = g.seg_panels[s];
+    std::vector<double> u;
+    u.push_back(0.0);
+    if (corner[s])
+      for (int l = g.grade; l >= 1; --l) u.push_back(ldexp(1.0, -l) / n);
+    for (int k = 1; k < n; ++k) u.push_back((double)k / n);
+    if (corner[s + 1])
+      for (int l = 1; l <= g.grade; ++l) u.push_back(1.0 - ldexp(1.0, -l) / n);
+    u.push_back(1.0);
+    for (size_t k = 0; k + 1 < u.size(); ++k) {
+      pa.push_back(r0 + u[k] * dr);
+      pz.push_back(z0 + u[k] * dz);
+      pl.push_back((u[k + 1] - u[k]) * dr);
+      pdz.push_back((u[k + 1] - u[k]) * dz);
+    }
+  }
+}
+
+bool Geometry::above(double r, double zz) const {
+  if (!poly) return zz > h(r);
+  if (r >= rho_end()) return zz > 0.0;
+  // vertical ray from the point upward: an even number of crossings with the
+  // curve means the point lies above it
+  const int nv = (int)verts.size() / 2;
+  int cross = 0;
+  for (int j = 0; j + 1 < nv; ++j) {
+    const double r0 = verts[2 * j], z0 = verts[2 * j + 1], r1 = verts[2 * j + 2], z1 = verts[2 * j + 3];
+    if ((r0 < r) == (r1 < r)) continue;
+    const double zc = z0 + (r - r0) / (r1 - r0) * (z1 - z0);
+    if (zc > zz) ++cross;
+  }
+  return (cross & 1) == 0;
+}
+
+const char* Geometry::poly_pml_error(double a1) const {
+  if (!poly) return nullptr;
+  const int nv = (int)verts.size() / 2;
+  for (int j = 0; j + 1 < nv; ++j) {
+    const double r0 = verts[2 * j], r1 = verts[2 * j + 2];
+    const double lo = std::min(r0, r1), hi = std::max(r0, r1);
+    if (hi > a1 && lo < a1)
+      return "set_media_pml: a polyline vertex must lie at rho = a1 (no segment may straddle the start of the PML)";
+    if (hi > a1 && (verts[2 * j + 1] != 0.0 || verts[2 * j + 3] != 0.0))
+      return "set_media_pml: the polyline must be flat (z = 0) where rho > a1";
+  }
+  return nullptr;
 }
 
 void Geometry::build() {
-  if (breaks.size() != 5) throw std::invalid_argument("geometry: need 5 segment breaks");
-  if (nodes_per_segment <= 0 || nodes_per_segment % 16)
-    throw std::invalid_argument("geometry: nodes per segment must be a positive multiple of 16");
   gauss_legendre(16, glx, glw);
-  const int nsub = nodes_per_segment / 16;
-  pa.clear();
-  pl.clear();
-  for (int s = 0; s < 4; ++s) {
-    double a = breaks[s], b = breaks[s + 1];
-    if (!(b > a)) throw std::invalid_argument("geometry: segment breaks must increase");
-    for (int k = 0; k < nsub; ++k) {
-      pa.push_back(a + (b - a) * k / nsub);
-      pl.push_back((b - a) / nsub);
+  if (poly) {
+    poly_layout(*this, pa, pl, pz, pdz);
+    plen.resize(pa.size());
+    for (size_t p = 0; p < pa.size(); ++p) plen[p] = hypot(pl[p], pdz[p]);
+  } else {
+    if (breaks.size() != 5) throw std::invalid_argument("geometry: need 5 segment breaks");
+    if (nodes_per_segment <= 0 || nodes_per_segment % 16)
+      throw std::invalid_argument("geometry: nodes per segment must be a positive multiple of 16");
+    const int nsub = nodes_per_segment / 16;
+    pa.clear();
+    pl.clear();
+    for (int s = 0; s < 4; ++s) {
+      double a = breaks[s], b = breaks[s + 1];
+      if (!(b > a)) throw std::invalid_argument("geometry: segment breaks must increase");
+      for (int k = 0; k < nsub; ++k) {
+        pa.push_back(a + (b - a) * k / nsub);
+        pl.push_back((b - a) / nsub);
+      }
     }
+    // the parameter is linear in rho on a graph panel
+    plen = pl;
   }
   const int np = npanels(), N = np * 16;
   Ipa.assign(np, 0.0);
@@ -184,10 +274,16 @@ void Geometry::build() {
       const int i = 16 * p + j;
       zd nr, nz;
       point(p, glx[j], rho[i], I[i], z[i], nr, nz, jac[i]);
-      hp[i] = hprime(rho[i]);
-      double sq = sqrt(1.0 + hp[i] * hp[i]);
-      nur[i] = hp[i] / sq;
-      nuz[i] = -1.0 / sq;
+      if (poly) {
+        hp[i] = 0.0;  // not a graph
+        nur[i] = pdz[p] / plen[p];
+        nuz[i] = -pl[p] / plen[p];
+      } else {
+        hp[i] = hprime(rho[i]);
+        double sq = sqrt(1.0 + hp[i] * hp[i]);
+        nur[i] = hp[i] / sq;
+        nuz[i] = -1.0 / sq;
+      }
       nr_re[i] = nr.re; nr_im[i] = nr.im; nz_re[i] = nz.re; nz_im[i] = nz.im;
       W[i] = glw[j] * rho[i] * jac[i];
       t[i] = glx[j];
@@ -219,8 +315,13 @@ static void lagrange16(const double* xn, double tq, double* out) {
 // interval mapped by t = eps u^6 (smooths the log singularity), 16 points
 // each.  Neighbour panels: intervals shrinking by 4 toward the shared
 // endpoint until their length is below the target's distance to that end.
+// Every interval longer than hmax (physical length) is cut into equal pieces
+// of at most hmax, and the self-panel levels continue until the mapped
+// interval is that short too: the kernel oscillates and grows at the rate
+// |k| |1 + i sigma|, and the 16-point rule must resolve it times a degree-15
+// Lagrange factor.
 void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
-                          std::vector<NearJob>& jobs, int self_levels) const {
+                          std::vector<NearJob>& jobs, int self_levels, double hmax) const {
   const int N = n(), np = npanels();
   struct Local {
     std::vector<PairGeom> g;
@@ -241,15 +342,25 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
       // points as (anchor, offset, side sign, weight): t = anchor + sgn * off
       struct AP { double anchor, off, sgn, w; };
       std::vector<AP> pts;
+      // half the physical length per unit of panel parameter
+      const double hs = 0.5 * plen[pn];
+      // 16-point rule on offsets [lo, hi], in pieces of physical length <= hmax
+      auto interval = [&](double anchor, double sgn, double lo, double hi) {
+        const int np = std::max(1, (int)ceil((hi - lo) * hs / hmax - 1e-9));
+        for (int k = 0; k < np; ++k) {
+          const double a = lo + (hi - lo) * k / np, b = lo + (hi - lo) * (k + 1) / np;
+          for (int j = 0; j < 16; ++j)
+            pts.push_back({anchor, a + 0.5 * (b - a) * (1.0 + glx[j]), sgn, 0.5 * (b - a) * glw[j]});
+        }
+      };
       if (pn == p0) {
         const double ti = t[i];
         for (int side = -1; side <= 1; side += 2) {
           const double h = side > 0 ? 1.0 - ti : ti + 1.0;
           double hi = h;
-          for (int lv = 0; lv < self_levels; ++lv) {
+          for (int lv = 0; lv < self_levels || hi * hs > hmax; ++lv) {
             double lo = hi * 0.25;
-            for (int j = 0; j < 16; ++j)
-              pts.push_back({ti, lo + 0.5 * (hi - lo) * (1.0 + glx[j]), (double)side, 0.5 * (hi - lo) * glw[j]});
+            interval(ti, (double)side, lo, hi);
             hi = lo;
           }
           const double eps = hi;
@@ -264,7 +375,7 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
         const double anchor = pn < p0 ? 1.0 : -1.0;
         const double sgn = pn < p0 ? -1.0 : 1.0;
         // target distance to the shared end, in neighbour-panel units
-        const double dist = (pn < p0 ? (1.0 + t[i]) : (1.0 - t[i])) * pl[p0] / pl[pn];
+        const double dist = (pn < p0 ? (1.0 + t[i]) : (1.0 - t[i])) * plen[p0] / plen[pn];
         double hi = 2.0;
         int nint = 0;
         while (true) {
@@ -273,8 +384,7 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
           // Lagrange factor when the target is far from the shared end
           if (hi <= dist && nint >= 2) lo = 0.0;
           ++nint;
-          for (int j = 0; j < 16; ++j)
-            pts.push_back({anchor, lo + 0.5 * (hi - lo) * (1.0 + glx[j]), sgn, 0.5 * (hi - lo) * glw[j]});
+          interval(anchor, sgn, lo, hi);
           if (lo == 0.0) break;
           hi = lo;
         }
@@ -285,14 +395,19 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
         zd nr, nz;
         point(pn, tp, r, Ir, zz, nr, nz, jc);
         // target minus source, from the exact offset on the self panel
-        double dr;
-        if (pn == p0) dr = -a.sgn * a.off * 0.5 * pl[pn];
-        else dr = rho[i] - r;
+        double dr, dzv;
+        if (pn == p0) {
+          dr = -a.sgn * a.off * 0.5 * pl[pn];
+          dzv = poly ? -a.sgn * a.off * 0.5 * pdz[pn] : hdiff(rho[i], dr);
+        } else {
+          dr = rho[i] - r;
+          dzv = poly ? z[i] - zz : hdiff(rho[i], dr);
+        }
         PairGeom g;
         g.rt = zd{rho[i], I[i]};
         g.rs = zd{r, Ir};
         g.drho = zd{dr, fabs(dr) < 1e-2 ? Idiff(rho[i], dr) : I[i] - Ir};
-        g.dz = zd{hdiff(rho[i], dr), 0.0};
+        g.dz = zd{dzv, 0.0};
         g.nr = nr;
         g.nz = nz;
         L.g.push_back(g);

@@ -19,18 +19,32 @@ struct Pml {
   int p = 6;
 };
 
+// Two curve models.  Graph: z = h~(rho) over four rho segments of equal
+// panels.  Polyline: straight segments between vertices (rho_j, z_j) with
+// corners allowed (Sec. 4, the graded mesh of eq. eqsxi); each segment holds
+// a given number of equal panels, and the panel touching a corner is split
+// geometrically toward it (`grade` halvings) so that the nodes cluster at the
+// corner singularities.
 class Geometry {
  public:
   Interface itf;
   Pml pml;
-  std::vector<double> breaks;  // segment breaks in rho, 5 values
+  std::vector<double> breaks;  // graph: segment breaks in rho, 5 values
   int nodes_per_segment = 0;
+  // polyline model (used when poly is set)
+  bool poly = false;
+  std::vector<double> verts;   // 2 * n_vert: rho_0, z_0, rho_1, z_1, ...
+  std::vector<int> seg_panels;  // equal panels per segment before grading
+  int grade = 0;
 
   // Gauss-Legendre rule of 16 nodes on [-1, 1].
   double glx[16], glw[16];
 
   // panels
-  std::vector<double> pa, pl;  // start rho and rho-length
+  std::vector<double> pa, pl;  // start rho and rho-length (signed for polylines)
+  std::vector<double> pz, pdz;  // polyline: start z and z-length
+  std::vector<double> plen;     // panel length in the variable its parameter is linear in
+                                // (arclength for a polyline, rho for a graph)
   std::vector<double> Ipa;     // Im rho~ at each panel start
   // node tables
   std::vector<double> rho, I, z, hp, nur, nuz, jac, W, t;
@@ -40,6 +54,14 @@ class Geometry {
   void build();  // panels + node tables
   int n() const { return (int)rho.size(); }
   int npanels() const { return (int)pa.size(); }
+
+  double rho_end() const { return poly ? verts[verts.size() - 2] : breaks[4]; }
+  // the point lies above the curve (in the upper medium); points on the
+  // curve are not classified
+  bool above(double r, double zz) const;
+  // polyline checks against the PML: no panel straddles a1 and the curve is
+  // flat (z = 0) wherever rho > a1; returns an error text or nullptr
+  const char* poly_pml_error(double a1) const;
 
   double h(double r) const;            // h~(rho)
   double hprime(double r) const;       // h~'(rho)
@@ -55,7 +77,7 @@ class Geometry {
   // near-panel product integration: auxiliary points, their pair geometry
   // relative to the target, Lagrange-weighted quadrature coefficients, jobs
   void build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
-                  std::vector<NearJob>& jobs, int self_levels) const;
+                  std::vector<NearJob>& jobs, int self_levels, double hmax) const;
 
  private:
   double graw(double r) const;

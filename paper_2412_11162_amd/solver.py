@@ -61,6 +61,11 @@ class Solver:
         self._chk(self.L.pmlbie_set_geometry(self.h, len(bumps), _p(b), float(cos_freq), float(rho_c),
                                              _p(s), int(nodes_per_segment)))
 
+    def set_polyline(self, verts: Sequence[Tuple[float, float]], panels: Sequence[int], grade: int):
+        v = np.ascontiguousarray(np.array(verts, dtype=np.float64).reshape(-1))
+        pn = np.ascontiguousarray(np.array(panels, dtype=np.int32))
+        self._chk(self.L.pmlbie_set_polyline(self.h, v.size // 2, _p(v), _p(pn), int(grade)))
+
     def set_media_pml(self, k1: complex, k2: complex, a1: float, T: float, S: float, a2: float,
                       T2: float, S2: float, p: int = 6):
         k1, k2 = complex(k1), complex(k2)
@@ -198,7 +203,10 @@ def from_workload(wl, device: int = 0, n_theta: int = None, m_max: int = None,
                   precision: int = B.PMLBIE_FP64, flags: int = 0, build: bool = True) -> Solver:
     """Set up a solver for one of the synthetic workloads."""
     s = Solver(device)
-    s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
+    if wl.polyline:
+        s.set_polyline(wl.polyline, wl.panels, wl.grade)
+    else:
+        s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
     s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
     if build:
         s.build_modal_operators(n_theta or wl.n_theta, wl.m_max if m_max is None else m_max,

@@ -5,7 +5,7 @@ parameters, discretisation sizes and incidences, plus the seeded draws for
 the randomised shapes.  It contains none of the method's arithmetic, so both
 the oracle and the HIP path may import it.
 
-Interface family (shared by every workload): a graph z = h~(rho) with
+Interface family (every workload but the polyline ones): a graph z = h~(rho) with
 
     h(rho)  = [sum_i a_i exp(-((rho - c_i)/w_i)^2)] * (cos(f rho) if f else 1)
     h~(rho) = h(rho) - h(a1)  for rho < a1,   0 for rho >= a1,
@@ -47,6 +47,12 @@ class Workload:
     m_max_: int
     # incidences: ("point", rho*, z*) or ("plane", phi_inc)
     incidences: Tuple[Tuple, ...] = field(default_factory=tuple)
+    # polyline curve with corners (replaces the graph when set): vertices
+    # (rho, z) from the axis outward, equal panels per segment, and the number
+    # of geometric halvings of the panels that touch a corner
+    polyline: Tuple[Tuple[float, float], ...] = ()
+    panels: Tuple[int, ...] = ()
+    grade: int = 0
 
     @property
     def m_max(self) -> int:
@@ -126,7 +132,23 @@ def tiny(nodes_per_segment: int = 16, n_theta: int = 32, **kw) -> Workload:
     return w.with_(**kw) if kw else w
 
 
-ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny}
+def corner(panels: Tuple[int, ...] = (2, 2, 2, 2), grade: int = 1, **kw) -> Workload:
+    """The rectangular perturbation of depth and radius 1 (Sec. 5, Example 1;
+    the same polyline carries the corner test of Sec. 4.3): vertices (0, -1),
+    (1, -1), (1, 0), then flat z = 0 through the PML start a1 = 2 to
+    a1 + T = 4; two corners, at (1, -1) and (1, 0).  k1 = 2 pi, k2 = 3 pi,
+    sigma0 = 2, point source on the axis at (0, 0, 1), 32 theta samples,
+    modes 0..8."""
+    w = small().with_(
+        name="corner", bumps=(), cos_freq=0.0, a1=2.0, T=2.0, S=2.0, a2=2.0, T2=1.0, S2=2.0,
+        n_theta=32, m_max_=8, incidences=(("point", 0.0, 1.0),),
+        polyline=((0.0, -1.0), (1.0, -1.0), (1.0, 0.0), (2.0, 0.0), (4.0, 0.0)),
+        panels=tuple(panels), grade=grade)
+    return w.with_(**kw) if kw else w
+
+
+ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny,
+       "corner": corner}
 
 
 def seeded_pairs(n_nodes: int, count: int, seed: int) -> np.ndarray:
