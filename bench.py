@@ -158,8 +158,8 @@ def cpu_baseline(wl, seconds: float = 15.0):
     units = done * len(ks) * len(modes)
     return {"value": units / dt, "unit": "pairs*modes/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d random node pairs of the paper-scale workload, both media, modes 0..%d, "
-                      "adaptive azimuthal quadrature (%.1f s)" % (done, wl.m_max, dt)}
+            "sample": "%d random node pairs of the %s workload, both media, modes 0..%d, "
+                      "adaptive azimuthal quadrature (%.1f s)" % (done, wl.name, wl.m_max, dt)}
 
 
 def field_leg(s, wl, N):
@@ -170,8 +170,13 @@ def field_leg(s, wl, N):
     rng = np.random.default_rng(2412)
     npf = 1024
     rho_f = rng.uniform(0.05, 0.95 * wl.a1, npf)
-    zc = np.interp(rho_f, nd[:, 0], nd[:, 2])
-    z_f = zc + np.where(rng.uniform(size=npf) < 0.5, 1.0, -1.0) * rng.uniform(0.3, 0.6 * wl.a2, npf)
+    if wl.polyline:
+        # above the highest and below the lowest point of the curve
+        z_f = np.where(rng.uniform(size=npf) < 0.5, nd[:, 2].max() + rng.uniform(0.2, 0.5, npf),
+                       nd[:, 2].min() - rng.uniform(0.2, 0.5, npf))
+    else:
+        zc = np.interp(rho_f, nd[:, 0], nd[:, 2])
+        z_f = zc + np.where(rng.uniform(size=npf) < 0.5, 1.0, -1.0) * rng.uniform(0.3, 0.6 * wl.a2, npf)
     rtz = np.stack([rho_f, rng.uniform(0.0, 2.0 * np.pi, npf), z_f], axis=1)
     nrhs = len(wl.incidences)
     s.evaluate_field(rtz[:8], nrhs)
@@ -224,7 +229,10 @@ def main():
         return
 
     def step(precision=0):
-        s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
+        if wl.polyline:
+            s.set_polyline(wl.polyline, wl.panels, wl.grade)
+        else:
+            s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
         s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
         s.build_modal_operators(wl.n_theta, wl.m_max, precision)
         return s.solve_modes(list(wl.incidences))

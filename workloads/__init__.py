@@ -147,8 +147,32 @@ def corner(panels: Tuple[int, ...] = (2, 2, 2, 2), grade: int = 1, **kw) -> Work
     return w.with_(**kw) if kw else w
 
 
+def corner_paper() -> Workload:
+    """The rectangular perturbation at the node count of the paper-scale
+    workload: 24 panels per segment and eight halvings at each corner
+    (128 panels, 2048 nodes); modes 0..32 (the paper keeps |n| <= 20 and 30
+    for its two incidences, Sec. 5), 128 theta samples; a point source on the
+    axis and a plane wave."""
+    return corner(panels=(24, 24, 24, 24), grade=8).with_(
+        name="corner_paper", n_theta=128, m_max_=32,
+        incidences=(("point", 0.0, 1.0), ("plane", 0.5)))
+
+
+def stepped() -> Workload:
+    """The stepped perturbation of Sec. 5, Example 3: vertices (0, -0.5),
+    (0.5, -0.5), (0.5, -0.7), (0.25, -0.7), (0.25, -1), (1, -1), (1, 0), then
+    flat through a1 = 2 to a1 + T = 4; six corners and a segment that runs back
+    toward the axis.  Two panels per segment, one halving at each corner
+    (28 panels, 448 nodes); otherwise as the corner workload."""
+    return corner().with_(
+        name="stepped",
+        polyline=((0.0, -0.5), (0.5, -0.5), (0.5, -0.7), (0.25, -0.7), (0.25, -1.0), (1.0, -1.0),
+                  (1.0, 0.0), (2.0, 0.0), (4.0, 0.0)),
+        panels=(2,) * 8, grade=1)
+
+
 ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny,
-       "corner": corner}
+       "corner": corner, "corner_paper": corner_paper, "stepped": stepped}
 
 
 def seeded_pairs(n_nodes: int, count: int, seed: int) -> np.ndarray:
