@@ -4,7 +4,12 @@ Calls only the oracle (``oracle/``) and the workload definitions
 (``workloads``); nothing here touches the HIP path.
 
     python tests/golden/make_golden.py small        # ~3 min on 8 cores
-    python tests/golden/make_golden.py paper_scale  # ~30 min on 8 cores
+    python tests/golden/make_golden.py paper_scale  # more than a day on 8 cores
+
+The paper-scale file needs every one of the ~4.1M far node pairs by adaptive
+quadrature (19 CPU-hours were not enough); the GPU tests hold the paper scale
+to the oracle through exact operator rows and the solution's backward error
+against them, and use this file only when it exists.
 """
 
 import os

@@ -33,7 +33,7 @@ def _solver(wl, **kw):
 
 def _golden(name):
     """Stored oracle boundary data (written by tests/golden/make_golden.py);
-    the paper-scale file takes hours of oracle time and may not exist yet."""
+    the paper-scale file takes more than a day of oracle time and may not exist."""
     path = os.path.join(HERE, "golden", "boundary_%s.npz" % name)
     if not os.path.exists(path):
         pytest.skip("stored oracle result %s not generated: python tests/golden/make_golden.py %s"
