@@ -84,6 +84,17 @@ double Geometry::hdiff(double r, double dr) const {
   return 0.0;
 }
 
+// x^p for an integer p >= 0 by repeated squaring
+static inline double ipow(double x, int p) {
+  double r = 1.0;
+  while (p > 0) {
+    if (p & 1) r *= x;
+    x *= x;
+    p >>= 1;
+  }
+  return r;
+}
+
 // sigma_1 of eq. eqsgm1
 double Geometry::sigma(double r) const {
   const double a1 = pml.a1, T = pml.T, S = pml.S;
@@ -93,7 +104,7 @@ double Geometry::sigma(double r) const {
   double rb = (r - (a1 + T)) / T;
   double f1 = (0.5 - 1.0 / p) * rb * rb * rb + rb / p + 0.5;
   double f2 = 1.0 - f1;
-  double f1p = pow(f1, p), f2p = pow(f2, p);
+  double f1p = ipow(f1, p), f2p = ipow(f2, p);
   return 2.0 * S * f1p / (f1p + f2p);
 }
 
@@ -291,15 +302,17 @@ void Geometry::build() {
     }
 }
 
-// Lagrange basis on the 16 Gauss-Legendre nodes, barycentric form.
-static void lagrange16(const double* xn, double tq, double* out) {
-  double bw[16];
+// Lagrange basis on the 16 Gauss-Legendre nodes, barycentric form; bw holds
+// the barycentric weights 1 / prod_{m != l} (x_l - x_m).
+static void lagrange_weights16(const double* xn, double* bw) {
   for (int l = 0; l < 16; ++l) {
     double p = 1.0;
     for (int m = 0; m < 16; ++m)
       if (m != l) p *= (xn[l] - xn[m]);
     bw[l] = 1.0 / p;
   }
+}
+static void lagrange16(const double* xn, const double* bw, double tq, double* out) {
   for (int l = 0; l < 16; ++l)
     if (tq == xn[l]) {
       for (int m = 0; m < 16; ++m) out[m] = m == l ? 1.0 : 0.0;
@@ -323,6 +336,8 @@ static void lagrange16(const double* xn, double tq, double* out) {
 void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
                           std::vector<NearJob>& jobs, int self_levels, double hmax) const {
   const int N = n(), np = npanels();
+  double bw[16];
+  lagrange_weights16(glx, bw);
   struct Local {
     std::vector<PairGeom> g;
     std::vector<double> c;
@@ -332,6 +347,9 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
 #pragma omp parallel for schedule(dynamic, 8)
   for (int i = 0; i < N; ++i) {
     Local& L = loc[i];
+    L.g.reserve(512);
+    L.c.reserve(16 * 512);
+    L.j.reserve(3);
     const int p0 = panel[i];
     for (int pn = p0 - 1; pn <= p0 + 1; ++pn) {
       if (pn < 0 || pn >= np) continue;
@@ -412,7 +430,7 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
         g.nz = nz;
         L.g.push_back(g);
         double Lg[16];
-        lagrange16(glx, tp, Lg);
+        lagrange16(glx, bw, tp, Lg);
         const double base = 2.0 * a.w * r * jc;
         for (int l = 0; l < 16; ++l) L.c.push_back(base * Lg[l]);
       }
@@ -420,26 +438,29 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
       L.j.push_back(J);
     }
   }
-  size_t tot = 0, totj = 0;
-  for (const Local& L : loc) {
-    tot += L.g.size();
-    totj += L.j.size();
+  // concatenate in target order: offsets first, then every target copies its
+  // own tables in parallel
+  std::vector<size_t> og(N + 1, 0), oj(N + 1, 0);
+  for (int i = 0; i < N; ++i) {
+    og[i + 1] = og[i] + loc[i].g.size();
+    oj[i + 1] = oj[i] + loc[i].j.size();
   }
-  geom.clear();
-  coef.clear();
-  jobs.clear();
-  geom.reserve(tot);
-  coef.reserve(tot * 16);
-  jobs.reserve(totj);
-  for (const Local& L : loc) {
-    const int base = (int)geom.size();
-    geom.insert(geom.end(), L.g.begin(), L.g.end());
-    coef.insert(coef.end(), L.c.begin(), L.c.end());
-    for (NearJob J : L.j) {
-      J.q0 += base;
-      J.q1 += base;
-      jobs.push_back(J);
+  geom.resize(og[N]);
+  coef.resize(16 * og[N]);
+  jobs.resize(oj[N]);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < N; ++i) {
+    Local& L = loc[i];
+    std::copy(L.g.begin(), L.g.end(), geom.begin() + og[i]);
+    std::copy(L.c.begin(), L.c.end(), coef.begin() + 16 * og[i]);
+    for (size_t k = 0; k < L.j.size(); ++k) {
+      NearJob J = L.j[k];
+      J.q0 += (int)og[i];
+      J.q1 += (int)og[i];
+      jobs[oj[i] + k] = J;
     }
+    std::vector<PairGeom>().swap(L.g);
+    std::vector<double>().swap(L.c);
   }
 }
 
