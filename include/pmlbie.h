@@ -159,9 +159,12 @@ int pmlbie_solve_modes(pmlbie_ctx* ctx, int n_rhs, const pmlbie_incidence* inc, 
                        void* d_phi1, void* d_u2, void* d_phi2);
 
 /* Scattered field at n_pts points (host array rtz of (rho, theta, z)
- * triples, physical region, at least one panel length away from the
- * curve), by the Green representation of each medium (Sec. 4.2, eq.
- * eqfujs) and the modal synthesis.  out: host array, n_rhs * n_pts
+ * triples, physical region, off the curve), by the Green representation of
+ * each medium (Sec. 4.2, eq. eqfujs) and the modal synthesis.  A panel closer
+ * to a point than the panel's arclength is integrated on auxiliary points
+ * graded toward the closest curve point, against the Lagrange interpolant of
+ * the densities on its nodes (the panel rule alone fails there); the other
+ * panels use their nodes.  out: host array, n_rhs * n_pts
  * complex128, layout [rhs][point].  n_pts = 0 is allowed.  The points are
  * processed in chunks whose point x node modal kernels take about 2 GiB of
  * device memory, so any number of points fits; PMLBIE_EINVAL for a point

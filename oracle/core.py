@@ -432,6 +432,60 @@ def field_modes(g: Geometry, modes: Sequence[int], sol, pts: np.ndarray, medium:
     return out
 
 
+def _panel_point(g: Geometry, p: int, t: np.ndarray):
+    """(rho, z) of panel p at parameters t (graph: linear in rho; polyline:
+    linear along the straight panel)."""
+    ra, dr, za, dz = g.panels[p]
+    u = 0.5 * (1.0 + np.asarray(t))
+    rho = ra + u * dr
+    if g.wl.polyline:
+        return rho, za + u * dz
+    L = lib()
+    return rho, np.array([L.or_h(float(x)) for x in np.atleast_1d(rho)])
+
+
+def field_modes_exact(g: Geometry, modes: Sequence[int], sol, pts: np.ndarray, medium: int,
+                      reltol: float = 1e-13):
+    """Scattered-field modes at points pts [P, 2] (rho, z) off the curve by the
+    Green representation (Sec. 4.2, eq. eqfujs) with the densities of each
+    panel interpolated on its 16 nodes and every panel integrated adaptively
+    (no fixed rule): exact for the discretised densities at any distance from
+    the curve."""
+    wl = g.wl
+    _set_geometry(wl)
+    L = lib()
+    L.or_set_reltol(1e-14)
+    u1, p1, u2, p2 = sol[:4]
+    k = wl.k1 if medium == 1 else wl.k2
+    u, p = (u1, p1) if medium == 1 else (u2, p2)
+    sgn = 1.0 if medium == 1 else -1.0
+    m = np.ascontiguousarray(np.asarray(modes, dtype=np.int32))
+    kri = _kri([k])
+    P = len(g.panels)
+    ts = np.linspace(-1.0, 1.0, 201)
+    out = np.zeros((len(modes), pts.shape[0]), dtype=np.complex128)
+    for q in range(pts.shape[0]):
+        rho_p, z_p = float(pts[q, 0]), float(pts[q, 1])
+        I_p = L.or_I(rho_p)
+        tinfo, pan = [], []
+        for pp in range(P):
+            r, z = _panel_point(g, pp, ts)
+            tstar = float(ts[int(np.argmin((r - rho_p) ** 2 + (z - z_p) ** 2))])
+            tinfo.append([rho_p, I_p, z_p, tstar, 2.0])
+            pan.append(g.panels[pp])
+        tinfo = np.ascontiguousarray(np.array(tinfo, dtype=np.float64))
+        pan = np.ascontiguousarray(np.array(pan, dtype=np.float64))
+        res = np.zeros((P, 16, 1, 2, len(m)), dtype=np.complex128)
+        bad = L.or_near_panels(P, _p(tinfo), _p(pan), 1, _p(kri), len(m), _p(m), reltol, _p(res))
+        if bad:
+            raise RuntimeError("oracle: field quadrature budget exhausted on %d panels" % bad)
+        IS = res[:, :, 0, 0, :].reshape(P * 16, len(m))
+        IK = res[:, :, 0, 1, :].reshape(P * 16, len(m))
+        for j in range(len(m)):
+            out[j, q] = sgn * (IS[:, j] @ p[j] - IK[:, j] @ u[j])
+    return out
+
+
 def lib_I(wl, rho: float) -> float:
     _set_geometry(wl)
     return lib().or_I(float(rho))

@@ -397,6 +397,7 @@ typedef struct {
   double pa, L;              /* panel: rho = pa + (1 + t) L / 2 */
   double za, dzp;            /* straight panel: z = za + (1 + t) dzp / 2 */
   int self;                  /* 1: target lies on this panel at t_i */
+  int offc;                  /* 1: target off the curve (a field point), closest to t_i */
   double ti;
   int nk;
   cplx k[2];
@@ -456,7 +457,7 @@ static void near_integrand(double t, void *vctx, cplx *out) {
        uses that same difference, so the pair geometry stays consistent down to
        the log singularity */
     drho = c->rho_t - rho;
-    dz = or_hdiff(c->rho_t, rho);
+    dz = c->offc ? c->z_t - g[2] : or_hdiff(c->rho_t, rho);
   }
   double dI = or_Idiff(c->rho_t, rho);
   pairctx p;
@@ -482,7 +483,8 @@ static void near_integrand(double t, void *vctx, cplx *out) {
 /*
  * Product integrals of nt targets against panels.  For target q:
  * tinfo[5*q] = (rho_t, I_t, z_t, t_i or 2 (not on panel), which: 0 self,
- * -1 left neighbour, +1 right neighbour), panel[4*q] = (pa, L, za, dz): the
+ * -1 left neighbour, +1 right neighbour, 2 a point off the curve whose
+ * closest panel parameter is t_i), panel[4*q] = (pa, L, za, dz): the
  * start rho and rho-extent, and (straight panels only) the start z and
  * z-extent.
  * out[q][l][(2*ik+{S,K})][j] = int_{-1}^{1} F_n(r_q, r(t)) rho |dr/dt| l_l(t) dt.
@@ -502,6 +504,7 @@ int or_near_panels(int nt, const double *tinfo, const double *panel, int nk,
     c.za = panel[4 * q + 2]; c.dzp = panel[4 * q + 3];
     int which = (int)ti[4];
     c.self = which == 0;
+    c.offc = which == 2;
     c.ti = ti[3];
     c.nk = nk;
     c.k[0] = kri[0] + kri[1] * (cplx)_Complex_I;
@@ -521,6 +524,17 @@ int or_near_panels(int nt, const double *tinfo, const double *panel, int nk,
       for (int g = 0; g < ngl; ++g) brk[nb++] = gl[g];
       brk[nb++] = c.ti;
       for (int g = ngr - 1; g >= 0; --g) brk[nb++] = gr[g];
+      brk[nb++] = 1.0;
+    } else if (which == 2) {
+      /* off-curve target: breakpoints graded toward its closest point t_i */
+      brk[nb++] = -1.0;
+      double gl[30], gr[30];
+      int ngl = 0, ngr = 0;
+      for (double h = 0.5 * (c.ti + 1.0); h > 1e-6 && ngl < 30; h *= 0.25) gl[ngl++] = c.ti - h;
+      for (double h = 0.5 * (1.0 - c.ti); h > 1e-6 && ngr < 30; h *= 0.25) gr[ngr++] = c.ti + h;
+      for (int g = 0; g < ngl; ++g) if (gl[g] > -1.0) brk[nb++] = gl[g];
+      if (c.ti > -1.0 && c.ti < 1.0) brk[nb++] = c.ti;
+      for (int g = ngr - 1; g >= 0; --g) if (gr[g] < 1.0) brk[nb++] = gr[g];
       brk[nb++] = 1.0;
     } else if (which == -1) {
       /* panel to the left: the shared endpoint is t = +1 */

@@ -869,8 +869,27 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
     const int chunk = (int)std::max(1L, std::min((long)n_pts, (2L << 30) / per_pt));
     std::vector<PairGeom> g;
     g.reserve((size_t)chunk * N);
+    // points closer to a panel than its arclength: that panel's entries by
+    // product integration (same interval cap as the build's near panels)
+    const double keff = std::max(cabs_(c->k1), cabs_(c->k2)) * sqrt(1.0 + c->geo.pml.S * c->geo.pml.S);
+    const double near_hmax = keff > 0.0 ? 4.0 / keff : 1e300;
+    std::vector<PairGeom> fg;
+    std::vector<double> fc;
+    std::vector<NearJob> fj;
+    DBuf<zd> fraw;
+    DBuf<double> fcoef;
+    DBuf<NearJob> fjobs;
     for (int p0 = 0; p0 < n_pts; p0 += chunk) {
       const int np = std::min(chunk, n_pts - p0);
+      fg.clear();
+      fc.clear();
+      fj.clear();
+      for (int p = p0; p < p0 + np; ++p)
+        c->geo.field_near(rtz[3 * p], rtz[3 * p + 2], p - p0, 1.0, near_hmax, fg, fc, fj);
+      for (const NearJob& J : fj)
+        if (J.target < 0 || J.target >= np || J.panel < 0 || 16L * J.panel + 15 >= N || J.q0 < 0 ||
+            J.q1 > (int)fg.size() || J.q0 > J.q1)
+          return fail(c, PMLBIE_EDEVICE, "evaluate_field: inconsistent near-curve tables");
       g.clear();
       for (int p = p0; p < p0 + np; ++p) {
         const double r = rtz[3 * p], zz = rtz[3 * p + 2];
@@ -887,6 +906,19 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
       }
       c->raw.alloc(g.size() * 4 * (M + 1));
       run_pair_list(c, g, c->raw.p, nullptr);  // synchronous: g may be reused
+      if (!fj.empty()) {
+        fraw.alloc(fg.size() * 4 * (M + 1));
+        run_pair_list(c, fg, fraw.p, nullptr);
+        fcoef.alloc(fc.size());
+        fjobs.alloc(fj.size());
+        HIPCHK(hipMemcpyAsync(fcoef.p, fc.data(), fc.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(fjobs.p, fj.data(), fj.size() * sizeof(NearJob), hipMemcpyHostToDevice,
+                              c->stream));
+        launch_field_near(fjobs.p, (int)fj.size(), fcoef.p, fraw.p, N, M, c->raw.p, c->stream);
+        HIPCHK(hipGetLastError());
+        // the host tables are refilled for the next chunk
+        HIPCHK(hipStreamSynchronize(c->stream));
+      }
       launch_field(c->raw.p, c->nodes.p + 3L * N, N, M, c->m0, c->nrhs, np, dmed.p + p0, dth.p + p0,
                    c->u1.p, c->p1.p, c->u2.p, c->p2.p, dout.p + p0, n_pts, c->stream);
       HIPCHK(hipGetLastError());

@@ -300,6 +300,9 @@ void Geometry::build() {
       t[i] = glx[j];
       panel[i] = p;
     }
+  parc.assign(np, 0.0);
+  for (int p = 0; p < np; ++p)
+    for (int j = 0; j < 16; ++j) parc[p] += glw[j] * jac[16 * p + j];
 }
 
 // Lagrange basis on the 16 Gauss-Legendre nodes, barycentric form; bw holds
@@ -461,6 +464,93 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
     }
     std::vector<PairGeom>().swap(L.g);
     std::vector<double>().swap(L.c);
+  }
+}
+
+void Geometry::field_near(double r, double zz, int tag, double factor, double hmax,
+                          std::vector<PairGeom>& geom, std::vector<double>& coef,
+                          std::vector<NearJob>& jobs) const {
+  double bw[16];
+  lagrange_weights16(glx, bw);
+  const double It = Iint(r);
+  for (int pn = 0; pn < npanels(); ++pn) {
+    // every point of the panel lies within its arclength of the middle node
+    const double dmid = hypot(r - rho[16 * pn + 8], zz - z[16 * pn + 8]);
+    if (dmid - parc[pn] >= factor * parc[pn]) continue;
+    double dmin = 1e300;
+    for (int j = 0; j < 16; ++j) dmin = std::min(dmin, hypot(r - rho[16 * pn + j], zz - z[16 * pn + j]));
+    if (!(dmin < factor * parc[pn])) continue;
+    // closest curve point: the best of 65 samples, refined by golden sections
+    auto dist2 = [&](double tp) {
+      double rr, Ir, z2, jc;
+      zd nr, nz;
+      point(pn, tp, rr, Ir, z2, nr, nz, jc);
+      return (r - rr) * (r - rr) + (zz - z2) * (zz - z2);
+    };
+    int kb = 0;
+    double db = 1e300;
+    for (int k = 0; k <= 64; ++k) {
+      const double d2 = dist2(-1.0 + k / 32.0);
+      if (d2 < db) {
+        db = d2;
+        kb = k;
+      }
+    }
+    double a = std::max(-1.0, -1.0 + (kb - 1) / 32.0), b = std::min(1.0, -1.0 + (kb + 1) / 32.0);
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1 = dist2(x1), f2 = dist2(x2);
+    for (int it = 0; it < 60; ++it) {
+      if (f1 < f2) {
+        b = x2; x2 = x1; f2 = f1; x1 = b - gr * (b - a); f1 = dist2(x1);
+      } else {
+        a = x1; x1 = x2; f1 = f2; x2 = a + gr * (b - a); f2 = dist2(x2);
+      }
+    }
+    const double ts = 0.5 * (a + b);
+    const double hs = 0.5 * parc[pn];  // physical length per unit of parameter (mean)
+    // distance in units of the parameter; the rule on each side of ts shrinks
+    // by 4 toward ts until the intervals are below it
+    const double dpar = std::max(sqrt(dist2(ts)) / hs, 1e-12);
+    NearJob J;
+    J.target = tag;
+    J.panel = pn;
+    J.q0 = (int)geom.size();
+    for (int side = -1; side <= 1; side += 2) {
+      const double hside = side > 0 ? 1.0 - ts : ts + 1.0;
+      if (!(hside > 0.0)) continue;
+      double hi = hside;
+      for (int nint = 0;; ++nint) {
+        double lo = hi * 0.25;
+        if ((hi <= dpar && nint >= 2) || nint >= 40) lo = 0.0;
+        const int npc = std::max(1, (int)ceil((hi - lo) * hs / hmax - 1e-9));
+        for (int k = 0; k < npc; ++k) {
+          const double ia = lo + (hi - lo) * k / npc, ib = lo + (hi - lo) * (k + 1) / npc;
+          for (int j = 0; j < 16; ++j) {
+            const double off = ia + 0.5 * (ib - ia) * (1.0 + glx[j]);
+            const double w = 0.5 * (ib - ia) * glw[j];
+            const double tp = ts + side * off;
+            double rr, Ir, z2, jc;
+            zd nr, nz;
+            point(pn, tp, rr, Ir, z2, nr, nz, jc);
+            PairGeom g;
+            g.rt = zd{r, It};
+            g.rs = zd{rr, Ir};
+            g.drho = zd{r - rr, It - Ir};
+            g.dz = zd{zz - z2, 0.0};
+            g.nr = nr;
+            g.nz = nz;
+            geom.push_back(g);
+            double Lg[16];
+            lagrange16(glx, bw, tp, Lg);
+            for (int l = 0; l < 16; ++l) coef.push_back(w * rr * jc * Lg[l] / W[16 * pn + l]);
+          }
+        }
+        if (lo == 0.0) break;
+        hi = lo;
+      }
+    }
+    J.q1 = (int)geom.size();
+    jobs.push_back(J);
   }
 }
 

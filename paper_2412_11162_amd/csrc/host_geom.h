@@ -43,6 +43,7 @@ class Geometry {
   // panels
   std::vector<double> pa, pl;  // start rho and rho-length (signed for polylines)
   std::vector<double> pz, pdz;  // polyline: start z and z-length
+  std::vector<double> parc;     // panel arclength
   std::vector<double> plen;     // panel length in the variable its parameter is linear in
                                 // (arclength for a polyline, rho for a graph)
   std::vector<double> Ipa;     // Im rho~ at each panel start
@@ -78,6 +79,15 @@ class Geometry {
   // relative to the target, Lagrange-weighted quadrature coefficients, jobs
   void build_near(std::vector<PairGeom>& geom, std::vector<double>& coef,
                   std::vector<NearJob>& jobs, int self_levels, double hmax) const;
+
+  // Field point (r, z) off the curve: for every panel closer than `factor`
+  // times its arclength, auxiliary points graded toward the closest curve
+  // point and coefficients w rho |r'| l_l(t) / W_l that turn their modal
+  // kernels into the panel's 16 node entries (product integration of the
+  // Lagrange-interpolated densities); appended as jobs with target = tag.
+  void field_near(double r, double zz, int tag, double factor, double hmax,
+                  std::vector<PairGeom>& geom, std::vector<double>& coef,
+                  std::vector<NearJob>& jobs) const;
 
  private:
   double graw(double r) const;

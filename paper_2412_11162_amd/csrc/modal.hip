@@ -645,6 +645,36 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
   }
 }
 
+// Field points near the curve: the modal kernels of a point against the 16
+// nodes of a nearby panel are replaced by product integrals over the panel
+// (auxiliary points graded toward the closest curve point, Lagrange basis of
+// the panel), already divided by the node weights that the field sum applies.
+// One workgroup per (point, panel) job; raw_aux[q][s][n] at the auxiliary
+// points, raw[(point * N + node)][s][n] the chunk's kernels.
+__global__ __launch_bounds__(256) void k_field_near(const NearJob* __restrict__ jobs, int njobs,
+                                                    const double* __restrict__ coef,
+                                                    const zd* __restrict__ raw_aux, int N, int M,
+                                                    zd* __restrict__ raw) {
+  const int jb = blockIdx.x;
+  if (jb >= njobs) return;
+  const NearJob J = jobs[jb];
+  const int tot = 4 * (M + 1);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    zd acc[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) acc[l] = zd{0.0, 0.0};
+    for (int q = J.q0; q < J.q1; ++q) {
+      const zd v = raw_aux[(long)q * tot + e];
+      const double* c = coef + (long)q * 16;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) acc[l] = acc[l] + c[l] * v;
+    }
+    zd* dst = raw + ((long)J.target * N + (long)J.panel * 16) * tot + e;
+#pragma unroll
+    for (int l = 0; l < 16; ++l) dst[(long)l * tot] = acc[l];
+  }
+}
+
 // ------------------------------------------------------------------------
 // Plane-wave right-hand sides (Sec. 2): the jump of the reference field
 //   [u_tot0] = e^{-i k1 rho sin(phi) cos(theta)} g(z),
@@ -821,6 +851,12 @@ void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* r
   if (njobs <= 0) return;
   OutSpec o{A, n2, mstride, nullptr, nullptr, M, m0};
   hipLaunchKernelGGL(k_near, dim3(njobs), dim3(256), 0, st, jobs, njobs, coef, raw, M, o);
+}
+
+void launch_field_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw_aux, int N,
+                       int M, zd* raw, hipStream_t st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_field_near, dim3(njobs), dim3(256), 0, st, jobs, njobs, coef, raw_aux, N, M, raw);
 }
 
 }  // namespace pmlbie

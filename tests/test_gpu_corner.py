@@ -245,3 +245,53 @@ def test_stepped_perturbation_rows_and_solution():
     s.solve_modes([("point", 0.6, -0.9)])            # inside the lower step: upper
     with pytest.raises(PmlbieError):
         s.solve_modes([("point", 0.4, -0.6)])        # in the pocket: lower medium
+
+
+def _field_ref(g, modes, sol, pts, med, theta):
+    import oracle
+    ref = np.zeros(len(pts), dtype=complex)
+    for q in range(len(pts)):
+        fm = oracle.core.field_modes_exact(g, modes, sol, pts[q:q + 1], med[q])[:, 0]
+        ref[q] = (fm[0] + 2 * np.sum(fm[1:] * np.cos(np.arange(1, len(modes)) * theta[q]))) / (2 * np.pi)
+    return ref
+
+
+def test_field_near_the_curve_graph_and_corners(corner_ref):
+    """Field points closer to the curve than a panel length, where the
+    panel rule fails: the library integrates the nearby panels on auxiliary
+    points graded toward the closest curve point; the oracle integrates
+    every panel adaptively.  Graph curve (tiny workload, panels of length
+    about 1) at distances 0.02 to 0.6, and the rectangular cavity next to both
+    corners, both media."""
+    import oracle
+    wl = workloads.tiny()
+    g = oracle.geometry(wl)
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    sol = oracle.solve(g, modes, b1, b2)
+    pts, med = [], []
+    assert g.rho[31] < wl.a1    # nodes 0..31 lie in the physical region
+    for l, d in ((5, 0.02), (12, 0.05), (20, 0.1), (25, 0.3), (29, 0.6)):
+        nu = g.nu[l]
+        pts.append([g.rho[l] - d * nu[0], g.z[l] - d * nu[1]]); med.append(1)
+        pts.append([g.rho[l] + d * nu[0], g.z[l] + d * nu[1]]); med.append(2)
+    pts = np.array(pts)
+    theta = np.linspace(0.0, 2.5, len(pts))
+    ref = _field_ref(g, modes, sol, pts, med, theta)
+    s = _solver(wl)
+    s.solve_modes([("point", 0.3, 1.0)])
+    out = s.evaluate_field(np.stack([pts[:, 0], theta, pts[:, 1]], axis=1), 1)[0]
+    assert np.max(np.abs(out - ref)) <= 1e-8 * np.max(np.abs(ref)), np.abs(out - ref) / np.max(np.abs(ref))
+
+    wl, g, A, modes = corner_ref
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.0, 1.0)
+    sol = oracle.solve(g, modes, b1, b2, A=A)
+    pts = np.array([[0.98, -0.98], [1.03, -0.5], [0.5, -0.95], [1.5, 0.04], [1.5, -0.04], [0.97, -0.02],
+                    [1.02, -1.02]])
+    med = [1, 2, 1, 1, 2, 1, 2]
+    theta = np.linspace(0.3, 2.0, len(pts))
+    ref = _field_ref(g, modes, sol, pts, med, theta)
+    s = _solver(wl)
+    s.solve_modes([("point", 0.0, 1.0)])
+    out = s.evaluate_field(np.stack([pts[:, 0], theta, pts[:, 1]], axis=1), 1)[0]
+    assert np.max(np.abs(out - ref)) <= 1e-8 * np.max(np.abs(ref)), np.abs(out - ref) / np.max(np.abs(ref))

@@ -1,10 +1,13 @@
 """Pins of the oracle's polyline curves (corners, graded panels; Sec. 4 and
 Sec. 5, Examples 1 and 3) against closed forms, the graph-curve path that the
-other pins hold, and the paper's explicit-solution protocol (Sec. 4.3).
+other pins hold, and the paper's explicit-solution protocol (Sec. 4.3); and of
+its exact field near the curve (every panel integrated adaptively) against
+the fixed rule far away and the boundary data at the curve.
 
 None of these tests uses the HIP path.
 """
 
+import functools
 import math
 
 import numpy as np
@@ -100,3 +103,50 @@ def test_corner_explicit_solution():
                    int(np.argmin(np.abs(g.z + 0.5) + np.abs(g.rho - 1.0))), g.n - 5})
     res, _ = _explicit_residual(wl, [0, 1, 3], rows)
     assert np.all(res < 1e-7), res
+
+
+# ------------------------------------------------- field near the curve
+
+@functools.lru_cache(maxsize=1)
+def _tiny_solution():
+    wl = workloads.tiny()
+    g = oracle.geometry(wl)
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    return g, modes, oracle.solve(g, modes, b1, b2)
+
+
+def test_exact_field_matches_the_fixed_rule_far_from_the_curve():
+    """Away from the curve the 16-point panel rule is exact to rounding, so
+    the oracle's adaptive product integration of every panel must agree with
+    the plain node sum there (both media)."""
+    g, modes, sol = _tiny_solution()
+    for pt, med in (([0.5, 1.4], 1), ([1.2, -0.9], 2)):
+        pts = np.array([pt])
+        fe = oracle.core.field_modes_exact(g, modes, sol, pts, med)
+        ff = oracle.field_modes(g, modes, sol, pts, med)
+        assert np.max(np.abs(fe - ff)) <= 1e-11 * np.max(np.abs(ff))
+
+
+def test_exact_field_tends_to_the_boundary_data():
+    """Green's representation reproduces the field up to the boundary: at a
+    distance d from a node, on the side of either medium, the field modes
+    differ from that medium's boundary data (u1 above, u2 below) by O(d),
+    i.e. the double-layer jump is captured exactly; a missing or doubled jump
+    leaves an O(1) difference."""
+    g, modes, sol = _tiny_solution()
+    for l in (20, 37):
+        nu = g.nu[l]
+        errs = {}
+        for d in (1e-3, 1e-4):
+            up = np.array([[g.rho[l] - d * nu[0], g.z[l] - d * nu[1]]])
+            lo = np.array([[g.rho[l] + d * nu[0], g.z[l] + d * nu[1]]])
+            fu = oracle.core.field_modes_exact(g, modes, sol, up, 1)[:, 0]
+            fl = oracle.core.field_modes_exact(g, modes, sol, lo, 2)[:, 0]
+            eu = np.max(np.abs(fu - sol[0][:, l])) / np.max(np.abs(sol[0][:, l]))
+            el = np.max(np.abs(fl - sol[2][:, l])) / np.max(np.abs(sol[2][:, l]))
+            errs[d] = (eu, el)
+            assert eu < 100 * d and el < 100 * d, (l, d, eu, el)
+        # first order in d
+        for a, b in zip(errs[1e-3], errs[1e-4]):
+            assert 5.0 < a / b < 20.0
