@@ -170,7 +170,7 @@ def field_leg(s, wl, N):
     rng = np.random.default_rng(2412)
     npf = 1024
     rho_f = rng.uniform(0.05, 0.95 * wl.a1, npf)
-    if wl.polyline:
+    if wl.polyline or wl.curve_nodes is not None:
         # above the highest and below the lowest point of the curve
         z_f = np.where(rng.uniform(size=npf) < 0.5, nd[:, 2].max() + rng.uniform(0.2, 0.5, npf),
                        nd[:, 2].min() - rng.uniform(0.2, 0.5, npf))
@@ -229,7 +229,9 @@ def main():
         return
 
     def step(precision=0):
-        if wl.polyline:
+        if wl.curve_nodes is not None:
+            s.set_panels(wl.curve_nodes)
+        elif wl.polyline:
             s.set_polyline(wl.polyline, wl.panels, wl.grade)
         else:
             s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)

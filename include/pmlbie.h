@@ -19,7 +19,7 @@
  *   - Every call returns PMLBIE_OK (0) or a negative status; nothing throws
  *     or aborts across the ABI.  pmlbie_last_error() describes the last
  *     failure of a context.
- *   - Calls run in order: set_geometry (or set_polyline) -> set_media_pml ->
+ *   - Calls run in order: set_geometry (or set_polyline, set_panels) -> set_media_pml ->
  *     build_modal_operators -> solve_modes -> evaluate_field; a call out of
  *     order returns PMLBIE_ESTATE.  Changing geometry or media invalidates
  *     later stages.
@@ -97,6 +97,22 @@ int pmlbie_set_geometry(pmlbie_ctx* ctx, int n_bumps, const double* bumps, doubl
 #define PMLBIE_POLY_MAX_VERTS 64
 int pmlbie_set_polyline(pmlbie_ctx* ctx, int n_vert, const double* verts, const int* panels,
                         int grade);
+
+/* Generating curve given by its panels (any piecewise smooth curve, e.g.
+ * the smooth non-graph curve of Sec. 5, Example 2, with the panels graded
+ * toward its corners by the caller): nodes[32 * p + 2 * j + {0, 1}] = (rho, z)
+ * of panel p at the j-th of the 16 Gauss-Legendre points of [-1, 1] (host,
+ * ascending points, panels in curve order from the axis outward).  The curve
+ * on a panel is the degree-15 interpolant of its nodes; consecutive panels
+ * must join (to 1e-9 of the coordinates), the first must start on the axis
+ * and the curve must be flat (z = 0) where rho > a1, no panel straddling a1,
+ * and end at a1 + T (checked by pmlbie_set_media_pml).  The unit normal is
+ * (z', -rho') / |r'|, into the lower medium.  Node i lies on panel i / 16.
+ * Errors: PMLBIE_EINVAL for n_panels outside [4, PMLBIE_MAX_PANELS] or not a
+ * multiple of 4, a node with rho <= 0 or non-finite, panels that do not join,
+ * a curve that does not start on the axis. */
+#define PMLBIE_MAX_PANELS 65536
+int pmlbie_set_panels(pmlbie_ctx* ctx, int n_panels, const double* nodes);
 
 /* Media and PML (Sec. 2, Sec. 3.1 eq. eqsgm1): wavenumbers k1 (upper medium),
  * k2 (lower medium), real or complex; radial PML from a1 with thickness T and

@@ -99,6 +99,7 @@ class Geometry:
     sigma: np.ndarray
     w: np.ndarray              # GL weight on [-1, 1]
     W: np.ndarray              # w * rho * |dr/dt|: physical measure rho' ds
+    cheb: Optional[np.ndarray] = None  # curved panels: [P, 64] Chebyshev series of rho, z, rho', z'
 
     @property
     def n(self) -> int:
@@ -124,7 +125,7 @@ def _set_geometry(wl) -> None:
     x, _ = gl16()
     L.or_set_geometry(len(wl.bumps), _p(bumps), float(wl.cos_freq), float(wl.a1),
                       float(wl.T), float(wl.S), int(wl.p), _p(np.ascontiguousarray(x)))
-    L.or_set_poly(1 if wl.polyline else 0)
+    L.or_set_poly(2 if wl.curve_nodes is not None else (1 if wl.polyline else 0))
 
 
 def sigma(wl, rho: float) -> float:
@@ -186,11 +187,65 @@ def _polyline_geometry(wl) -> Geometry:
         w=w, W=w * rho * jac)
 
 
+def _curved_geometry(wl) -> Geometry:
+    """Node tables of a curve given by its panels: on each panel the curve is
+    the degree-15 polynomial through the 16 given nodes, here as Chebyshev
+    series (the 16 x 16 Chebyshev-Vandermonde system at the nodes, condition
+    number ~3, solved directly) with their derivatives."""
+    from numpy.polynomial import chebyshev as C
+    L = lib()
+    x, wq = gl16()
+    nodes = np.asarray(wl.curve_nodes, dtype=np.float64)
+    P = nodes.shape[0]
+    cheb = np.zeros((P, 64))
+    panels = np.zeros((P, 4))
+    cols = {k: [] for k in ("rho", "I", "z", "nu", "jac", "nr", "nz", "sg", "p", "t", "w")}
+    V = C.chebvander(x, 15)
+    for p in range(P):
+        cr = np.linalg.solve(V, nodes[p, :, 0])
+        cz = np.linalg.solve(V, nodes[p, :, 1])
+        dcr, dcz = C.chebder(cr), C.chebder(cz)
+        cheb[p, :16], cheb[p, 16:32] = cr, cz
+        cheb[p, 32:32 + len(dcr)], cheb[p, 48:48 + len(dcz)] = dcr, dcz
+        e = C.chebval(np.array([-1.0, 1.0]), np.stack([cr, cz], axis=1))  # [coordinate, end]
+        panels[p] = (e[0, 0], e[0, 1] - e[0, 0], e[1, 0], e[1, 1] - e[1, 0])
+        dr, dz = C.chebval(x, dcr), C.chebval(x, dcz)
+        for q in range(16):
+            rho, zz = nodes[p, q]
+            ln = math.hypot(dr[q], dz[q])
+            nu = (dz[q] / ln, -dr[q] / ln)
+            Iv = L.or_I(rho)
+            sg = L.or_sigma(rho)
+            rt = rho + 1j * Iv
+            cols["rho"].append(rho); cols["I"].append(Iv); cols["z"].append(zz)
+            cols["nu"].append(nu); cols["jac"].append(ln)
+            cols["nr"].append(nu[0] * rt / rho); cols["nz"].append(nu[1] * rt * (1 + 1j * sg) / rho)
+            cols["sg"].append(sg); cols["p"].append(p); cols["t"].append(x[q]); cols["w"].append(wq[q])
+    rho = np.array(cols["rho"]); jac = np.array(cols["jac"]); w = np.array(cols["w"])
+    return Geometry(
+        wl=wl, panels=panels, panel_of=np.array(cols["p"]), t=np.array(cols["t"]), rho=rho,
+        I=np.array(cols["I"]), z=np.array(cols["z"]), hp=np.zeros_like(rho), nu=np.array(cols["nu"]),
+        jac=jac, nrho=np.array(cols["nr"]), nz=np.array(cols["nz"]), sigma=np.array(cols["sg"]),
+        w=w, W=w * rho * jac, cheb=cheb)
+
+
+def _panel_records(g: Geometry, idx) -> np.ndarray:
+    """[len(idx), 68] panel records of the C near-panel integrals."""
+    idx = np.asarray(idx, dtype=np.int64)
+    rec = np.zeros((len(idx), 68))
+    rec[:, :4] = g.panels[idx]
+    if g.cheb is not None:
+        rec[:, 4:] = g.cheb[idx]
+    return np.ascontiguousarray(rec)
+
+
 def geometry(wl) -> Geometry:
     """Gauss-Legendre node tables: four segments split into equal-rho
-    sub-panels of 16 nodes each (graph curves), or graded straight panels
-    (polylines)."""
+    sub-panels of 16 nodes each (graph curves), graded straight panels
+    (polylines), or the caller's curved panels."""
     _set_geometry(wl)
+    if wl.curve_nodes is not None:
+        return _curved_geometry(wl)
     if wl.polyline:
         return _polyline_geometry(wl)
     L = lib()
@@ -262,14 +317,23 @@ def modal_kernels_nodes(g: Geometry, pairs: np.ndarray, ks: Sequence[complex],
     # graph curves: z differences from the interface formula without
     # cancellation; polylines: plain coordinate differences
     return modal_kernels_points(g.wl, g.tgt_table(pairs[:, 0]), g.src_table(pairs[:, 1]), ks,
-                                modes, oncurve=not g.wl.polyline, reltol=reltol)
+                                modes, oncurve=not (g.wl.polyline or g.cheb is not None),
+                                reltol=reltol)
 
 
 def near_integrals(g: Geometry, targets: Iterable[int], ks: Sequence[complex],
                    modes: Sequence[int], reltol: float = 1e-13) -> Dict[int, Dict[int, np.ndarray]]:
     """Exact product integrals of the near panels (self and neighbours):
     result[i][panel] = [16, len(ks), 2, len(modes)] of
-    int_{-1}^{1} F_n(r_i, r(t)) rho(t) |dr/dt| l_l(t) dt."""
+    int_{-1}^{1} F_n(r_i, r(t)) rho(t) |dr/dt| l_l(t) dt.
+
+    On curved panels the tolerance is at least 1e-11: next to a small
+    neighbour's end the double-layer numerator n . (r - r') cancels to
+    curvature x distance^2 while its rounding stays eps x distance, which
+    leaves ~1e-12 relative noise in the integrand that no tighter rule can
+    get below."""
+    if g.cheb is not None:
+        reltol = max(reltol, 1e-11)
     _set_geometry(g.wl)
     L = lib()
     L.or_set_reltol(1e-14)
@@ -281,11 +345,11 @@ def near_integrals(g: Geometry, targets: Iterable[int], ks: Sequence[complex],
             jobs.append((i, p, which))
     tinfo = np.array([[g.rho[i], g.I[i], g.z[i], g.t[i] if w == 0 else 2.0, w] for i, p, w in jobs],
                      dtype=np.float64)
-    pan = np.array([g.panels[p] for _, p, _ in jobs], dtype=np.float64)
+    pan = _panel_records(g, [p for _, p, _ in jobs])
     m = np.ascontiguousarray(np.asarray(modes, dtype=np.int32))
     out = np.zeros((len(jobs), 16, len(ks), 2, len(m)), dtype=np.complex128)
     kri = _kri(ks)
-    bad = L.or_near_panels(len(jobs), _p(tinfo), _p(np.ascontiguousarray(pan)), len(ks), _p(kri),
+    bad = L.or_near_panels(len(jobs), _p(tinfo), _p(pan), len(ks), _p(kri),
                            len(m), _p(m), reltol, _p(out))
     if bad:
         raise RuntimeError("oracle: near-panel quadrature budget exhausted on %d jobs" % bad)
@@ -435,6 +499,9 @@ def field_modes(g: Geometry, modes: Sequence[int], sol, pts: np.ndarray, medium:
 def _panel_point(g: Geometry, p: int, t: np.ndarray):
     """(rho, z) of panel p at parameters t (graph: linear in rho; polyline:
     linear along the straight panel)."""
+    if g.cheb is not None:
+        from numpy.polynomial import chebyshev as C
+        return C.chebval(np.asarray(t), g.cheb[p, :16]), C.chebval(np.asarray(t), g.cheb[p, 16:32])
     ra, dr, za, dz = g.panels[p]
     u = 0.5 * (1.0 + np.asarray(t))
     rho = ra + u * dr
@@ -451,6 +518,13 @@ def field_modes_exact(g: Geometry, modes: Sequence[int], sol, pts: np.ndarray, m
     panel interpolated on its 16 nodes and every panel integrated adaptively
     (no fixed rule): exact for the discretised densities at any distance from
     the curve."""
+    if g.cheb is not None:
+        reltol = max(reltol, 1e-11)   # the rounding floor of curved panels (near_integrals)
+    return _field_modes_exact(g, modes, sol, pts, medium, reltol)
+
+
+def _field_modes_exact(g: Geometry, modes: Sequence[int], sol, pts: np.ndarray, medium: int,
+                       reltol: float):
     wl = g.wl
     _set_geometry(wl)
     L = lib()
@@ -472,9 +546,8 @@ def field_modes_exact(g: Geometry, modes: Sequence[int], sol, pts: np.ndarray, m
             r, z = _panel_point(g, pp, ts)
             tstar = float(ts[int(np.argmin((r - rho_p) ** 2 + (z - z_p) ** 2))])
             tinfo.append([rho_p, I_p, z_p, tstar, 2.0])
-            pan.append(g.panels[pp])
         tinfo = np.ascontiguousarray(np.array(tinfo, dtype=np.float64))
-        pan = np.ascontiguousarray(np.array(pan, dtype=np.float64))
+        pan = _panel_records(g, range(P))
         res = np.zeros((P, 16, 1, 2, len(m)), dtype=np.complex128)
         bad = L.or_near_panels(P, _p(tinfo), _p(pan), 1, _p(kri), len(m), _p(m), reltol, _p(res))
         if bad:

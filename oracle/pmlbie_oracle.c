@@ -154,7 +154,8 @@ typedef struct {
   double a1, T, S;
   int p;
   double gl[16]; /* Gauss-Legendre nodes on [-1, 1] for the Lagrange basis */
-  int poly;      /* 1: the curve is a polyline of straight panels (Sec. 4, graded mesh) */
+  int poly;      /* 1: polyline of straight panels (Sec. 4, graded mesh); 2: curved panels
+                    given by Chebyshev series */
 } geom_t;
 
 static geom_t G_;
@@ -170,9 +171,35 @@ void or_set_geometry(int nb, const double *bumps, double cosf, double a1,
   G_.poly = 0;
 }
 
-/* Switch the near-panel integrals to straight panels: a panel is then given
-   by its start (rho_a, z_a) and its extent (d rho, d z). */
+/* Switch the near-panel integrals to straight panels (1: a panel is given by
+   its start (rho_a, z_a) and its extent (d rho, d z)) or curved panels (2:
+   Chebyshev series of rho(t), z(t) and of their derivatives). */
 void or_set_poly(int on) { G_.poly = on; }
+
+/* Chebyshev series sum_k c_k T_k(t), k < 16, by Clenshaw's recurrence. */
+static double cheb_sum(const double *c, double t) {
+  double b1 = 0.0, b2 = 0.0;
+  for (int k = 15; k >= 1; --k) {
+    double b0 = 2.0 * t * b1 - b2 + c[k];
+    b2 = b1;
+    b1 = b0;
+  }
+  return t * b1 - b2 + c[0];
+}
+
+/* (f(a) - f(b)) for a Chebyshev series without cancellation: the divided
+   differences D_k = (T_k(a) - T_k(b)) / (a - b) obey D_0 = 0, D_1 = 1,
+   D_{k+1} = 2 T_k(a) + 2 b D_k - D_{k-1}. */
+static double cheb_diff(const double *c, double a, double b) {
+  double Tm = 1.0, Tk = a, Dm = 0.0, Dk = 1.0, s = c[1];
+  for (int k = 1; k < 15; ++k) {
+    double Dn = 2.0 * Tk + 2.0 * b * Dk - Dm;
+    double Tn = 2.0 * a * Tk - Tm;
+    s += c[k + 1] * Dn;
+    Dm = Dk; Dk = Dn; Tm = Tk; Tk = Tn;
+  }
+  return (a - b) * s;
+}
 
 static double gsum(double r) {
   double s = 0;
@@ -396,6 +423,7 @@ typedef struct {
   double rho_t, I_t, z_t;    /* target node */
   double pa, L;              /* panel: rho = pa + (1 + t) L / 2 */
   double za, dzp;            /* straight panel: z = za + (1 + t) dzp / 2 */
+  const double *cheb;        /* curved panel: 4 x 16 Chebyshev coefficients of rho, z, rho', z' */
   int self;                  /* 1: target lies on this panel at t_i */
   int offc;                  /* 1: target off the curve (a field point), closest to t_i */
   double ti;
@@ -434,11 +462,37 @@ static void poly_point(const nearctx *c, double t, double *out) {
   out[11] = sg;
 }
 
+/* Curved panel at parameter t: the same 12 values as or_point. */
+static void curved_point(const nearctx *c, double t, double *out) {
+  double rho = cheb_sum(c->cheb, t), zz = cheb_sum(c->cheb + 16, t);
+  double dr = cheb_sum(c->cheb + 32, t), dz = cheb_sum(c->cheb + 48, t);
+  double len = hypot(dr, dz);
+  double nur = dz / len, nuz = -dr / len;
+  double Iv = or_I(rho), sg = or_sigma(rho);
+  cplx rhot = rho + Iv * (cplx)_Complex_I;
+  cplx nr = nur * rhot / rho;
+  cplx nz = nuz * rhot * (1.0 + sg * (cplx)_Complex_I) / rho;
+  out[0] = rho; out[1] = Iv; out[2] = zz; out[3] = 0.0;
+  out[4] = nur; out[5] = nuz; out[6] = len;
+  out[7] = creal(nr); out[8] = cimag(nr); out[9] = creal(nz); out[10] = cimag(nz);
+  out[11] = sg;
+}
+
 static void near_integrand(double t, void *vctx, cplx *out) {
   nearctx *c = (nearctx *)vctx;
   double g[12];
   double rho, drho, dz;
-  if (G_.poly) {
+  if (G_.poly == 2) {
+    curved_point(c, t, g);
+    rho = g[0];
+    if (c->self) {
+      drho = cheb_diff(c->cheb, c->ti, t);
+      dz = cheb_diff(c->cheb + 16, c->ti, t);
+    } else {
+      drho = c->rho_t - rho;
+      dz = c->z_t - g[2];
+    }
+  } else if (G_.poly) {
     poly_point(c, t, g);
     rho = g[0];
     if (c->self) {
@@ -484,9 +538,9 @@ static void near_integrand(double t, void *vctx, cplx *out) {
  * Product integrals of nt targets against panels.  For target q:
  * tinfo[5*q] = (rho_t, I_t, z_t, t_i or 2 (not on panel), which: 0 self,
  * -1 left neighbour, +1 right neighbour, 2 a point off the curve whose
- * closest panel parameter is t_i), panel[4*q] = (pa, L, za, dz): the
- * start rho and rho-extent, and (straight panels only) the start z and
- * z-extent.
+ * closest panel parameter is t_i), panel[68*q] = (pa, L, za, dz, 64
+ * Chebyshev coefficients): the start rho and rho-extent, (straight panels)
+ * the start z and z-extent, (curved panels) the series of rho, z, rho', z'.
  * out[q][l][(2*ik+{S,K})][j] = int_{-1}^{1} F_n(r_q, r(t)) rho |dr/dt| l_l(t) dt.
  */
 int or_near_panels(int nt, const double *tinfo, const double *panel, int nk,
@@ -500,8 +554,9 @@ int or_near_panels(int nt, const double *tinfo, const double *panel, int nk,
     nearctx c;
     const double *ti = tinfo + 5 * q;
     c.rho_t = ti[0]; c.I_t = ti[1]; c.z_t = ti[2];
-    c.pa = panel[4 * q]; c.L = panel[4 * q + 1];
-    c.za = panel[4 * q + 2]; c.dzp = panel[4 * q + 3];
+    c.pa = panel[68 * q]; c.L = panel[68 * q + 1];
+    c.za = panel[68 * q + 2]; c.dzp = panel[68 * q + 3];
+    c.cheb = panel + 68 * q + 4;
     int which = (int)ti[4];
     c.self = which == 0;
     c.offc = which == 2;

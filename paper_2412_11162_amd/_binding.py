@@ -23,6 +23,7 @@ PMLBIE_USE_SURROGATE = 2
 
 EXPORTS = (
     "pmlbie_create", "pmlbie_destroy", "pmlbie_last_error", "pmlbie_set_geometry", "pmlbie_set_polyline",
+    "pmlbie_set_panels",
     "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_build_modal_operators_range",
     "pmlbie_solve_modes",
     "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
@@ -58,6 +59,7 @@ def load():
     L.pmlbie_last_error.restype = ctypes.c_char_p
     L.pmlbie_set_geometry.argtypes = [P, i, P, d, d, P, i]
     L.pmlbie_set_polyline.argtypes = [P, i, P, P, i]
+    L.pmlbie_set_panels.argtypes = [P, i, P]
     L.pmlbie_set_media_pml.argtypes = [P, d, d, d, d, d, d, d, d, d, d, i]
     L.pmlbie_build_modal_operators.argtypes = [P, i, i, i, i]
     L.pmlbie_build_modal_operators_range.argtypes = [P, i, i, i, i, i]

@@ -380,6 +380,24 @@ int pmlbie_set_polyline(pmlbie_ctx* c, int n_vert, const double* verts, const in
   });
 }
 
+int pmlbie_set_panels(pmlbie_ctx* c, int n_panels, const double* nodes) {
+  return guarded(c, [&]() -> int {
+    if (n_panels < 4 || n_panels > PMLBIE_MAX_PANELS || n_panels % 4 || !nodes)
+      return fail(c, PMLBIE_EINVAL, "set_panels: need a multiple of 4 panels in [4, 65536] and their nodes");
+    for (long i = 0; i < 32L * n_panels; ++i)
+      if (!std::isfinite(nodes[i])) return fail(c, PMLBIE_EINVAL, "set_panels: non-finite node coordinate");
+    for (long i = 0; i < 16L * n_panels; ++i)
+      if (!(nodes[2 * i] > 0.0)) return fail(c, PMLBIE_EINVAL, "set_panels: every node needs rho > 0");
+    Geometry g;
+    g.curved = true;
+    g.cnodes.assign(nodes, nodes + 32L * n_panels);
+    if (const char* e = g.prepare_curved()) return fail(c, PMLBIE_EINVAL, e);
+    c->geo = g;
+    c->stage = 1;
+    return PMLBIE_OK;
+  });
+}
+
 int pmlbie_set_media_pml(pmlbie_ctx* c, double k1_re, double k1_im, double k2_re, double k2_im,
                          double a1, double T, double S, double a2, double T2, double S2, int p) {
   return guarded(c, [&]() -> int {

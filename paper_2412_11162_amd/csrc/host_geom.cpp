@@ -154,7 +154,13 @@ double Geometry::Idiff(double r, double dr) const {
 void Geometry::point(int pn, double tpar, double& r, double& Ir, double& zz, zd& nr, zd& nz,
                      double& jacobian) const {
   double nu_r, nu_z, sq;
-  if (poly) {
+  if (curved) {
+    double drt, dzt;
+    curve_eval(pn, tpar, r, zz, drt, dzt);
+    sq = hypot(drt, dzt);  // |dr/dt|
+    nu_r = dzt / sq;
+    nu_z = -drt / sq;
+  } else if (poly) {
     // straight panel: r(t) = start + (1 + t)/2 (d rho, d z); the normal
     // (z', -rho') / |r'| points into the lower medium for a curve run from
     // the axis outward
@@ -179,8 +185,100 @@ void Geometry::point(int pn, double tpar, double& r, double& Ir, double& zz, zd&
   // n_rho = nu_rho rho~ alpha_z / rho, n_z = nu_z rho~ alpha_rho / rho (alpha_z = 1 on the curve)
   nr = (nu_r / r) * rt;
   nz = (nu_z / r) * (rt * ar);
-  jacobian = poly ? 0.5 * plen[pn] : 0.5 * pl[pn] * sq;
+  jacobian = curved ? sq : (poly ? 0.5 * plen[pn] : 0.5 * pl[pn] * sq);
 }
+
+// Legendre series on [-1, 1]: P_{k+1} = ((2k + 1) t P_k - k P_{k-1}) / (k + 1),
+// P'_{k+1} = P'_{k-1} + (2k + 1) P_k.
+void Geometry::curve_eval(int p, double t, double& r, double& zz, double& dr, double& dz) const {
+  const double* cr = &cleg[32 * (size_t)p];
+  const double* cz = cr + 16;
+  double P0 = 1.0, P1 = t, D0 = 0.0, D1 = 1.0;
+  r = cr[0] + cr[1] * t;
+  zz = cz[0] + cz[1] * t;
+  dr = cr[1];
+  dz = cz[1];
+  for (int k = 1; k < 15; ++k) {
+    const double P2 = ((2 * k + 1) * t * P1 - k * P0) / (k + 1);
+    const double D2 = D0 + (2 * k + 1) * P1;
+    r += cr[k + 1] * P2;
+    zz += cz[k + 1] * P2;
+    dr += cr[k + 1] * D2;
+    dz += cz[k + 1] * D2;
+    P0 = P1; P1 = P2; D0 = D1; D1 = D2;
+  }
+}
+
+// Divided differences Q_k = (P_k(a) - P_k(b)) / (a - b): Q_0 = 0, Q_1 = 1,
+// Q_{k+1} = ((2k + 1)(P_k(a) + b Q_k) - k Q_{k-1}) / (k + 1).  h = ta - tb is
+// passed exactly: the auxiliary offsets next to a target fall far below the
+// spacing of doubles near ta, where ta - tb would round to zero.
+void Geometry::curve_diff(int p, double ta, double tb, double h, double& dr, double& dz) const {
+  const double* cr = &cleg[32 * (size_t)p];
+  const double* cz = cr + 16;
+  double P0 = 1.0, P1 = ta, Q0 = 0.0, Q1 = 1.0;
+  double sr = cr[1], sz = cz[1];
+  for (int k = 1; k < 15; ++k) {
+    const double Q2 = ((2 * k + 1) * (P1 + tb * Q1) - k * Q0) / (k + 1);
+    const double P2 = ((2 * k + 1) * ta * P1 - k * P0) / (k + 1);
+    sr += cr[k + 1] * Q2;
+    sz += cz[k + 1] * Q2;
+    P0 = P1; P1 = P2; Q0 = Q1; Q1 = Q2;
+  }
+  dr = h * sr;
+  dz = h * sz;
+}
+
+const char* Geometry::prepare_curved() {
+  gauss_legendre(16, glx, glw);
+  const size_t np = cnodes.size() / 32;
+  cleg.assign(32 * np, 0.0);
+  // c_k = (2k + 1)/2 sum_j w_j P_k(x_j) f_j, exact for the degree-15
+  // interpolant; the panel's mean coordinate is taken out first, so that the
+  // rounding of the coefficients scales with the panel's size and not with
+  // its distance from the origin (the tangent of a short panel far out would
+  // otherwise lose digits)
+  for (size_t p = 0; p < np; ++p) {
+    double mr = 0.0, mz = 0.0;
+    for (int j = 0; j < 16; ++j) {
+      mr += cnodes[32 * p + 2 * j] / 16.0;
+      mz += cnodes[32 * p + 2 * j + 1] / 16.0;
+    }
+    for (int j = 0; j < 16; ++j) {
+      double Pm = 0.0, Pk = 1.0;  // P_{k-1}, P_k at x_j
+      for (int k = 0; k < 16; ++k) {
+        const double f = 0.5 * (2 * k + 1) * glw[j] * Pk;
+        cleg[32 * p + k] += f * (cnodes[32 * p + 2 * j] - mr);
+        cleg[32 * p + 16 + k] += f * (cnodes[32 * p + 2 * j + 1] - mz);
+        const double Pn = ((2 * k + 1) * glx[j] * Pk - k * Pm) / (k + 1);
+        Pm = Pk;
+        Pk = Pn;
+      }
+    }
+    cleg[32 * p] += mr;
+    cleg[32 * p + 16] += mz;
+  }
+  // outline: 33 points per panel for the medium test; joins and the axis
+  outline.clear();
+  for (size_t p = 0; p < np; ++p) {
+    for (int k = (p == 0 ? 0 : 1); k <= 32; ++k) {
+      double r, zz, a, b;
+      curve_eval((int)p, -1.0 + k / 16.0, r, zz, a, b);
+      outline.push_back(r);
+      outline.push_back(zz);
+    }
+    if (p + 1 < np) {
+      double r0, z0, r1, z1, a, b;
+      curve_eval((int)p, 1.0, r0, z0, a, b);
+      curve_eval((int)p + 1, -1.0, r1, z1, a, b);
+      const double scale = std::max(1.0, fabs(r0) + fabs(z0));
+      if (hypot(r1 - r0, z1 - z0) > 1e-9 * scale) return "set_panels: consecutive panels must join";
+    }
+  }
+  if (fabs(outline[0]) > 1e-10) return "set_panels: the curve must start on the axis (rho = 0)";
+  return nullptr;
+}
+
 
 // Panels of the polyline model.  Segment s runs from vertex s to vertex s+1
 // and is cut at the fractions 0, 1/n, ..., 1 of its length (n = seg_panels[s]);
@@ -220,14 +318,16 @@ static void poly_layout(const Geometry& g, std::vector<double>& pa, std::vector<
 }
 
 bool Geometry::above(double r, double zz) const {
-  if (!poly) return zz > h(r);
+  if (!poly && !curved) return zz > h(r);
   if (r >= rho_end()) return zz > 0.0;
   // vertical ray from the point upward: an even number of crossings with the
-  // curve means the point lies above it
-  const int nv = (int)verts.size() / 2;
+  // curve (the polyline, or the outline of the curved panels) means the
+  // point lies above it
+  const std::vector<double>& V = curved ? outline : verts;
+  const int nv = (int)V.size() / 2;
   int cross = 0;
   for (int j = 0; j + 1 < nv; ++j) {
-    const double r0 = verts[2 * j], z0 = verts[2 * j + 1], r1 = verts[2 * j + 2], z1 = verts[2 * j + 3];
+    const double r0 = V[2 * j], z0 = V[2 * j + 1], r1 = V[2 * j + 2], z1 = V[2 * j + 3];
     if ((r0 < r) == (r1 < r)) continue;
     const double zc = z0 + (r - r0) / (r1 - r0) * (z1 - z0);
     if (zc > zz) ++cross;
@@ -236,6 +336,23 @@ bool Geometry::above(double r, double zz) const {
 }
 
 const char* Geometry::poly_pml_error(double a1) const {
+  if (curved) {
+    const size_t np = cnodes.size() / 32;
+    for (size_t p = 0; p < np; ++p) {
+      double lo = 1e300, hi = -1e300, zmax = 0.0;
+      for (int k = 0; k <= 32; ++k) {
+        double r, zz, a, b;
+        curve_eval((int)p, -1.0 + k / 16.0, r, zz, a, b);
+        lo = std::min(lo, r);
+        hi = std::max(hi, r);
+      }
+      for (int j = 0; j < 16; ++j) zmax = std::max(zmax, fabs(cnodes[32 * p + 2 * j + 1]));
+      if (hi > a1 * (1 + 1e-12) && lo < a1 * (1 - 1e-12))
+        return "set_media_pml: a panel may not straddle the start of the PML (rho = a1)";
+      if (hi > a1 * (1 + 1e-12) && zmax != 0.0) return "set_media_pml: the curve must be flat (z = 0) where rho > a1";
+    }
+    return nullptr;
+  }
   if (!poly) return nullptr;
   const int nv = (int)verts.size() / 2;
   for (int j = 0; j + 1 < nv; ++j) {
@@ -251,7 +368,17 @@ const char* Geometry::poly_pml_error(double a1) const {
 
 void Geometry::build() {
   gauss_legendre(16, glx, glw);
-  if (poly) {
+  if (curved) {
+    const int np = (int)(cnodes.size() / 32);
+    pa.assign(np, 0.0); pl.assign(np, 0.0); pz.assign(np, 0.0); pdz.assign(np, 0.0);
+    for (int p = 0; p < np; ++p) {
+      double r0, z0, r1, z1, a, b;
+      curve_eval(p, -1.0, r0, z0, a, b);
+      curve_eval(p, 1.0, r1, z1, a, b);
+      pa[p] = r0; pl[p] = r1 - r0; pz[p] = z0; pdz[p] = z1 - z0;
+    }
+    plen.assign(np, 1.0);  // replaced by the arclength below
+  } else if (poly) {
     poly_layout(*this, pa, pl, pz, pdz);
     plen.resize(pa.size());
     for (size_t p = 0; p < pa.size(); ++p) plen[p] = hypot(pl[p], pdz[p]);
@@ -285,7 +412,22 @@ void Geometry::build() {
       const int i = 16 * p + j;
       zd nr, nz;
       point(p, glx[j], rho[i], I[i], z[i], nr, nz, jac[i]);
-      if (poly) {
+      if (curved) {
+        // the nodes are the given coordinates (the interpolant passes
+        // through them); the tangent is the interpolant's
+        double r2, z2, drt, dzt;
+        curve_eval(p, glx[j], r2, z2, drt, dzt);
+        const double sp = hypot(drt, dzt);
+        rho[i] = cnodes[32 * (size_t)p + 2 * j];
+        z[i] = cnodes[32 * (size_t)p + 2 * j + 1];
+        I[i] = Ipanel(p, rho[i]);
+        hp[i] = 0.0;
+        nur[i] = dzt / sp;
+        nuz[i] = -drt / sp;
+        const zd rt{rho[i], I[i]}, ar{1.0, sigma(rho[i])};
+        nr = (nur[i] / rho[i]) * rt;
+        nz = (nuz[i] / rho[i]) * (rt * ar);
+      } else if (poly) {
         hp[i] = 0.0;  // not a graph
         nur[i] = pdz[p] / plen[p];
         nuz[i] = -pl[p] / plen[p];
@@ -303,6 +445,9 @@ void Geometry::build() {
   parc.assign(np, 0.0);
   for (int p = 0; p < np; ++p)
     for (int j = 0; j < 16; ++j) parc[p] += glw[j] * jac[16 * p + j];
+  // on curved panels the parameter is not linear in a known length; the
+  // arclength serves to size the auxiliary rules
+  if (curved) plen = parc;
 }
 
 // Lagrange basis on the 16 Gauss-Legendre nodes, barycentric form; bw holds
@@ -418,11 +563,15 @@ void Geometry::build_near(std::vector<PairGeom>& geom, std::vector<double>& coef
         // target minus source, from the exact offset on the self panel
         double dr, dzv;
         if (pn == p0) {
-          dr = -a.sgn * a.off * 0.5 * pl[pn];
-          dzv = poly ? -a.sgn * a.off * 0.5 * pdz[pn] : hdiff(rho[i], dr);
+          if (curved) {
+            curve_diff(pn, t[i], tp, -a.sgn * a.off, dr, dzv);
+          } else {
+            dr = -a.sgn * a.off * 0.5 * pl[pn];
+            dzv = poly ? -a.sgn * a.off * 0.5 * pdz[pn] : hdiff(rho[i], dr);
+          }
         } else {
           dr = rho[i] - r;
-          dzv = poly ? z[i] - zz : hdiff(rho[i], dr);
+          dzv = (poly || curved) ? z[i] - zz : hdiff(rho[i], dr);
         }
         PairGeom g;
         g.rt = zd{rho[i], I[i]};

@@ -36,6 +36,20 @@ class Geometry {
   std::vector<double> verts;   // 2 * n_vert: rho_0, z_0, rho_1, z_1, ...
   std::vector<int> seg_panels;  // equal panels per segment before grading
   int grade = 0;
+  // curved-panel model (used when curved is set): the caller gives the
+  // coordinates (rho, z) at the 16 Gauss-Legendre points of every panel, and
+  // the curve on a panel is their degree-15 interpolant
+  bool curved = false;
+  std::vector<double> cnodes;   // [P][16][2] node coordinates
+  std::vector<double> cleg;     // [P][2][16] Legendre coefficients of rho(t) and z(t)
+  std::vector<double> outline;  // 2 * K points along the curve (medium test)
+  // Legendre coefficients from cnodes; returns an error text or nullptr
+  const char* prepare_curved();
+  // r(t) and r'(t) on curved panel p
+  void curve_eval(int p, double t, double& r, double& zz, double& dr, double& dz) const;
+  // r(ta) - r(tb) on curved panel p without cancellation (divided
+  // differences), h = ta - tb given exactly
+  void curve_diff(int p, double ta, double tb, double h, double& dr, double& dz) const;
 
   // Gauss-Legendre rule of 16 nodes on [-1, 1].
   double glx[16], glw[16];
@@ -56,7 +70,10 @@ class Geometry {
   int n() const { return (int)rho.size(); }
   int npanels() const { return (int)pa.size(); }
 
-  double rho_end() const { return poly ? verts[verts.size() - 2] : breaks[4]; }
+  double rho_end() const {
+    if (curved) return outline[outline.size() - 2];
+    return poly ? verts[verts.size() - 2] : breaks[4];
+  }
   // the point lies above the curve (in the upper medium); points on the
   // curve are not classified
   bool above(double r, double zz) const;

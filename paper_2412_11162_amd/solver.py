@@ -66,6 +66,11 @@ class Solver:
         pn = np.ascontiguousarray(np.array(panels, dtype=np.int32))
         self._chk(self.L.pmlbie_set_polyline(self.h, v.size // 2, _p(v), _p(pn), int(grade)))
 
+    def set_panels(self, nodes: np.ndarray):
+        """nodes: [P, 16, 2] (rho, z) at the 16 Gauss-Legendre points of each panel."""
+        a = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1))
+        self._chk(self.L.pmlbie_set_panels(self.h, a.size // 32, _p(a)))
+
     def set_media_pml(self, k1: complex, k2: complex, a1: float, T: float, S: float, a2: float,
                       T2: float, S2: float, p: int = 6):
         k1, k2 = complex(k1), complex(k2)
@@ -203,7 +208,9 @@ def from_workload(wl, device: int = 0, n_theta: int = None, m_max: int = None,
                   precision: int = B.PMLBIE_FP64, flags: int = 0, build: bool = True) -> Solver:
     """Set up a solver for one of the synthetic workloads."""
     s = Solver(device)
-    if wl.polyline:
+    if wl.curve_nodes is not None:
+        s.set_panels(wl.curve_nodes)
+    elif wl.polyline:
         s.set_polyline(wl.polyline, wl.panels, wl.grade)
     else:
         s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)

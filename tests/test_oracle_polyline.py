@@ -150,3 +150,60 @@ def test_exact_field_tends_to_the_boundary_data():
         # first order in d
         for a, b in zip(errs[1e-3], errs[1e-4]):
             assert 5.0 < a / b < 20.0
+
+
+# ------------------------------------------------- curves given by their panels
+
+def _nodes_of(g):
+    return np.stack([g.rho, g.z], axis=1).reshape(-1, 16, 2)
+
+
+def test_curved_panels_through_straight_nodes_reproduce_the_polyline():
+    """The rectangular perturbation handed over as curved panels (its node
+    coordinates only): the degree-15 interpolants are the straight panels, so
+    node tables and operator rows (near-panel integrals with divided-difference
+    offsets) match the polyline path to rounding."""
+    wl = workloads.corner(panels=(2, 2, 2, 2), grade=2)
+    gp = oracle.geometry(wl)
+    gc = oracle.geometry(wl.with_(polyline=(), panels=(), grade=0, curve_nodes=_nodes_of(gp)))
+    assert np.max(np.abs(gc.W - gp.W)) <= 1e-14
+    assert np.max(np.abs(gc.nu - gp.nu)) <= 1e-14
+    rows = [3, 40, 63, 64, 100, 150, gp.n - 2]
+    Sp, Kp = oracle.core.operator_rows(gp, rows, [wl.k1, wl.k2], [0, 2])
+    Sc, Kc = oracle.core.operator_rows(gc, rows, [wl.k1, wl.k2], [0, 2])
+    assert np.max(np.abs(Sc - Sp)) <= 1e-12 * np.max(np.abs(Sp))
+    assert np.max(np.abs(Kc - Kp)) <= 1e-12 * np.max(np.abs(Kp))
+
+
+def test_curved_quarter_circle_closed_forms():
+    """A quarter circle of radius 1 from (0, -1) to (1, 0) on curved panels,
+    then flat to 4: int rho ds = 1 + 15/2 and int rho z ds = -1/2 to the
+    interpolation accuracy, normals radial (into the lower medium)."""
+    x, _ = np.polynomial.legendre.leggauss(16)
+    pans = []
+    for k in range(8):
+        phi = (k + 0.5 * (1 + x)) * (np.pi / 2) / 8
+        pans.append(np.stack([np.sin(phi), -np.cos(phi)], axis=1))
+    for lo, hi in ((1.0, 1.5), (1.5, 2.0), (2.0, 3.0), (3.0, 4.0)):
+        r = lo + 0.5 * (1 + x) * (hi - lo)
+        pans.append(np.stack([r, np.zeros_like(r)], axis=1))
+    wl = workloads.corner().with_(polyline=(), panels=(), grade=0, curve_nodes=np.array(pans))
+    g = oracle.geometry(wl)
+    assert abs(g.W.sum() - 8.5) <= 1e-13
+    assert abs((g.W * g.z).sum() + 0.5) <= 1e-13
+    arc = g.panel_of < 8
+    radial = np.stack([g.rho[arc], g.z[arc]], axis=1)
+    assert np.max(np.abs(g.nu[arc] - radial)) <= 1e-13
+
+
+def test_rippled_bowl_explicit_solution():
+    """The explicit-solution protocol of Sec. 4.3 on the curve of Sec. 5,
+    Example 2 (curved panels, graded toward the corner where the bowl meets
+    the flat part): rows near the axis, on the ripples, at the corner and in
+    the PML."""
+    wl = workloads.bowl().with_(S=4.0)
+    g = oracle.geometry(wl)
+    c = int(np.argmin(np.hypot(g.rho - 1.0, g.z)))
+    rows = sorted({0, 40, 100, 170, c - 1, c, c + 1, g.n - 5})
+    res, _ = _explicit_residual(wl, [0, 1, 3], rows)
+    assert np.all(res < 1e-6), res

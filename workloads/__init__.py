@@ -53,6 +53,9 @@ class Workload:
     polyline: Tuple[Tuple[float, float], ...] = ()
     panels: Tuple[int, ...] = ()
     grade: int = 0
+    # curve given by its panels (replaces the graph when set): [P, 16, 2]
+    # (rho, z) at the 16 Gauss-Legendre points of each panel
+    curve_nodes: object = field(default=None, compare=False)
 
     @property
     def m_max(self) -> int:
@@ -171,8 +174,51 @@ def stepped() -> Workload:
         panels=(2,) * 8, grade=1)
 
 
+def _bowl_nodes(n_bowl: int, grade: int, n_flat: Tuple[int, int], a1: float, b: float) -> np.ndarray:
+    """Panel nodes of the curve of Sec. 5, Example 2:
+        rho(s) = [1 - 0.1 sin(3 pi s)] sin(pi s / 2),
+        z(s)   = -[1 - 0.1 sin(3 pi s)] cos(pi s / 2),   s in [0, 1],
+    from (0, -1) on the axis to (1, 0), then flat to a1 and on to b.  The
+    bowl is cut into n_bowl equal parts in s and the flat stretch [1, a1]
+    into n_flat[0]; the parts touching (1, 0), where the curve turns, are cut
+    again at 2^-grade, ..., 1/2 toward it; [a1, b] gets n_flat[1] parts."""
+    x, _ = np.polynomial.legendre.leggauss(16)
+
+    def cuts(n, toward_end, toward_start):
+        c = [k / n for k in range(n + 1)]
+        if toward_start:
+            c = [0.0] + [2.0 ** -l / n for l in range(grade, 0, -1)] + c[1:]
+        if toward_end:
+            c = c[:-1] + [1.0 - 2.0 ** -l / n for l in range(1, grade + 1)] + [1.0]
+        return c
+
+    panels = []
+    cb = cuts(n_bowl, True, False)
+    for s0, s1 in zip(cb[:-1], cb[1:]):
+        sv = s0 + 0.5 * (1.0 + x) * (s1 - s0)
+        f = 1.0 - 0.1 * np.sin(3 * np.pi * sv)
+        panels.append(np.stack([f * np.sin(0.5 * np.pi * sv), -f * np.cos(0.5 * np.pi * sv)], axis=1))
+    for (lo, hi), n, tg in (((1.0, a1), n_flat[0], True), ((a1, b), n_flat[1], False)):
+        cf = cuts(n, False, tg)
+        for u0, u1 in zip(cf[:-1], cf[1:]):
+            r = lo + (u0 + 0.5 * (1.0 + x) * (u1 - u0)) * (hi - lo)
+            panels.append(np.stack([r, np.zeros_like(r)], axis=1))
+    return np.array(panels)
+
+
+def bowl(n_bowl: int = 8, grade: int = 4, n_flat: Tuple[int, int] = (2, 2), **kw) -> Workload:
+    """The smooth rippled bowl of Sec. 5, Example 2 (not a graph of rho; a
+    corner where it meets the flat part), given by its panels: n_bowl parts
+    of the bowl and n_flat flat ones, `grade` halvings toward the corner
+    (8 + 4 + 2 + 4 + 2 = 20 panels, 320 nodes by default); media, PML,
+    incidence and modes as the corner workload."""
+    w = corner().with_(name="bowl", polyline=(), panels=(), grade=0,
+                       curve_nodes=_bowl_nodes(n_bowl, grade, n_flat, 2.0, 4.0))
+    return w.with_(**kw) if kw else w
+
+
 ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny,
-       "corner": corner, "corner_paper": corner_paper, "stepped": stepped}
+       "corner": corner, "corner_paper": corner_paper, "stepped": stepped, "bowl": bowl}
 
 
 def seeded_pairs(n_nodes: int, count: int, seed: int) -> np.ndarray:
