@@ -217,8 +217,20 @@ def bowl(n_bowl: int = 8, grade: int = 4, n_flat: Tuple[int, int] = (2, 2), **kw
     return w.with_(**kw) if kw else w
 
 
+def bowl_paper() -> Workload:
+    """Example 2's rippled bowl at the node count of the paper-scale
+    workload: 48 bowl parts and 24 + 40 flat ones, eight halvings toward the
+    corner on both sides (128 panels, 2048 nodes); modes 0..32, 128 theta
+    samples, a
+    point source and a plane wave."""
+    return bowl(n_bowl=48, grade=8, n_flat=(24, 40)).with_(
+        name="bowl_paper", n_theta=128, m_max_=32,
+        incidences=(("point", 0.0, 1.0), ("plane", 0.5)))
+
+
 ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny,
-       "corner": corner, "corner_paper": corner_paper, "stepped": stepped, "bowl": bowl}
+       "corner": corner, "corner_paper": corner_paper, "stepped": stepped, "bowl": bowl,
+       "bowl_paper": bowl_paper}
 
 
 def seeded_pairs(n_nodes: int, count: int, seed: int) -> np.ndarray:
