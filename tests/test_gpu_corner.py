@@ -383,3 +383,30 @@ def test_rippled_bowl_on_curved_panels():
     s2.solve_modes([("point", 0.0, 1.0)])
     fo = s2.evaluate_field(np.stack([pts[:, 0], theta, pts[:, 1]], axis=1), 1)[0]
     assert np.max(np.abs(fo - ref)) <= 1e-8 * np.max(np.abs(ref)), np.abs(fo - ref) / np.max(np.abs(ref))
+
+
+def test_panel_curve_argument_errors():
+    from paper_2412_11162_amd.solver import Solver, PmlbieError
+    wl = workloads.bowl()
+    nodes = np.array(wl.curve_nodes)
+    s = Solver(0)
+    shifted = nodes.copy()
+    shifted[5:, :, 1] += 0.01                          # panels 4 and 5 do not join
+    off_axis = nodes.copy()
+    off_axis[0, :, 0] += 0.05                          # the first panel does not start on the axis
+    neg = nodes.copy()
+    neg[3, 2, 0] = -0.1                                # a node with rho <= 0
+    for bad in (nodes[:2], nodes[:18], shifted, off_axis, neg):
+        with pytest.raises(PmlbieError) as e:
+            s.set_panels(bad)
+        assert e.value.code == -1
+    # not flat beyond the PML start (the two panels past a1 = 2 tilted, still
+    # joined at (2, 0))
+    tilted = nodes.copy()
+    tilted[-2:, :, 1] = 1e-3 * (tilted[-2:, :, 0] - 2.0)
+    s.set_panels(tilted)
+    with pytest.raises(PmlbieError) as e:
+        s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2)
+    assert e.value.code == -1
+    s.set_panels(nodes)
+    s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2)
