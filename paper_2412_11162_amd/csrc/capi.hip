@@ -885,8 +885,20 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
     // points in chunks whose modal kernels against every node take about 2 GiB
     const long per_pt = (long)N * 4 * (M + 1) * (long)sizeof(zd);
     const int chunk = (int)std::max(1L, std::min((long)n_pts, (2L << 30) / per_pt));
-    std::vector<PairGeom> g;
-    g.reserve((size_t)chunk * N);
+    std::vector<double> hpts(2L * chunk);
+    DBuf<double> dpts;
+    dpts.alloc(2L * chunk);
+    NodesDev nd;
+    nd.N = N;
+    nd.rho = c->nodes.p;
+    nd.I = c->nodes.p + N;
+    nd.z = c->nodes.p + 2L * N;
+    nd.W = c->nodes.p + 3L * N;
+    nd.nr_re = c->nodes.p + 4L * N;
+    nd.nr_im = c->nodes.p + 5L * N;
+    nd.nz_re = c->nodes.p + 6L * N;
+    nd.nz_im = c->nodes.p + 7L * N;
+    nd.panel = c->dpanel.p;
     // points closer to a panel than its arclength: that panel's entries by
     // product integration (same interval cap as the build's near panels)
     const double keff = std::max(cabs_(c->k1), cabs_(c->k2)) * sqrt(1.0 + c->geo.pml.S * c->geo.pml.S);
@@ -908,22 +920,19 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
         if (J.target < 0 || J.target >= np || J.panel < 0 || 16L * J.panel + 15 >= N || J.q0 < 0 ||
             J.q1 > (int)fg.size() || J.q0 > J.q1)
           return fail(c, PMLBIE_EDEVICE, "evaluate_field: inconsistent near-curve tables");
-      g.clear();
-      for (int p = p0; p < p0 + np; ++p) {
-        const double r = rtz[3 * p], zz = rtz[3 * p + 2];
-        for (int l = 0; l < N; ++l) {
-          PairGeom q;
-          q.rt = zd{r, 0.0};
-          q.rs = zd{c->geo.rho[l], c->geo.I[l]};
-          q.drho = zd{r - c->geo.rho[l], -c->geo.I[l]};
-          q.dz = zd{zz - c->geo.z[l], 0.0};
-          q.nr = zd{c->geo.nr_re[l], c->geo.nr_im[l]};
-          q.nz = zd{c->geo.nz_re[l], c->geo.nz_im[l]};
-          g.push_back(q);
-        }
+      // the point x node pair geometry is formed on the device from the
+      // node tables already there
+      for (int p = 0; p < np; ++p) {
+        hpts[2 * p] = rtz[3 * (p0 + p)];
+        hpts[2 * p + 1] = rtz[3 * (p0 + p) + 2];
       }
-      c->raw.alloc(g.size() * 4 * (M + 1));
-      run_pair_list(c, g, c->raw.p, nullptr);  // synchronous: g may be reused
+      HIPCHK(hipMemcpyAsync(dpts.p, hpts.data(), 2L * np * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      const size_t tot = (size_t)np * N;
+      c->xgeom.alloc(tot);
+      launch_field_pairs(nd, dpts.p, np, c->xgeom.p, c->stream);
+      HIPCHK(hipGetLastError());
+      c->raw.alloc(tot * 4 * (M + 1));
+      run_pair_list_dev(c, tot, c->raw.p, nullptr);  // synchronous: hpts may be reused
       if (!fj.empty()) {
         fraw.alloc(fg.size() * 4 * (M + 1));
         run_pair_list(c, fg, fraw.p, nullptr);

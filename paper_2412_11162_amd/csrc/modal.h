@@ -85,6 +85,9 @@ void launch_rhs_plane(int nt, const double* rho, const double* z, const double* 
                       int m0, int nrhs, zd* b1, zd* b2, hipStream_t st);
 void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, int m0,
                  zd* A, long n2, long mstride, hipStream_t st);
+// Pair geometry of np field points pts[2 * p] = (rho, z) (physical region)
+// against every node, out[p * N + l].
+void launch_field_pairs(const NodesDev& nd, const double* pts, int np, PairGeom* out, hipStream_t st);
 // Near-curve field points: job targets are chunk-local point indices,
 // raw[(point * N + node)][4][M + 1] receives the panel's 16 corrected entries.
 void launch_field_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw_aux, int N,

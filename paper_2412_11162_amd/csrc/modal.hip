@@ -645,6 +645,25 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
   }
 }
 
+// Pair geometry of field points (rho, z; physical region, Im rho~ = 0) against
+// every node: out[p * N + l], one thread per pair.
+__global__ __launch_bounds__(256) void k_field_pairs(NodesDev nd, const double* __restrict__ pts, int np,
+                                                     PairGeom* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = nd.N;
+  if (e >= (long)np * N) return;
+  const int p = (int)(e / N), l = (int)(e % N);
+  const double r = pts[2 * p], zz = pts[2 * p + 1];
+  PairGeom q;
+  q.rt = zd{r, 0.0};
+  q.rs = zd{nd.rho[l], nd.I[l]};
+  q.drho = zd{r - nd.rho[l], -nd.I[l]};
+  q.dz = zd{zz - nd.z[l], 0.0};
+  q.nr = zd{nd.nr_re[l], nd.nr_im[l]};
+  q.nz = zd{nd.nz_re[l], nd.nz_im[l]};
+  out[e] = q;
+}
+
 // Field points near the curve: the modal kernels of a point against the 16
 // nodes of a nearby panel are replaced by product integrals over the panel
 // (auxiliary points graded toward the closest curve point, Lagrange basis of
@@ -851,6 +870,12 @@ void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* r
   if (njobs <= 0) return;
   OutSpec o{A, n2, mstride, nullptr, nullptr, M, m0};
   hipLaunchKernelGGL(k_near, dim3(njobs), dim3(256), 0, st, jobs, njobs, coef, raw, M, o);
+}
+
+void launch_field_pairs(const NodesDev& nd, const double* pts, int np, PairGeom* out, hipStream_t st) {
+  const long tot = (long)np * nd.N;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_field_pairs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nd, pts, np, out);
 }
 
 void launch_field_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw_aux, int N,
