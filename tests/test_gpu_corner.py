@@ -320,8 +320,9 @@ def test_rippled_bowl_on_curved_panels():
     (degree-15 interpolants, graded toward the corner where the bowl meets
     the flat part): node tables, oracle operator rows near the axis, on the
     ripples, at the corner and in the PML against the GPU matrices, the GPU
-    solution's backward error against those rows, and the field close to the
-    bowl on both sides."""
+    solution's backward error against those rows, the boundary data against
+    the oracle's full solve (FP64 and mixed precision), and the field close to
+    the bowl on both sides."""
     import oracle
     from paper_2412_11162_amd._binding import PMLBIE_KEEP_OPERATORS
     wl = workloads.bowl().with_(m_max_=4)
@@ -380,9 +381,15 @@ def test_rippled_bowl_on_curved_panels():
     theta = np.linspace(0.1, 2.2, len(pts))
     ref = _field_ref(g, allm, sol, pts, med, theta)
     s2 = _solver(wl)
-    s2.solve_modes([("point", 0.0, 1.0)])
+    out2 = [o[:, 0, :].cpu().numpy() for o in s2.solve_modes([("point", 0.0, 1.0)])]
+    assert np.max(_boundary_err(out2, sol[:4])) <= BOUNDARY_TOL
     fo = s2.evaluate_field(np.stack([pts[:, 0], theta, pts[:, 1]], axis=1), 1)[0]
     assert np.max(np.abs(fo - ref)) <= 1e-8 * np.max(np.abs(ref)), np.abs(fo - ref) / np.max(np.abs(ref))
+    # complex64 LU with FP64 refinement on the curved panels: the mixed bar
+    from paper_2412_11162_amd._binding import PMLBIE_MIXED
+    s3 = _solver(wl, precision=PMLBIE_MIXED)
+    out3 = [o[:, 0, :].cpu().numpy() for o in s3.solve_modes([("point", 0.0, 1.0)])]
+    assert np.max(_boundary_err(out3, sol[:4])) <= 1e-6
 
 
 def test_panel_curve_argument_errors():
