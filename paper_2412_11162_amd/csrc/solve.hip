@@ -77,17 +77,18 @@ __global__ void k_outputs(const zd* __restrict__ x, const zd* __restrict__ b1,
 // built modes n = m0..M (boundary data stored from index 0):
 //   u_n(x) = sgn sum_l W_l [S_n(x, r_l) phi_n(r_l) - K_n(x, r_l) u_n(r_l)],
 // sgn = +1 in the upper medium, -1 in the lower one.  raw[(p * N + l)][s][n].
-// One workgroup per (point, right-hand side): threads take nodes l (the
-// solution values of one mode are read coalesced), a block reduction sums
-// them; the result goes to out[r * ldo + p].
+// One workgroup per point: threads take nodes l (the solution values of one
+// mode are read coalesced), each node's kernels serve every right-hand side,
+// a block reduction sums them; the result goes to out[r * ldo + p].
+template <int RB>
 __global__ __launch_bounds__(256) void k_field(const zd* __restrict__ raw, const double* __restrict__ W,
                                                int N, int M, int m0, int nrhs, const int* __restrict__ medium,
                                                const double* __restrict__ theta, const zd* __restrict__ u1,
                                                const zd* __restrict__ p1, const zd* __restrict__ u2,
                                                const zd* __restrict__ p2, zd* __restrict__ out, long ldo) {
   __shared__ double fn[FIELD_MAX_MODES];
-  __shared__ zd part[4];
-  const int p = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  __shared__ zd part[4][RB];
+  const int p = blockIdx.x, tid = threadIdx.x;
   const int md = medium[p];
   const double sgn = md == 1 ? 1.0 : -1.0;
   const int sS = md == 1 ? 0 : 2, sK = md == 1 ? 1 : 3;
@@ -96,24 +97,40 @@ __global__ __launch_bounds__(256) void k_field(const zd* __restrict__ raw, const
   for (int n = m0 + tid; n <= M; n += 256)
     fn[n - m0] = (n == 0 ? 1.0 : 2.0) * cos(n * theta[p]) * sgn * (0.5 / PMLBIE_PI);
   __syncthreads();
-  zd acc{0.0, 0.0};
+  // every node's kernels are read once and weighted by the densities of all
+  // right-hand sides (loops over the compile-time bound RB >= nrhs keep the
+  // accumulators in registers)
+  zd acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = zd{0.0, 0.0};
   for (int l = tid; l < N; l += 256) {
     const zd* rw = raw + ((long)p * N + l) * 4 * (M + 1);
-    zd ul{0.0, 0.0};
+    zd ul[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) ul[r] = zd{0.0, 0.0};
     for (int n = m0; n <= M; ++n) {
-      const long idx = ((long)(n - m0) * nrhs + r) * N + l;
-      ul = ul + fn[n - m0] * (rw[sS * (M + 1) + n] * P[idx] - rw[sK * (M + 1) + n] * U[idx]);
+      const zd sv = fn[n - m0] * rw[sS * (M + 1) + n];
+      const zd kv = fn[n - m0] * rw[sK * (M + 1) + n];
+      const long base = (long)(n - m0) * nrhs * N + l;
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nrhs) ul[r] = ul[r] + (sv * P[base + (long)r * N] - kv * U[base + (long)r * N]);
     }
-    acc = acc + W[l] * ul;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = acc[r] + W[l] * ul[r];
   }
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    acc.re += __shfl_xor(acc.re, off);
-    acc.im += __shfl_xor(acc.im, off);
+  for (int r = 0; r < RB; ++r) {
+    if (r >= nrhs) break;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      acc[r].re += __shfl_xor(acc[r].re, off);
+      acc[r].im += __shfl_xor(acc[r].im, off);
+    }
+    if ((tid & 63) == 0) part[tid >> 6][r] = acc[r];
   }
-  if ((tid & 63) == 0) part[tid >> 6] = acc;
   __syncthreads();
-  if (tid == 0) out[(long)r * ldo + p] = part[0] + part[1] + part[2] + part[3];
+  if (tid < nrhs) out[(long)tid * ldo + p] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
 }
 
 // FP64 -> FP32 copy of the operators (complex128 -> complex64).
@@ -229,8 +246,15 @@ void launch_field(const zd* raw, const double* W, int N, int M, int m0, int nrhs
                   const int* medium, const double* theta, const zd* u1, const zd* p1, const zd* u2,
                   const zd* p2, zd* out, long ldo, hipStream_t st) {
   if (npts <= 0 || nrhs <= 0) return;
-  hipLaunchKernelGGL(k_field, dim3(npts, nrhs), dim3(256), 0, st, raw, W, N, M, m0, nrhs, medium, theta, u1,
-                     p1, u2, p2, out, ldo);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_field<1>, dim3(npts), dim3(256), 0, st, raw, W, N, M, m0, nrhs, medium, theta, u1,
+                       p1, u2, p2, out, ldo);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL(k_field<4>, dim3(npts), dim3(256), 0, st, raw, W, N, M, m0, nrhs, medium, theta, u1,
+                       p1, u2, p2, out, ldo);
+  else
+    hipLaunchKernelGGL(k_field<LU_MAX_RHS>, dim3(npts), dim3(256), 0, st, raw, W, N, M, m0, nrhs, medium,
+                       theta, u1, p1, u2, p2, out, ldo);
 }
 
 }  // namespace pmlbie

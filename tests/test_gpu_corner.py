@@ -417,3 +417,20 @@ def test_panel_curve_argument_errors():
     assert e.value.code == -1
     s.set_panels(nodes)
     s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2)
+
+
+def test_field_with_several_right_hand_sides(corner_ref):
+    """Field synthesis for three incidences in one call equals the same
+    points evaluated one incidence at a time (each node's kernels are read
+    once for all right-hand sides)."""
+    wl, g, A, modes = corner_ref
+    incs = [("point", 0.0, 1.0), ("plane", 0.5), ("point", 0.3, 0.8)]
+    rtz = np.array([[0.5, -0.5, 0.3], [1.4, 0.7, -0.5], [0.3, 1.1, 0.8], [1.6, 2.0, -1.2]])  # rho, theta, z
+    s = _solver(wl)
+    s.solve_modes(incs)
+    many = s.evaluate_field(rtz, len(incs))
+    for r, inc in enumerate(incs):
+        s1 = _solver(wl)
+        s1.solve_modes([inc])
+        one = s1.evaluate_field(rtz, 1)[0]
+        assert np.max(np.abs(many[r] - one)) <= 1e-12 * np.max(np.abs(one)), r
