@@ -434,3 +434,21 @@ def test_field_with_several_right_hand_sides(corner_ref):
         s1.solve_modes([inc])
         one = s1.evaluate_field(rtz, 1)[0]
         assert np.max(np.abs(many[r] - one)) <= 1e-12 * np.max(np.abs(one)), r
+
+
+def test_field_on_the_axis():
+    """Points on the axis (rho = 0), where 4 rho~ rho~' vanishes and only
+    mode 0 survives: the library's field equals the oracle's representation
+    in both media."""
+    import oracle
+    wl = workloads.tiny()
+    g = oracle.geometry(wl)
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    sol = oracle.solve(g, modes, b1, b2)
+    pts = np.array([[0.0, 1.2], [0.0, -0.8]])
+    ref = _field_ref(g, modes, sol, pts, [1, 2], np.zeros(2))
+    s = _solver(wl)
+    s.solve_modes([("point", 0.3, 1.0)])
+    out = s.evaluate_field(np.stack([pts[:, 0], np.array([0.0, 1.3]), pts[:, 1]], axis=1), 1)[0]
+    assert np.max(np.abs(out - ref)) <= 1e-8 * np.max(np.abs(ref))
