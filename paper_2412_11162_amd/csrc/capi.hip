@@ -234,7 +234,8 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
 
 // Explicit pair list (host) -> raw modal values raw[q][s][n]: upload, classify
 // on the device into far / split / direct lists, run the three paths.
-void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts);
+void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts,
+                       const int* medium = nullptr, int Nm = 0);
 
 void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long long* counts) {
   const size_t tot = g.size();
@@ -244,8 +245,10 @@ void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long 
   run_pair_list_dev(c, tot, raw, counts);
 }
 
-// The same with the pair geometry already in c->xgeom.
-void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts) {
+// The same with the pair geometry already in c->xgeom.  With medium (field
+// points, rows q = p * Nm + l), the far pairs get the kernels of their point's
+// medium only.
+void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, const int* medium, int Nm) {
   if (tot == 0) return;
   c->lgeom.alloc(3 * tot > c->lgeom.n ? 3 * tot : c->lgeom.n);
   c->ldest.alloc(3 * tot > c->ldest.n ? 3 * tot : c->ldest.n);
@@ -263,8 +266,12 @@ void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts) {
     counts[1] += cnt[1];
     counts[2] += cnt[2];
   }
-  launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, 0, c->k1, c->k2, c->tw_far.p, nullptr, 0,
-                  0, nullptr, raw, nullptr, c->stream);
+  if (medium)
+    launch_list_far_one(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, c->k1, c->k2, c->tw_far.p, raw, medium,
+                        Nm, c->stream);
+  else
+    launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, 0, c->k1, c->k2, c->tw_far.p, nullptr, 0,
+                    0, nullptr, raw, nullptr, c->stream);
   HIPCHK(hipGetLastError());
   run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw);
   launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
@@ -932,7 +939,7 @@ int pmlbie_evaluate_field(pmlbie_ctx* c, int n_pts, const double* rtz, double* o
       launch_field_pairs(nd, dpts.p, np, c->xgeom.p, c->stream);
       HIPCHK(hipGetLastError());
       c->raw.alloc(tot * 4 * (M + 1));
-      run_pair_list_dev(c, tot, c->raw.p, nullptr);  // synchronous: hpts may be reused
+      run_pair_list_dev(c, tot, c->raw.p, nullptr, dmed.p + p0, N);  // synchronous: hpts may be reused
       if (!fj.empty()) {
         fraw.alloc(fg.size() * 4 * (M + 1));
         run_pair_list(c, fg, fraw.p, nullptr);

@@ -85,6 +85,10 @@ void launch_rhs_plane(int nt, const double* rho, const double* z, const double* 
                       int m0, int nrhs, zd* b1, zd* b2, hipStream_t st);
 void launch_near(const NearJob* jobs, int njobs, const double* coef, const zd* raw, int M, int m0,
                  zd* A, long n2, long mstride, hipStream_t st);
+// Far pairs of a field chunk (raw rows q = p * N + l) for the medium of each
+// point only: raw sequences (0, 1) where medium[p] == 1, (2, 3) where it is 2.
+void launch_list_far_one(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
+                         zd k1, zd k2, const zd* tw, zd* raw, const int* medium, int N, hipStream_t st);
 // Pair geometry of np field points pts[2 * p] = (rho, z) (physical region)
 // against every node, out[p * N + l].
 void launch_field_pairs(const NodesDev& nd, const double* pts, int np, PairGeom* out, hipStream_t st);

@@ -291,6 +291,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
+// Field points lie in one medium: the far pairs of a field chunk need the
+// kernels of that medium's wavenumber only, i.e. sequences (0, 1) for the
+// upper medium and (2, 3) for the lower one, half the samples, transforms and
+// writes of far_pair.  The point of raw row q is q / N (rows p * N + l);
+// medium[p] is 1 or 2.
+template <int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_list_far_one(
+    const PairGeom* __restrict__ geom, const int2* __restrict__ dest, long first, long count, zd k1, zd k2,
+    const zd* __restrict__ tw, OutSpec o, const int* __restrict__ medium, int N) {
+  constexpr int L = 64 * R, H = L / 2 + 1;
+  __shared__ zd lds[far_lds<R>()];
+  zd* P1 = pair_p1<R>(lds);
+  zd* E = pair_e<R>(lds);
+  const double w4pi = 0.25 / PMLBIE_PI;
+  for (long t = blockIdx.x; t < count; t += gridDim.x) {
+    const PairGeom g = geom[first + t];
+    const int2 dst = dest[first + t];
+    const PairInv v = pair_invariants(g);
+    const int md = medium[dst.x / N];
+    const zd k = md == 1 ? k1 : k2;
+#pragma unroll 1
+    for (int j = threadIdx.x; j < H; j += 64) {
+      const zd tt = tw[j];
+      const double s2 = tt.re >= 0.0 ? tt.im * tt.im / (2.0 + 2.0 * tt.re) : 0.5 - 0.5 * tt.re;
+      const zd Rd = csqrt_(v.d2 + s2 * v.c4);
+      const zd iR = inv(Rd);
+      const zd ikR = zd{0.0, 1.0} * (k * Rd);
+      const zd e = cexp_(ikR) * (iR * w4pi);
+      P1[j] = e;
+      P1[H + j] = (v.N0 + s2 * v.N1) * e * (ikR - 1.0) * (iR * iR);
+    }
+    __syncthreads();
+    transform_emit<R>(P1, E, tw, o, dst, md == 1 ? 0 : 2);
+  }
+}
+
 // ------------------------------------------------------------------------
 // Split pairs, phase 1 (one lane per pair): Q_{m-1/2}(chi), m = 0..MQ,
 // chi = 1 + d2/(2 rho~ rho~'), and the factors that turn it into the
@@ -787,6 +823,27 @@ static void launch_list_far_t(const PairGeom* geom, const int2* dest, long first
   int grid = (int)std::min<long>(count, 256L * 128);
   hipLaunchKernelGGL(k_list_far<R>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2,
                      tw, o, cp ? *cp : ClassParams{}, cp ? 1 : 0);
+}
+
+template <int R>
+static void launch_list_far_one_t(const PairGeom* geom, const int2* dest, long first, long count, zd k1,
+                                  zd k2, const zd* tw, const OutSpec& o, const int* medium, int N,
+                                  hipStream_t st) {
+  int grid = (int)std::min<long>(count, 256L * 128);
+  hipLaunchKernelGGL(k_list_far_one<R>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, k1, k2, tw, o,
+                     medium, N);
+}
+
+void launch_list_far_one(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
+                         zd k1, zd k2, const zd* tw, zd* raw, const int* medium, int N, hipStream_t st) {
+  if (count <= 0) return;
+  OutSpec o{nullptr, 0, 0, nullptr, raw, M, 0};
+  switch (nt) {
+    case 512: launch_list_far_one_t<8>(geom, dest, first, count, k1, k2, tw, o, medium, N, st); break;
+    case 1024: launch_list_far_one_t<16>(geom, dest, first, count, k1, k2, tw, o, medium, N, st); break;
+    case 2048: launch_list_far_one_t<32>(geom, dest, first, count, k1, k2, tw, o, medium, N, st); break;
+    default: break;
+  }
 }
 
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
