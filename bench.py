@@ -287,7 +287,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "nodes": N, "unknowns_per_mode": 2 * N, "modes": M + 1,
                    "n_theta": wl.n_theta, "media": 2, "precision": "fp64",
-                   "incidence": "point source (%.1f, 0, %.1f)" % (wl.incidences[0][1], wl.incidences[0][2])},
+                   "incidence": ", ".join("point source (%.1f, 0, %.1f)" % (inc[1], inc[2]) if inc[0] == "point"
+                                          else "plane wave (polar angle %.2f)" % inc[1] for inc in wl.incidences)},
         "time_to_solution_s": ms_step * 1e-3,
         "kernel_stage_pairs_modes_per_s": units / (kernel_ms * 1e-3) if kernel_ms > 0 else None,
         "stage_ms": {"setup": st[0], "far": st[1], "split": st[2], "direct": st[3], "near": st[4],
