@@ -426,6 +426,39 @@ def test_mode_batches_reproduce_the_full_build():
     assert np.max(np.abs(f_sum - f_full)) <= 1e-10 * np.max(np.abs(f_full))
 
 
+def test_single_mode_builds(tiny_ref):
+    """The degenerate batch of one mode: the axisymmetric problem alone
+    (m_max = 0) in FP64 and mixed precision, and one higher mode on its own
+    (m_min = m_max = 5), against the oracle's matrices and boundary data."""
+    from paper_2412_11162_amd import _binding as B
+    wl, g, A, sol = tiny_ref
+    inc = [wl.incidences[0]]
+    for prec, tol in ((B.PMLBIE_FP64, BOUNDARY_TOL), (B.PMLBIE_MIXED, 1e-6)):
+        keep = B.PMLBIE_KEEP_OPERATORS if prec == B.PMLBIE_FP64 else 0
+        s = _solver(wl, m_max=0, precision=prec, flags=keep)
+        if prec == B.PMLBIE_FP64:
+            assert _normwise(s.get_operator(0).cpu().numpy(), A[0]) <= KERNEL_TOL
+        out = [o[:, 0, :].cpu().numpy() for o in s.solve_modes(inc)]
+        assert out[0].shape == (1, g.n)
+        errs = _boundary_err(out, [x[:1] for x in sol[:4]])
+        assert np.max(errs) <= tol, (prec, errs)
+    # mode 5 alone: an off-axis source excites it; the source on the axis
+    # (tiny's incidence) excites mode 0 only, so there it must vanish
+    import oracle
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    off = oracle.solve(g, modes, b1, b2, A=A)
+    s = _solver(wl, build=False)
+    s.build_modal_operators(wl.n_theta, 5, B.PMLBIE_FP64, B.PMLBIE_KEEP_OPERATORS, m_min=5)
+    assert _normwise(s.get_operator(5).cpu().numpy(), A[5]) <= KERNEL_TOL
+    got = s.solve_modes([("point", 0.3, 1.0)] + inc)
+    out = [o[:, 0, :].cpu().numpy() for o in got]
+    errs = _boundary_err(out, [x[5:6] for x in off[:4]])
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+    scale = max(np.max(np.abs(x[0])) for x in sol[:4])
+    assert max(np.max(np.abs(o[:, 1, :].cpu().numpy())) for o in got) <= 1e-14 * scale
+
+
 def test_modes_on_the_2048_grid_against_oracle(tiny_ref):
     """m_max = 500 needs the 2048-point angle grid (R = 32 register FFTs, one
     sequence at a time, for the far and split pairs); every mode comes out of
