@@ -459,6 +459,23 @@ def test_single_mode_builds(tiny_ref):
     assert max(np.max(np.abs(o[:, 1, :].cpu().numpy())) for o in got) <= 1e-14 * scale
 
 
+def test_plane_wave_at_normal_incidence(tiny_ref):
+    """A plane wave travelling down the axis (polar angle 0) is axisymmetric:
+    the oracle's data are exactly zero above mode 0, and the library, which
+    samples the wave in theta and transforms, matches mode 0 to the boundary
+    bar and leaves only rounding in the other modes."""
+    import oracle
+    wl, g, A, _ = tiny_ref
+    modes = list(range(wl.m_max + 1))
+    b1, b2 = oracle.rhs_plane_wave(g, modes, 0.0)
+    ref = oracle.solve(g, modes, b1, b2, A=A)[:4]
+    out = [o[:, 0, :].cpu().numpy() for o in _solver(wl).solve_modes([("plane", 0.0)])]
+    errs = _boundary_err(out, ref)
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+    big = max(np.max(np.abs(r[0])) for r in ref)
+    assert max(np.max(np.abs(o[1:])) for o in out) <= 1e-12 * big
+
+
 def test_modes_on_the_2048_grid_against_oracle(tiny_ref):
     """m_max = 500 needs the 2048-point angle grid (R = 32 register FFTs, one
     sequence at a time, for the far and split pairs); every mode comes out of
