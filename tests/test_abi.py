@@ -80,3 +80,19 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_binding_constants_match_the_header():
+    """Status codes, precisions and flags: the binding's copies carry the
+    header's names and values (a flag off by one would build silently with
+    the wrong options)."""
+    from paper_2412_11162_amd import _binding
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", txt, flags=re.S):
+        for name, val in re.findall(r"\b(PMLBIE_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            consts[name] = int(val)
+    assert {"PMLBIE_OK", "PMLBIE_EINVAL", "PMLBIE_FP64", "PMLBIE_MIXED",
+            "PMLBIE_KEEP_OPERATORS", "PMLBIE_USE_SURROGATE"} <= set(consts)
+    for name, val in consts.items():
+        assert getattr(_binding, name) == val, name
