@@ -476,6 +476,28 @@ def test_plane_wave_at_normal_incidence(tiny_ref):
     assert max(np.max(np.abs(o[1:])) for o in out) <= 1e-12 * big
 
 
+def test_lossy_lower_medium():
+    """A complex wavenumber in the lower medium (k2 = 3 pi + 0.8i, an
+    absorbing medium): the far-pair rule's sampling bound takes |Im k| into
+    account; matrices of modes 0, 3 and 8 within the kernel bar and the
+    boundary data of an off-axis point source within the boundary bar."""
+    import oracle
+    from paper_2412_11162_amd._binding import PMLBIE_KEEP_OPERATORS
+    base = workloads.tiny()
+    wl = base.with_(k2=complex(base.k2, 0.8))
+    g = oracle.geometry(wl)
+    modes = [0, 3, 8]
+    A, _, _ = oracle.assemble(g, modes)
+    b1, b2 = oracle.rhs_point_source(g, modes, 0.3, 1.0)
+    ref = oracle.solve(g, modes, b1, b2, A=A)[:4]
+    s = _solver(wl, flags=PMLBIE_KEEP_OPERATORS)
+    for j, n in enumerate(modes):
+        assert _normwise(s.get_operator(n).cpu().numpy(), A[j]) <= KERNEL_TOL, n
+    out = [o[modes, 0, :].cpu().numpy() for o in s.solve_modes([("point", 0.3, 1.0)])]
+    errs = _boundary_err(out, ref)
+    assert np.max(errs) <= BOUNDARY_TOL, errs
+
+
 def test_modes_on_the_2048_grid_against_oracle(tiny_ref):
     """m_max = 500 needs the 2048-point angle grid (R = 32 register FFTs, one
     sequence at a time, for the far and split pairs); every mode comes out of
