@@ -28,7 +28,8 @@ _lib = None
 __all__ = [
     "build_oracle", "lib", "Geometry", "geometry", "modal_kernels_nodes",
     "modal_kernels_points", "near_integrals", "assemble", "rhs_point_source",
-    "rhs_plane_wave", "solve", "field_modes", "gl16", "sigma", "num_threads",
+    "rhs_plane_wave", "plane_wave_coeffs", "plane_wave_reference", "solve", "field_modes",
+    "gl16", "sigma", "num_threads",
 ]
 
 
@@ -363,9 +364,11 @@ def near_integrals(g: Geometry, targets: Iterable[int], ks: Sequence[complex],
 # Nystrom matrices and the coupled per-mode system (Sec. 4.1, Sec. 4.2).
 
 def operator_rows(g: Geometry, rows: Sequence[int], ks: Sequence[complex], modes: Sequence[int],
-                  reltol: float = 1e-14):
+                  reltol: float = 1e-14, near_reltol: float = 1e-13):
     """Rows of the Nystrom matrices S and K for each wavenumber and mode:
-    returns S, K of shape [len(ks), len(modes), len(rows), N]."""
+    returns S, K of shape [len(ks), len(modes), len(rows), N].  reltol is the
+    azimuthal quadrature's tolerance, near_reltol that of the near-panel
+    product integrals in the panel parameter."""
     rows = list(rows)
     N = g.n
     nk, nm = len(ks), len(modes)
@@ -384,7 +387,7 @@ def operator_rows(g: Geometry, rows: Sequence[int], ks: Sequence[complex], modes
         for ik in range(nk):
             S[ik, :, far[:, 0], far[:, 2]] = 2.0 * W[:, None] * kern[:, ik, 0, :]
             K[ik, :, far[:, 0], far[:, 2]] = 2.0 * W[:, None] * kern[:, ik, 1, :]
-    near = near_integrals(g, rows, ks, modes)
+    near = near_integrals(g, rows, ks, modes, reltol=near_reltol)
     for r, i in enumerate(rows):
         for p, o in near[i].items():
             cols = np.arange(16 * p, 16 * p + 16)
@@ -428,19 +431,52 @@ def rhs_point_source(g: Geometry, modes: Sequence[int], rho_s: float, z_s: float
     return -u.T.copy(), -du.T.copy()
 
 
-def rhs_plane_wave(g: Geometry, modes: Sequence[int], phi_inc: float):
-    """b1, b2 for a plane wave (theta_inc = 0) via the Jacobi-Anger expansion
-    of exp(-i k1 x sin(phi)) and the flat-interface reference field (Sec. 2).
-    On the flat part of the curve the jump vanishes identically."""
-    from scipy.special import jv, jvp
-    wl = g.wl
-    k1, k2 = complex(wl.k1), complex(wl.k2)
+def plane_wave_coeffs(k1: complex, k2: complex, phi_inc: float):
+    """Reflection coefficient R and vertical wavenumber k* of the flat-interface
+    reference field of a plane wave with polar angle phi_inc (Sec. 2):
+    k* = sqrt(k2^2 - k1^2 sin^2 phi) when k2 > |k1 sin phi| (a transmitted
+    wave travelling down), i sqrt(k1^2 sin^2 phi - k2^2) otherwise (a wave
+    decaying below the interface), and R = 2 / (1 + k* / (k1 cos phi)) - 1."""
+    k1, k2 = complex(k1), complex(k2)
     c, s = math.cos(phi_inc), math.sin(phi_inc)
     if k2.real > abs(k1.real * s):
         kst = np.sqrt(k2 ** 2 - k1 ** 2 * s ** 2)
     else:
         kst = 1j * np.sqrt(k1 ** 2 * s ** 2 - k2 ** 2)
     Rc = 2.0 / (1.0 + kst / (k1 * c)) - 1.0
+    return complex(Rc), complex(kst)
+
+
+def plane_wave_reference(wl, phi_inc: float, x, z):
+    """The flat-interface reference field u^{tot,0} of Sec. 2 (theta_inc = 0)
+    at Cartesian points (x, y, z) (it does not depend on y), both of its
+    formulas evaluated at every point: returns (upper, lower) with
+    upper = e^{-i k1 (x sin phi + z cos phi)} + R e^{-i k1 (x sin phi - z cos phi)},
+    lower = (1 + R) e^{-i k1 x sin phi - i k* z}."""
+    k1 = complex(wl.k1)
+    Rc, kst = plane_wave_coeffs(wl.k1, wl.k2, phi_inc)
+    c, s = math.cos(phi_inc), math.sin(phi_inc)
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    ex = np.exp(-1j * k1 * s * x)
+    up = ex * (np.exp(-1j * k1 * c * z) + Rc * np.exp(1j * k1 * c * z))
+    lo = ex * (1.0 + Rc) * np.exp(-1j * kst * z)
+    return up, lo
+
+
+def rhs_plane_wave(g: Geometry, modes: Sequence[int], phi_inc: float):
+    """b1, b2 for a plane wave (theta_inc = 0): the jump of the reference field
+    (Sec. 2) across the curve, [u^{tot,0}] = e^{-i k1 x sin phi} g(z) with
+    g(z) = e^{-i k1 z cos phi} + R e^{i k1 z cos phi} - (1 + R) e^{-i k* z},
+    and its normal derivative, turned into azimuthal modes by the
+    Jacobi-Anger expansion e^{-i a cos theta} = sum_n (-i)^n J_n(a) e^{i n theta}.
+    On the flat part of the curve (z = 0, where the PML acts) the jump and its
+    normal derivative vanish, so the conormal there is the plain normal."""
+    from scipy.special import jv, jvp
+    wl = g.wl
+    k1 = complex(wl.k1)
+    Rc, kst = plane_wave_coeffs(wl.k1, wl.k2, phi_inc)
+    c, s = math.cos(phi_inc), math.sin(phi_inc)
     z = g.z
     gz = np.exp(-1j * k1 * z * c) + Rc * np.exp(1j * k1 * z * c) - (1 + Rc) * np.exp(-1j * kst * z)
     gzp = (-1j * k1 * c) * np.exp(-1j * k1 * z * c) + Rc * (1j * k1 * c) * np.exp(1j * k1 * z * c) \
@@ -451,7 +487,6 @@ def rhs_plane_wave(g: Geometry, modes: Sequence[int], phi_inc: float):
     for j, n in enumerate(modes):
         f = 2 * np.pi * (-1j) ** n
         b1[j] = -f * jv(n, arg) * gz
-        # the data vanish where sigma_1 != 0 (flat part), so nu_c = nu there
         b2[j] = -(g.nu[:, 0] * f * (k1 * s).real * jvp(n, arg) * gz + g.nu[:, 1] * f * jv(n, arg) * gzp)
     return b1, b2
 

@@ -99,19 +99,30 @@ typedef struct { double a, b, err, absint; int depth; } ivl;
  * rounding floor below which no quadrature of f can resolve the integral; an
  * interval whose estimate is within 50 eps of its own int |f| is not split
  * further -- or the interval budget is spent.
+ *
+ * Bookkeeping: the vector of partial results is kept as a running sum (the
+ * bisected interval's contribution taken out, its two halves added), so a
+ * bisection costs O(nout) plus a scan of the scalar estimates, not a re-sum of
+ * every interval's vector.  The running sum only serves the stopping test's
+ * scale max_j |I_j|; the returned result is summed afresh over the final
+ * intervals.  The rule (which interval is split, when to stop) is unchanged.
  * Returns the number of intervals used (negative if the budget ran out).
  */
 static int adapt(vfun f, void *ctx, int nout, const double *brk, int nbrk,
                  double reltol, double abstol, int maxivl, cplx *result) {
   ivl *iv = (ivl *)malloc(sizeof(ivl) * maxivl);
   cplx *store = (cplx *)malloc(sizeof(cplx) * (size_t)nout * maxivl);
-  cplx *tmp = (cplx *)malloc(sizeof(cplx) * nout * 2);
+  cplx *tmp = (cplx *)malloc(sizeof(cplx) * nout * 3);
   cplx *gs = tmp + nout;
+  cplx *run = tmp + 2 * (size_t)nout;
   int n = 0;
+  for (int j = 0; j < nout; ++j) run[j] = 0;
   for (int s = 0; s + 1 < nbrk; ++s) {
     if (!(brk[s + 1] > brk[s])) continue;
     iv[n].a = brk[s]; iv[n].b = brk[s + 1]; iv[n].depth = 0;
-    iv[n].err = gk15(f, ctx, nout, brk[s], brk[s + 1], store + (size_t)n * nout, tmp, gs, &iv[n].absint);
+    cplx *r = store + (size_t)n * nout;
+    iv[n].err = gk15(f, ctx, nout, brk[s], brk[s + 1], r, tmp, gs, &iv[n].absint);
+    for (int j = 0; j < nout; ++j) run[j] += r[j];
     ++n;
   }
   int ok = 1;
@@ -119,27 +130,32 @@ static int adapt(vfun f, void *ctx, int nout, const double *brk, int nbrk,
     double tot = 0, scale = 0, absint = 0;
     int worst = -1;
     double werr = -1;
-    for (int j = 0; j < nout; ++j) result[j] = 0;
     for (int s = 0; s < n; ++s) {
       tot += iv[s].err;
       absint += iv[s].absint;
       /* an interval whose estimate is at its own rounding level is final */
       int at_floor = iv[s].err <= 50.0 * DBL_EPSILON * iv[s].absint;
       if (iv[s].err > werr && iv[s].depth < 200 && !at_floor) { werr = iv[s].err; worst = s; }
-      cplx *r = store + (size_t)s * nout;
-      for (int j = 0; j < nout; ++j) result[j] += r[j];
     }
-    for (int j = 0; j < nout; ++j) { double m = cabs(result[j]); if (m > scale) scale = m; }
+    for (int j = 0; j < nout; ++j) { double m = cabs(run[j]); if (m > scale) scale = m; }
     double tol = fmax(abstol, fmax(reltol * scale, 200.0 * DBL_EPSILON * absint));
     if (tot <= tol || worst < 0) break;
     if (n + 1 >= maxivl) { ok = 0; break; }
     double a = iv[worst].a, b = iv[worst].b, m = 0.5 * (a + b);
     int d = iv[worst].depth + 1;
+    cplx *rw = store + (size_t)worst * nout, *rn = store + (size_t)n * nout;
+    for (int j = 0; j < nout; ++j) run[j] -= rw[j];
     iv[worst].b = m; iv[worst].depth = d;
-    iv[worst].err = gk15(f, ctx, nout, a, m, store + (size_t)worst * nout, tmp, gs, &iv[worst].absint);
+    iv[worst].err = gk15(f, ctx, nout, a, m, rw, tmp, gs, &iv[worst].absint);
     iv[n].a = m; iv[n].b = b; iv[n].depth = d;
-    iv[n].err = gk15(f, ctx, nout, m, b, store + (size_t)n * nout, tmp, gs, &iv[n].absint);
+    iv[n].err = gk15(f, ctx, nout, m, b, rn, tmp, gs, &iv[n].absint);
+    for (int j = 0; j < nout; ++j) run[j] += rw[j] + rn[j];
     ++n;
+  }
+  for (int j = 0; j < nout; ++j) result[j] = 0;
+  for (int s = 0; s < n; ++s) {
+    cplx *r = store + (size_t)s * nout;
+    for (int j = 0; j < nout; ++j) result[j] += r[j];
   }
   free(iv); free(store); free(tmp);
   return ok ? n : -n;
@@ -322,17 +338,18 @@ static void pair_integrand(double D, void *vctx, cplx *out) {
   cplx R = csqrt(R2);                                /* principal branch, Sec. 3.1 */
   /* nu_c'.(r~' - r~ rotated) = n'_rho (rho~' - rho~ cos D) + n'_z (z~' - z~) */
   cplx N = -(p->nrs * p->drho + p->nzs * p->dz) + 2.0 * p->nrs * p->rt * s2;
+  cplx Gv[2], Kv[2];
   for (int ik = 0; ik < p->nk; ++ik) {
     cplx ikR = p->k[ik] * R * (cplx)_Complex_I;
     cplx e = cexp(ikR);
-    cplx Gv = e / (4.0 * M_PI * R);
-    cplx Kv = N * e * (ikR - 1.0) / (4.0 * M_PI * R * R2);
-    cplx *oS = out + (2 * ik) * p->nmode, *oK = out + (2 * ik + 1) * p->nmode;
-    for (int j = 0; j < p->nmode; ++j) {
-      int n = p->modes[j];
-      double cn = cos(n * D);
-      oS[j] = 2.0 * cn * Gv;
-      oK[j] = 2.0 * cn * Kv;
+    Gv[ik] = e / (4.0 * M_PI * R);
+    Kv[ik] = N * e * (ikR - 1.0) / (4.0 * M_PI * R * R2);
+  }
+  for (int j = 0; j < p->nmode; ++j) {
+    double cn = 2.0 * cos(p->modes[j] * D);
+    for (int ik = 0; ik < p->nk; ++ik) {
+      out[(2 * ik) * p->nmode + j] = cn * Gv[ik];
+      out[(2 * ik + 1) * p->nmode + j] = cn * Kv[ik];
     }
   }
 }

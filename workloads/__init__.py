@@ -127,6 +127,13 @@ def largest(seed: int = 11162) -> Workload:
     )
 
 
+def largest_reduced() -> Workload:
+    """The largest configuration's physics (media, rings, PML, angle grid,
+    modes 0..256, the 16 plane waves) on 64 nodes per segment (256 nodes), a
+    size the oracle can solve; the parity case of that configuration."""
+    return largest().with_(name="largest_reduced", nodes_per_segment=64)
+
+
 def tiny(nodes_per_segment: int = 16, n_theta: int = 32, **kw) -> Workload:
     """A reduced version of the small workload (used for oracle-vs-kernel
     parity on the CPU side and for fast end-to-end checks)."""
@@ -228,7 +235,8 @@ def bowl_paper() -> Workload:
         incidences=(("point", 0.0, 1.0), ("plane", 0.5)))
 
 
-ALL = {"small": small, "paper_scale": paper_scale, "largest": largest, "tiny": tiny,
+ALL = {"small": small, "paper_scale": paper_scale, "largest": largest,
+       "largest_reduced": largest_reduced, "tiny": tiny,
        "corner": corner, "corner_paper": corner_paper, "stepped": stepped, "bowl": bowl,
        "bowl_paper": bowl_paper}
 
