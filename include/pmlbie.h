@@ -170,7 +170,13 @@ typedef struct {
  * medium on the curve, phi1 = its conormal derivative, u2, phi2 the same for
  * the lower medium (u2 = u1 - b1, phi2 = phi1 - b2 by the transmission
  * conditions).  Any output pointer may be NULL.
- * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOCONV (mixed precision). */
+ * Mixed precision refines x += LU32^{-1} (b - A64 x) in FP64 until
+ * ||b - A64 x|| <= tol ||b|| for every mode and right-hand side
+ * (pmlbie_set_refinement; default tol 1e-10, at most 30 iterations); the
+ * iterate of the last step is returned even when it stops short.
+ * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOCONV (mixed precision: the
+ * rule was not met within the iteration cap; the outputs hold the last
+ * iterate and pmlbie_last_error the residual reached). */
 int pmlbie_solve_modes(pmlbie_ctx* ctx, int n_rhs, const pmlbie_incidence* inc, void* d_u1,
                        void* d_phi1, void* d_u2, void* d_phi2);
 
@@ -187,7 +193,21 @@ int pmlbie_solve_modes(pmlbie_ctx* ctx, int n_rhs, const pmlbie_incidence* inc, 
  * outside rho < a1 or for more than 1024 summed modes. */
 int pmlbie_evaluate_field(pmlbie_ctx* ctx, int n_pts, const double* rtz, double* out);
 
+/* Stopping rule of the mixed-precision refinement (Sec. 4.2 systems solved
+ * with complex64 factors and FP64 residuals): relative residual tol
+ * (0 < tol < 1) and at most max_iter iterations (1..100).  Takes effect at
+ * the next solve_modes.  Errors: PMLBIE_EINVAL. */
+int pmlbie_set_refinement(pmlbie_ctx* ctx, double tol, int max_iter);
+
 /* ---- inspection ---------------------------------------------------------- */
+
+/* Test hook of the zero-pivot path (Sec. 4.2 per-mode LU): the next build
+ * sets column col (0 <= col < 2N) of mode `mode`'s assembled matrix to zero
+ * before factoring it, so that its LU meets an exactly zero pivot and the
+ * build returns PMLBIE_ESINGULAR naming the mode and column.  One shot: the
+ * hook is cleared by that build; a mode outside the build's range leaves the
+ * matrices untouched.  Errors: PMLBIE_EINVAL, PMLBIE_ESTATE (no media). */
+int pmlbie_test_zero_column(pmlbie_ctx* ctx, int mode, int col);
 
 /* Sizes of the current build: info[0] = N, [1] = m_max, [2] = angle grid L
  * of the split, [3] = angle grid of the far path (the same L), [4] = far

@@ -27,7 +27,7 @@ EXPORTS = (
     "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_build_modal_operators_range",
     "pmlbie_solve_modes",
     "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
-    "pmlbie_get_operator", "pmlbie_get_stats",
+    "pmlbie_get_operator", "pmlbie_get_stats", "pmlbie_set_refinement", "pmlbie_test_zero_column",
     "pmlbie_surrogate_nparams", "pmlbie_surrogate_init", "pmlbie_surrogate_make_samples",
     "pmlbie_surrogate_train", "pmlbie_surrogate_eval", "pmlbie_surrogate_set_tolerance",
     "pmlbie_surrogate_save", "pmlbie_surrogate_load", "pmlbie_surrogate_params",
@@ -70,6 +70,8 @@ def load():
     L.pmlbie_modal_kernels.argtypes = [P, i, P, P]
     L.pmlbie_get_operator.argtypes = [P, i, P]
     L.pmlbie_get_stats.argtypes = [P, P, P]
+    L.pmlbie_set_refinement.argtypes = [P, d, i]
+    L.pmlbie_test_zero_column.argtypes = [P, i, i]
     ul, l, sz = ctypes.c_ulonglong, ctypes.c_long, ctypes.c_size_t
     L.pmlbie_surrogate_nparams.argtypes = []
     L.pmlbie_surrogate_init.argtypes = [P, ul]

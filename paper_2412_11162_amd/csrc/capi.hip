@@ -104,6 +104,11 @@ struct pmlbie_ctx {
   DBuf<zd> b1, b2, x, u1, p1, u2, p2;
   double stage_ms[16] = {0};
   double counters[16] = {0};
+  // refinement stopping rule of the mixed-precision solve
+  double ref_tol = 1e-10;
+  int ref_maxit = 30;
+  // one-shot test hook: zero this column of this mode's matrix before the LU
+  int zc_mode = -1, zc_col = -1;
   // learned surrogate of the far-pair modes
   SgNet sg;
   SgWork sgw;
@@ -613,6 +618,11 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->stage_ms[4] = t_near.stop();
     // the near-panel pairs of the grid were not counted as far
     c->cnt_far -= 16LL * (long long)ajobs.size();
+    if (c->zc_mode >= m0 && c->zc_mode <= M) {
+      launch_zero_column(c->A.p + (size_t)(c->zc_mode - m0) * ms, n2, c->zc_col, c->stream);
+      HIPCHK(hipGetLastError());
+    }
+    c->zc_mode = c->zc_col = -1;
 
     // keep what the solve needs: the unfactored operator (FP64) -- the lower
     // block row [K2 - D2, -S2] for the right-hand sides, and in mixed
@@ -712,6 +722,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       }
     }
     auto t0 = std::chrono::steady_clock::now();
+    c->stage = 3;  // the solution of an earlier solve is being replaced
     const int N = c->N, M = c->M, m0 = c->m0, nm = M - m0 + 1;
     const long n2 = 2L * N, ms = n2 * n2;
     c->nrhs = n_rhs;
@@ -796,6 +807,7 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     c->stage_ms[8] = t_rhs.stop();
     Timer t_sol(c->stream);
     double t_ref = 0.0;
+    std::string noconv;  // set when the refinement stops short of its rule
     c->counters[0] = 0;
     c->counters[1] = 0;
     if (!mixed) {
@@ -811,8 +823,8 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       c->xs.alloc(len);
       c->rsq.alloc(len);
       c->rnorm.alloc(2 * nv);
-      const double tol = 1e-10;
-      const int maxit = 30;
+      const double tol = c->ref_tol;
+      const int maxit = c->ref_maxit;
       HIPCHK(hipMemsetAsync(c->xs.p, 0, len * sizeof(zd), c->stream));
       HIPCHK(hipMemcpyAsync(c->rbuf.p, c->x.p, len * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
       launch_sq(c->x.p, len, c->rsq.p, c->stream);
@@ -844,8 +856,8 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
       c->counters[1] = worst;
       HIPCHK(hipMemcpyAsync(c->x.p, c->xs.p, len * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
       if (worst > tol)
-        return fail(c, PMLBIE_ENOCONV, "solve: refinement stopped at relative residual " +
-                                           std::to_string(worst) + " after " + std::to_string(it) + " iterations");
+        noconv = "solve: refinement stopped at relative residual " + std::to_string(worst) + " after " +
+                 std::to_string(it) + " iterations";
     }
     c->u1.alloc(vec);
     c->p1.alloc(vec);
@@ -861,6 +873,9 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     c->stage_ms[9] = t_ref;
     c->stage_ms[7] = t_sol.stop() + c->stage_ms[8];
     (void)t0;
+    // the outputs hold the last iterate either way; only a converged solve
+    // opens the field evaluation
+    if (!noconv.empty()) return fail(c, PMLBIE_ENOCONV, noconv);
     c->stage = 4;
     return PMLBIE_OK;
   });
@@ -1023,6 +1038,25 @@ int pmlbie_get_operator(pmlbie_ctx* c, int mode, void* d_out) {
     HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;
   });
+}
+
+int pmlbie_set_refinement(pmlbie_ctx* c, double tol, int max_iter) {
+  if (!c) return PMLBIE_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0) || max_iter < 1 || max_iter > 100)
+    return fail(c, PMLBIE_EINVAL, "set_refinement: need 0 < tol < 1 and 1 <= max_iter <= 100");
+  c->ref_tol = tol;
+  c->ref_maxit = max_iter;
+  return PMLBIE_OK;
+}
+
+int pmlbie_test_zero_column(pmlbie_ctx* c, int mode, int col) {
+  if (!c) return PMLBIE_EINVAL;
+  if (c->stage < 2) return fail(c, PMLBIE_ESTATE, "test_zero_column: set geometry and media first");
+  if (mode < 0 || col < 0 || col >= 2 * c->N)
+    return fail(c, PMLBIE_EINVAL, "test_zero_column: need mode >= 0 and 0 <= col < 2N");
+  c->zc_mode = mode;
+  c->zc_col = col;
+  return PMLBIE_OK;
 }
 
 int pmlbie_get_stats(const pmlbie_ctx* c, double* stage_ms, double* counters) {

@@ -207,6 +207,16 @@ __global__ void k_axpy(zd* __restrict__ x, const zd* __restrict__ d, long count)
   if (e < count) x[e] = x[e] + d[e];
 }
 
+// Column `col` of a row-major n x n matrix set to zero (test hook of the
+// zero-pivot path).
+__global__ void k_zero_column(zd* __restrict__ A, long n, int col) {
+  const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) A[r * n + col] = zd{0.0, 0.0};
+}
+
+void launch_zero_column(zd* A, long n, int col, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_column, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, n, col);
+}
 void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st) {
   hipLaunchKernelGGL(k_to_c64, dim3(256 * 32), dim3(256), 0, st, src, dst, count);
 }

@@ -197,6 +197,12 @@ class Solver:
         self._chk(self.L.pmlbie_surrogate_label(self.h, s.shape[0], _p(s), _p(y)))
         return y
 
+    def set_refinement(self, tol: float, max_iter: int):
+        self._chk(self.L.pmlbie_set_refinement(self.h, float(tol), int(max_iter)))
+
+    def test_zero_column(self, mode: int, col: int):
+        self._chk(self.L.pmlbie_test_zero_column(self.h, int(mode), int(col)))
+
     def stats(self):
         s = np.zeros(16)
         c = np.zeros(16)
