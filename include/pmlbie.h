@@ -229,6 +229,20 @@ int pmlbie_get_nodes(const pmlbie_ctx* ctx, double* out);
  * complex128, layout [pair][S1, K1, S2, K2][mode]. */
 int pmlbie_modal_kernels(pmlbie_ctx* ctx, int n_pairs, const double* geom, void* d_out);
 
+/* Allocation-free variant of pmlbie_modal_kernels, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernels and output,
+ * but every work buffer (pair records, the far / split / direct work lists,
+ * the split path's singular-mode tables) lives in a fixed scratch array of
+ * the library (about 14.3 MB per device, held until the process ends) and no
+ * device or library allocation is made.  At most PMLBIE_NOALLOC_MAX_PAIRS
+ * pairs per call (PMLBIE_EINVAL beyond).  All calls on one device share that
+ * device's scratch: calls that overlap in time on one device (several host
+ * threads, or several streams) race and must be serialised by the caller.
+ * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE (no build), PMLBIE_EDEVICE. */
+#define PMLBIE_NOALLOC_MAX_PAIRS 4096
+int pmlbie_modal_kernels_noalloc(pmlbie_ctx* ctx, int n_pairs, const double* geom, void* d_out);
+
 /* Copy the assembled (unfactored) matrix of mode n (row-major 2N x 2N
  * complex128) to d_out; needs PMLBIE_KEEP_OPERATORS at build. */
 int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);

@@ -20,6 +20,7 @@ PMLBIE_FP64 = 0
 PMLBIE_MIXED = 1
 PMLBIE_KEEP_OPERATORS = 1
 PMLBIE_USE_SURROGATE = 2
+PMLBIE_NOALLOC_MAX_PAIRS = 4096
 
 EXPORTS = (
     "pmlbie_create", "pmlbie_destroy", "pmlbie_last_error", "pmlbie_set_geometry", "pmlbie_set_polyline",
@@ -27,6 +28,7 @@ EXPORTS = (
     "pmlbie_set_media_pml", "pmlbie_build_modal_operators", "pmlbie_build_modal_operators_range",
     "pmlbie_solve_modes",
     "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
+    "pmlbie_modal_kernels_noalloc",
     "pmlbie_get_operator", "pmlbie_get_stats", "pmlbie_set_refinement", "pmlbie_test_zero_column",
     "pmlbie_surrogate_nparams", "pmlbie_surrogate_init", "pmlbie_surrogate_make_samples",
     "pmlbie_surrogate_train", "pmlbie_surrogate_eval", "pmlbie_surrogate_set_tolerance",
@@ -68,6 +70,7 @@ def load():
     L.pmlbie_get_info.argtypes = [P, P]
     L.pmlbie_get_nodes.argtypes = [P, P]
     L.pmlbie_modal_kernels.argtypes = [P, i, P, P]
+    L.pmlbie_modal_kernels_noalloc.argtypes = [P, i, P, P]
     L.pmlbie_get_operator.argtypes = [P, i, P]
     L.pmlbie_get_stats.argtypes = [P, P, P]
     L.pmlbie_set_refinement.argtypes = [P, d, i]

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <future>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -285,6 +286,46 @@ void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, co
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free modal-kernel call
+// (pmlbie_modal_kernels_noalloc): a fixed array in the code object, one copy
+// per device, held until the process ends.  Layout (bytes, 256-aligned):
+// pair geometry, the far / split / direct work lists, their counters and the
+// split path's singular-mode tables for chunks of kNaSplitChunk pairs.
+constexpr long kNaMaxPairs = PMLBIE_NOALLOC_MAX_PAIRS;
+constexpr long kNaSplitChunk = 256;
+constexpr long kNaMaxModesQ = 1024;  // MQ + 1 = L / 2 <= 1024 (L <= 2048)
+constexpr size_t na_round(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kNaGeom = 0;
+constexpr size_t kNaLGeom = kNaGeom + na_round(sizeof(PairGeom) * kNaMaxPairs);
+constexpr size_t kNaLDest = kNaLGeom + na_round(3 * sizeof(PairGeom) * kNaMaxPairs);
+constexpr size_t kNaCount = kNaLDest + na_round(3 * sizeof(int2) * kNaMaxPairs);
+constexpr size_t kNaQtab = kNaCount + 256;
+constexpr size_t kNaTable = sizeof(zd) * kNaSplitChunk * kNaMaxModesQ;
+constexpr size_t kNaZhat = kNaQtab + na_round(kNaTable);
+constexpr size_t kNaPhat = kNaZhat + na_round(kNaTable);
+constexpr size_t kNaCoef = kNaPhat + na_round(kNaTable);
+constexpr size_t kNaBytes = kNaCoef + na_round(sizeof(zd) * 4 * kNaSplitChunk);
+static_assert(sizeof(PairGeom) == 12 * sizeof(double), "the host pair layout is copied as is");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Device address of `scratch` per device (the array's name is a host-side
+// stand-in), resolved once per device by pmlbie_create with that device current.
+constexpr int kNaMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kNaMaxDevices] = {};
+
+hipError_t resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kNaMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch[device]) return hipSuccess;
+  unsigned char* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[device] = ptr;
+  return e;
+}
+
 std::vector<zd> twiddles(int nt, bool full = false) {
   std::vector<zd> t(full ? nt : nt / 2);
   for (int k = 0; k < (int)t.size(); ++k) {
@@ -310,6 +351,12 @@ int pmlbie_create(pmlbie_ctx** out, int device, void* stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PMLBIE_EDEVICE;
   if (device < 0 || device >= ndev) return PMLBIE_EINVAL;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return PMLBIE_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return PMLBIE_EDEVICE;
+  const hipError_t se = resolve_scratch(device);
+  (void)hipSetDevice(prev);
+  if (se != hipSuccess) return PMLBIE_EDEVICE;
   pmlbie_ctx* c = new (std::nothrow) pmlbie_ctx();
   if (!c) return PMLBIE_ENOMEM;
   c->device = device;
@@ -1021,6 +1068,57 @@ int pmlbie_modal_kernels(pmlbie_ctx* c, int n_pairs, const double* geom, void* d
       g[q].nz = zd{s[10], s[11]};
     }
     run_pair_list(c, g, (zd*)d_out, nullptr);
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_modal_kernels_noalloc(pmlbie_ctx* c, int n_pairs, const double* geom, void* d_out) {
+  return guarded(c, [&]() -> int {
+    if (c->stage < 3) return fail(c, PMLBIE_ESTATE, "modal_kernels_noalloc: build the operators first");
+    if (n_pairs < 0 || (n_pairs > 0 && (!geom || !d_out)))
+      return fail(c, PMLBIE_EINVAL, "modal_kernels_noalloc: bad arguments");
+    if (n_pairs > kNaMaxPairs)
+      return fail(c, PMLBIE_EINVAL, "modal_kernels_noalloc: " + std::to_string(n_pairs) +
+                                        " pairs exceed the scratch limit of " + std::to_string(kNaMaxPairs));
+    if (c->MQ + 1 > kNaMaxModesQ) return fail(c, PMLBIE_EINVAL, "modal_kernels_noalloc: angle grid too long");
+    if (n_pairs == 0) return PMLBIE_OK;
+    unsigned char* sp = g_scratch[c->device];
+    if (!sp) return fail(c, PMLBIE_EDEVICE, "modal_kernels_noalloc: no scratch on this device");
+    const long np = n_pairs;
+    PairGeom* geo = reinterpret_cast<PairGeom*>(sp + kNaGeom);
+    PairGeom* lg = reinterpret_cast<PairGeom*>(sp + kNaLGeom);
+    int2* ld = reinterpret_cast<int2*>(sp + kNaLDest);
+    unsigned* cnt = reinterpret_cast<unsigned*>(sp + kNaCount);
+    zd* qtab = reinterpret_cast<zd*>(sp + kNaQtab);
+    zd* zhat = reinterpret_cast<zd*>(sp + kNaZhat);
+    zd* phat = reinterpret_cast<zd*>(sp + kNaPhat);
+    zd* qcoef = reinterpret_cast<zd*>(sp + kNaCoef);
+    zd* raw = reinterpret_cast<zd*>(d_out);
+    // the host records (rho~_t, rho~_s, drho~, dz~, n_rho, n_z) are PairGeom
+    HIPCHK(hipMemcpyAsync(geo, geom, np * sizeof(PairGeom), hipMemcpyHostToDevice, c->stream));
+    launch_fill_u32(cnt, 3, 0u, c->stream);
+    WorkList wf{lg, ld, cnt, (unsigned)np};
+    WorkList ws{lg + np, ld + np, cnt + 1, (unsigned)np};
+    WorkList wd{lg + 2 * np, ld + 2 * np, cnt + 2, (unsigned)np};
+    launch_classify_list(geo, np, c->cp, wf, ws, wd, c->stream);
+    HIPCHK(hipGetLastError());
+    unsigned h[3];
+    HIPCHK(hipMemcpy(h, cnt, sizeof(h), hipMemcpyDeviceToHost));
+    launch_list_far(c->nt_far, wf.geom, wf.dest, 0, h[0], c->M, 0, c->k1, c->k2, c->tw_far.p, nullptr, 0, 0,
+                    nullptr, raw, nullptr, c->stream);
+    HIPCHK(hipGetLastError());
+    for (long f = 0; f < (long)h[1]; f += kNaSplitChunk) {
+      const long cn = std::min<long>(kNaSplitChunk, (long)h[1] - f);
+      launch_split_singular(ws.geom, f, cn, c->MQ, qtab, qcoef, zhat, phat, c->stream);
+      HIPCHK(hipGetLastError());
+      launch_split(c->nt_int, ws.geom, ws.dest, f, cn, c->M, 0, c->MQ, c->k1, c->k2, c->tw_int.p, zhat, phat,
+                   nullptr, 0, 0, nullptr, raw, c->stream);
+      HIPCHK(hipGetLastError());
+    }
+    launch_direct(wd.geom, wd.dest, 0, h[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0, nullptr,
+                  raw, kOmegaPiece, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;
   });
 }

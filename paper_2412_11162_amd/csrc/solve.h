@@ -14,6 +14,7 @@ void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int n
                     zd* u2, zd* p2, hipStream_t st);
 void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st);
 void launch_zero_column(zd* A, long n, int col, hipStream_t st);
+void launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd* x, const zd* rhs,
                      zd* r, double* rs2, hipStream_t st);
 void launch_sumsq(const double* sq, int n, int nvec, double* out, hipStream_t st);

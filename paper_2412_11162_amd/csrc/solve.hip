@@ -214,6 +214,16 @@ __global__ void k_zero_column(zd* __restrict__ A, long n, int col) {
   if (r < n) A[r * n + col] = zd{0.0, 0.0};
 }
 
+// n unsigned counters set to v (a kernel, not a memset: callers may capture
+// the work that uses it in a graph).
+__global__ void k_fill_u32(unsigned* __restrict__ p, int n, unsigned v) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+void launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
 void launch_zero_column(zd* A, long n, int col, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_column, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, n, col);
 }

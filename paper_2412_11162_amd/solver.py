@@ -127,6 +127,16 @@ class Solver:
         self._chk(self.L.pmlbie_modal_kernels(self.h, geom.shape[0], _p(geom), ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def modal_kernels_noalloc(self, geom: np.ndarray, out: torch.Tensor) -> torch.Tensor:
+        """The allocation-free variant: the caller provides the output
+        ([n_pairs, 4, M + 1] complex128 on the device)."""
+        geom = np.ascontiguousarray(np.asarray(geom, dtype=np.float64).reshape(-1, 12))
+        assert out.dtype == torch.complex128 and out.is_contiguous()
+        assert tuple(out.shape) == (geom.shape[0], 4, self.M + 1)
+        self._chk(self.L.pmlbie_modal_kernels_noalloc(self.h, geom.shape[0], _p(geom),
+                                                       ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def get_operator(self, mode: int) -> torch.Tensor:
         n2 = 2 * self.N
         out = torch.empty((n2, n2), dtype=torch.complex128, device=torch.device("cuda", self.device))
