@@ -255,7 +255,8 @@ int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
  * all LU trailing updates (8 per complex multiply-add), [3] number of
  * trailing-update launches (stage [6] is the sum of their durations),
  * [4] far pairs offered to the surrogate, [5] pairs whose surrogate modes
- * were accepted. */
+ * were accepted, [6] far pairs transformed on the full angle grid (the others
+ * on the shortest grid that holds modes 0..m_max, when that is shorter). */
 int pmlbie_get_stats(const pmlbie_ctx* ctx, double* stage_ms, double* counters);
 
 /* ---- Learned surrogate of the far-pair modes ------------------------------

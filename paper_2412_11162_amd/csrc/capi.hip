@@ -77,14 +77,15 @@ struct pmlbie_ctx {
   int n_theta = 0, M = 0, m0 = 0, nt_int = 0, nt_far = 0, B = 0, MQ = 0, precision = 0, flags = 0;
   int N = 0;
   ClassParams cp{};
-  long long cnt_far = 0, cnt_split = 0, cnt_direct = 0, cnt_aux = 0;
+  long long cnt_far = 0, cnt_split = 0, cnt_direct = 0, cnt_aux = 0, cnt_far_big = 0;
   // device data
   DBuf<double> nodes;  // 10 N doubles: rho, I, z, W, nr_re, nr_im, nz_re, nz_im, nu_rho, nu_z
   DBuf<PlaneWave> dpw;
   DBuf<zd> tw_pw;
   DBuf<int> rmap;
   DBuf<int> dpanel;
-  DBuf<zd> tw_far, tw_int;
+  DBuf<zd> tw_far, tw_int, tw_small;
+  int nt_small = 0;  // grid of the main far pass (<= nt_far)
   DBuf<double> glx, glw;
   DBuf<zd> A, Alow, Akeep;
   DBuf<zf> A32;               // complex64 factors (mixed precision)
@@ -538,6 +539,11 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->cp.kmax_im = std::max(fabs(c->k1.im), fabs(c->k2.im));
     c->cp.c_far = 34.0;
     c->cp.g_split = 9.0;
+    c->cp.nt_small = 0;
+    // the main far pass runs on the shortest grid that holds modes 0..M
+    // (512 at least); far pairs whose aliasing bound needs the full grid L
+    // are listed and transformed on it afterwards
+    c->nt_small = std::min(L, std::max(512, pow2_at_least(2.0 * (M + 1))));
 
     Timer t_setup(c->stream);
     // node tables
@@ -559,11 +565,13 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->dpanel.alloc(N);
     HIPCHK(hipMemcpyAsync(c->dpanel.p, c->geo.panel.data(), N * sizeof(int), hipMemcpyHostToDevice,
                           c->stream));
-    auto twf = twiddles(c->nt_far, true), twi = twiddles(c->nt_int, true);
+    auto twf = twiddles(c->nt_far, true), twi = twiddles(c->nt_int, true), tws = twiddles(c->nt_small, true);
     c->tw_far.alloc(twf.size());
     c->tw_int.alloc(twi.size());
+    c->tw_small.alloc(tws.size());
     HIPCHK(hipMemcpyAsync(c->tw_far.p, twf.data(), twf.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->tw_int.p, twi.data(), twi.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->tw_small.p, tws.data(), tws.size() * sizeof(zd), hipMemcpyHostToDevice, c->stream));
     c->glx.alloc(16);
     c->glw.alloc(16);
     HIPCHK(hipMemcpyAsync(c->glx.p, c->geo.glx, 16 * 8, hipMemcpyHostToDevice, c->stream));
@@ -623,13 +631,18 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     WorkList ws{c->lgeom.p, c->ldest.p, c->lcount.p, (unsigned)cap};
     WorkList wd{c->lgeom.p + cap, c->ldest.p + cap, c->lcount.p + 1, (unsigned)cap};
 
-    // far pairs: raw-kernel FFT in the grid, or listed for the surrogate
+    // far pairs: raw-kernel FFT in the grid (those that need the full grid
+    // listed in wf and transformed from the list), or listed for the surrogate
     WorkList wf{c->lgeom.p + 2 * cap, c->ldest.p + 2 * cap, c->lcount.p + 2, (unsigned)cap};
     Timer t_far(c->stream);
-    if (use_sg)
+    if (use_sg) {
       launch_grid_classify(nd, c->cp, wf, ws, wd, c->stream);
-    else
-      launch_grid_far(c->nt_far, nd, c->cp, c->k1, c->k2, c->tw_far.p, c->A.p, ms, m0, nd.W, ws, wd, c->stream);
+    } else {
+      ClassParams cpg = c->cp;
+      cpg.nt_small = c->nt_small;
+      launch_grid_far(nd, cpg, c->k1, c->k2, c->nt_small < c->nt_far ? c->tw_small.p : c->tw_far.p, c->A.p, ms,
+                      m0, nd.W, ws, wd, wf, c->stream);
+    }
     HIPCHK(hipGetLastError());
     unsigned counts[3] = {0, 0, 0};
     HIPCHK(hipMemcpy(counts, c->lcount.p, 3 * sizeof(unsigned), hipMemcpyDeviceToHost));
@@ -637,7 +650,15 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
       return fail(c, PMLBIE_EDEVICE, "build: work list overflow");
     c->counters[4] = 0;
     c->counters[5] = 0;
-    if (use_sg) run_surrogate(c, wf.geom, wf.dest, counts[2], n2, ms, nd.W);
+    c->cnt_far_big = use_sg ? 0 : counts[2];
+    c->counters[6] = (double)c->cnt_far_big;
+    if (use_sg) {
+      run_surrogate(c, wf.geom, wf.dest, counts[2], n2, ms, nd.W);
+    } else if (counts[2] > 0) {
+      launch_list_far(c->nt_far, wf.geom, wf.dest, 0, counts[2], M, m0, c->k1, c->k2, c->tw_far.p, c->A.p, n2, ms,
+                      nd.W, nullptr, &c->cp, c->stream);
+      HIPCHK(hipGetLastError());
+    }
     c->stage_ms[1] = t_far.stop();
     c->cnt_split = counts[0];
     c->cnt_direct = counts[1];
@@ -666,7 +687,9 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     // the near-panel pairs of the grid were not counted as far
     c->cnt_far -= 16LL * (long long)ajobs.size();
     if (c->zc_mode >= m0 && c->zc_mode <= M) {
-      launch_zero_column(c->A.p + (size_t)(c->zc_mode - m0) * ms, n2, c->zc_col, c->stream);
+      // the hook's column is in block order: u1 of node c, or phi1 of node c - N
+      const int col = c->zc_col < N ? 2 * c->zc_col : 2 * (c->zc_col - N) + 1;
+      launch_zero_column(c->A.p + (size_t)(c->zc_mode - m0) * ms, n2, col, c->stream);
       HIPCHK(hipGetLastError());
     }
     c->zc_mode = c->zc_col = -1;
@@ -679,10 +702,10 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
       c->Alow.release();
     } else {
       c->A32.release();
+      // the lower-medium equations are the odd rows of the interleaved system
       c->Alow.alloc((size_t)nm * N * n2);
-      for (int n = 0; n < nm; ++n)
-        HIPCHK(hipMemcpyAsync(c->Alow.p + (size_t)n * N * n2, c->A.p + (size_t)n * ms + (size_t)N * n2,
-                              (size_t)N * n2 * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpy2DAsync(c->Alow.p, (size_t)n2 * sizeof(zd), c->A.p + n2, 2 * (size_t)n2 * sizeof(zd),
+                              (size_t)n2 * sizeof(zd), (size_t)nm * N, hipMemcpyDeviceToDevice, c->stream));
     }
     if ((flags & PMLBIE_KEEP_OPERATORS) && !mixed) {
       c->Akeep.alloc((size_t)nm * ms);
@@ -741,7 +764,8 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     for (int n = 0; n < nm; ++n)
       if (info[n])
         return fail(c, PMLBIE_ESINGULAR,
-                    "build: mode " + std::to_string(m0 + n) + " has a zero pivot at column " + std::to_string(info[n] - 1));
+                    "build: mode " + std::to_string(m0 + n) + " has a zero pivot at column " +
+                        std::to_string((info[n] - 1) % 2 == 0 ? (info[n] - 1) / 2 : N + (info[n] - 1) / 2));
     c->stage_ms[10] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_all).count();
     c->stage = 3;
     return PMLBIE_OK;
@@ -847,9 +871,9 @@ int pmlbie_solve_modes(pmlbie_ctx* c, int n_rhs, const pmlbie_incidence* inc, vo
     }
     const bool mixed = c->precision == PMLBIE_MIXED;
     if (mixed)
-      launch_lower_rhs(c->A.p + (size_t)N * n2, ms, N, nm, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+      launch_lower_rhs(c->A.p + n2, ms, 2 * n2, N, nm, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
     else
-      launch_lower_rhs(c->Alow.p, (long)N * n2, N, nm, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
+      launch_lower_rhs(c->Alow.p, (long)N * n2, n2, N, nm, n_rhs, c->b1.p, c->b2.p, c->x.p, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[8] = t_rhs.stop();
     Timer t_sol(c->stream);
@@ -1131,8 +1155,9 @@ int pmlbie_get_operator(pmlbie_ctx* c, int mode, void* d_out) {
     if (!src) return fail(c, PMLBIE_ESTATE, "get_operator: build with PMLBIE_KEEP_OPERATORS");
     if (mode < c->m0 || mode > c->M || !d_out) return fail(c, PMLBIE_EINVAL, "get_operator: mode outside the build");
     const size_t ms = (size_t)4 * c->N * c->N;
-    HIPCHK(hipMemcpyAsync(d_out, src + (size_t)(mode - c->m0) * ms, ms * sizeof(zd), hipMemcpyDeviceToDevice,
-                          c->stream));
+    // stored interleaved (node by node); returned in the block order of the ABI
+    launch_deinterleave(src + (size_t)(mode - c->m0) * ms, 2L * c->N, (zd*)d_out, c->stream);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;
   });

@@ -16,6 +16,7 @@
 // just before using that panel's columns of L, which are stored in the row
 // order that was current when the panel was factored.
 #include "lu.h"
+#include "rows16.h"
 
 namespace pmlbie {
 
@@ -694,55 +695,35 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
   for (int e = tid; e < nb * nrhs; e += 256) b[(long)(e / nb) * n + k0 + e % nb] = yb[e % nb][e / nb];
 }
 
-// rows [r0, r1) of b -= A[rows][k0 .. k0+nb) * b[k0 .. k0+nb); a wavefront
-// per 4 rows (all four rows' loads in flight together), lanes over the panel
-// columns; grid (row blocks of 16, matrices).
+// rows [r0, r1) of b -= A[rows][k0 .. k0+nb) * b[k0 .. k0+nb) for every
+// right-hand side: 64 rows per workgroup, LDS-staged tiles, lane per row
+// (rows16.h); grid (row blocks of 64, matrices).
 template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ A, long ms, int n,
                                                       int k0, int nb, cx<TB>* __restrict__ B,
                                                       int nrhs, int r0, int r1) {
   const cx<T>* a = A + (long)blockIdx.y * ms;
   cx<TB>* b = B + (long)blockIdx.y * nrhs * n;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  __shared__ cx<TB> yb[LU_MAX_RHS][LU_NB];
-  for (int e = tid; e < nb * nrhs; e += 256) yb[e / nb][e % nb] = b[(long)(e / nb) * n + k0 + e % nb];
-  __syncthreads();
-  constexpr int RW = 4, NC = LU_NB / 64;
-  const int rb = r0 + blockIdx.x * 16 + wid * RW;
-  if (rb >= r1) return;
-  // unconditional loads: rows past r1 re-read row r1 - 1, columns past nb
-  // re-read column nb - 1 (their products are dropped below)
-  cx<T> lv[RW][NC];
+  const int rbase = r0 + blockIdx.x * R16_ROWS;
+  zd acc[4];
+  bool ow;
+  int og;
+  rows16_acc<T>(a, n, rbase, r1, k0, k0 + nb, nrhs,
+                [&](int s2, int c) {
+                  const cx<TB> v = b[(long)s2 * n + c];
+                  return zd{(double)v.re, (double)v.im};
+                },
+                acc, ow, og);
+  const int lane = threadIdx.x & 63;
+  const int row = rbase + lane;
+  if (row >= r1 || !ow) return;
 #pragma unroll
-  for (int q = 0; q < RW; ++q) {
-    const cx<T>* row = a + (long)min(rb + q, r1 - 1) * n + k0;
-#pragma unroll
-    for (int t = 0; t < NC; ++t) lv[q][t] = row[min(lane + 64 * t, nb - 1)];
-  }
-  for (int s = 0; s < nrhs; ++s) {
-    cx<TB> acc[RW];
-#pragma unroll
-    for (int q = 0; q < RW; ++q) acc[q] = cx<TB>{TB(0), TB(0)};
-#pragma unroll
-    for (int t = 0; t < NC; ++t) {
-      const int j = lane + 64 * t;
-      if (j < nb) {
-        const cx<TB> y = yb[s][j];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) acc[q] = acc[q] + cx<TB>{(TB)lv[q][t].re, (TB)lv[q][t].im} * y;
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int s2 = 4 * og + q;
+    if (s2 < nrhs) {
+      cx<TB>& o = b[(long)s2 * n + row];
+      o = cx<TB>{o.re - (TB)acc[q].re, o.im - (TB)acc[q].im};
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-      for (int q = 0; q < RW; ++q) {
-        acc[q].re += __shfl_xor(acc[q].re, off);
-        acc[q].im += __shfl_xor(acc[q].im, off);
-      }
-    if (lane == 0)
-#pragma unroll
-      for (int q = 0; q < RW; ++q)
-        if (rb + q < r1) b[(long)s * n + rb + q] = b[(long)s * n + rb + q] - acc[q];
   }
 }
 
@@ -820,16 +801,16 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
                        B, nrhs, 0);
     const int r0 = k0 + nb, r1 = n;
     if (r1 > r0)
-      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((r1 - r0 + 15) / 16, batch), dim3(256), 0, st,
-                         A, ms, n, k0, nb, B, nrhs, r0, r1);
+      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((r1 - r0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0,
+                         st, A, ms, n, k0, nb, B, nrhs, r0, r1);
   }
   for (int k0 = ((n - 1) / LU_NB) * LU_NB; k0 >= 0; k0 -= LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
     hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
                        B, nrhs, 1);
     if (k0 > 0)
-      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((k0 + 15) / 16, batch), dim3(256), 0, st, A, ms,
-                         n, k0, nb, B, nrhs, 0, k0);
+      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((k0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0, st,
+                         A, ms, n, k0, nb, B, nrhs, 0, k0);
   }
 }
 

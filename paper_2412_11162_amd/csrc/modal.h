@@ -7,7 +7,9 @@
 
 namespace pmlbie {
 
-enum { CLASS_FAR = 0, CLASS_SPLIT = 1, CLASS_DIRECT = 2 };
+// CLASS_FAR_BIG: a far pair whose aliasing bound holds on the full angle grid
+// but not on the shorter grid the main pass runs on (see ClassParams.nt_small).
+enum { CLASS_FAR = 0, CLASS_SPLIT = 1, CLASS_DIRECT = 2, CLASS_FAR_BIG = 3 };
 
 // Node tables of the Nystrom discretisation, structure of arrays on the device.
 struct NodesDev {
@@ -26,6 +28,10 @@ struct ClassParams {
   double kmax_im; // max |Im k|
   double c_far;   // far if (nt_far - M - B) * delta >= c_far
   double g_split; // split if max |Im kR| <= g_split, else direct quadrature
+  // > 0 and < nt_far: the main pass transforms far pairs on this shorter grid
+  // when their aliasing bound holds there, and classes the other far pairs
+  // CLASS_FAR_BIG (transformed on the full grid from a list)
+  int nt_small = 0;
 };
 
 // Device work list of pairs handed from the classifier to the split and
@@ -54,9 +60,12 @@ struct NearJob {
 
 // The main grid over all node pairs off the near panels: far pairs are
 // transformed in place, split and direct pairs appended to their lists.
-void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
+// The pass runs on the grid of cp.nt_small when it is set (tw its
+// twiddles), on cp.nt_far otherwise; far pairs that need the full grid go to
+// far_big.
+void launch_grid_far(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
                      const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
-                     WorkList direct, hipStream_t st);
+                     WorkList direct, WorkList far_big, hipStream_t st);
 // Classification only (surrogate path): far / split / direct lists with
 // destinations (i, l).
 void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,

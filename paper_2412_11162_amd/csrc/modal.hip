@@ -19,12 +19,11 @@ __device__ __forceinline__ void emit_val(const OutSpec& o, int2 dst, int s, int 
                                          zd val) {
   if (dst.y >= 0) {
     if (n < o.m0) return;
-    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
+    const long i = dst.x, l = dst.y;
     const double w2 = 2.0 * o.W[l] * scale;
-    // S blocks carry the minus sign of [[K1 + I, -S1], [K2 - I, -S2]]
+    // S entries carry the minus sign of [[K1 + I, -S1], [K2 - I, -S2]]
     const double f = (s & 1) ? w2 : -w2;
-    const long row = (s < 2 ? i : N + i), col = ((s & 1) ? l : N + l);
-    o.A[(long)(n - o.m0) * o.mstride + row * o.n2 + col] = f * val;
+    o.A[(long)(n - o.m0) * o.mstride + sys_offset(o.n2, i, l, s)] = f * val;
   } else {
     o.raw[(long)dst.x * 4 * (o.M + 1) + (long)s * (o.M + 1) + n] = scale * val;
   }
@@ -179,12 +178,13 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
 }
 
 // Main grid: every (target i, source l) pair off the near panels.  Far pairs
-// are finished here (raw-kernel FFT over theta); the others are appended to
-// the split / direct work lists.  One wavefront per pair.
+// are finished here (raw-kernel FFT over theta on this pass's grid of 64 R
+// angles); the others are appended to the split / direct work lists, and far
+// pairs that need a longer grid to the far_big list.  One wavefront per pair.
 template <int R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
-                                                 WorkList split, WorkList direct) {
+                                                 WorkList split, WorkList direct, WorkList far_big) {
   __shared__ zd lds[far_lds<R>()];
   const int N = nd.N;
   const long total = (long)N * N;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int cls = classify(g, v, cp, &coarse);
     if (cls != CLASS_FAR) {
       if (threadIdx.x == 0) {
-        WorkList& wl = cls == CLASS_SPLIT ? split : direct;
+        WorkList& wl = cls == CLASS_SPLIT ? split : (cls == CLASS_DIRECT ? direct : far_big);
         unsigned slot = atomicAdd(wl.count, 1u);
         if (slot < wl.cap) {
           wl.geom[slot] = g;
@@ -650,7 +650,6 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
   const int jb = blockIdx.x;
   if (jb >= njobs) return;
   const NearJob J = jobs[jb];
-  const long N = o.n2 >> 1;
   const int tot = 4 * (M + 1);
   // thread -> (sequence s, mode n): each raw value is read once per job and
   // weighted by the 16 Lagrange coefficients of its auxiliary point
@@ -667,16 +666,15 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
     }
     if (n < o.m0) continue;
     const long i = J.target;
-    const long row = sq < 2 ? i : N + i;
-    const long col0 = (sq & 1) ? 0 : N;
-    zd* dst = o.A + (long)(n - o.m0) * o.mstride + row * o.n2 + col0 + (long)J.panel * 16;
-    // K blocks carry the identity term, S blocks the minus sign
+    zd* An = o.A + (long)(n - o.m0) * o.mstride;
+    // K entries carry the identity term, S entries the minus sign
     const double diag = sq == 1 ? 1.0 : (sq == 3 ? -1.0 : 0.0);
 #pragma unroll
     for (int l = 0; l < 16; ++l) {
+      const long src = (long)J.panel * 16 + l;
       zd v = (sq & 1) ? acc[l] : -1.0 * acc[l];
-      if ((long)J.panel * 16 + l == i) v.re += diag;
-      dst[l] = v;
+      if (src == i) v.re += diag;
+      An[sys_offset(o.n2, i, src, sq)] = v;
     }
   }
 }
@@ -790,21 +788,22 @@ __global__ __launch_bounds__(64) void k_rhs_plane(const double* __restrict__ rho
 // Host launchers.
 template <int R>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
-                         const OutSpec& o, WorkList split, WorkList direct, hipStream_t st) {
+                         const OutSpec& o, WorkList split, WorkList direct, WorkList far_big, hipStream_t st) {
   long total = (long)nd.N * nd.N;
   int grid = (int)std::min<long>((total + 7) / 8 * 8, 256L * 128);  // a multiple of 8
   hipLaunchKernelGGL(k_grid_far<R>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
-                     direct);
+                     direct, far_big);
 }
 
-void launch_grid_far(int nt, const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
+void launch_grid_far(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
                      const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
-                     WorkList direct, hipStream_t st) {
+                     WorkList direct, WorkList far_big, hipStream_t st) {
   OutSpec o{A, 2L * nd.N, mstride, W, nullptr, cp.M, m0};
+  const int nt = (cp.nt_small > 0 && cp.nt_small < cp.nt_far) ? cp.nt_small : cp.nt_far;
   switch (nt) {
-    case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, st); break;
-    case 2048: launch_far_t<32>(nd, cp, k1, k2, tw, o, split, direct, st); break;
+    case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, far_big, st); break;
+    case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, far_big, st); break;
+    case 2048: launch_far_t<32>(nd, cp, k1, k2, tw, o, split, direct, far_big, st); break;
     default: break;
   }
 }

@@ -7,9 +7,16 @@ namespace pmlbie {
 
 // Output: either the per-mode system matrices or a raw modal buffer.
 //
-// System matrix of mode n, row-major 2N x 2N at A + (n - m0) * mstride:
-//   [[K1 - D1, -S1], [K2 - D2, -S2]],  K_il = 2 W_l K_n(r_i, r_l),
-//   S_il = 2 W_l S_n(r_i, r_l) for l off the near panels of i.
+// System matrix of mode n, row-major 2N x 2N at A + (n - m0) * mstride, with
+// the unknowns and equations of each node interleaved: unknown 2l is u1 at
+// node l and 2l + 1 is phi1 there; equation 2i is the upper medium's at node
+// i and 2i + 1 the lower medium's.  The 2 x 2 block of a pair (i, l) is
+//   [[K1_il - D1_il, -S1_il], [K2_il - D2_il, -S2_il]],
+//   K_il = 2 W_l K_n(r_i, r_l), S_il = 2 W_l S_n(r_i, r_l),
+// i.e. the system [[K1 - D1, -S1], [K2 - D2, -S2]] with rows and columns
+// permuted symmetrically.  A pair's two entries of one equation are adjacent
+// (32 bytes, one aligned sector), so the scattered per-pair mode writes of
+// the far, split and direct paths fill whole sectors.
 // Raw modal buffer: out[q][s][n], s in {S1, K1, S2, K2}.
 struct OutSpec {
   zd* A;
@@ -21,17 +28,25 @@ struct OutSpec {
   int m0;        // first mode kept in A (A + (n - m0) * mstride holds mode n)
 };
 
+// Element offset of sequence s (S1, K1, S2, K2) of pair (i, l) in a mode's
+// interleaved matrix: equation 2i (+1 for the lower medium), unknown 2l for
+// a K entry, 2l + 1 for an S entry.
+__device__ __forceinline__ long sys_offset(long n2, long i, long l, int s) {
+  return (2 * i + (s >> 1)) * n2 + 2 * l + ((s & 1) ? 0 : 1);
+}
+
 __device__ __forceinline__ void emit(const OutSpec& o, int2 dst, int n, zd S1, zd K1, zd S2,
                                      zd K2) {
   if (dst.y >= 0) {
     if (n < o.m0) return;
-    const long i = dst.x, l = dst.y, N = o.n2 >> 1;
+    const long i = dst.x, l = dst.y;
     const double w2 = 2.0 * o.W[l];
     zd* An = o.A + (long)(n - o.m0) * o.mstride;
-    An[i * o.n2 + l] = w2 * K1;
-    An[i * o.n2 + N + l] = (-w2) * S1;
-    An[(N + i) * o.n2 + l] = w2 * K2;
-    An[(N + i) * o.n2 + N + l] = (-w2) * S2;
+    zd* up = An + 2 * i * o.n2 + 2 * l;
+    up[0] = w2 * K1;
+    up[1] = (-w2) * S1;
+    up[o.n2] = w2 * K2;
+    up[o.n2 + 1] = (-w2) * S2;
   } else {
     zd* r = o.raw + (long)dst.x * 4 * (o.M + 1);
     r[n] = S1;
@@ -83,7 +98,9 @@ __device__ __forceinline__ int bitrev(int j) {
 // kernel; close pairs by the split; close pairs deep in the PML by graded
 // direct quadrature, where cos(kR) grows like exp(max |Im kR|)).
 // A far pair is also marked coarse when the same aliasing bound holds on the
-// grid of half the length (its modes beyond L/2 - M are as negligible).
+// grid of half the length (its modes beyond L/2 - M are as negligible).  With
+// cp.nt_small set, far pairs are judged on that shorter grid first (the main
+// pass's grid) and the ones that need the full grid are CLASS_FAR_BIG.
 __device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, const ClassParams& cp,
                                         bool* coarse = nullptr) {
   double delta, re0;
@@ -91,7 +108,12 @@ __device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, con
   const double sc = sqrt(cabs_(g.rt * g.rs));
   const double bw = cp.bw * cp.kmax * sc;
   if ((cp.nt_far - cp.M - bw) * delta >= cp.c_far) {
-    if (coarse) *coarse = (cp.nt_far / 2 - cp.M - bw) * delta >= cp.c_far;
+    int nt = cp.nt_far;
+    if (cp.nt_small > 0 && cp.nt_small < cp.nt_far) {
+      if ((cp.nt_small - cp.M - bw) * delta < cp.c_far) return CLASS_FAR_BIG;
+      nt = cp.nt_small;
+    }
+    if (coarse) *coarse = (nt / 2 - cp.M - bw) * delta >= cp.c_far;
     return CLASS_FAR;
   }
   zd Rpi = csqrt_(v.d2 + v.c4);

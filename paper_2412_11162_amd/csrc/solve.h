@@ -8,8 +8,13 @@ namespace pmlbie {
 
 void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int M, int m0, int nrhs,
                              zd* b1, zd* b2, hipStream_t st);
-void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
+// Interleaved system (equation 2i / 2i + 1 = upper / lower medium at node i,
+// unknown 2l / 2l + 1 = u1 / phi1 at node l).  Right-hand sides from the
+// lower-medium equations: row i of mode n at Alow + n * lstride + i * rstride.
+void launch_lower_rhs(const zd* Alow, long lstride, long rstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st);
+// One mode's interleaved matrix copied out in the block order [[K1 + I, -S1], [K2 - I, -S2]].
+void launch_deinterleave(const zd* A, long n2, zd* out, hipStream_t st);
 void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,
                     zd* u2, zd* p2, hipStream_t st);
 void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st);

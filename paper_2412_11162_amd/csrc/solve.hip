@@ -1,5 +1,6 @@
 // Right-hand sides, coupled-system data flow and field synthesis (Sec. 4.2).
 #include "solve.h"
+#include "rows16.h"
 
 namespace pmlbie {
 
@@ -25,38 +26,42 @@ __global__ void k_rhs_gather_point(const zd* __restrict__ raw, const int* __rest
   b2[o] = -raw[q2 * 4 * (M + 1) + (M + 1) + n];
 }
 
-// rhs[n][r] = [0 ; Alow_n [b1; b2]], Alow_n = [K2 - D2, -S2] (N x 2N, row-major):
-// one wavefront per row, lanes over the columns.
-__global__ __launch_bounds__(256) void k_lower_rhs(const zd* __restrict__ Alow, long lstride,
+// Right-hand sides of the interleaved system (equation 2i upper medium,
+// 2i + 1 lower medium; unknown 2l = u1, 2l + 1 = phi1 at node l):
+// rhs[2i] = 0, rhs[2i + 1] = sum_l Alow_i(2l) b1_l + Alow_i(2l + 1) b2_l, where
+// Alow_i is the lower-medium equation [K2 - D2, -S2] of node i (row i of
+// Alow at Alow + n * lstride + i * rstride).  64 rows per workgroup, every
+// right-hand side at once (rows16.h); grid (row blocks, modes).
+__global__ __launch_bounds__(256) void k_lower_rhs(const zd* __restrict__ Alow, long lstride, long rstride,
                                                    int N, int nrhs, const zd* __restrict__ b1,
                                                    const zd* __restrict__ b2, zd* __restrict__ rhs) {
   const int n = blockIdx.y;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= N) return;
-  const zd* row = Alow + (long)n * lstride + (long)i * 2 * N;
+  const zd* a = Alow + (long)n * lstride;
   const zd* x1 = b1 + (long)n * nrhs * N;
   const zd* x2 = b2 + (long)n * nrhs * N;
   zd* out = rhs + (long)n * nrhs * 2 * N;
-  for (int r = 0; r < nrhs; ++r) {
-    zd acc{0.0, 0.0};
-    for (int c = lane; c < 2 * N; c += 64) {
-      const zd xv = c < N ? x1[(long)r * N + c] : x2[(long)r * N + c - N];
-      acc = cfma(row[c], xv, acc);
-    }
-    for (int off = 32; off >= 1; off >>= 1) {
-      acc.re += __shfl_xor(acc.re, off);
-      acc.im += __shfl_xor(acc.im, off);
-    }
-    if (lane == 0) {
-      out[(long)r * 2 * N + i] = zd{0.0, 0.0};
-      out[(long)r * 2 * N + N + i] = acc;
+  const int rbase = blockIdx.x * R16_ROWS;
+  zd acc[4];
+  bool ow;
+  int og;
+  rows16_acc<double>(a, rstride, rbase, N, 0, 2 * N, nrhs,
+                     [&](int s, int c) { return (c & 1) ? x2[(long)s * N + (c >> 1)] : x1[(long)s * N + (c >> 1)]; },
+                     acc, ow, og);
+  const int lane = threadIdx.x & 63;
+  const int i = rbase + lane;
+  if (i >= N || !ow) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int s = 4 * og + q;
+    if (s < nrhs) {
+      out[(long)s * 2 * N + 2 * i] = zd{0.0, 0.0};
+      out[(long)s * 2 * N + 2 * i + 1] = acc[q];
     }
   }
 }
 
-// u1 = x[0:N], phi1 = x[N:2N], u2 = u1 - b1, phi2 = phi1 - b2 (transmission
-// conditions), layout [mode][rhs][node].
+// u1 = x[2i], phi1 = x[2i + 1] (interleaved unknowns), u2 = u1 - b1,
+// phi2 = phi1 - b2 (transmission conditions), layout [mode][rhs][node].
 __global__ void k_outputs(const zd* __restrict__ x, const zd* __restrict__ b1,
                           const zd* __restrict__ b2, int N, int M, int nrhs, zd* __restrict__ u1,
                           zd* __restrict__ p1, zd* __restrict__ u2, zd* __restrict__ p2) {
@@ -65,11 +70,24 @@ __global__ void k_outputs(const zd* __restrict__ x, const zd* __restrict__ b1,
   if (e >= tot) return;
   const int i = (int)(e % N);
   const long nr = e / N;  // mode * nrhs + r
-  const zd xu = x[nr * 2 * N + i], xp = x[nr * 2 * N + N + i];
+  const zd xu = x[nr * 2 * N + 2 * i], xp = x[nr * 2 * N + 2 * i + 1];
   if (u1) u1[e] = xu;
   if (p1) p1[e] = xp;
   if (u2) u2[e] = xu - b1[e];
   if (p2) p2[e] = xp - b2[e];
+}
+
+// The interleaved system of one mode in the block order of the C ABI:
+// out[R][C] with R, C < N the upper-medium equation / u1 unknown of node R, C
+// and R, C >= N the lower-medium equation / phi1 unknown of node R - N, C - N.
+__global__ void k_deinterleave(const zd* __restrict__ A, long n2, zd* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n2 * n2) return;
+  const long N = n2 >> 1;
+  const long R = e / n2, C = e % n2;
+  const long r = R < N ? 2 * R : 2 * (R - N) + 1;
+  const long c = C < N ? 2 * C : 2 * (C - N) + 1;
+  out[e] = A[r * n2 + c];
 }
 
 // Field modes by the Green representation (Sec. 4.2, eq. eqfujs) and the
@@ -142,40 +160,30 @@ __global__ void k_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, long 
 }
 
 // Residual of the FP64 systems: r = rhs - A x for all modes and right-hand
-// sides (A row-major 2N x 2N per mode), one wavefront per row; the row is read
-// once and multiplied into every right-hand side; rs2 receives |r_i|^2 for
-// the convergence test.
+// sides (A row-major n x n per mode), 64 rows per workgroup with every
+// right-hand side at once (rows16.h: A read once, lane per row); rs2 receives
+// |r_i|^2 for the convergence test.  Grid (row blocks, modes).
 __global__ __launch_bounds__(256) void k_residual(const zd* __restrict__ A, long ms, int n,
                                                   int nrhs, const zd* __restrict__ x,
                                                   const zd* __restrict__ rhs, zd* __restrict__ r,
                                                   double* __restrict__ rs2) {
   const int md = blockIdx.y;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const zd* row = A + (long)md * ms + (long)i * n;
+  const zd* a = A + (long)md * ms;
   const zd* xm = x + (long)md * nrhs * n;
-  zd acc[LU_MAX_RHS];
+  const int rbase = blockIdx.x * R16_ROWS;
+  zd acc[4];
+  bool ow;
+  int og;
+  rows16_acc<double>(a, n, rbase, n, 0, n, nrhs, [&](int s, int c) { return xm[(long)s * n + c]; }, acc, ow, og);
+  const int lane = threadIdx.x & 63;
+  const int i = rbase + lane;
+  if (i >= n || !ow) return;
 #pragma unroll
-  for (int s = 0; s < LU_MAX_RHS; ++s) acc[s] = zd{0.0, 0.0};
-  for (int c = lane; c < n; c += 64) {
-    const zd a = row[c];
-#pragma unroll
-    for (int s = 0; s < LU_MAX_RHS; ++s)
-      if (s < nrhs) acc[s] = cfma(a, xm[(long)s * n + c], acc[s]);
-  }
-#pragma unroll
-  for (int s = 0; s < LU_MAX_RHS; ++s) {
-    if (s >= nrhs) continue;
-    zd v = acc[s];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      v.re += __shfl_xor(v.re, off);
-      v.im += __shfl_xor(v.im, off);
-    }
-    if (lane == 0) {
+  for (int q = 0; q < 4; ++q) {
+    const int s = 4 * og + q;
+    if (s < nrhs) {
       const long e = ((long)md * nrhs + s) * n + i;
-      const zd d = rhs[e] - v;
+      const zd d = rhs[e] - acc[q];
       r[e] = d;
       rs2[e] = abs2(d);
     }
@@ -232,8 +240,8 @@ void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st) {
 }
 void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd* x, const zd* rhs,
                      zd* r, double* rs2, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3((n + 3) / 4, modes), dim3(256), 0, st, A, ms, n, nrhs, x, rhs, r,
-                     rs2);
+  hipLaunchKernelGGL(k_residual, dim3((n + R16_ROWS - 1) / R16_ROWS, modes), dim3(256), 0, st, A, ms, n, nrhs,
+                     x, rhs, r, rs2);
 }
 void launch_sumsq(const double* sq, int n, int nvec, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sumsq, dim3(nvec), dim3(256), 0, st, sq, n, out);
@@ -251,10 +259,14 @@ void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int
   hipLaunchKernelGGL(k_rhs_gather_point, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, raw,
                      rmap, npt, N, M, m0, nrhs, b1, b2);
 }
-void launch_lower_rhs(const zd* Alow, long lstride, int N, int modes, int nrhs, const zd* b1,
+void launch_lower_rhs(const zd* Alow, long lstride, long rstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_lower_rhs, dim3((N + 3) / 4, modes), dim3(256), 0, st, Alow, lstride, N,
-                     nrhs, b1, b2, rhs);
+  hipLaunchKernelGGL(k_lower_rhs, dim3((N + R16_ROWS - 1) / R16_ROWS, modes), dim3(256), 0, st, Alow, lstride,
+                     rstride, N, nrhs, b1, b2, rhs);
+}
+void launch_deinterleave(const zd* A, long n2, zd* out, hipStream_t st) {
+  const long tot = n2 * n2;
+  hipLaunchKernelGGL(k_deinterleave, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, n2, out);
 }
 void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,
                     zd* u2, zd* p2, hipStream_t st) {
