@@ -346,7 +346,13 @@ static void pair_integrand(double D, void *vctx, cplx *out) {
     Kv[ik] = N * e * (ikR - 1.0) / (4.0 * M_PI * R * R2);
   }
   for (int j = 0; j < p->nmode; ++j) {
-    double cn = 2.0 * cos(p->modes[j] * D);
+    /* cos(n D) with the rounding of the product n D compensated: n D = a + b
+       exactly (b by a fused multiply-add), cos(a + b) = cos a - b sin a to
+       O(b^2); plain cos(n D) would carry an absolute error ~ n D eps, ~1e-13
+       at n = 256, D ~ pi, above the quadrature's stopping floor */
+    const double nn = (double)p->modes[j];
+    const double a = nn * D, b = fma(nn, D, -a);
+    double cn = 2.0 * (cos(a) - b * sin(a));
     for (int ik = 0; ik < p->nk; ++ik) {
       out[(2 * ik) * p->nmode + j] = cn * Gv[ik];
       out[(2 * ik + 1) * p->nmode + j] = cn * Kv[ik];
