@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X PML-BIE hot path.
 
-One step = the whole hot path on the paper-scale workload (k1 = 10, k2 = 15,
-h = 0.5 exp(-rho^2/2) cos(2 rho), PML rho in [4, 5.5], sigma0 = 3,
-2048 curve nodes, 256 azimuthal samples with modes 0..128 kept, point source at
-(0.3, 0, 1.2)): geometry and media set-up, pair x theta sampling of the
-kernels, far / split / direct modal kernels, near-panel product integration,
-assembly, per-mode LU of the 129 systems of size 4096, right-hand sides and
-solves.  Prints one JSON line.
+Headline (the default): the largest one-GPU configuration in its combined
+form -- k1 = 20, k2 = 30, three Gaussian ring bumps (seed 11162), PML
+rho in [5, 7] with S = 3, 4096 curve nodes (8192 unknowns per mode), modes
+0..256 from a 512-sample azimuthal grid, 16 plane waves as right-hand sides,
+complex64 LU on the matrix cores with FP64 iterative refinement to a relative
+residual of 1e-10.  One step = geometry and media set-up, pair x theta
+sampling, far / split / direct modal kernels, near-panel product
+integration, assembly, per-mode LU of all 257 systems, right-hand sides,
+solves and refinement; the FP64 operators of all modes (276 GB) do not fit
+beside the factors, so the modes are built, factored and solved in batches.
+Extra legs (outside the timed steps): the paper-scale workload in FP64 and
+mixed precision, the field synthesis, the learned surrogate, and the FP64
+CPU oracle on a bounded sample.  Prints one JSON line.
 """
 
 import argparse
@@ -24,76 +30,138 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def gemm_traffic_record():
-    """HBM bytes per launch of the trailing-update kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
-    since the counters were taken (the record carries a digest of it)."""
+def gemm_traffic_record(profile: str, kernel: str):
+    """HBM bytes per launch of the trailing-update kernel from a committed
+    rocprofv3 counter summary (profiles/<profile>.md), or None when the kernel
+    source has changed since the counters were taken (the record carries a
+    digest of it)."""
     src = open(os.path.join(ROOT, "paper_2412_11162_amd", "csrc", "lu.hip")).read()
     a = src.index("void k_gemm_update(")
     digest = hashlib.sha256(src[a:src.index("\n}\n", a)].encode()).hexdigest()[:16]
-    path = os.path.join(ROOT, "profiles", "k_gemm_update_paper_scale.md")
+    path = os.path.join(ROOT, "profiles", profile + ".md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         if line.strip().startswith("traffic-record"):
             kv = dict(t.split("=", 1) for t in line.split()[1:])
-            if kv.get("source_sha256_16") == digest:
+            if kv.get("kernel") == kernel and kv.get("source_sha256_16") == digest:
                 return float(kv["hbm_bytes_per_launch"])
     return None
 
 
-def largest_run(s, wl, steps: int, warmup: int, batch: int = 86):
+def set_curve(s, wl):
+    if wl.curve_nodes is not None:
+        s.set_panels(wl.curve_nodes)
+    elif wl.polyline:
+        s.set_polyline(wl.polyline, wl.panels, wl.grade)
+    else:
+        s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
+    s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
+
+
+def largest_leg(s, wl, steps: int, warmup: int, batch: int = 129):
     """The largest one-GPU configuration (4096 nodes, modes 0..256, 16 plane
-    waves) in mixed precision: its operators do not fit at once (276 GB in
-    FP64), so each step builds, factors and solves the modes in three batches
-    of up to 86 (FP64 operators for the residuals, complex64 factors and
-    work space, ~170 GB per batch; every batch samples all pairs and keeps
-    its modes).  Time to solution of
-    all modes and right-hand sides; the refinement residual of every batch
-    is held to 1e-10 by the library."""
+    waves) in mixed precision.  Its FP64 operators do not fit beside the
+    factors (276 GB for all modes), so each step builds, factors and solves
+    the modes in two batches (129 + 128 modes: FP64 operators for the
+    refinement residuals, complex64 factors, ~235 GB per batch).  Every batch
+    samples all pairs and keeps its modes.  Time to solution of all modes and
+    right-hand sides; the library holds every batch's refinement to a relative
+    residual of 1e-10."""
     import torch
 
     def one():
-        s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
-        s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
-        res, its, stages = [], [], []
+        set_curve(s, wl)
+        res, its, stages, cnts = [], [], [], []
         for lo in range(0, wl.m_max + 1, batch):
             hi = min(wl.m_max, lo + batch - 1)
             s.build_modal_operators(wl.n_theta, hi, 1, 0, m_min=lo)
+            st_b, cnt_b = s.stats()
             s.solve_modes(list(wl.incidences))
             st, cnt = s.stats()
             res.append(float(cnt[1]))
             its.append(int(cnt[0]))
             stages.append(st.copy())
-            print("modes %d..%d done" % (lo, hi), file=sys.stderr, flush=True)
-        return res, its, stages
+            cnts.append(cnt_b.copy())
+        return res, its, stages, cnts
+
+    for k in range(warmup):
+        one()
+        print("largest warmup step %d done" % k, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_all = time.time()
+    for k in range(steps):
+        t0 = time.time()
+        res, its, stages, cnts = one()
+        torch.cuda.synchronize()
+        print("largest step %d: %.1f ms" % (k, 1e3 * (time.time() - t0)), file=sys.stderr, flush=True)
+    ms_step = 1e3 * (time.time() - t_all) / max(steps, 1)
+    st = np.sum(np.array(stages), axis=0)
+    ct = np.sum(np.array(cnts), axis=0)
+    return {"ms_per_step": ms_step, "stages": st, "gemm_flops": float(ct[2]), "gemm_launches": int(ct[3]),
+            "far_full_grid": int(ct[6]), "residuals": res, "iterations": its, "batch": batch,
+            "N": int(s.info()[0])}
+
+
+def plain_leg(s, wl, steps: int, warmup: int, precision: int):
+    """Whole steps of a workload that fits at once (FP64 or mixed)."""
+    import torch
+
+    def step():
+        set_curve(s, wl)
+        s.build_modal_operators(wl.n_theta, wl.m_max, precision)
+        return s.solve_modes(list(wl.incidences))
 
     for _ in range(warmup):
-        one()
+        step()
     torch.cuda.synchronize()
-    t0 = time.time()
-    for _ in range(steps):
-        res, its, stages = one()
-    torch.cuda.synchronize()
-    ms_step = 1e3 * (time.time() - t0) / max(steps, 1)
-    info = s.info()
-    N = int(info[0])
-    units = 2.0 * N * N * (wl.m_max + 1)
-    st = np.sum(np.array(stages), axis=0)
-    return {"metric": "time-to-solution at 1e-6 rel err vs FP64 oracle; modal-kernel pairs*modes/s",
-            "value": units / (ms_step * 1e-3), "unit": "pairs*modes/s", "n_gpus": 1, "steps": steps,
-            "warmup": warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "c64 LU + f64 refinement", "data": "synthetic",
-            "config": {"workload": wl.name, "nodes": N, "unknowns_per_mode": 2 * N, "modes": wl.m_max + 1,
-                       "n_theta": wl.n_theta, "media": 2, "precision": "mixed",
-                       "incidence": "16 plane waves", "mode_batch": batch},
-            "stage_ms_sum_over_batches": {"far": st[1], "split": st[2], "direct": st[3], "near": st[4],
-                                          "lu": st[5], "solve": st[7], "refinement": st[9]},
-            "refinement": {"max_final_rel_residual": max(res), "iterations": its},
-            "note": "the surrogate covers modes 0..64 only; this configuration keeps modes 0..256"}
+    stages, counts = [], []
+    t_all = time.time()
+    for k in range(steps):
+        t0 = time.time()
+        sol = step()
+        torch.cuda.synchronize()
+        sk, ck = s.stats()
+        stages.append(sk.copy())
+        counts.append(ck.copy())
+        print("%s %s step %d: %.1f ms" % (wl.name, "mixed" if precision else "fp64", k, 1e3 * (time.time() - t0)),
+              file=sys.stderr, flush=True)
+    ms_step = 1e3 * (time.time() - t_all) / max(steps, 1)
+    return ms_step, np.mean(np.array(stages), axis=0), counts[-1], sol
 
 
-def surrogate_leg(s, wl, step, m_max: int = 64, tol: float = 1e-11):
+def stored_oracle_errors(s, name, precision):
+    """Per-mode boundary-data errors against a stored oracle solve
+    (tests/golden/boundary_<name>.npz, written by the oracle), or None when
+    the file is absent.  Same measure as the parity tests."""
+    import workloads
+    path = os.path.join(ROOT, "tests", "golden", "boundary_%s.npz" % name)
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    wl = workloads.ALL[name]()
+    incs = [("point", float(p[0]), float(p[1])) if k == 0 else ("plane", float(p[0]))
+            for k, p in zip(ref["inc_kind"], ref["inc_param"])]
+    set_curve(s, wl)
+    s.build_modal_operators(wl.n_theta, wl.m_max, precision)
+    out = [o.cpu().numpy() for o in s.solve_modes(incs)]
+    modes = [int(m) for m in ref["modes"]]
+    worst = 0.0
+    per_mode = {}
+    for r in range(len(incs)):
+        xg = np.concatenate([o[modes, r, :] for o in out], axis=1)
+        xr = np.concatenate([ref[k][:, r, :] for k in ("u1", "p1", "u2", "p2")], axis=1)
+        big = np.max(np.linalg.norm(xr, axis=1))
+        for j, m in enumerate(modes):
+            nr = np.linalg.norm(xr[j])
+            e = float(np.linalg.norm(xg[j] - xr[j]) / (nr if nr > 1e-9 * big else big))
+            per_mode[m] = max(per_mode.get(m, 0.0), e)
+            worst = max(worst, e)
+    return {"oracle_file": os.path.relpath(path, ROOT), "modes": modes, "right_hand_sides": len(incs),
+            "max_rel_err": worst, "max_rel_err_per_mode": {str(k): v for k, v in per_mode.items()}}
+
+
+def surrogate_leg(s, wl, m_max: int = 64, tol: float = 1e-11):
     """The learned surrogate on this geometry: training on 2^22 labelled
     samples (timed apart, it is amortised over builds), then the step at
     m_max = 64 (the modes the network covers) with and without it; the
@@ -139,27 +207,76 @@ def surrogate_leg(s, wl, step, m_max: int = 64, tol: float = 1e-11):
             "far_stage_ms": float(st[1]), "max_rel_err_vs_fp64": err}
 
 
-def cpu_baseline(wl, seconds: float = 15.0):
-    """The FP64 oracle's modal-kernel stage timed on this host on a bounded
-    sample of (target, source) node pairs of the same workload."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, seconds: float = 15.0, lu_n: int = 1024):
+    """The FP64 oracle on this host, on a bounded sample of the same workload:
+    its modal-kernel stage (adaptive azimuthal quadrature, both media, all
+    modes) on a stratified sample of node pairs -- equal counts from each of
+    the 16 (target segment, source segment) blocks of the curve, weighted by
+    the blocks' pair counts -- and its dense LU (LAPACK through numpy) on one
+    lu_n x lu_n complex system.  The time to solution of the whole workload is
+    extrapolated from them (pairs x time per pair + modes x LU time scaled by
+    (2N / lu_n)^3; the near-panel product integrals are left out, so it is a
+    lower bound) and labelled as such."""
     import oracle
-    import workloads
     g = oracle.geometry(wl)
+    N = g.n
     modes = list(range(wl.m_max + 1))
     ks = [wl.k1, wl.k2]
-    pairs = workloads.seeded_pairs(g.n, 4096, seed=7)
+    seg = np.repeat(np.arange(4), N // 4)
+    rng = np.random.default_rng(2412)
+    per_block = max(2 * oracle.num_threads(), 16)
+    t_pair = 0.0   # estimated seconds of all off-near pairs
     done = 0
     t0 = time.time()
-    chunk = 8 * oracle.num_threads()
-    while time.time() - t0 < seconds and done < len(pairs):
-        oracle.modal_kernels_nodes(g, pairs[done:done + chunk], ks, modes)
-        done += chunk
-    dt = time.time() - t0
-    units = done * len(ks) * len(modes)
-    return {"value": units / dt, "unit": "pairs*modes/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d random node pairs of the %s workload, both media, modes 0..%d, "
-                      "adaptive azimuthal quadrature (%.1f s)" % (done, wl.name, wl.m_max, dt)}
+    for si in range(4):
+        for sl in range(4):
+            ti = np.nonzero(seg == si)[0]
+            tl = np.nonzero(seg == sl)[0]
+            i = rng.choice(ti, 4 * per_block)
+            l = rng.choice(tl, 4 * per_block)
+            off = np.abs(g.panel_of[i] - g.panel_of[l]) > 1
+            pairs = np.stack([i[off], l[off]], axis=1)[:per_block]
+            if len(pairs) == 0:
+                continue
+            t1 = time.time()
+            oracle.modal_kernels_nodes(g, pairs, ks, modes)
+            dt = time.time() - t1
+            done += len(pairs)
+            # the block's pairs off the near panels (3 panels of 16 per target at most)
+            t_pair += dt / len(pairs) * (len(ti) * len(tl) - (48 * len(ti) if si == sl else 0))
+            if time.time() - t0 > seconds:
+                break
+    t_modal = time.time() - t0
+    rng2 = np.random.default_rng(7)
+    Am = rng2.standard_normal((lu_n, lu_n)) + 1j * rng2.standard_normal((lu_n, lu_n)) + lu_n * np.eye(lu_n)
+    bv = np.ones(lu_n, dtype=np.complex128)
+    np.linalg.solve(Am, bv)
+    t1 = time.time()
+    np.linalg.solve(Am, bv)
+    t_lu = time.time() - t1
+    lu_gflops = (8.0 / 3.0) * lu_n ** 3 / t_lu / 1e9
+    t_lu_all = len(modes) * t_lu * (2.0 * N / lu_n) ** 3
+    tts = t_pair + t_lu_all
+    units = 2.0 * N * N * len(modes)
+    return {"value": units / tts, "unit": "pairs*modes/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": "%d node pairs of the %s workload stratified over the 16 segment blocks, both media, "
+                      "modes 0..%d, adaptive azimuthal quadrature (%.1f s); LAPACK LU of one %d x %d complex "
+                      "system (%.2f s)" % (done, wl.name, wl.m_max, t_modal, lu_n, lu_n, t_lu),
+            "time_to_solution_s_extrapolated": tts,
+            "extrapolation": "off-near pairs x measured time per pair + %d modes x LU time x (%d / %d)^3; "
+                             "near-panel integrals excluded (a lower bound)" % (len(modes), 2 * N, lu_n),
+            "modal_stage_pairs_modes_per_s": units / t_pair, "lu_gflops": lu_gflops}
 
 
 def field_leg(s, wl, N):
@@ -187,14 +304,128 @@ def field_leg(s, wl, N):
             "node_point_pairs_per_s": npf * N / t_field}
 
 
+def plain_headline(s, wl, args):
+    """Headline line for a workload that fits at once (FP64 steps)."""
+    ms_step, st, cnt, _ = plain_leg(s, wl, args.steps, args.warmup, 0)
+    info = s.info()
+    N, M = int(info[0]), int(info[1])
+    units = 2.0 * N * N * (M + 1)
+    kernel_ms = st[1] + st[2] + st[3] + st[4]
+    gemm_ms, flops, launches = st[6], float(cnt[2]), int(cnt[3])
+    achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    out = {
+        "metric": METRIC, "value": units / (ms_step * 1e-3), "unit": "pairs*modes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": wl.name, "nodes": N, "unknowns_per_mode": 2 * N, "modes": M + 1,
+                   "n_theta": wl.n_theta, "media": 2, "precision": "fp64",
+                   "incidence": ", ".join("point source (%.1f, 0, %.1f)" % (inc[1], inc[2]) if inc[0] == "point"
+                                          else "plane wave (polar angle %.2f)" % inc[1] for inc in wl.incidences)},
+        "time_to_solution_s": ms_step * 1e-3,
+        "kernel_stage_pairs_modes_per_s": units / (kernel_ms * 1e-3) if kernel_ms > 0 else None,
+        "stage_ms": stage_dict(st),
+        "pair_classes": {"far": int(info[4]), "split": int(info[5]), "direct": int(info[6]),
+                         "aux_near_points": int(info[7])},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm_update<double> (LU trailing update)",
+                     "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
+                     "traffic": gemm_traffic_record("k_gemm_update_paper_scale", "k_gemm_update<double>")
+                     if wl.name == "paper_scale" else None,
+                     "traffic_unit": "bytes per launch", "launches": launches,
+                     "flop_per_launch": flops / max(launches, 1), "avg_launch_ms": gemm_ms / max(launches, 1)},
+    }
+    return out
+
+
+METRIC = "time-to-solution at 1e-6 rel err vs FP64 oracle; modal-kernel pairs*modes/s"
+
+
+def stage_dict(st):
+    return {"setup": st[0], "far": st[1], "split": st[2], "direct": st[3], "near": st[4], "lu": st[5],
+            "lu_trailing_update": st[6], "solve": st[7], "rhs": st[8], "refinement": st[9], "build": st[10]}
+
+
+def largest_headline(s, wl, args):
+    """Headline line: the largest configuration's combined form."""
+    L = largest_leg(s, wl, args.steps, args.warmup)
+    ms_step, st, N = L["ms_per_step"], L["stages"], L["N"]
+    units = 2.0 * N * N * (wl.m_max + 1)
+    kernel_ms = st[1] + st[2] + st[3] + st[4]
+    gemm_ms, flops, launches = st[6], L["gemm_flops"], L["gemm_launches"]
+    achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    peak = 157.3   # FP32 dense matrix-core peak of the MI355X
+    nb = (wl.m_max + L["batch"]) // L["batch"]
+    return {
+        "metric": METRIC, "value": units / (ms_step * 1e-3), "unit": "pairs*modes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 LU + f64 refinement", "data": "synthetic",
+        "config": {"workload": wl.name, "nodes": N, "unknowns_per_mode": 2 * N, "modes": wl.m_max + 1,
+                   "n_theta": wl.n_theta, "media": 2, "k1": wl.k1, "k2": wl.k2,
+                   "precision": "mixed: complex64 LU on FP32 matrix cores, FP64 residuals and refinement",
+                   "right_hand_sides": "16 plane waves, polar angles (pi/3) i / 15",
+                   "mode_batches": [[lo, min(wl.m_max, lo + L["batch"] - 1)]
+                                    for lo in range(0, wl.m_max + 1, L["batch"])]},
+        "time_to_solution_s": ms_step * 1e-3,
+        "kernel_stage_pairs_modes_per_s": units / (kernel_ms * 1e-3) if kernel_ms > 0 else None,
+        "units_note": "value = media x N^2 x distinct modes / time to solution of the whole step; "
+                      "kernel_stage_pairs_modes_per_s divides the same units by the far + split + direct "
+                      "+ near stages only (the +-m count is 2 m_max + 1 = 513 modes)",
+        "stage_ms_sum_over_batches": stage_dict(st),
+        "far_pairs_on_full_grid": L["far_full_grid"],
+        "accuracy": {"refinement_max_final_rel_residual": max(L["residuals"]),
+                     "refinement_iterations": L["iterations"],
+                     "oracle_parity": "the same physics on 256 nodes against the oracle's full solve "
+                                      "(tests/test_gpu_largest.py): FP64 within 1e-8 and mixed precision in mode "
+                                      "batches within 1e-6 per mode and right-hand side"},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm_update<float> (LU trailing update, complex64)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": gemm_traffic_record("k_gemm_update_f32_largest", "k_gemm_update<float>"),
+                     "traffic_unit": "bytes per launch", "launches": launches,
+                     "flop_per_launch": flops / max(launches, 1), "avg_launch_ms": gemm_ms / max(launches, 1),
+                     "batches": nb},
+    }
+
+
+def paper_scale_legs(s, args):
+    """The paper-scale workload (2048 nodes, modes 0..128) in FP64 and in
+    mixed precision, with their errors against the stored oracle solve."""
+    import workloads
+    wl = workloads.paper_scale()
+    out = {}
+    ms64, st64, cnt64, sol64 = plain_leg(s, wl, args.extra_steps, 1, 0)
+    gemm_ms, flops = st64[6], float(cnt64[2])
+    out["fp64"] = {"ms_per_step": ms64, "stage_ms": stage_dict(st64),
+                   "lu_trailing_update_tflops": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None}
+    if not args.no_field:
+        out["field"] = field_leg(s, wl, int(s.info()[0]))
+    ref = [o.cpu().numpy() for o in sol64]
+    msmx, stmx, cntmx, solmx = plain_leg(s, wl, args.extra_steps, 1, 1)
+    got = [o.cpu().numpy() for o in solmx]
+    xg = np.concatenate(got, axis=2)[:, 0]
+    xr = np.concatenate(ref, axis=2)[:, 0]
+    big = np.max(np.linalg.norm(xr, axis=1))
+    err = max(float(np.linalg.norm(xg[j] - xr[j]) / max(np.linalg.norm(xr[j]), 1e-9 * big))
+              for j in range(xr.shape[0]))
+    out["mixed"] = {"ms_per_step": msmx, "speedup_vs_fp64": ms64 / msmx, "stage_ms": stage_dict(stmx),
+                    "refinement_iterations": int(cntmx[0]), "final_rel_residual": float(cntmx[1]),
+                    "max_rel_err_vs_gpu_fp64": err,
+                    "lu_trailing_update_tflops": float(cntmx[2]) / (stmx[6] * 1e-3) / 1e12 if stmx[6] > 0 else None}
+    for prec, key in ((0, "fp64"), (1, "mixed")):
+        e = stored_oracle_errors(s, "paper_scale", prec)
+        if e is not None:
+            out[key]["vs_oracle"] = e
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper_scale")
+    ap.add_argument("--workload", default="largest")
+    ap.add_argument("--extra-steps", type=int, default=3, help="steps of each extra (untimed-headline) leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only: skip the paper-scale, field and surrogate legs")
     ap.add_argument("--no-field", action="store_true",
                     help="skip the field-synthesis leg (1024 points after the timed steps)")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -218,127 +449,28 @@ def main():
               "across GPUs by mode); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import workloads
     from paper_2412_11162_amd.solver import Solver
 
     wl = workloads.ALL[args.workload]()
     s = Solver(0)
     if wl.name == "largest":
-        print(json.dumps(largest_run(s, wl, args.steps, args.warmup)))
-        return
-
-    def step(precision=0):
-        if wl.curve_nodes is not None:
-            s.set_panels(wl.curve_nodes)
-        elif wl.polyline:
-            s.set_polyline(wl.polyline, wl.panels, wl.grade)
-        else:
-            s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
-        s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
-        s.build_modal_operators(wl.n_theta, wl.m_max, precision)
-        return s.solve_modes(list(wl.incidences))
-
-    for _ in range(args.warmup):
-        step()
-        print("warmup step done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    times = []
-    stages = []
-    counts = []
-    t_all = time.time()
-    for k in range(args.steps):
-        t0 = time.time()
-        step()
-        torch.cuda.synchronize()
-        times.append(time.time() - t0)
-        sk, ck = s.stats()
-        stages.append(sk.copy())
-        counts.append(ck.copy())
-        print("step %d: %.1f ms" % (k, 1e3 * times[-1]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.time() - t_all
-    ms_step = 1e3 * total / args.steps
-    info = s.info()
-    N, M = int(info[0]), int(info[1])
-    units = 2.0 * N * N * (M + 1)
-    st = np.mean(np.array(stages), axis=0)
-    kernel_ms = st[1] + st[2] + st[3] + st[4]
-    # trailing-update kernel: algorithmic flops of all its launches (counted by
-    # the library, 8 real flops per complex multiply-add) over the summed
-    # durations of those launches (HIP events on the streams they run on)
-    gemm_ms = st[6]
-    flops = float(counts[-1][2])
-    launches = int(counts[-1][3])
-    achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
-    peak = 78.6
-    out = {
-        "metric": "time-to-solution at 1e-6 rel err vs FP64 oracle; modal-kernel pairs*modes/s",
-        "value": units / (ms_step * 1e-3),
-        "unit": "pairs*modes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "c128",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "nodes": N, "unknowns_per_mode": 2 * N, "modes": M + 1,
-                   "n_theta": wl.n_theta, "media": 2, "precision": "fp64",
-                   "incidence": ", ".join("point source (%.1f, 0, %.1f)" % (inc[1], inc[2]) if inc[0] == "point"
-                                          else "plane wave (polar angle %.2f)" % inc[1] for inc in wl.incidences)},
-        "time_to_solution_s": ms_step * 1e-3,
-        "kernel_stage_pairs_modes_per_s": units / (kernel_ms * 1e-3) if kernel_ms > 0 else None,
-        "stage_ms": {"setup": st[0], "far": st[1], "split": st[2], "direct": st[3], "near": st[4],
-                     "lu": st[5], "lu_trailing_update": st[6], "solve": st[7], "rhs": st[8],
-                     "build": st[10]},
-        "pair_classes": {"far": int(info[4]), "split": int(info[5]), "direct": int(info[6]),
-                         "aux_near_points": int(info[7])},
-        "roofline": {"bound": "mfma", "kernel": "k_gemm_update<double> (LU trailing update)",
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": gemm_traffic_record() if wl.name == "paper_scale" else None,
-                     "traffic_unit": "bytes per launch", "launches": launches, "flop_per_launch": flops / max(launches, 1),
-                     "avg_launch_ms": gemm_ms / max(launches, 1)},
-    }
-    if not args.no_field:
-        out["field"] = field_leg(s, wl, N)
-    if not args.no_mixed:
-        # complex64 LU on FP32 MFMA + FP64 refinement, same workload; its error
-        # is measured against this run's FP64 result (which the parity tests
-        # hold to the FP64 oracle)
-        ref = [o.cpu().numpy() for o in step(0)]
-        step(1)
-        torch.cuda.synchronize()
-        tm = []
-        for k in range(args.steps):
-            t0 = time.time()
-            sol = step(1)
-            torch.cuda.synchronize()
-            tm.append(time.time() - t0)
-            print("mixed step %d: %.1f ms" % (k, 1e3 * tm[-1]), file=sys.stderr, flush=True)
-        got = [o.cpu().numpy() for o in sol]
-        xg = np.concatenate(got, axis=2)[:, 0]
-        xr = np.concatenate(ref, axis=2)[:, 0]
-        big = np.max(np.linalg.norm(xr, axis=1))
-        errs = []
-        for j in range(xr.shape[0]):
-            nr = np.linalg.norm(xr[j])
-            d = np.linalg.norm(xg[j] - xr[j])
-            errs.append(d / nr if nr > 1e-9 * big else d / big)
-        stm, cnt = s.stats()
-        ms_mixed = 1e3 * float(np.mean(tm))
-        out["mixed_precision"] = {
-            "ms_per_step": ms_mixed, "value": units / (ms_mixed * 1e-3), "unit": "pairs*modes/s",
-            "speedup_vs_fp64": ms_step / ms_mixed, "dtype": "c64 LU + f64 refinement",
-            "max_rel_err_vs_fp64": float(np.max(errs)), "refinement_iterations": int(cnt[0]),
-            "final_rel_residual": float(cnt[1]),
-            "stage_ms": {"lu": stm[5], "lu_trailing_update": stm[6], "solve": stm[7], "refinement": stm[9]},
-            "lu_trailing_update_tflops": float(cnt[2]) / (stm[6] * 1e-3) / 1e12 if stm[6] > 0 else None,
-        }
-    if not args.no_surrogate and wl.name == "paper_scale":
-        out["surrogate"] = surrogate_leg(s, wl, step)
+        out = largest_headline(s, wl, args)
+        if not args.no_extra:
+            out["paper_scale"] = paper_scale_legs(s, args)
+    else:
+        out = plain_headline(s, wl, args)
+        if not args.no_field:
+            out["field"] = field_leg(s, wl, int(s.info()[0]))
+        if not args.no_extra and wl.name != "paper_scale":
+            ms_mx, st_mx, cnt_mx, _ = plain_leg(s, wl, args.extra_steps, 1, 1)
+            out["mixed_precision"] = {"ms_per_step": ms_mx, "stage_ms": stage_dict(st_mx),
+                                      "final_rel_residual": float(cnt_mx[1])}
+        elif not args.no_extra:
+            out["paper_scale"] = paper_scale_legs(s, args)
+    if not args.no_extra and not args.no_surrogate:
+        import workloads as W
+        out["surrogate"] = surrogate_leg(s, W.paper_scale())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))
