@@ -161,50 +161,67 @@ def stored_oracle_errors(s, name, precision):
             "max_rel_err": worst, "max_rel_err_per_mode": {str(k): v for k, v in per_mode.items()}}
 
 
-def surrogate_leg(s, wl, m_max: int = 64, tol: float = 1e-11):
-    """The learned surrogate on this geometry: training on 2^22 labelled
-    samples (timed apart, it is amortised over builds), then the step at
-    m_max = 64 (the modes the network covers) with and without it; the
-    surrogate step's error is measured against the plain FP64 step."""
+def surrogate_leg(s, wl, tol: float = 2e-8, steps: int = 12288):
+    """The learned surrogate in the combined form on the paper-scale workload:
+    training on 2^22 labelled samples (timed apart: it is amortised over
+    builds; three passes over the set), then the mixed-precision step (all
+    modes 0..128; modes beyond 64 only for pairs whose decay bound makes
+    them negligible) with and without it.  The acceptance tolerance follows
+    from the 1e-6 bar (the boundary data move by a few times tol); the error
+    is measured against the plain mixed step and, when stored, the oracle."""
     import torch
     from paper_2412_11162_amd import _binding as B
 
+    set_curve(s, wl)
     t0 = time.time()
     s.surrogate_init(2412)
     s.surrogate_make_samples(0, 1 << 22, 2412_11162)
     s.surrogate_make_samples(1, 1 << 18, 2412_11163)
     t_samples = time.time() - t0
+    mse0 = s.surrogate_eval(1)
     t0 = time.time()
-    loss = s.surrogate_train(4096, 1024, 1e-3)
+    loss = s.surrogate_train(steps, 1024, 1e-3)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     mse = s.surrogate_eval(1)
+    rel = s.surrogate_eval_modes(1)
 
     def run(flags):
-        s.set_geometry(wl.bumps, wl.cos_freq, wl.a1, wl.seg_breaks, wl.nodes_per_segment)
-        s.set_media_pml(wl.k1, wl.k2, wl.a1, wl.T, wl.S, wl.a2, wl.T2, wl.S2, wl.p)
+        set_curve(s, wl)
         t = time.time()
-        s.build_modal_operators(wl.n_theta, m_max, 0, flags)
+        s.build_modal_operators(wl.n_theta, wl.m_max, B.PMLBIE_MIXED, flags)
         sol = s.solve_modes(list(wl.incidences))
         torch.cuda.synchronize()
         return time.time() - t, [o.cpu().numpy() for o in sol], s.stats()
 
-    s.surrogate_set_tolerance(tol)
+    def err_of(got):
+        xg = np.concatenate(got, axis=2)[:, 0]
+        xr = np.concatenate(ref, axis=2)[:, 0]
+        big = np.max(np.linalg.norm(xr, axis=1))
+        return max(float(np.linalg.norm(xg[j] - xr[j]) / max(np.linalg.norm(xr[j]), 1e-9 * big))
+                   for j in range(xr.shape[0]))
+
     run(0)
     t_plain, ref, _ = run(0)
+    # what the network's accuracy buys at looser tolerances (beyond the bar)
+    sweep = []
+    for t in (1e-6, 1e-4, 1e-2):
+        s.surrogate_set_tolerance(t)
+        _, g_t, (_, c_t) = run(B.PMLBIE_USE_SURROGATE)
+        sweep.append({"tolerance": t, "acceptance": float(c_t[5]) / max(float(c_t[4]), 1.0),
+                      "max_rel_err_vs_plain_mixed": err_of(g_t)})
+    s.surrogate_set_tolerance(tol)
     t_sg, got, (st, cnt) = run(B.PMLBIE_USE_SURROGATE)
-    xg = np.concatenate(got, axis=2)[:, 0]
-    xr = np.concatenate(ref, axis=2)[:, 0]
-    big = np.max(np.linalg.norm(xr, axis=1))
-    err = max(float(np.linalg.norm(xg[j] - xr[j]) / max(np.linalg.norm(xr[j]), 1e-9 * big))
-              for j in range(xr.shape[0]))
+    err = err_of(got)
     return {"samples": {"train": 1 << 22, "held_out": 1 << 18, "seconds": t_samples},
-            "training": {"steps": 4096, "batch": 1024, "seconds": t_train, "loss_first": float(loss[:64].mean()),
-                         "loss_last": float(loss[-64:].mean()), "held_out_mse": mse},
-            "m_max": m_max, "tolerance": tol, "far_pairs": int(cnt[4]), "accepted": int(cnt[5]),
-            "acceptance": float(cnt[5]) / max(float(cnt[4]), 1.0),
+            "training": {"steps": steps, "batch": 1024, "seconds": t_train, "loss_first": float(loss[:64].mean()),
+                         "loss_last": float(loss[-64:].mean()), "held_out_mse_before": mse0, "held_out_mse": mse,
+                         "held_out_rel_err_per_mode": {str(m): float(rel[m]) for m in (0, 1, 2, 4, 8, 16, 32, 48, 64)}},
+            "m_max": wl.m_max, "precision": "mixed", "tolerance": tol, "far_pairs": int(cnt[4]),
+            "accepted": int(cnt[5]), "acceptance": float(cnt[5]) / max(float(cnt[4]), 1.0),
             "ms_plain": 1e3 * t_plain, "ms_surrogate": 1e3 * t_sg, "speedup": t_plain / t_sg,
-            "far_stage_ms": float(st[1]), "max_rel_err_vs_fp64": err}
+            "far_stage_ms": float(st[1]), "max_rel_err_vs_plain_mixed": err,
+            "tolerance_sweep": sweep}
 
 
 def cpu_model() -> str:

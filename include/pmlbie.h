@@ -136,10 +136,12 @@ int pmlbie_set_media_pml(pmlbie_ctx* ctx, double k1_re, double k1_im, double k2_
  * flags: PMLBIE_KEEP_OPERATORS keeps a copy of the assembled matrices for
  * pmlbie_get_operator; PMLBIE_USE_SURROGATE offers the well-separated
  * ("far") pairs to the learned surrogate first (needs a network for this PML
- * geometry, real wavenumbers and m_max <= 64): its modes are kept where its
- * modal synthesis at four angles matches direct kernel samples to the
- * tolerance of pmlbie_surrogate_set_tolerance, the raw-kernel FFT takes the
- * rest.
+ * geometry and real wavenumbers): its modes 0..64 are kept where its modal
+ * synthesis matches direct kernel samples at eight angles with a per-pair
+ * offset to the tolerance of pmlbie_surrogate_set_tolerance; with m_max > 64
+ * only pairs whose modes beyond 64 are negligible by the decay bound of the
+ * classification are offered (their modes 65..m_max are zero); the
+ * raw-kernel FFT takes the rest.
  * Errors: PMLBIE_EINVAL, PMLBIE_ESTATE, PMLBIE_ENOMEM, PMLBIE_EDEVICE,
  * PMLBIE_ESINGULAR (a zero pivot; pmlbie_last_error names the mode). */
 int pmlbie_build_modal_operators(pmlbie_ctx* ctx, int n_theta, int m_max, int precision,
@@ -260,7 +262,9 @@ int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
 int pmlbie_get_stats(const pmlbie_ctx* ctx, double* stage_ms, double* counters);
 
 /* ---- Learned surrogate of the far-pair modes ------------------------------
- * A multilayer perceptron (inputs rho, rho', dz, k, S; four hidden layers of
+ * A multilayer perceptron (raw inputs rho, rho', dz, k, S, Im rho~, Im rho~';
+ * features: those scaled to O(1) plus the phase scale k |R0| and the phase
+ * swing k (|R(pi)| - |R0|) of e^{ikR} over the angle; four hidden layers of
  * 256 with the erf GELU; 390 outputs) trained on modal kernels that the
  * raw-kernel FFT of the build generates.  It predicts modes 0..64 of
  *   S = G~, P = (-(rho~ - rho~') + 2 rho~ sin^2(D/2)) f, Q = -(z - z') f,
@@ -296,9 +300,16 @@ int pmlbie_surrogate_train(pmlbie_ctx* ctx, int steps, int batch, double lr, dou
 /* Mean squared error of the network over sample set `which`. */
 int pmlbie_surrogate_eval(pmlbie_ctx* ctx, int which, double* mse);
 
+/* Relative RMS error per mode over sample set `which`: rel[n] (host, 65
+ * doubles) = sqrt(sum |y - t|^2 / sum |t|^2) over the samples, the three
+ * heads and both parts at mode n (normalised targets). */
+int pmlbie_surrogate_eval_modes(pmlbie_ctx* ctx, int which, double* rel);
+
 /* Acceptance tolerance of the build: a pair's surrogate modes are kept when
- * 4 pi W_l max |synthesis - direct sample| <= tol over four angles and both
- * media (W_l the quadrature weight of the source node).  0 rejects all. */
+ * 4 pi W_l max |synthesis - direct sample| <= tol over the eight check
+ * angles and both media (W_l the quadrature weight of the source node); the
+ * quantity bounds every mode's error in the pair's matrix entries.  0
+ * rejects all. */
 int pmlbie_surrogate_set_tolerance(pmlbie_ctx* ctx, double tol);
 
 /* Serialise / restore the network (header + FP32 parameters).  save with
@@ -307,7 +318,7 @@ int pmlbie_surrogate_save(pmlbie_ctx* ctx, void* blob, size_t* bytes);
 int pmlbie_surrogate_load(pmlbie_ctx* ctx, const void* blob, size_t bytes);
 
 /* Test hooks (host arrays).  params: get (1) or set (0) the FP32 parameters
- * (nparams doubles).  forward: x n x 5 raw features -> y n x 390 outputs.
+ * (nparams doubles).  forward: x n x 7 raw inputs -> y n x 390 outputs.
  * grad: loss and gradient of the mean squared error against targets t
  * (n x 390) for the current parameters (no update).  label: normalised
  * FFT targets (n x 390) of samples s (n x 6: Re, Im rho~, Re, Im rho~',

@@ -25,7 +25,7 @@ import numpy as np
 from scipy.special import erf
 
 D = [32, 256, 256, 256, 256, 400]
-IN, MODES, OUT = 5, 65, 390
+IN, MODES, OUT = 7, 65, 390
 
 
 def layout() -> Tuple[List[int], List[int], int]:
@@ -55,7 +55,10 @@ def bf16(a: np.ndarray) -> np.ndarray:
 
 
 def features(x: np.ndarray, rho_max: float) -> np.ndarray:
-    """(rho, rho', dz, k, S) -> the network input, padded to 32 columns."""
+    """Raw inputs (rho, rho', dz, k, S, Im rho~, Im rho~') -> the network
+    input, padded to 32 columns: the first five scaled to O(1), the two
+    stretchings, k |R0| / 50 and k (|R(pi)| - |R0|) / 100 with R0, R(pi) the
+    complex distance at D = 0 and pi."""
     x = np.asarray(x, dtype=np.float64)
     h = np.zeros((x.shape[0], D[0]))
     h[:, 0] = 2.0 * x[:, 0] / rho_max - 1.0
@@ -63,6 +66,14 @@ def features(x: np.ndarray, rho_max: float) -> np.ndarray:
     h[:, 2] = x[:, 2]
     h[:, 3] = (x[:, 3] - 17.5) / 12.5
     h[:, 4] = (x[:, 4] - 2.5) / 1.5
+    h[:, 5] = x[:, 5]
+    h[:, 6] = x[:, 6]
+    rt = x[:, 0] + 1j * x[:, 5]
+    rs = x[:, 1] + 1j * x[:, 6]
+    d2 = (rt - rs) ** 2 + x[:, 2] ** 2
+    r0 = np.abs(np.sqrt(d2))
+    h[:, 7] = x[:, 3] * r0 / 50.0
+    h[:, 8] = x[:, 3] * (np.abs(np.sqrt(d2 + 4.0 * rt * rs)) - r0) / 100.0
     return h
 
 

@@ -31,7 +31,8 @@ EXPORTS = (
     "pmlbie_modal_kernels_noalloc",
     "pmlbie_get_operator", "pmlbie_get_stats", "pmlbie_set_refinement", "pmlbie_test_zero_column",
     "pmlbie_surrogate_nparams", "pmlbie_surrogate_init", "pmlbie_surrogate_make_samples",
-    "pmlbie_surrogate_train", "pmlbie_surrogate_eval", "pmlbie_surrogate_set_tolerance",
+    "pmlbie_surrogate_train", "pmlbie_surrogate_eval", "pmlbie_surrogate_eval_modes",
+    "pmlbie_surrogate_set_tolerance",
     "pmlbie_surrogate_save", "pmlbie_surrogate_load", "pmlbie_surrogate_params",
     "pmlbie_surrogate_forward", "pmlbie_surrogate_grad", "pmlbie_surrogate_label",
 )
@@ -81,6 +82,7 @@ def load():
     L.pmlbie_surrogate_make_samples.argtypes = [P, i, l, ul]
     L.pmlbie_surrogate_train.argtypes = [P, i, i, d, P]
     L.pmlbie_surrogate_eval.argtypes = [P, i, P]
+    L.pmlbie_surrogate_eval_modes.argtypes = [P, i, P]
     L.pmlbie_surrogate_set_tolerance.argtypes = [P, d]
     L.pmlbie_surrogate_save.argtypes = [P, P, ctypes.POINTER(sz)]
     L.pmlbie_surrogate_load.argtypes = [P, P, sz]

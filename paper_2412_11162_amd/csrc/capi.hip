@@ -86,6 +86,7 @@ struct pmlbie_ctx {
   DBuf<int> dpanel;
   DBuf<zd> tw_far, tw_int, tw_small;
   int nt_small = 0;  // grid of the main far pass (<= nt_far)
+  double split_rho_small = 0.0;  // split pairs up to this |rho~| use the nt_small grid (0: none)
   DBuf<double> glx, glw;
   DBuf<zd> A, Alow, Akeep;
   DBuf<zf> A32;               // complex64 factors (mixed precision)
@@ -188,10 +189,15 @@ struct Timer {
 // Split-path work on a device list [first, first+count): phase 1 (singular
 // modes) in chunks, phase 2 (smooth FFTs + convolution).
 void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count, zd* A, long n2,
-               long ms, const double* W, zd* raw) {
+               long ms, const double* W, zd* raw, bool small_grid = false) {
+  // the full grid L (singular modes to MQ = L/2 - 1), or the shorter grid
+  // of the pairs classed CLASS_SPLIT under ClassParams.split_rho_small
+  const int nt = small_grid ? c->nt_small : c->nt_int;
+  const int MQ = nt / 2 - 1;
+  const zd* tw = small_grid ? c->tw_small.p : c->tw_int.p;
   // chunks of pairs sized to about 1 GiB per singular-part table: the
   // Legendre recurrences run one pair per lane and are latency bound, so the
-  // chunk must hold several wavefronts per SIMD
+  // chunk must hold several wavefronts per SIMD (tables sized for the full grid)
   const long CH = std::max(1L << 15, std::min(1L << 18, (1L << 30) / (16L * (c->MQ + 1))));
   for (long f = 0; f < count; f += CH) {
     const long cn = std::min(CH, count - f);
@@ -199,10 +205,10 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
     c->phat.alloc((size_t)CH * (c->MQ + 1));
     c->qtab.alloc((size_t)CH * (c->MQ + 1));
     c->qcoef.alloc((size_t)CH * 4);
-    launch_split_singular(geom, f, cn, c->MQ, c->qtab.p, c->qcoef.p, c->zhat.p, c->phat.p, c->stream);
+    launch_split_singular(geom, f, cn, MQ, c->qtab.p, c->qcoef.p, c->zhat.p, c->phat.p, c->stream);
     HIPCHK(hipGetLastError());
-    launch_split(c->nt_int, geom, dest, f, cn, c->M, c->m0, c->MQ, c->k1, c->k2, c->tw_int.p, c->zhat.p,
-                 c->phat.p, A, n2, ms, W, raw, c->stream);
+    launch_split(nt, geom, dest, f, cn, c->M, c->m0, MQ, c->k1, c->k2, tw, c->zhat.p, c->phat.p, A, n2, ms, W,
+                 raw, c->stream);
     HIPCHK(hipGetLastError());
   }
 }
@@ -226,15 +232,15 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
     sg_pair_features(geom + s, cn, c->k1.re, c->k2.re, c->geo.pml.S, c->sgfx.p, c->stream);
     sg_features(c->sgfx.p, (int)(2 * cn), f, c->sgw, c->stream);
     sg_forward(c->sg, c->sgw, (int)(2 * cn), c->stream);
-    sg_accept(geom + s, dest + s, cn, c->sgw.z[SG_NL - 1], c->M, c->k1, c->k2, c->sg_tol, c->A.p, n2, ms,
-              W, fb, c->sgcnt.p, c->stream);
+    sg_accept(geom + s, dest + s, cn, c->sgw.z[SG_NL - 1], c->M, c->m0, c->k1, c->k2, c->sg_tol, c->A.p, n2, ms,
+              W, fb, c->sgcnt.p, c->cp, c->stream);
     HIPCHK(hipGetLastError());
   }
   unsigned h[2];
   HIPCHK(hipMemcpy(h, c->sgcnt.p, sizeof(h), hipMemcpyDeviceToHost));
   c->counters[4] = (double)count;
   c->counters[5] = (double)h[0];
-  launch_list_far(c->nt_far, c->sgfb_geom.p, c->sgfb_dest.p, 0, h[1], c->M, 0, c->k1, c->k2, c->tw_far.p,
+  launch_list_far(c->nt_far, c->sgfb_geom.p, c->sgfb_dest.p, 0, h[1], c->M, c->m0, c->k1, c->k2, c->tw_far.p,
                   c->A.p, n2, ms, W, nullptr, &c->cp, c->stream);
   HIPCHK(hipGetLastError());
 }
@@ -242,7 +248,7 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
 // Explicit pair list (host) -> raw modal values raw[q][s][n]: upload, classify
 // on the device into far / split / direct lists, run the three paths.
 void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts,
-                       const int* medium = nullptr, int Nm = 0);
+                       const int* medium = nullptr, int Nm = 0, bool two_grids = false);
 
 void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long long* counts) {
   const size_t tot = g.size();
@@ -255,22 +261,26 @@ void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long 
 // The same with the pair geometry already in c->xgeom.  With medium (field
 // points, rows q = p * Nm + l), the far pairs get the kernels of their point's
 // medium only.
-void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, const int* medium, int Nm) {
+void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, const int* medium, int Nm,
+                       bool two_grids) {
   if (tot == 0) return;
-  c->lgeom.alloc(3 * tot > c->lgeom.n ? 3 * tot : c->lgeom.n);
-  c->ldest.alloc(3 * tot > c->ldest.n ? 3 * tot : c->ldest.n);
-  c->lcount.alloc(3);
-  HIPCHK(hipMemsetAsync(c->lcount.p, 0, 3 * sizeof(unsigned), c->stream));
+  c->lgeom.alloc(4 * tot > c->lgeom.n ? 4 * tot : c->lgeom.n);
+  c->ldest.alloc(4 * tot > c->ldest.n ? 4 * tot : c->ldest.n);
+  c->lcount.alloc(4);
+  HIPCHK(hipMemsetAsync(c->lcount.p, 0, 4 * sizeof(unsigned), c->stream));
   WorkList wf{c->lgeom.p, c->ldest.p, c->lcount.p, (unsigned)tot};
   WorkList ws{c->lgeom.p + tot, c->ldest.p + tot, c->lcount.p + 1, (unsigned)tot};
   WorkList wd{c->lgeom.p + 2 * tot, c->ldest.p + 2 * tot, c->lcount.p + 2, (unsigned)tot};
-  launch_classify_list(c->xgeom.p, (long)tot, c->cp, wf, ws, wd, c->stream);
+  WorkList wsb{c->lgeom.p + 3 * tot, c->ldest.p + 3 * tot, c->lcount.p + 3, (unsigned)tot};
+  ClassParams cpl = c->cp;
+  if (two_grids) cpl.split_rho_small = c->split_rho_small;
+  launch_classify_list(c->xgeom.p, (long)tot, cpl, wf, ws, wd, wsb, c->stream);
   HIPCHK(hipGetLastError());
-  unsigned cnt[3];
+  unsigned cnt[4];
   HIPCHK(hipMemcpy(cnt, c->lcount.p, sizeof(cnt), hipMemcpyDeviceToHost));
   if (counts) {
     counts[0] += cnt[0];
-    counts[1] += cnt[1];
+    counts[1] += cnt[1] + cnt[3];
     counts[2] += cnt[2];
   }
   if (medium)
@@ -280,7 +290,8 @@ void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, co
     launch_list_far(c->nt_far, wf.geom, wf.dest, 0, cnt[0], c->M, 0, c->k1, c->k2, c->tw_far.p, nullptr, 0,
                     0, nullptr, raw, nullptr, c->stream);
   HIPCHK(hipGetLastError());
-  run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw);
+  run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw, cpl.split_rho_small > 0.0);
+  run_split(c, wsb.geom, wsb.dest, cnt[3], nullptr, 0, 0, nullptr, raw);
   launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
                 nullptr, raw, kOmegaPiece, c->stream);
   HIPCHK(hipGetLastError());
@@ -501,8 +512,6 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     const bool use_sg = (flags & PMLBIE_USE_SURROGATE) != 0;
     if (use_sg) {
       if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "build: no surrogate network (init, train or load one)");
-      if (m_max > SG_MODES - 1 || m_min != 0)
-        return fail(c, PMLBIE_EINVAL, "build: the surrogate covers modes 0..64 only (from mode 0)");
       if (c->k1.im != 0.0 || c->k2.im != 0.0)
         return fail(c, PMLBIE_EINVAL, "build: the surrogate takes real wavenumbers");
       if (fabs(c->geo.pml.a1 - c->sg_a1) > 1e-12 || fabs(c->geo.pml.T - c->sg_T) > 1e-12 ||
@@ -544,6 +553,13 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     // (512 at least); far pairs whose aliasing bound needs the full grid L
     // are listed and transformed on it afterwards
     c->nt_small = std::min(L, std::max(512, pow2_at_least(2.0 * (M + 1))));
+    // split pairs whose smooth parts' bandwidth 1.15 |k| max(|rho~_t|, |rho~_s|) + 16
+    // fits below the shorter grid (MQ_small - M of it) are split on that grid
+    c->split_rho_small = 0.0;
+    if (c->nt_small < L && kmax > 0.0) {
+      const double r = ((double)(c->nt_small / 2 - 1 - M) - 16.0) / (1.15 * kmax);
+      if (r > 0.0) c->split_rho_small = r;
+    }
 
     Timer t_setup(c->stream);
     // node tables
@@ -582,12 +598,13 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->luw.alloc((size_t)nm * LU_NB * LU_NB);
     c->info.alloc(nm);
     HIPCHK(hipMemsetAsync(c->info.p, 0, nm * sizeof(int), c->stream));
-    // work lists of the grid (split, direct and far share one allocation)
+    // work lists of the grid (split, direct, far and split on the full grid
+    // share one allocation)
     const size_t cap = (size_t)N * N;
-    c->lgeom.alloc(3 * cap);
-    c->ldest.alloc(3 * cap);
-    c->lcount.alloc(3);
-    HIPCHK(hipMemsetAsync(c->lcount.p, 0, 3 * sizeof(unsigned), c->stream));
+    c->lgeom.alloc(4 * cap);
+    c->ldest.alloc(4 * cap);
+    c->lcount.alloc(4);
+    HIPCHK(hipMemsetAsync(c->lcount.p, 0, 4 * sizeof(unsigned), c->stream));
     // auxiliary near-panel points: built on the host while the device runs
     // the far, split and direct stages, into host tables that the context
     // keeps between builds (refilled every time; keeping the memory spares
@@ -634,19 +651,21 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     // far pairs: raw-kernel FFT in the grid (those that need the full grid
     // listed in wf and transformed from the list), or listed for the surrogate
     WorkList wf{c->lgeom.p + 2 * cap, c->ldest.p + 2 * cap, c->lcount.p + 2, (unsigned)cap};
+    WorkList wsb{c->lgeom.p + 3 * cap, c->ldest.p + 3 * cap, c->lcount.p + 3, (unsigned)cap};
     Timer t_far(c->stream);
+    ClassParams cpg = c->cp;
+    cpg.split_rho_small = c->split_rho_small;
     if (use_sg) {
-      launch_grid_classify(nd, c->cp, wf, ws, wd, c->stream);
+      launch_grid_classify(nd, cpg, wf, ws, wd, wsb, c->stream);
     } else {
-      ClassParams cpg = c->cp;
       cpg.nt_small = c->nt_small;
       launch_grid_far(nd, cpg, c->k1, c->k2, c->nt_small < c->nt_far ? c->tw_small.p : c->tw_far.p, c->A.p, ms,
-                      m0, nd.W, ws, wd, wf, c->stream);
+                      m0, nd.W, ws, wd, wf, wsb, c->stream);
     }
     HIPCHK(hipGetLastError());
-    unsigned counts[3] = {0, 0, 0};
-    HIPCHK(hipMemcpy(counts, c->lcount.p, 3 * sizeof(unsigned), hipMemcpyDeviceToHost));
-    if (counts[0] > cap || counts[1] > cap || counts[2] > cap)
+    unsigned counts[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpy(counts, c->lcount.p, 4 * sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (counts[0] > cap || counts[1] > cap || counts[2] > cap || counts[3] > cap)
       return fail(c, PMLBIE_EDEVICE, "build: work list overflow");
     c->counters[4] = 0;
     c->counters[5] = 0;
@@ -660,12 +679,13 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
       HIPCHK(hipGetLastError());
     }
     c->stage_ms[1] = t_far.stop();
-    c->cnt_split = counts[0];
+    c->cnt_split = counts[0] + counts[3];
     c->cnt_direct = counts[1];
-    c->cnt_far = (long long)N * N - counts[0] - counts[1];
+    c->cnt_far = (long long)N * N - counts[0] - counts[1] - counts[3];
 
     Timer t_split(c->stream);
-    run_split(c, c->lgeom.p, c->ldest.p, counts[0], c->A.p, n2, ms, nd.W, nullptr);
+    run_split(c, c->lgeom.p, c->ldest.p, counts[0], c->A.p, n2, ms, nd.W, nullptr, c->split_rho_small > 0.0);
+    run_split(c, wsb.geom, wsb.dest, counts[3], c->A.p, n2, ms, nd.W, nullptr);
     c->stage_ms[2] = t_split.stop();
     Timer t_direct(c->stream);
     launch_direct(c->lgeom.p + cap, c->ldest.p + cap, 0, counts[1], M, m0, c->k1, c->k2, c->glx.p,
@@ -680,7 +700,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->cnt_aux = (long long)ageom.size();
     c->raw.alloc(std::max<size_t>(ageom.size(), 1) * 4 * (M + 1));
     long long dummy[3] = {0, 0, 0};
-    run_pair_list_dev(c, ageom.size(), c->raw.p, dummy);
+    run_pair_list_dev(c, ageom.size(), c->raw.p, dummy, nullptr, 0, true);
     launch_near(c->jobs.p, (int)ajobs.size(), c->coef.p, c->raw.p, M, m0, c->A.p, n2, ms, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[4] = t_near.stop();
@@ -1120,11 +1140,14 @@ int pmlbie_modal_kernels_noalloc(pmlbie_ctx* c, int n_pairs, const double* geom,
     zd* raw = reinterpret_cast<zd*>(d_out);
     // the host records (rho~_t, rho~_s, drho~, dz~, n_rho, n_z) are PairGeom
     HIPCHK(hipMemcpyAsync(geo, geom, np * sizeof(PairGeom), hipMemcpyHostToDevice, c->stream));
-    launch_fill_u32(cnt, 3, 0u, c->stream);
+    launch_fill_u32(cnt, 4, 0u, c->stream);
     WorkList wf{lg, ld, cnt, (unsigned)np};
     WorkList ws{lg + np, ld + np, cnt + 1, (unsigned)np};
     WorkList wd{lg + 2 * np, ld + 2 * np, cnt + 2, (unsigned)np};
-    launch_classify_list(geo, np, c->cp, wf, ws, wd, c->stream);
+    // c->cp has no split on a shorter grid, so the fourth list stays empty
+    // (capacity 0: nothing is ever written to it)
+    WorkList wnone{lg, ld, cnt + 3, 0u};
+    launch_classify_list(geo, np, c->cp, wf, ws, wd, wnone, c->stream);
     HIPCHK(hipGetLastError());
     unsigned h[3];
     HIPCHK(hipMemcpy(h, cnt, sizeof(h), hipMemcpyDeviceToHost));
@@ -1232,7 +1255,7 @@ int pmlbie_surrogate_init(pmlbie_ctx* c, unsigned long long seed) {
     std::vector<float> p(L.total, 0.0f);
     Rng r(seed);
     for (int l = 0; l < SG_NL; ++l) {
-      const int fin = l == 0 ? SG_IN : SG_D[l], fout = l == SG_NL - 1 ? SG_OUT : SG_D[l + 1];
+      const int fin = l == 0 ? SG_NF : SG_D[l], fout = l == SG_NL - 1 ? SG_OUT : SG_D[l + 1];
       const double a = sqrt(6.0 / (fin + fout));
       for (int o = 0; o < fout; ++o)
         for (int i = 0; i < fin; ++i) p[L.w[l] + (long)o * SG_D[l] + i] = (float)(a * (2.0 * r.u() - 1.0));
@@ -1256,7 +1279,7 @@ int pmlbie_surrogate_make_samples(pmlbie_ctx* c, int which, long n, unsigned lon
     if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_make_samples: no network");
     Rng r(seed);
     std::vector<SgSample> smp(n);
-    std::vector<double> x(5 * n);
+    std::vector<double> x((size_t)SG_IN * n);
     const double a1 = c->sg_a1, T = c->sg_T;
     long q = 0;
     while (q < n) {
@@ -1284,8 +1307,8 @@ int pmlbie_surrogate_make_samples(pmlbie_ctx* c, int which, long n, unsigned lon
         const double k1 = 5.0 + 10.0 * r.u();
         const double k = r.u() < 0.5 ? k1 : k1 * (1.2 + 0.8 * r.u());
         smp[q] = SgSample{g.rho[i], S * g.I[i], g.rho[l], S * g.I[l], dz, k};
-        const double xs[5] = {g.rho[i], g.rho[l], dz, k, S};
-        for (int j = 0; j < 5; ++j) x[5 * q + j] = xs[j];
+        const double xs[SG_IN] = {g.rho[i], g.rho[l], dz, k, S, S * g.I[i], S * g.I[l]};
+        for (int j = 0; j < SG_IN; ++j) x[SG_IN * q + j] = xs[j];
         ++q;
         ++t;
       }
@@ -1293,7 +1316,7 @@ int pmlbie_surrogate_make_samples(pmlbie_ctx* c, int which, long n, unsigned lon
     for (long a = n - 1; a > 0; --a) {  // shuffle the geometries together
       const long b = std::min(a, (long)(r.u() * (a + 1)));
       std::swap(smp[a], smp[b]);
-      for (int j = 0; j < 5; ++j) std::swap(x[5 * a + j], x[5 * b + j]);
+      for (int j = 0; j < SG_IN; ++j) std::swap(x[SG_IN * a + j], x[SG_IN * b + j]);
     }
     DBuf<SgSample> ds;
     ds.alloc(n);
@@ -1303,7 +1326,7 @@ int pmlbie_surrogate_make_samples(pmlbie_ctx* c, int which, long n, unsigned lon
     c->sgtw.alloc(tw.size());
     HIPCHK(hipMemcpy(c->sgtw.p, tw.data(), tw.size() * sizeof(zd), hipMemcpyHostToDevice));
     c->sgT[which].alloc((size_t)n * SG_OUT);
-    c->sgx[which].alloc((size_t)n * 5);
+    c->sgx[which].alloc((size_t)n * SG_IN);
     HIPCHK(hipMemcpy(c->sgx[which].p, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice));
     sg_label(ds.p, n, L, c->sgtw.p, c->sgT[which].p, c->stream);
     HIPCHK(hipGetLastError());
@@ -1329,7 +1352,7 @@ int pmlbie_surrogate_train(pmlbie_ctx* c, int steps, int batch, double lr, doubl
       if (off + batch > n) off = 0;
       // cosine decay of the step size from lr to lr / 20
       const double lr_s = lr * (0.05 + 0.475 * (1.0 + cos(PMLBIE_PI * s / std::max(steps, 1))));
-      sg_features(c->sgx[0].p + 5 * off, batch, f, c->sgw, c->stream);
+      sg_features(c->sgx[0].p + (long)SG_IN * off, batch, f, c->sgw, c->stream);
       sg_forward(c->sg, c->sgw, batch, c->stream);
       sg_backward(c->sg, c->sgw, batch, c->sgT[0].p + (long)SG_OUT * off, c->stream);
       sg_adam(c->sg, lr_s, c->stream);
@@ -1354,7 +1377,7 @@ int pmlbie_surrogate_eval(pmlbie_ctx* c, int which, double* mse) {
     double tot = 0.0;
     for (long off = 0; off < n; off += CH) {
       const int cn = (int)std::min(CH, n - off);
-      sg_features(c->sgx[which].p + 5 * off, cn, f, c->sgw, c->stream);
+      sg_features(c->sgx[which].p + (long)SG_IN * off, cn, f, c->sgw, c->stream);
       sg_forward(c->sg, c->sgw, cn, c->stream);
       sg_loss(c->sgw, cn, c->sgT[which].p + (long)SG_OUT * off, c->stream);
       double l = 0;
@@ -1362,6 +1385,33 @@ int pmlbie_surrogate_eval(pmlbie_ctx* c, int which, double* mse) {
       tot += l;
     }
     if (mse) *mse = tot / ((double)n * SG_OUT);
+    return PMLBIE_OK;
+  });
+}
+
+int pmlbie_surrogate_eval_modes(pmlbie_ctx* c, int which, double* rel) {
+  return guarded(c, [&]() -> int {
+    if (which != 0 && which != 1) return fail(c, PMLBIE_EINVAL, "surrogate_eval_modes: which is 0 or 1");
+    if (!rel) return fail(c, PMLBIE_EINVAL, "surrogate_eval_modes: null output");
+    if (!c->sg_ready || c->sgn[which] <= 0)
+      return fail(c, PMLBIE_ESTATE, "surrogate_eval_modes: no network or samples");
+    const long n = c->sgn[which], CH = 1L << 15;
+    HIPCHK(sg_work_alloc(c->sgw, (int)CH));
+    DBuf<double> acc;
+    acc.alloc(2 * SG_MODES);
+    HIPCHK(hipMemsetAsync(acc.p, 0, 2 * SG_MODES * sizeof(double), c->stream));
+    SgFeat f{c->sg_a1 + c->sg_T};
+    for (long off = 0; off < n; off += CH) {
+      const int cn = (int)std::min(CH, n - off);
+      sg_features(c->sgx[which].p + (long)SG_IN * off, cn, f, c->sgw, c->stream);
+      sg_forward(c->sg, c->sgw, cn, c->stream);
+      sg_mode_errors(c->sgw.z[SG_NL - 1], c->sgT[which].p + (long)SG_OUT * off, cn, acc.p, acc.p + SG_MODES,
+                     c->stream);
+      HIPCHK(hipGetLastError());
+    }
+    double h[2 * SG_MODES];
+    HIPCHK(hipMemcpy(h, acc.p, sizeof(h), hipMemcpyDeviceToHost));
+    for (int m = 0; m < SG_MODES; ++m) rel[m] = h[SG_MODES + m] > 0 ? sqrt(h[m] / h[SG_MODES + m]) : 0.0;
     return PMLBIE_OK;
   });
 }
@@ -1449,8 +1499,8 @@ int pmlbie_surrogate_forward(pmlbie_ctx* c, int n, const double* x, double* y) {
     if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "surrogate_forward: no network");
     HIPCHK(sg_work_alloc(c->sgw, n));
     DBuf<double> dx;
-    dx.alloc((size_t)n * 5);
-    HIPCHK(hipMemcpy(dx.p, x, (size_t)n * 5 * sizeof(double), hipMemcpyHostToDevice));
+    dx.alloc((size_t)n * SG_IN);
+    HIPCHK(hipMemcpy(dx.p, x, (size_t)n * SG_IN * sizeof(double), hipMemcpyHostToDevice));
     SgFeat f{c->sg_a1 + c->sg_T};
     sg_features(dx.p, n, f, c->sgw, c->stream);
     sg_forward(c->sg, c->sgw, n, c->stream);
@@ -1472,12 +1522,12 @@ int pmlbie_surrogate_grad(pmlbie_ctx* c, int n, const double* x, const double* t
     SgLayout L;
     HIPCHK(sg_work_alloc(c->sgw, n));
     DBuf<double> dx;
-    dx.alloc((size_t)n * 5);
+    dx.alloc((size_t)n * SG_IN);
     DBuf<float> dt;
     dt.alloc((size_t)n * SG_OUT);
     std::vector<float> tf((size_t)n * SG_OUT);
     for (size_t i = 0; i < tf.size(); ++i) tf[i] = (float)t[i];
-    HIPCHK(hipMemcpy(dx.p, x, (size_t)n * 5 * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dx.p, x, (size_t)n * SG_IN * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dt.p, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice));
     SgFeat f{c->sg_a1 + c->sg_T};
     sg_features(dx.p, n, f, c->sgw, c->stream);

@@ -9,7 +9,9 @@ namespace pmlbie {
 
 // CLASS_FAR_BIG: a far pair whose aliasing bound holds on the full angle grid
 // but not on the shorter grid the main pass runs on (see ClassParams.nt_small).
-enum { CLASS_FAR = 0, CLASS_SPLIT = 1, CLASS_DIRECT = 2, CLASS_FAR_BIG = 3 };
+// CLASS_SPLIT_BIG: a split pair whose smooth parts need the full grid (its
+// |rho~| exceeds ClassParams.split_rho_small).
+enum { CLASS_FAR = 0, CLASS_SPLIT = 1, CLASS_DIRECT = 2, CLASS_FAR_BIG = 3, CLASS_SPLIT_BIG = 4 };
 
 // Node tables of the Nystrom discretisation, structure of arrays on the device.
 struct NodesDev {
@@ -32,6 +34,10 @@ struct ClassParams {
   // when their aliasing bound holds there, and classes the other far pairs
   // CLASS_FAR_BIG (transformed on the full grid from a list)
   int nt_small = 0;
+  // > 0: split pairs with max(|rho~_t|, |rho~_s|) above this are
+  // CLASS_SPLIT_BIG; the others are resolved on the shorter grid nt_small
+  // (their smooth parts' bandwidth 1.15 |k| |rho~| + 16 fits below it)
+  double split_rho_small = 0.0;
 };
 
 // Device work list of pairs handed from the classifier to the split and
@@ -65,18 +71,18 @@ struct NearJob {
 // far_big.
 void launch_grid_far(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
                      const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
-                     WorkList direct, WorkList far_big, hipStream_t st);
+                     WorkList direct, WorkList far_big, WorkList split_big, hipStream_t st);
 // Classification only (surrogate path): far / split / direct lists with
 // destinations (i, l).
 void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,
-                          WorkList direct, hipStream_t st);
+                          WorkList direct, WorkList split_big, hipStream_t st);
 // Far pairs of an explicit list; with cp, the pairs the classification marks
 // coarse are sampled on the half-length grid, as in the main grid.
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                      int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride,
                      const double* W, zd* raw, const ClassParams* cp, hipStream_t st);
 void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
-                          WorkList split, WorkList direct, hipStream_t st);
+                          WorkList split, WorkList direct, WorkList split_big, hipStream_t st);
 // Singular-part modes of split pairs: qtab ([MQ + 1][count], mode-major)
 // and coef (4 per pair) are work space; zhat, phat receive [count][MQ + 1]
 // (pair-major), read by launch_split.

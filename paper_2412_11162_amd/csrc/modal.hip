@@ -184,7 +184,8 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
 template <int R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
-                                                 WorkList split, WorkList direct, WorkList far_big) {
+                                                 WorkList split, WorkList direct, WorkList far_big,
+                                                 WorkList split_big) {
   __shared__ zd lds[far_lds<R>()];
   const int N = nd.N;
   const long total = (long)N * N;
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int cls = classify(g, v, cp, &coarse);
     if (cls != CLASS_FAR) {
       if (threadIdx.x == 0) {
-        WorkList& wl = cls == CLASS_SPLIT ? split : (cls == CLASS_DIRECT ? direct : far_big);
+        WorkList& wl = cls == CLASS_SPLIT ? split
+                       : (cls == CLASS_DIRECT ? direct : (cls == CLASS_FAR_BIG ? far_big : split_big));
         unsigned slot = atomicAdd(wl.count, 1u);
         if (slot < wl.cap) {
           wl.geom[slot] = g;
@@ -218,14 +220,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // Wave-aggregated append of this lane's pair to the work list of its class
 // (one counter update per wavefront and class).
 __device__ __forceinline__ void append_by_class(int cls, const PairGeom& g, int2 dst, WorkList far,
-                                                WorkList split, WorkList direct) {
+                                                WorkList split, WorkList direct, WorkList split_big) {
   const int lane = threadIdx.x & 63;
+  // list slots: far (the far lists of this path are transformed on the full
+  // grid, so CLASS_FAR_BIG joins them), split, direct, split on the full grid
+  if (cls == CLASS_SPLIT_BIG) cls = 3;
+  else if (cls == CLASS_FAR_BIG) cls = CLASS_FAR;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 4; ++c) {
     const unsigned long long mask = __ballot(cls == c);
     if (mask == 0) continue;
     const int leader = __ffsll((long long)mask) - 1;
-    WorkList& wl = c == CLASS_FAR ? far : (c == CLASS_SPLIT ? split : direct);
+    WorkList& wl = c == CLASS_FAR ? far : (c == CLASS_SPLIT ? split : (c == CLASS_DIRECT ? direct : split_big));
     unsigned base = 0;
     if (lane == leader) base = atomicAdd(wl.count, (unsigned)__popcll(mask));
     base = __shfl(base, leader);
@@ -243,7 +249,7 @@ __device__ __forceinline__ void append_by_class(int cls, const PairGeom& g, int2
 // off the near panels goes to the far / split / direct work list of its class
 // with destination (i, l); one thread per pair.
 __global__ __launch_bounds__(256) void k_grid_classify(NodesDev nd, ClassParams cp, WorkList far,
-                                                       WorkList split, WorkList direct) {
+                                                       WorkList split, WorkList direct, WorkList split_big) {
   const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int N = nd.N;
   int cls = -1, i = 0, l = 0;
@@ -257,13 +263,13 @@ __global__ __launch_bounds__(256) void k_grid_classify(NodesDev nd, ClassParams 
       cls = classify(g, pair_invariants(g), cp);
     }
   }
-  append_by_class(cls, g, make_int2(i, l), far, split, direct);
+  append_by_class(cls, g, make_int2(i, l), far, split, direct, split_big);
 }
 
 // Classification of an explicit pair list into far / split / direct work
 // lists (destination = raw row q).
 __global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, ClassParams cp,
-                                WorkList far, WorkList split, WorkList direct) {
+                                WorkList far, WorkList split, WorkList direct, WorkList split_big) {
   const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
   int cls = -1;
   PairGeom g;
@@ -271,7 +277,7 @@ __global__ void k_classify_list(const PairGeom* __restrict__ geom, long count, C
     g = geom[q];
     cls = classify(g, pair_invariants(g), cp);
   }
-  append_by_class(cls, g, make_int2((int)q, -1), far, split, direct);
+  append_by_class(cls, g, make_int2((int)q, -1), far, split, direct, split_big);
 }
 
 // Explicit list of far pairs (right-hand sides, field points).
@@ -788,31 +794,32 @@ __global__ __launch_bounds__(64) void k_rhs_plane(const double* __restrict__ rho
 // Host launchers.
 template <int R>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
-                         const OutSpec& o, WorkList split, WorkList direct, WorkList far_big, hipStream_t st) {
+                         const OutSpec& o, WorkList split, WorkList direct, WorkList far_big,
+                         WorkList split_big, hipStream_t st) {
   long total = (long)nd.N * nd.N;
   int grid = (int)std::min<long>((total + 7) / 8 * 8, 256L * 128);  // a multiple of 8
   hipLaunchKernelGGL(k_grid_far<R>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
-                     direct, far_big);
+                     direct, far_big, split_big);
 }
 
 void launch_grid_far(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
                      const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
-                     WorkList direct, WorkList far_big, hipStream_t st) {
+                     WorkList direct, WorkList far_big, WorkList split_big, hipStream_t st) {
   OutSpec o{A, 2L * nd.N, mstride, W, nullptr, cp.M, m0};
   const int nt = (cp.nt_small > 0 && cp.nt_small < cp.nt_far) ? cp.nt_small : cp.nt_far;
   switch (nt) {
-    case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, far_big, st); break;
-    case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, far_big, st); break;
-    case 2048: launch_far_t<32>(nd, cp, k1, k2, tw, o, split, direct, far_big, st); break;
+    case 512: launch_far_t<8>(nd, cp, k1, k2, tw, o, split, direct, far_big, split_big, st); break;
+    case 1024: launch_far_t<16>(nd, cp, k1, k2, tw, o, split, direct, far_big, split_big, st); break;
+    case 2048: launch_far_t<32>(nd, cp, k1, k2, tw, o, split, direct, far_big, split_big, st); break;
     default: break;
   }
 }
 
 void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList far, WorkList split,
-                          WorkList direct, hipStream_t st) {
+                          WorkList direct, WorkList split_big, hipStream_t st) {
   const long total = (long)nd.N * nd.N;
   hipLaunchKernelGGL(k_grid_classify, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, nd, cp, far,
-                     split, direct);
+                     split, direct, split_big);
 }
 
 template <int R>
@@ -859,10 +866,10 @@ void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first,
 }
 
 void launch_classify_list(const PairGeom* geom, long count, const ClassParams& cp, WorkList far,
-                          WorkList split, WorkList direct, hipStream_t st) {
+                          WorkList split, WorkList direct, WorkList split_big, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_classify_list, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, geom,
-                     count, cp, far, split, direct);
+                     count, cp, far, split, direct, split_big);
 }
 
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* qtab, zd* coef,

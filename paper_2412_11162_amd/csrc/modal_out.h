@@ -118,7 +118,9 @@ __device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, con
   }
   zd Rpi = csqrt_(v.d2 + v.c4);
   double grow = cp.kmax * fabs(Rpi.im) + cp.kmax_im * fabs(Rpi.re);
-  return grow <= cp.g_split ? CLASS_SPLIT : CLASS_DIRECT;
+  if (grow > cp.g_split) return CLASS_DIRECT;
+  if (cp.split_rho_small > 0.0 && fmax(cabs_(g.rt), cabs_(g.rs)) > cp.split_rho_small) return CLASS_SPLIT_BIG;
+  return CLASS_SPLIT;
 }
 
 }  // namespace pmlbie

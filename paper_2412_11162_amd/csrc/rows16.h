@@ -32,16 +32,23 @@ __device__ __forceinline__ void rows16_acc(const cx<TA>* __restrict__ a, long ld
                                            int c0, int c1, int nrhs, F vec, zd (&acc)[4], bool& out_wave,
                                            int& out_group) {
   constexpr int PER = (R16_ROWS * R16_CHUNK) / 256;  // A elements per thread per chunk
-  __shared__ cx<TA> As[R16_ROWS][R16_CHUNK + 1];
+  // the tile of A and, after the last chunk, the partial sums of the column
+  // partitions share one LDS area
+  constexpr int AS_BYTES = sizeof(cx<TA>) * R16_ROWS * (R16_CHUNK + 1);
+  constexpr int RED_BYTES = sizeof(zd) * 3 * 4 * R16_ROWS;
+  __shared__ __align__(16) unsigned char area[AS_BYTES > RED_BYTES ? AS_BYTES : RED_BYTES];
   __shared__ zd Ys[16][R16_CHUNK];
-  __shared__ zd Red[3][4][R16_ROWS];
+  auto As = reinterpret_cast<cx<TA>(*)[R16_CHUNK + 1]>(area);
+  auto Red = reinterpret_cast<zd(*)[4][R16_ROWS]>(area);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int G = nrhs <= 4 ? 1 : (nrhs <= 8 ? 2 : 4);  // vector groups
   const int P = 4 / G;                                 // column partitions per group
   const int g = w % G, p = w / G;
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = zd{0.0, 0.0};
+  constexpr int YPER = (16 * R16_CHUNK) / 256;  // vector values per thread per chunk
   cx<TA> pre[PER];
+  zd ypre[YPER];
   auto load = [&](int cb) {
     const int cn = min(R16_CHUNK, c1 - cb);
 #pragma unroll
@@ -50,19 +57,24 @@ __device__ __forceinline__ void rows16_acc(const cx<TA>* __restrict__ a, long ld
       const int rr = min(rbase + r, rend - 1);
       pre[k] = c < cn ? a[(long)rr * lda + cb + c] : cx<TA>{TA(0), TA(0)};
     }
+#pragma unroll
+    for (int k = 0; k < YPER; ++k) {
+      const int e = tid + 256 * k, s = e / R16_CHUNK, c = e % R16_CHUNK;
+      ypre[k] = (s < nrhs && c < cn) ? vec(s, cb + c) : zd{0.0, 0.0};
+    }
   };
   if (c0 < c1) load(c0);
   for (int cb = c0; cb < c1; cb += R16_CHUNK) {
-    const int cn = min(R16_CHUNK, c1 - cb);
     __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + 256 * k;
       As[e / R16_CHUNK][e % R16_CHUNK] = pre[k];
     }
-    for (int e = tid; e < 16 * R16_CHUNK; e += 256) {
-      const int s = e / R16_CHUNK, c = e % R16_CHUNK;
-      Ys[s][c] = (s < nrhs && c < cn) ? vec(s, cb + c) : zd{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < YPER; ++k) {
+      const int e = tid + 256 * k;
+      Ys[e / R16_CHUNK][e % R16_CHUNK] = ypre[k];
     }
     __syncthreads();
     if (cb + R16_CHUNK < c1) load(cb + R16_CHUNK);  // in flight during the arithmetic below

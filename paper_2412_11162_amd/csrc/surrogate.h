@@ -15,7 +15,8 @@
 
 namespace pmlbie {
 
-constexpr int SG_IN = 5;          // features
+constexpr int SG_IN = 7;          // raw inputs (rho, rho', dz, k, S, Im rho~, Im rho~')
+constexpr int SG_NF = 9;          // features the input layer sees (padded to SG_D[0])
 constexpr int SG_MODES = 65;      // modes 0..64
 constexpr int SG_OUT = 6 * SG_MODES;  // 3 heads x (Re, Im) x modes = 390
 constexpr int SG_NL = 5;          // layers (4 hidden of 256 + output)
@@ -35,8 +36,11 @@ struct SgSample {
   double rt_re, rt_im, rs_re, rs_im, dz, k;
 };
 
-// Feature map (rho, rho', dz, k, S) -> network input, affine to O(1) ranges:
-// 2 rho / rho_max - 1, 2 rho' / rho_max - 1, dz, (k - 17.5) / 12.5, (S - 2.5) / 1.5.
+// Feature map of the raw inputs (rho, rho', dz, k, S, Im rho~, Im rho~') ->
+// network input, O(1) ranges: 2 rho / rho_max - 1, 2 rho' / rho_max - 1, dz,
+// (k - 17.5) / 12.5, (S - 2.5) / 1.5, Im rho~, Im rho~' (the PML stretching of
+// the two points), k |R0| / 50 and k (|R_pi| - |R0|) / 100 (the phase scale
+// and the phase swing of e^{ikR} over the angle; R0, R_pi = R at D = 0, pi).
 struct SgFeat {
   double rho_max;  // a1 + T of the PML the network is trained for
 };
@@ -93,17 +97,29 @@ void sg_loss(SgWork& w, int n, const float* T, hipStream_t st);
 void sg_adam(SgNet& net, double lr, hipStream_t st);
 // Labels of n samples by the raw-kernel FFT of length L (512 or 1024).
 void sg_label(const SgSample* s, long n, int L, const zd* tw, float* T, hipStream_t st);
-// Raw features of the far pairs of a list, two rows per pair (k1, k2):
-// x[row] = (rho, rho', dz, k, S).
+// Raw inputs of the far pairs of a list, two rows per pair (k1, k2):
+// x[row] = (rho, rho', dz, k, S, Im rho~, Im rho~').
 void sg_pair_features(const PairGeom* g, long n, double k1, double k2, double S, double* x,
                       hipStream_t st);
 // Acceptance of the network's modes for the far pairs [first, first + n) of a
-// list, Y rows 2q (k1) and 2q + 1 (k2): modes 0..M emitted into A when the
-// network's modal synthesis at four angles matches direct samples of S and
-// K to tol (entry scale 4 pi W_l |error|), otherwise the pair is appended
-// to the fallback list.
-void sg_accept(const PairGeom* g, const int2* dest, long n, const float* Y, int M, zd k1, zd k2,
+// list, Y rows 2q (k1) and 2q + 1 (k2): the network's modal synthesis
+// (modes 0..64) is compared with direct samples of S and K at SG_CHECK
+// angles pi (a + u) / SG_CHECK, a < SG_CHECK, with an offset u in [0, 1) drawn
+// per pair (splitmix64 of its destination), so that no fixed pattern of mode
+// errors can pass unseen for all pairs; the samples hold every mode, so the
+// check also bounds the modes beyond 64 the synthesis leaves out.  When
+// M > 64 a pair is only offered if its modes beyond 64 are below e^{-c_far}
+// by the decay bound of the classification ((65 - bw) delta >= c_far); its
+// modes 65..M are then zero.  Accepted pairs (4 pi W_l |error| <= tol over
+// the angles and both media) get modes 0..M in A; the others go to the
+// fallback list.
+constexpr int SG_CHECK = 8;
+void sg_accept(const PairGeom* g, const int2* dest, long n, const float* Y, int M, int m0, zd k1, zd k2,
                double tol, zd* A, long n2, long mstride, const double* W, WorkList fallback,
-               unsigned* accepted, hipStream_t st);
+               unsigned* accepted, const ClassParams& cp, hipStream_t st);
+// Relative RMS error per mode of the network over n samples (features x,
+// targets T): err2[m] += sum over the 3 heads of |Y - T|^2 at mode m,
+// ref2[m] += |T|^2 (device accumulators of 65 doubles each).
+void sg_mode_errors(const float* Y, const float* T, int n, double* err2, double* ref2, hipStream_t st);
 
 }  // namespace pmlbie

@@ -146,6 +146,16 @@ __global__ void k_sg_features(const double* __restrict__ x, int n, double rho_ma
   else if (c == 2) f = xr[2];
   else if (c == 3) f = (xr[3] - 17.5) / 12.5;
   else if (c == 4) f = (xr[4] - 2.5) / 1.5;
+  else if (c == 5) f = xr[5];
+  else if (c == 6) f = xr[6];
+  else if (c == 7 || c == 8) {
+    const zd rt{xr[0], xr[5]}, rs{xr[1], xr[6]};
+    const zd dr = rt - rs;
+    const zd d2 = dr * dr + zd{xr[2] * xr[2], 0.0};
+    const double r0 = cabs_(csqrt_(d2));
+    if (c == 7) f = xr[3] * r0 / 50.0;
+    else f = xr[3] * (cabs_(csqrt_(d2 + 4.0 * (rt * rs))) - r0) / 100.0;
+  }
   h0[e] = f2bf((float)f);
 }
 
@@ -272,16 +282,29 @@ __global__ void k_sg_pair_features(const PairGeom* __restrict__ g, long n, doubl
   o[2] = p.dz.re;
   o[3] = (r & 1) ? k2 : k1;
   o[4] = S;
+  o[5] = p.rt.im;
+  o[6] = p.rs.im;
+}
+
+// Uniform draw in [0, 1) from a 64-bit key: the splitmix64 output function
+// (Steele, Lea and Flood 2014) applied to key + its increment.
+__device__ __forceinline__ double sg_hash01(unsigned long long key) {
+  unsigned long long z = key + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
 }
 
 // Acceptance: one wavefront per pair; lane n < 64 holds mode n, lane 0 also
 // mode 64.  The modal synthesis (1/2pi)(F_0 + 2 sum_n F_n cos nD) of S and K
-// at D = 0, pi/3, 2pi/3, pi is compared with direct samples of the kernels.
+// at SG_CHECK angles with a per-pair offset is compared with direct samples
+// of the kernels (see sg_accept).
 __global__ __launch_bounds__(64) void k_sg_accept(const PairGeom* __restrict__ geom,
                                                   const int2* __restrict__ dest, long n,
                                                   const float* __restrict__ Y, int M, zd k1, zd k2,
                                                   double tol, OutSpec o, WorkList fb,
-                                                  unsigned* accepted) {
+                                                  unsigned* accepted, ClassParams cp) {
   constexpr int DY = SG_D[SG_NL];
   const int lane = threadIdx.x & 63;
   unsigned acc_count = 0;
@@ -289,8 +312,16 @@ __global__ __launch_bounds__(64) void k_sg_accept(const PairGeom* __restrict__ g
     const PairGeom g = geom[q];
     const int2 dst = dest[q];
     const PairInv v = pair_invariants(g);
-    zd Fs[2][2], Fk[2][2];  // [wavenumber][mode lane, mode 64]
     bool ok = true;
+    if (M >= SG_MODES) {
+      // modes beyond 64 must be negligible: the decay bound of the far class
+      double delta, re0;
+      singularity(v, delta, re0);
+      const double bw = cp.bw * cp.kmax * sqrt(cabs_(g.rt * g.rs));
+      ok = ((double)SG_MODES - bw) * delta >= cp.c_far;
+    }
+    zd Fs[2][2], Fk[2][2];  // [wavenumber][mode lane, mode 64]
+    const double u = sg_hash01(((unsigned long long)(unsigned)dst.x << 32) | (unsigned)dst.y);
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
       const zd k = w == 0 ? k1 : k2;
@@ -299,18 +330,19 @@ __global__ __launch_bounds__(64) void k_sg_accept(const PairGeom* __restrict__ g
       double sS, sK;
       sg_norm(g.rt, g.rs, g.dz.re, k.re, e0, sS, sK);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int m = u == 0 ? lane : 64;
+      for (int b = 0; b < 2; ++b) {
+        const int m = b == 0 ? lane : 64;
         const zd ys{y[2 * m], y[2 * m + 1]};
         const zd yp{y[2 * SG_MODES + 2 * m], y[2 * SG_MODES + 2 * m + 1]};
         const zd yq{y[4 * SG_MODES + 2 * m], y[4 * SG_MODES + 2 * m + 1]};
-        Fs[w][u] = (sS * e0) * ys;
-        Fk[w][u] = (sK * e0) * (g.nr * yp + g.nz * yq);
+        Fs[w][b] = (sS * e0) * ys;
+        Fk[w][b] = (sK * e0) * (g.nr * yp + g.nz * yq);
       }
+      if (!ok) continue;
       double err = 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const double D = a * (PMLBIE_PI / 3.0);
+#pragma unroll 1
+      for (int a = 0; a < SG_CHECK; ++a) {
+        const double D = (a + u) * (PMLBIE_PI / SG_CHECK);
         const double c0 = lane == 0 ? 1.0 : 2.0 * cos(lane * D);
         zd ps = c0 * Fs[w][0], pk = c0 * Fk[w][0];
         if (lane == 0) {
@@ -336,6 +368,8 @@ __global__ __launch_bounds__(64) void k_sg_accept(const PairGeom* __restrict__ g
     if (ok) {
       if (lane <= M) emit(o, dst, lane, Fs[0][0], Fk[0][0], Fs[1][0], Fk[1][0]);
       if (lane == 0 && M >= 64) emit(o, dst, 64, Fs[0][1], Fk[0][1], Fs[1][1], Fk[1][1]);
+      const zd z0{0.0, 0.0};
+      for (int m = SG_MODES + lane; m <= M; m += 64) emit(o, dst, m, z0, z0, z0, z0);
       ++acc_count;
     } else if (lane == 0) {
       const unsigned slot = atomicAdd(fb.count, 1u);
@@ -346,6 +380,37 @@ __global__ __launch_bounds__(64) void k_sg_accept(const PairGeom* __restrict__ g
     }
   }
   if (lane == 0 && acc_count) atomicAdd(accepted, acc_count);
+}
+
+// Per-mode error sums of the network outputs Y (rows of SG_D[SG_NL]) against
+// targets T (rows of SG_OUT): one thread per (row, mode), block sums in LDS.
+__global__ __launch_bounds__(256) void k_sg_mode_err(const float* __restrict__ Y, const float* __restrict__ T,
+                                                     int n, double* err2, double* ref2) {
+  __shared__ double se[SG_MODES], sr[SG_MODES];
+  for (int m = threadIdx.x; m < SG_MODES; m += blockDim.x) se[m] = sr[m] = 0.0;
+  __syncthreads();
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (long)n * SG_MODES) {
+    const long r = e / SG_MODES;
+    const int m = (int)(e % SG_MODES);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int h = 0; h < 3; ++h)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int j = h * 2 * SG_MODES + 2 * m + c;
+        const double t = T[r * SG_OUT + j], d = (double)Y[r * SG_D[SG_NL] + j] - t;
+        a += d * d;
+        b += t * t;
+      }
+    atomicAdd(&se[m], a);
+    atomicAdd(&sr[m], b);
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < SG_MODES; m += blockDim.x) {
+    atomicAdd(err2 + m, se[m]);
+    atomicAdd(ref2 + m, sr[m]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -525,14 +590,20 @@ void sg_pair_features(const PairGeom* g, long n, double k1, double k2, double S,
                      k2, S, x);
 }
 
-void sg_accept(const PairGeom* g, const int2* dest, long n, const float* Y, int M, zd k1, zd k2,
+void sg_accept(const PairGeom* g, const int2* dest, long n, const float* Y, int M, int m0, zd k1, zd k2,
                double tol, zd* A, long n2, long mstride, const double* W, WorkList fallback,
-               unsigned* accepted, hipStream_t st) {
+               unsigned* accepted, const ClassParams& cp, hipStream_t st) {
   if (n <= 0) return;
-  OutSpec o{A, n2, mstride, W, nullptr, M, 0};
+  OutSpec o{A, n2, mstride, W, nullptr, M, m0};
   const int grid = (int)std::min<long>(n, 256L * 32);
   hipLaunchKernelGGL(k_sg_accept, dim3(grid), dim3(64), 0, st, g, dest, n, Y, M, k1, k2, tol, o, fallback,
-                     accepted);
+                     accepted, cp);
+}
+
+void sg_mode_errors(const float* Y, const float* T, int n, double* err2, double* ref2, hipStream_t st) {
+  const long tot = (long)n * SG_MODES;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_sg_mode_err, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Y, T, n, err2, ref2);
 }
 
 }  // namespace pmlbie

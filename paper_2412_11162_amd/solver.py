@@ -163,6 +163,11 @@ class Solver:
         self._chk(self.L.pmlbie_surrogate_eval(self.h, int(which), _p(m)))
         return float(m[0])
 
+    def surrogate_eval_modes(self, which: int) -> np.ndarray:
+        rel = np.zeros(65)
+        self._chk(self.L.pmlbie_surrogate_eval_modes(self.h, int(which), _p(rel)))
+        return rel
+
     def surrogate_set_tolerance(self, tol: float):
         self._chk(self.L.pmlbie_surrogate_set_tolerance(self.h, float(tol)))
 

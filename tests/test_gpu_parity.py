@@ -45,8 +45,10 @@ def _normwise(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
-def _boundary_err(gpu, ref):
-    """gpu, ref: tuples of [modes, N] arrays (u1, phi1, u2, phi2)."""
+def _boundary_err(gpu, ref, significant=1e-9):
+    """gpu, ref: tuples of [modes, N] arrays (u1, phi1, u2, phi2).  Modes
+    whose data are below `significant` times the largest mode's are measured
+    against the largest mode (absolute), the others against themselves."""
     x_g = np.concatenate(gpu, axis=1)
     x_r = np.concatenate(ref, axis=1)
     big = np.max(np.linalg.norm(x_r, axis=1))
@@ -54,7 +56,7 @@ def _boundary_err(gpu, ref):
     for j in range(x_r.shape[0]):
         nr = np.linalg.norm(x_r[j])
         d = np.linalg.norm(x_g[j] - x_r[j])
-        errs.append(d / nr if nr > 1e-9 * big else d / big)
+        errs.append(d / nr if nr > significant * big else d / big)
     return np.array(errs)
 
 
@@ -349,14 +351,19 @@ def _stored_incidences(ref):
 def _stored_errors(out, ref, m0=0):
     """Per (mode, right-hand side) boundary-data errors of the GPU outputs
     ([mode - m0][rhs][node] arrays or tensors) against a stored oracle file
-    ([mode subset][rhs][node])."""
+    ([mode subset][rhs][node]).  A mode whose data are below 1e-6 of the
+    largest mode of its right-hand side is measured absolutely against the
+    largest: the plane-wave data are modes of azimuthal samples (FFT), whose
+    rounding is absolute (~1e-16 of the largest mode), so the relative
+    accuracy of a mode 1e-7 below the largest is ~1e-9 before the solve's
+    condition number acts on it."""
     modes = [int(m) for m in ref["modes"]]
     gpu = [o.cpu().numpy() if hasattr(o, "cpu") else np.asarray(o) for o in out]
     nr = ref["u1"].shape[1]
     errs = np.zeros((len(modes), nr))
     for r in range(nr):
         sel = [g[[m - m0 for m in modes], r, :] for g in gpu]
-        errs[:, r] = _boundary_err(sel, tuple(ref[k][:, r, :] for k in ("u1", "p1", "u2", "p2")))
+        errs[:, r] = _boundary_err(sel, tuple(ref[k][:, r, :] for k in ("u1", "p1", "u2", "p2")), 1e-6)
     return modes, errs
 
 

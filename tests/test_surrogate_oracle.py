@@ -21,7 +21,7 @@ def _params(seed=3):
     w, b, tot = mlp.layout()
     p = np.zeros(tot)
     for l in range(5):
-        fin = 5 if l == 0 else mlp.D[l]
+        fin = 9 if l == 0 else mlp.D[l]
         fout = 390 if l == 4 else mlp.D[l + 1]
         a = math.sqrt(6.0 / (fin + fout))
         W = np.zeros((mlp.D[l + 1], mlp.D[l]))
@@ -34,7 +34,8 @@ def _params(seed=3):
 def _batch(n=6, seed=4):
     rng = np.random.default_rng(seed)
     x = np.column_stack([rng.uniform(0.1, 5.4, n), rng.uniform(0.1, 5.4, n), rng.uniform(-1, 1, n),
-                         rng.uniform(5, 30, n), rng.uniform(1, 4, n)])
+                         rng.uniform(5, 30, n), rng.uniform(1, 4, n), rng.uniform(0, 1.5, n),
+                         rng.uniform(0, 1.5, n)])
     t = rng.normal(size=(n, 390))
     return x, t
 
@@ -48,7 +49,7 @@ def test_reference_gradient_matches_finite_differences():
     # weights of every layer (inside the unpadded block) and biases
     idx = []
     for l in range(5):
-        fin = 5 if l == 0 else mlp.D[l]
+        fin = 9 if l == 0 else mlp.D[l]
         fout = 390 if l == 4 else mlp.D[l + 1]
         for _ in range(6):
             o, i = rng.integers(fout), rng.integers(fin)
@@ -62,7 +63,7 @@ def test_reference_gradient_matches_finite_differences():
         fd = (mlp.loss_grad(pp, x, t, 5.5)[0] - mlp.loss_grad(pm, x, t, 5.5)[0]) / (2 * h)
         assert abs(fd - g[j]) <= 1e-6 * max(1.0, abs(g[j])) + 1e-9, (j, fd, g[j])
     # padded columns of the first layer and padded rows of the last get no gradient
-    assert np.all(g[w[0]:w[0] + mlp.D[1] * 32].reshape(mlp.D[1], 32)[:, 5:] == 0)
+    assert np.all(g[w[0]:w[0] + mlp.D[1] * 32].reshape(mlp.D[1], 32)[:, 9:] == 0)
     assert np.all(g[w[4]:w[4] + 400 * 256].reshape(400, 256)[390:] == 0)
 
 
