@@ -161,14 +161,16 @@ def stored_oracle_errors(s, name, precision):
             "max_rel_err": worst, "max_rel_err_per_mode": {str(k): v for k, v in per_mode.items()}}
 
 
-def surrogate_leg(s, wl, tol: float = 2e-8, steps: int = 12288):
+def surrogate_leg(s, wl, tol: float = 2.5e-9, steps: int = 12288):
     """The learned surrogate in the combined form on the paper-scale workload:
     training on 2^22 labelled samples (timed apart: it is amortised over
     builds; three passes over the set), then the mixed-precision step (all
     modes 0..128; modes beyond 64 only for pairs whose decay bound makes
     them negligible) with and without it.  The acceptance tolerance follows
-    from the 1e-6 bar (the boundary data move by a few times tol); the error
-    is measured against the plain mixed step and, when stored, the oracle."""
+    from the 1e-6 bar (the boundary data move by up to ~40 times tol, so
+    2.5e-9 leaves a factor of ~10); the error is measured against the plain
+    mixed step, and a sweep of looser tolerances shows what the network's
+    accuracy would buy beyond the bar."""
     import torch
     from paper_2412_11162_amd import _binding as B
 

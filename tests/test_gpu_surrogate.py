@@ -149,9 +149,10 @@ def test_rejection_storm_is_bit_identical_to_the_plain_path():
 
 # Acceptance tolerance derived from the 1e-6 bar: the check bounds every
 # mode's entry error of an accepted pair by tol, and the boundary data move by
-# a few times tol (measured: 4.6e-11 for tol 1e-11 at paper scale), so
-# tol = 2e-8 keeps a factor of ~10 below the bar.
-SG_TOL = 2e-8
+# up to ~40 times tol (measured at paper scale with a trained network: 6.6e-7
+# for tol 2e-8, 4.0e-5 for tol 1e-6), so tol = 2.5e-9 keeps a factor of ~10
+# below the bar.
+SG_TOL = 2.5e-9
 
 
 def test_surrogate_combined_form_against_the_oracle():
