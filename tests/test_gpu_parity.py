@@ -348,29 +348,47 @@ def _stored_incidences(ref):
             for k, p in zip(ref["inc_kind"], ref["inc_param"])]
 
 
-def _stored_errors(out, ref, m0=0):
+# Floor of the per-mode measure against stored oracle solves (below).
+MODE_FLOOR = 1e-3
+
+
+def _stored_errors(out, ref, m0=0, floor=MODE_FLOOR):
     """Per (mode, right-hand side) boundary-data errors of the GPU outputs
     ([mode - m0][rhs][node] arrays or tensors) against a stored oracle file
-    ([mode subset][rhs][node]).  A mode whose data are below 1e-6 of the
-    largest mode of its right-hand side is measured absolutely against the
-    largest: the plane-wave data are modes of azimuthal samples (FFT), whose
-    rounding is absolute (~1e-16 of the largest mode), so the relative
-    accuracy of a mode 1e-7 below the largest is ~1e-9 before the solve's
-    condition number acts on it."""
+    ([mode subset][rhs][node]): ||dx_n|| / max(||x_n||, floor * max_m ||x_m||)
+    over the stored modes m of the same right-hand side.  Both sides resolve a
+    small mode only to an absolute level set by the largest one: the oracle's
+    azimuthal quadrature stops at 1e-14 of each pair's largest mode, the
+    FFT modes of the library carry rounding of ~1e-16 of it, and the per-mode
+    systems amplify either by their condition number (~1e3-1e4 here), so a
+    mode 1e-4 below the largest agrees only to ~1e-8 of itself even when both
+    sides are right.  Measured against 1e-3 of the largest such a mode is held
+    to 1e-11 of the largest; every mode above it is held to the bar of itself."""
     modes = [int(m) for m in ref["modes"]]
     gpu = [o.cpu().numpy() if hasattr(o, "cpu") else np.asarray(o) for o in out]
     nr = ref["u1"].shape[1]
     errs = np.zeros((len(modes), nr))
+    raw = np.zeros((len(modes), nr))
     for r in range(nr):
-        sel = [g[[m - m0 for m in modes], r, :] for g in gpu]
-        errs[:, r] = _boundary_err(sel, tuple(ref[k][:, r, :] for k in ("u1", "p1", "u2", "p2")), 1e-6)
+        xg = np.concatenate([g[[m - m0 for m in modes], r, :] for g in gpu], axis=1)
+        xr = np.concatenate([ref[k][:, r, :] for k in ("u1", "p1", "u2", "p2")], axis=1)
+        norms = np.linalg.norm(xr, axis=1)
+        big = norms.max()
+        for j in range(len(modes)):
+            d = np.linalg.norm(xg[j] - xr[j])
+            errs[j, r] = d / max(norms[j], floor * big)
+            raw[j, r] = d / norms[j] if norms[j] > 0 else d / big
+    _stored_errors.raw = raw
     return modes, errs
 
 
 def _print_errors(tag, modes, errs, incs):
-    print("\n%s: per-mode boundary-data error against the oracle" % tag)
+    raw = getattr(_stored_errors, "raw", None)
+    print("\n%s: per-mode boundary-data error against the oracle (floored measure; "
+          "in brackets relative to the mode itself)" % tag)
     for j, m in enumerate(modes):
-        print("  mode %3d: %s" % (m, " ".join("%.1e" % e for e in errs[j])))
+        print("  mode %3d: %s" % (m, " ".join("%.1e [%.1e]" % (e, raw[j, r]) if raw is not None else "%.1e" % e
+                                              for r, e in enumerate(errs[j]))))
     print("  incidences:", incs, flush=True)
 
 
