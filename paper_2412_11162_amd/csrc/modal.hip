@@ -177,10 +177,126 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
   transform_emit<R>(P2, E, tw, o, dst, 2);
 }
 
-// Main grid: every (target i, source l) pair off the near panels.  Far pairs
-// are finished here (raw-kernel FFT over theta on this pass's grid of 64 R
-// angles); the others are appended to the split / direct work lists, and far
-// pairs that need a longer grid to the far_big list.  One wavefront per pair.
+// Modes m0..M of one transformed sequence into a mode-strided column of A:
+// base is the entry of mode m0, f the quadrature weight with the sign of the
+// block.
+template <int R>
+__device__ __forceinline__ void emit_strided(zd* base, long mstride, int m0, int M, double f,
+                                             const zd (&x)[R]) {
+  const int b = threadIdx.x & 63;
+#pragma unroll
+  for (int sl = 0; sl < R; ++sl) {
+    const int n = fft_wave_out_index<R>(b, sl);
+    if (n >= m0 && n <= M) base[(long)(n - m0) * mstride] = f * x[sl];
+  }
+}
+
+// Both orderings of a far pair at once: pair a = (i, l) (source l) and pair
+// b = (l, i) (source i) share the distance R and e^{ikR}, hence the single
+// layer S (reciprocity); only the double-layer numerators differ.  Per
+// wavenumber: the samples of S, K_a, K_b on the half circle are staged in
+// LDS, S and K_a are transformed together and emitted to a (S also to b),
+// then K_b alone to b.  Two of the four complex exponentials and two of the
+// eight transforms of two separate pairs are saved.  The coarse grid and the
+// weights follow far_pair.  LDS: K_b at [0, H), S and K_a at [H, 3H), the
+// exchange area of the transform from H on (S and K_a are in registers by
+// then); within far_lds<R>() for R <= 16.
+template <int R>
+__device__ __forceinline__ void far_pair_sym(const PairInv& v, zd N0b, zd N1b, zd k1, zd k2,
+                                             const zd* __restrict__ tw, zd* lds, const OutSpec& o, int2 da,
+                                             int2 db, bool coarse) {
+  if constexpr (R > 16) {
+    // the 2048-point grid stages one sequence at a time (far_pair): the two
+    // orderings are transformed separately
+    far_pair<R>(v, k1, k2, tw, lds, o, da, coarse);
+    PairInv vb = v;
+    vb.N0 = N0b;
+    vb.N1 = N1b;
+    __syncthreads();
+    far_pair<R>(vb, k1, k2, tw, lds, o, db, coarse);
+    return;
+  }
+  constexpr int L = 64 * R, H = L / 2 + 1;
+  zd* Kb = lds;
+  zd* SK = lds + H;
+  zd* E = lds + H;
+  const int ns = coarse ? L / 4 : L / 2 + 1;
+  const double w4pi = (coarse ? 2.0 : 1.0) * (0.25 / PMLBIE_PI);
+  const double scale = 2.0 * PMLBIE_PI / L;
+  // entries of mode m0 of both orderings (S entries at unknown 2l + 1 with
+  // the block's minus sign, K entries at 2l)
+  const double fa = 2.0 * o.W[da.y] * scale, fb = 2.0 * o.W[db.y] * scale;
+  zd* const pa = o.A + (2L * da.x) * o.n2 + 2L * da.y;
+  zd* const pb = o.A + (2L * db.x) * o.n2 + 2L * db.y;
+  const int b = threadIdx.x & 63;
+#pragma unroll 1
+  for (int w = 0; w < 2; ++w) {
+    const zd k = w == 0 ? k1 : k2;
+#pragma unroll 1
+    for (int q = b; q < ns; q += 64) {
+      const int j = coarse ? 2 * q + 1 : q;
+      const zd t = tw[j];
+      const double s2 = t.re >= 0.0 ? t.im * t.im / (2.0 + 2.0 * t.re) : 0.5 - 0.5 * t.re;
+      const zd Rd = csqrt_(v.d2 + s2 * v.c4);
+      const zd iR = inv(Rd);
+      const zd ikR = zd{0.0, 1.0} * (k * Rd);
+      const zd e = cexp_(ikR) * (iR * w4pi);
+      const zd iR2 = iR * iR;
+      // the same products, in the same order, as far_pair
+      SK[j] = e;
+      SK[H + j] = (v.N0 + s2 * v.N1) * e * (ikR - 1.0) * iR2;
+      Kb[j] = (N0b + s2 * N1b) * e * (ikR - 1.0) * iR2;
+      if (coarse) {
+        const zd z0{0.0, 0.0};
+        SK[j - 1] = z0;
+        SK[H + j - 1] = z0;
+        Kb[j - 1] = z0;
+      }
+    }
+    if (coarse && b == 0) {
+      const zd z0{0.0, 0.0};
+      SK[L / 2] = z0;
+      SK[H + L / 2] = z0;
+      Kb[L / 2] = z0;
+    }
+    __syncthreads();
+    const long row = w * o.n2;  // lower-medium equation: one row down
+    {
+      zd x[2][R];
+      load_even<R, 2>(SK, x);
+      __syncthreads();
+      fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[0]), E, tw);
+      emit_strided<R>(pa + row + 1, o.mstride, o.m0, o.M, -fa, x[0]);
+      emit_strided<R>(pb + row + 1, o.mstride, o.m0, o.M, -fb, x[0]);
+      fft_wave<R, 1>(*reinterpret_cast<zd(*)[1][R]>(&x[1]), E, tw);
+      emit_strided<R>(pa + row, o.mstride, o.m0, o.M, fa, x[1]);
+    }
+    {
+      zd x[1][R];
+      load_even<R, 1>(Kb, x);
+      __syncthreads();
+      fft_wave<R, 1>(x, E, tw);
+      emit_strided<R>(pb + row, o.mstride, o.m0, o.M, fb, x[0]);
+    }
+  }
+}
+
+// Main grid over the unordered pairs {i, l} (i < l) off the near panels,
+// both orderings at once (the class, the coarse flag and the far pass are
+// symmetric in the two points).  Far pairs are finished here (raw-kernel FFT
+// over theta on this pass's grid of 64 R angles); the others are appended to
+// the split / direct work lists in both orderings, and far pairs that need a
+// longer grid to the far_big list.  One wavefront per unordered pair.  The
+// pairs are walked in 4 x 4 tiles of nodes (tile rows I <= J of the triangle
+// of tiles, then i = 4 I + r / 4, l = 4 J + r % 4): the 16 pairs of a tile
+// fill whole 128-byte lines of both orderings' rows (4 nodes x (u, phi)
+// columns), where a walk along one row of the triangle would write the
+// transposed ordering one column at a time.
+constexpr int FAR_TILE = 4;
+__host__ __device__ inline long far_tile_slots(int N) {
+  const long nt = (N + FAR_TILE - 1) / FAR_TILE;
+  return nt * (nt + 1) / 2 * (FAR_TILE * FAR_TILE);
+}
 template <int R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
@@ -188,13 +304,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                  WorkList split_big) {
   __shared__ zd lds[far_lds<R>()];
   const int N = nd.N;
-  const long total = (long)N * N;
+  const long NT = (N + FAR_TILE - 1) / FAR_TILE;
+  const long total = far_tile_slots(N);
+  const double tn = 2.0 * NT + 1.0;
   // workgroups are dealt to the 8 XCDs round-robin; each XCD takes a
-  // contiguous run of pairs so that the partial cache lines its neighbouring
-  // sources write meet in one L2
+  // contiguous run of tiles so that the lines they write meet in one L2
   const long lb = (long)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   for (long p = lb; p < total; p += gridDim.x) {
-    const int l = (int)(p % N), i = (int)(p / N);  // neighbouring sources write neighbouring columns
+    const long t = p >> 4;
+    const int r = (int)(p & 15);
+    // tile row I starts at s(I) = I (2 NT + 1 - I) / 2
+    long I = (long)floor(0.5 * (tn - sqrt(tn * tn - 8.0 * (double)t)));
+    if (I < 0) I = 0;
+    while (I > 0 && I * (2 * NT + 1 - I) / 2 > t) --I;
+    while ((I + 1) * (2 * NT - I) / 2 <= t) ++I;
+    const long J = t - I * (2 * NT + 1 - I) / 2 + I;
+    const int i = (int)(FAR_TILE * I) + (r >> 2), l = (int)(FAR_TILE * J) + (r & 3);
+    if (l <= i || l >= N) continue;
     const int dp = nd.panel[i] - nd.panel[l];
     if (dp >= -1 && dp <= 1) continue;  // near panels: product integration
     const PairGeom g = node_pair(nd, i, l);
@@ -202,18 +328,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     bool coarse = false;
     const int cls = classify(g, v, cp, &coarse);
     if (cls != CLASS_FAR) {
-      if (threadIdx.x == 0) {
+      if (threadIdx.x < 2) {
         WorkList& wl = cls == CLASS_SPLIT ? split
                        : (cls == CLASS_DIRECT ? direct : (cls == CLASS_FAR_BIG ? far_big : split_big));
-        unsigned slot = atomicAdd(wl.count, 1u);
+        const unsigned slot = atomicAdd(wl.count, 1u);
         if (slot < wl.cap) {
-          wl.geom[slot] = g;
-          wl.dest[slot] = make_int2(i, l);
+          wl.geom[slot] = threadIdx.x == 0 ? g : node_pair(nd, l, i);
+          wl.dest[slot] = threadIdx.x == 0 ? make_int2(i, l) : make_int2(l, i);
         }
       }
       continue;
     }
-    far_pair<R>(v, k1, k2, tw, lds, o, make_int2(i, l), coarse);
+    // the conormal numerator of the ordering (l, i): source i, target l
+    const zd nrb{nd.nr_re[i], nd.nr_im[i]}, nzb{nd.nz_re[i], nd.nz_im[i]};
+    const zd N0b = nrb * g.drho + nzb * g.dz;  // -(n_i . (r~_l - r~_i))
+    const zd N1b = 2.0 * (nrb * g.rs);
+    far_pair_sym<R>(v, N0b, N1b, k1, k2, tw, lds, o, make_int2(i, l), make_int2(l, i), coarse);
   }
 }
 
@@ -796,8 +926,9 @@ template <int R>
 static void launch_far_t(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2, const zd* tw,
                          const OutSpec& o, WorkList split, WorkList direct, WorkList far_big,
                          WorkList split_big, hipStream_t st) {
-  long total = (long)nd.N * nd.N;
+  const long total = far_tile_slots(nd.N);  // tile slots of the unordered pairs
   int grid = (int)std::min<long>((total + 7) / 8 * 8, 256L * 128);  // a multiple of 8
+  if (grid < 8) grid = 8;
   hipLaunchKernelGGL(k_grid_far<R>, dim3(grid), dim3(64), 0, st, nd, cp, k1, k2, tw, o, split,
                      direct, far_big, split_big);
 }

@@ -25,10 +25,21 @@ struct PairInv {
   zd d2, c4, N0, N1;
 };
 
+// rho~_t rho~_s with both products rounded before the sum, so that the
+// result does not depend on the order of the two points (a fused
+// multiply-add of one ordering would round the other product only): the
+// invariants of (i, l) and (l, i) are then the same to the bit.
+HD zd rho_product(zd a, zd b) {
+#pragma clang fp contract(off)
+  const double p1 = a.re * b.re, p2 = a.im * b.im;
+  const double p3 = a.re * b.im, p4 = a.im * b.re;
+  return zd{p1 - p2, p3 + p4};
+}
+
 HD PairInv pair_invariants(const PairGeom& g) {
   PairInv v;
   v.d2 = g.drho * g.drho + g.dz * g.dz;
-  v.c4 = 4.0 * (g.rt * g.rs);
+  v.c4 = 4.0 * rho_product(g.rt, g.rs);
   v.N0 = -(g.nr * g.drho + g.nz * g.dz);
   v.N1 = 2.0 * (g.nr * g.rt);
   return v;

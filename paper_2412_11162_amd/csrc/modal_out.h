@@ -105,7 +105,7 @@ __device__ __forceinline__ int classify(const PairGeom& g, const PairInv& v, con
                                         bool* coarse = nullptr) {
   double delta, re0;
   singularity(v, delta, re0);
-  const double sc = sqrt(cabs_(g.rt * g.rs));
+  const double sc = sqrt(cabs_(rho_product(g.rt, g.rs)));
   const double bw = cp.bw * cp.kmax * sc;
   if ((cp.nt_far - cp.M - bw) * delta >= cp.c_far) {
     int nt = cp.nt_far;

@@ -1,7 +1,7 @@
 """GPU tests of the learned surrogate: labels against the FP64 oracle, the
 BF16 MFMA forward and backward passes against the FP64 reference network,
 training, persistence, and the operator build with the surrogate (rejection
-storm bit-identical to the plain path; accepted modes within the mixed
+storm equal to the plain path to rounding; accepted modes within the mixed
 precision + surrogate bar of 1e-6 on the boundary data)."""
 
 import numpy as np
@@ -131,7 +131,15 @@ def test_training_reduces_held_out_error_and_blob_round_trips():
     assert np.array_equal(s.surrogate_forward(x), t.surrogate_forward(x))
 
 
-def test_rejection_storm_is_bit_identical_to_the_plain_path():
+def test_rejection_storm_reproduces_the_plain_path():
+    """Tolerance 0 rejects every surrogate pair, so every far pair is
+    recomputed by its raw-kernel FFT, one ordering at a time.  The plain path
+    transforms both orderings of a far pair in one pass, whose instructions
+    round differently (fused multiply-adds placed differently), so the two
+    agree to rounding: a few units in the last place of the entry, or of the
+    mode's largest entry for entries that are far smaller.  A pair left out,
+    written to the wrong ordering or given the wrong numerator differs at the
+    entry's own size."""
     wl = workloads.tiny()
     plain = from_workload(wl, device=0, flags=B.PMLBIE_KEEP_OPERATORS)
     sg = _media_solver(wl)
@@ -141,10 +149,20 @@ def test_rejection_storm_is_bit_identical_to_the_plain_path():
                              B.PMLBIE_KEEP_OPERATORS | B.PMLBIE_USE_SURROGATE)
     _, cnt = sg.stats()
     assert cnt[4] > 0 and cnt[5] == 0
+    N = plain.N
+    worst = 0.0
     for n in range(wl.m_max + 1):
         a = plain.get_operator(n).cpu().numpy()
         b = sg.get_operator(n).cpu().numpy()
-        assert np.array_equal(a, b), n
+        assert np.array_equal(a == 0, b == 0), n
+        bound = 1e-14 * np.abs(a) + 1e-16 * np.abs(a).max()
+        d = np.abs(a - b)
+        worst = max(worst, float((d / bound).max()))
+        r, c = np.nonzero(d > bound)
+        where = [(int(i) // N, int(l) // N, int(i) % N, int(l) % N, complex(a[i, l]), complex(b[i, l]))
+                 for i, l in zip(r[:6], c[:6])]
+        assert r.size == 0, (n, r.size, where)
+    print("storm vs plain: worst difference / bound %.3g" % worst)
 
 
 # Acceptance tolerance derived from the 1e-6 bar: the check bounds every
