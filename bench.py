@@ -146,19 +146,27 @@ def stored_oracle_errors(s, name, precision):
     s.build_modal_operators(wl.n_theta, wl.m_max, precision)
     out = [o.cpu().numpy() for o in s.solve_modes(incs)]
     modes = [int(m) for m in ref["modes"]]
-    worst = 0.0
-    per_mode = {}
+    worst, worst_raw = 0.0, 0.0
+    per_mode, per_mode_raw = {}, {}
     for r in range(len(incs)):
         xg = np.concatenate([o[modes, r, :] for o in out], axis=1)
         xr = np.concatenate([ref[k][:, r, :] for k in ("u1", "p1", "u2", "p2")], axis=1)
         big = np.max(np.linalg.norm(xr, axis=1))
         for j, m in enumerate(modes):
             nr = np.linalg.norm(xr[j])
-            e = float(np.linalg.norm(xg[j] - xr[j]) / (nr if nr > 1e-9 * big else big))
+            d = float(np.linalg.norm(xg[j] - xr[j]))
+            # the parity tests' measure: a mode below 1e-3 of the largest mode of
+            # its right-hand side is measured against 1e-3 of the largest
+            e = d / max(nr, 1e-3 * big)
+            er = d / nr if nr > 0 else d / big
             per_mode[m] = max(per_mode.get(m, 0.0), e)
-            worst = max(worst, e)
+            per_mode_raw[m] = max(per_mode_raw.get(m, 0.0), er)
+            worst, worst_raw = max(worst, e), max(worst_raw, er)
     return {"oracle_file": os.path.relpath(path, ROOT), "modes": modes, "right_hand_sides": len(incs),
-            "max_rel_err": worst, "max_rel_err_per_mode": {str(k): v for k, v in per_mode.items()}}
+            "max_rel_err": worst, "max_rel_err_per_mode": {str(k): v for k, v in per_mode.items()},
+            "measure": "||dx_n|| / max(||x_n||, 1e-3 max_m ||x_m||) per right-hand side",
+            "max_rel_err_to_own_mode": worst_raw,
+            "rel_err_to_own_mode_per_mode": {str(k): v for k, v in per_mode_raw.items()}}
 
 
 def surrogate_leg(s, wl, tol: float = 2.5e-9, steps: int = 12288):
@@ -350,12 +358,22 @@ def plain_headline(s, wl, args):
                      "traffic": gemm_traffic_record("k_gemm_update_paper_scale", "k_gemm_update<double>")
                      if wl.name == "paper_scale" else None,
                      "traffic_unit": "bytes per launch", "launches": launches,
-                     "flop_per_launch": flops / max(launches, 1), "avg_launch_ms": gemm_ms / max(launches, 1)},
+                     "flop_per_launch": flops / max(launches, 1), "avg_launch_ms": gemm_ms / max(launches, 1),
+                     **mfma_executed(achieved, 78.6)},
     }
     return out
 
 
 METRIC = "time-to-solution at 1e-6 rel err vs FP64 oracle; modal-kernel pairs*modes/s"
+
+
+def mfma_executed(achieved, peak):
+    """The trailing update forms each complex product from three real
+    products (3M), so the matrix cores execute 6 of the 8 real flops the
+    algorithmic count (8 per complex multiply-add) assigns it: the executed
+    rate and its fraction of the peak, beside the algorithmic ones."""
+    return {"flop_count": "algorithmic: 8 real flop per complex multiply-add, (8/3)(2N)^3 per mode",
+            "mfma_executed_tflops": 0.75 * achieved, "mfma_executed_frac": 0.75 * achieved / peak}
 
 
 def stage_dict(st):
@@ -400,7 +418,7 @@ def largest_headline(s, wl, args):
                      "traffic": gemm_traffic_record("k_gemm_update_f32_largest", "k_gemm_update<float>"),
                      "traffic_unit": "bytes per launch", "launches": launches,
                      "flop_per_launch": flops / max(launches, 1), "avg_launch_ms": gemm_ms / max(launches, 1),
-                     "batches": nb},
+                     "batches": nb, **mfma_executed(achieved, peak)},
     }
 
 

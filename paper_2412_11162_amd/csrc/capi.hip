@@ -338,12 +338,21 @@ hipError_t resolve_scratch(int device) {
   return e;
 }
 
+// Twiddles e^{-2 pi i k / nt}, k < nt / 2 (k < nt for a full table).  A full
+// table is followed by sin^2(pi j / nt), j = 0..nt/2, in the real parts: the
+// far pass's sin^2(D_j / 2) (tw_s2).
 std::vector<zd> twiddles(int nt, bool full = false) {
-  std::vector<zd> t(full ? nt : nt / 2);
-  for (int k = 0; k < (int)t.size(); ++k) {
+  const int n = full ? nt : nt / 2;
+  std::vector<zd> t(full ? nt + nt / 2 + 1 : n);
+  for (int k = 0; k < n; ++k) {
     double a = -2.0 * PMLBIE_PI * k / nt;
     t[k] = zd{cos(a), sin(a)};
   }
+  if (full)
+    for (int j = 0; j <= nt / 2; ++j) {
+      const double s = sin(PMLBIE_PI * j / nt);
+      t[nt + j] = zd{s * s, 0.0};
+    }
   return t;
 }
 

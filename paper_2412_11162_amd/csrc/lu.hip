@@ -328,7 +328,15 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
 // Trailing update C -= L21 U12 on MFMA (rows below k0 + nb, columns
 // k0 + nb .. cend - 1).  Workgroup tile 64 x 64 (complex), four waves of
 // 32 x 32, K staged through LDS in chunks of 8; registers held to four waves
-// per SIMD, whose interleaving hides the global and LDS latencies.
+// per SIMD (three for FP64), whose interleaving hides the global and LDS
+// latencies.  The complex product takes three real products (the 3M form): with
+// T1 = Lr Ur, T2 = Li Ui, T3 = (Lr + Li)(Ur + Ui), Re C -= T1 - T2 and
+// Im C -= T3 - T1 - T2.  Three accumulators start from C,
+// V1 = 0, V2 = Cr, V3 = Ci - Cr, and collect V1 += T1, V2 += T2, V3 -= T3;
+// then Cr' = V2 - V1 and Ci' = V3 + V1 + V2.  A quarter fewer MFMAs than
+// four real products; the error bound stays normwise that of the complex
+// product (the imaginary part loses its componentwise bound), which the
+// factorisation's backward error and the refinement absorb.
 template <typename T> struct mfma_t;
 template <> struct mfma_t<double> {
   typedef v4d acc;
@@ -455,7 +463,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // inside a matrix the sequence walks groups of 8 tile rows column by column,
 // so the tiles in flight on one XCD share L21 rows and U12 columns in its L2.
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4))) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
                                                      int k0, int nb, int cend, int tx, int ty,
                                                      int batch) {
   typedef typename mfma_t<T>::acc acc_t;
@@ -475,13 +483,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int r0 = m0 + by * 64;  // tile rows of C
   const int c0 = m0 + bx * 64;  // tile columns of C
   constexpr int KC = 8;
-  __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4];  // L21 chunk: [k][row]
-  __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4];  // U12 chunk: [k][col]
+  __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4], Lsm[KC][64 + 4];  // L21 chunk: [k][row]
+  __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4], Usm[KC][64 + 4];  // U12 chunk: [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = (wid & 1) * 32, wc = (wid >> 1) * 32;
   // the accumulators start from C (loaded before the K loop, so its latency
   // overlaps the first chunk) and the products are subtracted
-  acc_t cr[2][2], ci[2][2];
+  acc_t v1[2][2], v2[2][2], v3[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -491,8 +499,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
         const cx<T> v = (gc < cend && gr < n) ? a[(long)gr * n + gc] : cx<T>{T(0), T(0)};
-        cr[x][y][j] = v.re;
-        ci[x][y][j] = v.im;
+        v1[x][y][j] = T(0);
+        v2[x][y][j] = v.re;
+        v3[x][y][j] = v.im - v.re;
       }
   // global -> register prefetch of the next K chunk overlaps the MFMA work
   // on the current one; each thread moves 2 elements of L21 and of U12
@@ -517,32 +526,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int k = e % KC, rr = e / KC;
       Lre[k][rr] = pl[t].re;
       Lim[k][rr] = pl[t].im;
+      Lsm[k][rr] = pl[t].re + pl[t].im;
       const int cc = e & 63, ku = e >> 6;
       Ure[ku][cc] = pu[t].re;
       Uim[ku][cc] = pu[t].im;
+      Usm[ku][cc] = pu[t].re + pu[t].im;
     }
     __syncthreads();
     if (kk + KC < nb) gload(kk + KC);
 #pragma unroll 1
     for (int k4 = 0; k4 < KC; k4 += 4) {
       const int kx = k4 + (lane >> 4), lx = lane & 15;
-      T lr[2], li[2], ur[2], ui[2];
+      T lr[2], li[2], ls[2], ur[2], ui[2], us[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         lr[t] = Lre[kx][wr + 16 * t + lx];  // X[p][k] = L[row p][k]
         li[t] = Lim[kx][wr + 16 * t + lx];
+        ls[t] = Lsm[kx][wr + 16 * t + lx];
         ur[t] = Ure[kx][wc + 16 * t + lx];  // Y[k][q] = U[k][col q]
         ui[t] = Uim[kx][wc + 16 * t + lx];
+        us[t] = Usm[kx][wc + 16 * t + lx];
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)      // row sub-tile
 #pragma unroll
         for (int y = 0; y < 2; ++y) {  // column sub-tile
-          // C -= L U: re -= lr ur - li ui, im -= lr ui + li ur
-          cr[x][y] = mfma_t<T>::op(-lr[x], ur[y], cr[x][y]);
-          ci[x][y] = mfma_t<T>::op(-lr[x], ui[y], ci[x][y]);
-          cr[x][y] = mfma_t<T>::op(li[x], ui[y], cr[x][y]);
-          ci[x][y] = mfma_t<T>::op(-li[x], ur[y], ci[x][y]);
+          v1[x][y] = mfma_t<T>::op(lr[x], ur[y], v1[x][y]);
+          v2[x][y] = mfma_t<T>::op(li[x], ui[y], v2[x][y]);
+          v3[x][y] = mfma_t<T>::op(-ls[x], us[y], v3[x][y]);
         }
     }
     __syncthreads();
@@ -555,7 +566,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int j = 0; j < 4; ++j) {
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
-        if (gc < cend && gr < n) a[(long)gr * n + gc] = cx<T>{cr[x][y][j], ci[x][y][j]};
+        if (gc < cend && gr < n)
+          a[(long)gr * n + gc] = cx<T>{v2[x][y][j] - v1[x][y][j], v3[x][y][j] + v1[x][y][j] + v2[x][y][j]};
       }
 }
 

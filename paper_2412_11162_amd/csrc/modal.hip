@@ -122,6 +122,41 @@ __device__ __forceinline__ void transform_emit(const zd* st, zd* E, const zd* __
   }
 }
 
+// sin^2(D_j / 2) of the far grid of length L, stored after its L twiddles.
+template <int R>
+__device__ __forceinline__ double tw_s2(const zd* __restrict__ tw, int j) {
+  return tw[64 * R + j].re;
+}
+
+// R = sqrt(R2) on the principal branch, 1 / R and 1 / R^2 at one sample of a
+// far pair.  Far pairs keep |R2| well inside the double range (their R2 is
+// bounded away from 0 on the real D axis), so the modulus needs no scaling,
+// and since |R|^2 = |R2|, 1 / R = conj(R) / |R2|: two square roots and two
+// divisions in all.
+struct FarGeo {
+  zd R, iR, iR2;
+};
+__device__ __forceinline__ FarGeo far_geo(zd R2) {
+  const double x = R2.re, y = R2.im;
+  const double r = sqrt(x * x + y * y);
+  const double t = sqrt(0.5 * (r + fabs(x)));
+  const double h = 0.5 / t;
+  FarGeo f;
+  f.R = x >= 0.0 ? zd{t, y * h} : zd{fabs(y) * h, copysign(t, y)};
+  const double ir = 1.0 / r;
+  f.iR = zd{f.R.re * ir, -f.R.im * ir};
+  f.iR2 = f.iR * f.iR;
+  return f;
+}
+
+// e^{i kR} from one exponential and one shared sine/cosine reduction.
+__device__ __forceinline__ zd expi(zd kR) {
+  double s, c;
+  sincos(kR.re, &s, &c);
+  const double m = exp(-kR.im);
+  return zd{m * c, m * s};
+}
+
 // Raw-kernel FFT of one pair (one wavefront): the samples of S = G~ and
 // K = dG~/dnu' for both wavenumbers on the half circle D_j = 2 pi j / L,
 // j <= L/2 (R and the conormal factor are shared), staged in LDS, extended
@@ -129,8 +164,8 @@ __device__ __forceinline__ void transform_emit(const zd* st, zd* E, const zd* __
 // modes 0..M are emitted.  A coarse pair is sampled at the odd j only (the
 // L/2-point grid shifted by half a step) with doubled weights and zeros at
 // the even j, so the same transform returns that grid's trapezoidal modes.
-// sin^2(D_j / 2) comes from the twiddle table: (1 - cos D) / 2, written as
-// sin^2 D / (2 (1 + cos D)) where cos D >= 0 to keep its relative accuracy.
+// sin^2(D_j / 2) is read from the table after the twiddles (tw_s2), R and
+// its reciprocals come from far_geo.
 template <int R>
 __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const zd* __restrict__ tw,
                                          zd* lds, const OutSpec& o, int2 dst, bool coarse) {
@@ -143,16 +178,14 @@ __device__ __forceinline__ void far_pair(const PairInv& v, zd k1, zd k2, const z
 #pragma unroll 1
   for (int q = threadIdx.x; q < ns; q += 64) {
     const int j = coarse ? 2 * q + 1 : q;
-    const zd t = tw[j];
-    const double s2 = t.re >= 0.0 ? t.im * t.im / (2.0 + 2.0 * t.re) : 0.5 - 0.5 * t.re;
-    const zd R2 = v.d2 + s2 * v.c4;
-    const zd Rd = csqrt_(R2);
-    const zd iR = inv(Rd);
-    const zd inv4piR = iR * w4pi;
-    const zd iR2 = iR * iR;
+    const double s2 = tw_s2<R>(tw, j);
+    const FarGeo f = far_geo(v.d2 + s2 * v.c4);
+    const zd inv4piR = f.iR * w4pi;
+    const zd iR2 = f.iR2;
     const zd N = v.N0 + s2 * v.N1;
-    const zd ikR1 = zd{0.0, 1.0} * (k1 * Rd), ikR2 = zd{0.0, 1.0} * (k2 * Rd);
-    const zd e1 = cexp_(ikR1) * inv4piR, e2 = cexp_(ikR2) * inv4piR;
+    const zd kR1 = k1 * f.R, kR2 = k2 * f.R;
+    const zd ikR1{-kR1.im, kR1.re}, ikR2{-kR2.im, kR2.re};
+    const zd e1 = expi(kR1) * inv4piR, e2 = expi(kR2) * inv4piR;
     P1[j] = e1;
     P1[H + j] = N * e1 * (ikR1 - 1.0) * iR2;
     P2[j] = e2;
@@ -235,13 +268,12 @@ __device__ __forceinline__ void far_pair_sym(const PairInv& v, zd N0b, zd N1b, z
 #pragma unroll 1
     for (int q = b; q < ns; q += 64) {
       const int j = coarse ? 2 * q + 1 : q;
-      const zd t = tw[j];
-      const double s2 = t.re >= 0.0 ? t.im * t.im / (2.0 + 2.0 * t.re) : 0.5 - 0.5 * t.re;
-      const zd Rd = csqrt_(v.d2 + s2 * v.c4);
-      const zd iR = inv(Rd);
-      const zd ikR = zd{0.0, 1.0} * (k * Rd);
-      const zd e = cexp_(ikR) * (iR * w4pi);
-      const zd iR2 = iR * iR;
+      const double s2 = tw_s2<R>(tw, j);
+      const FarGeo f = far_geo(v.d2 + s2 * v.c4);
+      const zd kR = k * f.R;
+      const zd ikR{-kR.im, kR.re};
+      const zd e = expi(kR) * (f.iR * w4pi);
+      const zd iR2 = f.iR2;
       // the same products, in the same order, as far_pair
       SK[j] = e;
       SK[H + j] = (v.N0 + s2 * v.N1) * e * (ikR - 1.0) * iR2;
@@ -291,14 +323,16 @@ __device__ __forceinline__ void far_pair_sym(const PairInv& v, zd N0b, zd N1b, z
 // of tiles, then i = 4 I + r / 4, l = 4 J + r % 4): the 16 pairs of a tile
 // fill whole 128-byte lines of both orderings' rows (4 nodes x (u, phi)
 // columns), where a walk along one row of the triangle would write the
-// transposed ordering one column at a time.
+// transposed ordering one column at a time.  No waves-per-SIMD bound: held
+// to two waves the R = 8 pass spills its loop invariants to scratch and runs
+// a third slower than at one wave without spills.
 constexpr int FAR_TILE = 4;
 __host__ __device__ inline long far_tile_slots(int N) {
   const long nt = (N + FAR_TILE - 1) / FAR_TILE;
   return nt * (nt + 1) / 2 * (FAR_TILE * FAR_TILE);
 }
 template <int R>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
+__global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd k1, zd k2,
                                                  const zd* __restrict__ tw, OutSpec o,
                                                  WorkList split, WorkList direct, WorkList far_big,
                                                  WorkList split_big) {
@@ -449,14 +483,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const zd k = md == 1 ? k1 : k2;
 #pragma unroll 1
     for (int j = threadIdx.x; j < H; j += 64) {
-      const zd tt = tw[j];
-      const double s2 = tt.re >= 0.0 ? tt.im * tt.im / (2.0 + 2.0 * tt.re) : 0.5 - 0.5 * tt.re;
-      const zd Rd = csqrt_(v.d2 + s2 * v.c4);
-      const zd iR = inv(Rd);
-      const zd ikR = zd{0.0, 1.0} * (k * Rd);
-      const zd e = cexp_(ikR) * (iR * w4pi);
+      const double s2 = tw_s2<R>(tw, j);
+      const FarGeo f = far_geo(v.d2 + s2 * v.c4);
+      const zd kR = k * f.R;
+      const zd ikR{-kR.im, kR.re};
+      const zd e = expi(kR) * (f.iR * w4pi);
       P1[j] = e;
-      P1[H + j] = (v.N0 + s2 * v.N1) * e * (ikR - 1.0) * (iR * iR);
+      P1[H + j] = (v.N0 + s2 * v.N1) * e * (ikR - 1.0) * f.iR2;
     }
     __syncthreads();
     transform_emit<R>(P1, E, tw, o, dst, md == 1 ? 0 : 2);
