@@ -63,6 +63,8 @@ struct pmlbie_ctx {
   hipStream_t stream = nullptr;
   hipStream_t up_stream = nullptr;  // uploads of the near-panel tables
   hipEvent_t up_done = nullptr;
+  hipStream_t lu_stream = nullptr;  // the LU's look-ahead panels
+  hipEvent_t lu_ev[2] = {nullptr, nullptr};
   // host near-panel tables of the last build (auxiliary pair geometry,
   // Lagrange-weighted coefficients, jobs), reused as workspace
   std::vector<PairGeom> h_ageom;
@@ -394,6 +396,12 @@ void pmlbie_destroy(pmlbie_ctx* c) {
     (void)hipStreamDestroy(c->up_stream);
   }
   if (c->up_done) (void)hipEventDestroy(c->up_done);
+  if (c->lu_stream) {
+    (void)hipStreamSynchronize(c->lu_stream);
+    (void)hipStreamDestroy(c->lu_stream);
+  }
+  for (hipEvent_t& e : c->lu_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -755,15 +763,18 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     LuTimers tm;
     tm.gemm_begin = gb.data();
     tm.gemm_end = ge.data();
+    if (!c->lu_stream) HIPCHK(hipStreamCreateWithFlags(&c->lu_stream, hipStreamNonBlocking));
+    for (hipEvent_t& e : c->lu_ev)
+      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (mixed) {
       c->A32.alloc((size_t)nm * ms);
       launch_to_c64(c->A.p, c->A32.p, (long)nm * ms, c->stream);
       HIPCHK(hipGetLastError());
       lu_factor_batched<float>(c->A32.p, ms, (int)n2, nm, c->ipiv.p, c->info.p,
-                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm);
+                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm, c->lu_stream, c->lu_ev);
     } else {
       lu_factor_batched<double>(c->A.p, ms, (int)n2, nm, c->ipiv.p, c->info.p, c->luw.p,
-                                c->stream, &tm);
+                                c->stream, &tm, c->lu_stream, c->lu_ev);
     }
     HIPCHK(hipGetLastError());
     c->stage_ms[5] = t_lu.stop();

@@ -21,9 +21,13 @@ struct LuTimers {
 // ipiv[b * n + j] = row interchanged with row j (0-based);
 // info[b] = first zero pivot (1-based), untouched otherwise.
 // work: batch * LU_NB * LU_NB elements (the inverses of the diagonal blocks).
+// With st2 (a second stream) and la_ev (two events), the next block column
+// is factored on st2 beside the rest of each trailing update; the work is
+// complete when st is (st waits for st2 before every step).
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
-                       hipStream_t st, LuTimers* tm = nullptr);
+                       hipStream_t st, LuTimers* tm = nullptr, hipStream_t st2 = nullptr,
+                       hipEvent_t* la_ev = nullptr);
 
 // Solve A x = b for nrhs right-hand sides per matrix, B[b][rhs][n] in place.
 template <typename T, typename TB>

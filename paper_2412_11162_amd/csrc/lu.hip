@@ -7,10 +7,13 @@
 //      sub-panels of 4 (8) columns held in registers (pivot search, row exchange
 //      and rank-1 updates never leave the chip), each followed by the update
 //      of the panel columns to its right;
-//   2. the triangular solve U12 = L11^{-1} A12 (the row interchanges of the
-//      trailing columns are done by the panel kernel as each pivot is chosen);
+//   2. the panel's row interchanges applied to the trailing columns, then the
+//      triangular solve U12 = L11^{-1} A12;
 //   3. trailing update A22 -= L21 U12 on the matrix cores (MFMA), a complex
-//      product as four real MFMA products.
+//      product as three real MFMA products.
+// Look-ahead: the update of step k is split into the next panel's columns
+// and the rest; the next panel is factored on a second stream while the rest
+// of the update runs (the panel touches only its own columns).
 // Row interchanges are not applied to the columns left of the current panel:
 // the forward solve applies each panel's interchanges to the right-hand side
 // just before using that panel's columns of L, which are stored in the row
@@ -43,7 +46,7 @@ __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
 // local rows t, t + PNL_T, ... (local row = row - k0); RPT rows per thread.
 template <typename T, int RPT>
 __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms, int n, int k0,
-                                                 int nb, int cs0, int* __restrict__ ipiv,
+                                                 int nb, int cs0, int ce, int* __restrict__ ipiv,
                                                  int* __restrict__ info) {
   // register sub-panel width: 8 columns where the registers allow it (FP32 up
   // to two rows per thread), which halves the passes of the in-leaf update
@@ -127,10 +130,11 @@ __global__ __launch_bounds__(PNL_T) void k_panel(cx<T>* __restrict__ A, long ms,
             if (q == qp)
 #pragma unroll
               for (int j2 = 0; j2 < SUB; ++j2) sx[1][j2] = x[q][j2];
-        // the rest of the two rows in memory, from column cs0 (the start of the
-        // enclosing LU_NB panel) to the end: the other panel columns and the
-        // trailing columns (the interchange of the trailing matrix happens here)
-        for (int c = cs0 - k0 + tid; c < m; c += PNL_T)
+        // the rest of the two rows in memory over the enclosing LU_NB panel,
+        // columns [cs0, ce); the trailing columns get the panel's interchanges
+        // afterwards (k_laswp), so that the panel may run beside an update of
+        // them
+        for (int c = cs0 - k0 + tid; c < ce - k0; c += PNL_T)
           if (c < s0 || c >= s0 + SUB) {
             cx<T>* r1 = a + (long)(k0 + cl) * n + k0 + c;
             cx<T>* r2 = a + (long)(k0 + p) * n + k0 + c;
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // so the tiles in flight on one XCD share L21 rows and U12 columns in its L2.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4))) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
-                                                     int k0, int nb, int cend, int tx, int ty,
+                                                     int k0, int nb, int cbeg, int cend, int tx, int ty,
                                                      int batch) {
   typedef typename mfma_t<T>::acc acc_t;
   const long tiles = (long)tx * ty * batch;
@@ -480,8 +484,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int by = grp * GM + in % rows_in_grp, bx = in / rows_in_grp;
   cx<T>* a = A + (long)bz * ms;
   const int m0 = k0 + nb;
-  const int r0 = m0 + by * 64;  // tile rows of C
-  const int c0 = m0 + bx * 64;  // tile columns of C
+  const int r0 = m0 + by * 64;    // tile rows of C
+  const int c0 = cbeg + bx * 64;  // tile columns of C (cbeg >= k0 + nb)
   constexpr int KC = 8;
   __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4], Lsm[KC][64 + 4];  // L21 chunk: [k][row]
   __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4], Usm[KC][64 + 4];  // U12 chunk: [k][col]
@@ -741,29 +745,52 @@ __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ 
 
 // ---------------------------------------------------------------------------
 template <typename T, int RPT>
-static void launch_panel(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int batch, int* ipiv,
+static void launch_panel(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int ce, int batch, int* ipiv,
                          int* info, hipStream_t st) {
-  hipLaunchKernelGGL((k_panel<T, RPT>), dim3(batch), dim3(PNL_T), 0, st, A, ms, n, k0, nb, cs0, ipiv,
+  hipLaunchKernelGGL((k_panel<T, RPT>), dim3(batch), dim3(PNL_T), 0, st, A, ms, n, k0, nb, cs0, ce, ipiv,
                      info);
 }
 
 template <typename T>
-static void panel_any(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int batch, int* ipiv,
+static void panel_any(cx<T>* A, long ms, int n, int k0, int nb, int cs0, int ce, int batch, int* ipiv,
                       int* info, hipStream_t st) {
   const int m = n - k0;
-  if (m <= 1 * PNL_T) launch_panel<T, 1>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
-  else if (m <= 2 * PNL_T) launch_panel<T, 2>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
-  else if (m <= 4 * PNL_T) launch_panel<T, 4>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
-  else launch_panel<T, 8>(A, ms, n, k0, nb, cs0, batch, ipiv, info, st);
+  if (m <= 1 * PNL_T) launch_panel<T, 1>(A, ms, n, k0, nb, cs0, ce, batch, ipiv, info, st);
+  else if (m <= 2 * PNL_T) launch_panel<T, 2>(A, ms, n, k0, nb, cs0, ce, batch, ipiv, info, st);
+  else if (m <= 4 * PNL_T) launch_panel<T, 4>(A, ms, n, k0, nb, cs0, ce, batch, ipiv, info, st);
+  else launch_panel<T, 8>(A, ms, n, k0, nb, cs0, ce, batch, ipiv, info, st);
 }
 
+// Row interchanges of rows [k0, k0 + nb) applied, in order, to columns
+// [c0, c1): one thread per column.
 template <typename T>
-static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch, hipStream_t st,
-                   cx<T>* W = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-  const int cols = cend - k0 - nb, rows = n - k0 - nb;
+__global__ __launch_bounds__(256) void k_laswp(cx<T>* __restrict__ A, long ms, int n, int k0, int nb, int c0,
+                                               int c1, const int* __restrict__ ipiv) {
+  cx<T>* a = A + (long)blockIdx.y * ms;
+  const int* piv = ipiv + (long)blockIdx.y * n;
+  const int c = c0 + blockIdx.x * 256 + threadIdx.x;
+  if (c >= c1) return;
+  for (int j = k0; j < k0 + nb; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      cx<T>* r1 = a + (long)j * n + c;
+      cx<T>* r2 = a + (long)p * n + c;
+      const cx<T> t1 = *r1;
+      *r1 = *r2;
+      *r2 = t1;
+    }
+  }
+}
+
+// U12 = L11^{-1} A12 for columns [k0 + nb, cend) of the rows [k0, k0 + nb):
+// with W, the inverse of the diagonal block by the column solver and the
+// product on MFMA; without, the column solver in place.
+template <typename T>
+static void trsm_part(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch, hipStream_t st,
+                      cx<T>* W) {
+  const int cols = cend - k0 - nb;
   if (cols <= 0) return;
   if (W) {
-    // U12 = (L11^{-1}) A12: the inverse by the column solver, the product on MFMA
     hipLaunchKernelGGL(k_trsm<T>, dim3((nb + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms, n, k0, nb,
                        cend, W);
     hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(512), 0, st, A, ms, n, k0,
@@ -772,35 +799,65 @@ static void update(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch
     hipLaunchKernelGGL(k_trsm<T>, dim3((cols + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms, n, k0, nb,
                        cend, (cx<T>*)nullptr);
   }
-  if (rows > 0) {
-    if (ev0) hipEventRecord(ev0, st);
-    const int tx = (cols + 63) / 64, ty = (rows + 63) / 64;
-    const long tiles = (long)tx * ty * batch;
-    const long grid = ((tiles + 7) / 8) * 8;
-    hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)grid), dim3(256), 0, st, A, ms, n, k0, nb, cend,
-                       tx, ty, batch);
-    if (ev1) hipEventRecord(ev1, st);
+}
+
+// A22 -= L21 U12 over the rows below k0 + nb and columns [cbeg, cend).
+template <typename T>
+static void gemm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int cend, int batch, hipStream_t st) {
+  const int cols = cend - cbeg, rows = n - k0 - nb;
+  if (cols <= 0 || rows <= 0) return;
+  const int tx = (cols + 63) / 64, ty = (rows + 63) / 64;
+  const long tiles = (long)tx * ty * batch;
+  const long grid = ((tiles + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)grid), dim3(256), 0, st, A, ms, n, k0, nb, cbeg, cend,
+                     tx, ty, batch);
+}
+
+// One LU_NB block column [k0, k0 + nb), rows [k0, n): leaves of LU_LEAF
+// columns by the register kernel, the block's columns right of a leaf
+// updated by a column solve and an MFMA update of width LU_LEAF.  Row
+// interchanges stay within the block's columns.
+template <typename T>
+static void factor_block(cx<T>* A, long ms, int n, int k0, int batch, int* ipiv, int* info, hipStream_t st) {
+  const int nb = std::min(LU_NB, n - k0), ce = k0 + nb;
+  for (int j0 = 0; j0 < nb; j0 += LU_LEAF) {
+    const int lb = std::min(LU_LEAF, nb - j0);
+    panel_any<T>(A, ms, n, k0 + j0, lb, k0, ce, batch, ipiv, info, st);
+    trsm_part<T>(A, ms, n, k0 + j0, lb, ce, batch, st, nullptr);
+    gemm_part<T>(A, ms, n, k0 + j0, lb, k0 + j0 + lb, ce, batch, st);
   }
 }
 
-// Each LU_NB panel is factored as leaves of LU_LEAF columns (register kernel),
-// the columns of the panel right of a leaf updated by a TRSM + MFMA update of
-// width LU_LEAF; then the trailing matrix gets the full-width update.
+// Step k: the block's interchanges on the trailing columns, U12, the update
+// of the next block's columns, then the rest of the update; with a second
+// stream the next block is factored there while the rest runs.
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
-                       hipStream_t st, LuTimers* tm) {
+                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev) {
+  const bool la = st2 != nullptr && la_ev != nullptr;
+  factor_block<T>(A, ms, n, 0, batch, ipiv, info, st);
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
-    const int nb = std::min(LU_NB, n - k0);
-    for (int j0 = 0; j0 < nb; j0 += LU_LEAF) {
-      const int lb = std::min(LU_LEAF, nb - j0);
-      panel_any<T>(A, ms, n, k0 + j0, lb, k0, batch, ipiv, info, st);
-      update<T>(A, ms, n, k0 + j0, lb, k0 + nb, batch, st);
+    const int nb = std::min(LU_NB, n - k0), c1 = k0 + nb;
+    if (c1 >= n) break;
+    hipLaunchKernelGGL(k_laswp<T>, dim3((n - c1 + 255) / 256, batch), dim3(256), 0, st, A, ms, n, k0, nb, c1, n,
+                       (const int*)ipiv);
+    trsm_part<T>(A, ms, n, k0, nb, n, batch, st, work);
+    const int c2 = std::min(n, c1 + LU_NB);
+    const bool t = tm && tm->gemm_begin && tm->gemm_end;
+    if (t) (void)hipEventRecord(tm->gemm_begin[k0 / LU_NB], st);
+    gemm_part<T>(A, ms, n, k0, nb, c1, c2, batch, st);
+    if (la) {
+      (void)hipEventRecord(la_ev[0], st);
+      (void)hipStreamWaitEvent(st2, la_ev[0], 0);
+      factor_block<T>(A, ms, n, c1, batch, ipiv, info, st2);
+      (void)hipEventRecord(la_ev[1], st2);
     }
-    if (n - k0 - nb > 0) {
-      const bool t = tm && tm->gemm_begin && tm->gemm_end;
-      update<T>(A, ms, n, k0, nb, n, batch, st, work, t ? tm->gemm_begin[k0 / LU_NB] : nullptr,
-                t ? tm->gemm_end[k0 / LU_NB] : nullptr);
-    }
+    gemm_part<T>(A, ms, n, k0, nb, c2, n, batch, st);
+    if (t) (void)hipEventRecord(tm->gemm_end[k0 / LU_NB], st);
+    if (la)
+      (void)hipStreamWaitEvent(st, la_ev[1], 0);
+    else
+      factor_block<T>(A, ms, n, c1, batch, ipiv, info, st);
   }
 }
 
@@ -826,8 +883,10 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
   }
 }
 
-template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, zd*, hipStream_t, LuTimers*);
-template void lu_factor_batched<float>(zf*, long, int, int, int*, int*, zf*, hipStream_t, LuTimers*);
+template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, zd*, hipStream_t, LuTimers*, hipStream_t,
+                                        hipEvent_t*);
+template void lu_factor_batched<float>(zf*, long, int, int, int*, int*, zf*, hipStream_t, LuTimers*, hipStream_t,
+                                       hipEvent_t*);
 template void lu_solve_batched<double, double>(const zd*, long, int, int, const int*, zd*, int,
                                                hipStream_t);
 template void lu_solve_batched<float, double>(const zf*, long, int, int, const int*, zd*, int,
