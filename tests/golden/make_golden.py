@@ -6,6 +6,7 @@ Calls only the oracle (``oracle/``) and the workload definitions
     python tests/golden/make_golden.py small            # ~3 min on 8 cores
     python tests/golden/make_golden.py paper_scale      # ~2 h on 8 cores
     python tests/golden/make_golden.py largest_reduced  # ~20 min on 8 cores
+    python tests/golden/make_golden.py largest_rows     # ~4 min on 8 cores
 
 The operators are assembled in blocks of target rows; each block is kept in
 a cache directory (``--cache DIR``, default ``$TMPDIR/pmlbie_golden``) so that
@@ -21,6 +22,13 @@ largest), and the plane wave of the paper's examples (polar angle pi/3,
 Sec. 5).  The reduced largest configuration stores modes 0, 1, 2, 64, 128,
 255, 256 for its 16 plane waves and a point source at (4, 0, 0.15) that
 excites the highest modes.
+
+The largest configuration at its full size (4096 nodes) is too large for a
+full oracle solve; `largest_rows` stores the oracle's operator rows of four
+nodes (near the axis, on the rings, right below the point source, in the PML)
+for modes 0, 1, 128, 129, 255, 256 and both media, with the right-hand-side data of the plane wave at polar
+angle pi/3 and of a point source at (4, 0, 0.15) at every node, for the
+backward-error tests of the full-size build.
 
 Tolerances.  Modal kernels at 1e-14 relative (azimuthal quadrature), and the
 near-panel product integrals at 1e-12 relative for the two larger cases: the
@@ -102,6 +110,35 @@ def assemble_cached(g, modes, near_reltol, block, cache):
     return A
 
 
+ROWS_LARGEST = dict(rows=[10, 1500, 1636, 3500], modes=[0, 1, 128, 129, 255, 256],
+                    incidences=[("plane", np.pi / 3), ("point", 4.0, 0.15)], near_reltol=1e-12)
+
+
+def make_rows(cache: str) -> str:
+    """Oracle rows and right-hand-side data of the full-size largest
+    configuration (see the module docstring)."""
+    spec = ROWS_LARGEST
+    wl = workloads.ALL["largest"]()
+    g = oracle.geometry(wl)
+    t0 = time.time()
+    S, K = oracle.core.operator_rows(g, spec["rows"], [wl.k1, wl.k2], spec["modes"],
+                                     near_reltol=spec["near_reltol"])
+    print("rows done in %.0f s" % (time.time() - t0), flush=True)
+    b1s, b2s = [], []
+    for inc in spec["incidences"]:
+        b1, b2 = rhs(g, spec["modes"], inc)
+        b1s.append(b1)
+        b2s.append(b2)
+    kinds = np.array([0 if i[0] == "point" else 1 for i in spec["incidences"]])
+    params = np.array([[i[1], i[2] if len(i) > 2 else 0.0] for i in spec["incidences"]])
+    path = os.path.join(HERE, "rows_largest.npz")
+    # S, K: [medium][mode][row][node]; b1, b2: [incidence][mode][node]
+    np.savez_compressed(path, rows=np.array(spec["rows"]), modes=np.array(spec["modes"]), S=S, K=K,
+                        b1=np.stack(b1s), b2=np.stack(b2s), inc_kind=kinds, inc_param=params)
+    print("wrote", path, "in %.0f s" % (time.time() - t0), flush=True)
+    return path
+
+
 def make(name: str, cache: str) -> str:
     spec = SPECS[name]
     wl = workloads.ALL[name]()
@@ -134,8 +171,11 @@ def make(name: str, cache: str) -> str:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("names", nargs="+", choices=sorted(SPECS))
+    ap.add_argument("names", nargs="+", choices=sorted(SPECS) + ["largest_rows"])
     ap.add_argument("--cache", default=os.path.join(tempfile.gettempdir(), "pmlbie_golden"))
     a = ap.parse_args()
     for n in a.names:
-        make(n, a.cache)
+        if n == "largest_rows":
+            make_rows(a.cache)
+        else:
+            make(n, a.cache)

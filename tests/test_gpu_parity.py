@@ -32,8 +32,8 @@ def _solver(wl, **kw):
 
 
 def _golden(name):
-    """Stored oracle boundary data (written by tests/golden/make_golden.py);
-    the paper-scale file takes more than a day of oracle time and may not exist."""
+    """Stored oracle boundary data (written by tests/golden/make_golden.py,
+    which calls only the oracle)."""
     path = os.path.join(HERE, "golden", "boundary_%s.npz" % name)
     if not os.path.exists(path):
         pytest.skip("stored oracle result %s not generated: python tests/golden/make_golden.py %s"
@@ -236,7 +236,7 @@ def test_paper_scale_operator_rows(paper_solver, paper_rows):
             assert _normwise(blkG, ref) <= KERNEL_TOL, n
 
 
-def _row_backward_errors(out, rows_data, rhs=0):
+def _row_backward_errors(out, rows_data, rhs=0, m0=0):
     """Backward errors of the GPU solution x = [u1; phi1] of right-hand side
     `rhs` in the oracle's rows of [[K1 + I, -S1], [K2 - I, -S2]] x =
     [0; (K2 - I) b1 - S2 b2]: per mode, the largest residual over the rows
@@ -246,14 +246,15 @@ def _row_backward_errors(out, rows_data, rhs=0):
     rounding level (norm >= 1e-10 of the largest mode's) is measured against
     its own scale; the data of a mode below that level are rounding noise on
     both sides (the benchmark source's modes 64 and 128 are ~1e-16 of mode 0),
-    so such a mode is measured against the largest scale of all modes."""
+    so such a mode is measured against the largest scale of all modes.
+    out[k][n - m0] holds mode n (a build of modes m0..M)."""
     g, rows, modes, S, K, b1, b2 = rows_data
     u1 = out[0][:, rhs, :].cpu().numpy()
     p1 = out[1][:, rhs, :].cpu().numpy()
     dn = np.array([np.linalg.norm(b1[j]) + np.linalg.norm(b2[j]) for j in range(len(modes))])
     per = []
     for j, n in enumerate(modes):
-        x1, x2 = u1[n], p1[n]
+        x1, x2 = u1[n - m0], p1[n - m0]
         res, den = [], []
         for q, i in enumerate(rows):
             res.append(abs(K[0, j][q] @ x1 + x1[i] - S[0, j][q] @ x2))
