@@ -331,7 +331,8 @@ __global__ __launch_bounds__(256) void k_trsm(cx<T>* __restrict__ A, long ms, in
 // ---------------------------------------------------------------------------
 // Trailing update C -= L21 U12 on MFMA (rows below k0 + nb, columns
 // k0 + nb .. cend - 1).  Workgroup tile 64 x 64 (complex), four waves of
-// 32 x 32, K staged through LDS in chunks of 8; registers held to four waves
+// 32 x 32, K staged through LDS in chunks (16 complex64 / 8 complex128
+// columns, two 4-wide MFMA steps unrolled together); registers held to four waves
 // per SIMD (three for FP64), whose interleaving hides the global and LDS
 // latencies.  The complex product takes three real products (the 3M form): with
 // T1 = Lr Ur, T2 = Li Ui, T3 = (Lr + Li)(Ur + Ui), Re C -= T1 - T2 and
@@ -486,7 +487,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int m0 = k0 + nb;
   const int r0 = m0 + by * 64;    // tile rows of C
   const int c0 = cbeg + bx * 64;  // tile columns of C (cbeg >= k0 + nb)
-  constexpr int KC = 8;
+  // K chunk: 16 for complex64 (half the barriers), 8 for complex128 (16
+  // would spill the prefetch registers at three waves per SIMD)
+  constexpr int KC = sizeof(T) == 4 ? 16 : 8;
+  constexpr int NP = KC / 4;  // prefetched elements of L21 and of U12 per thread
   __shared__ T Lre[KC][64 + 4], Lim[KC][64 + 4], Lsm[KC][64 + 4];  // L21 chunk: [k][row]
   __shared__ T Ure[KC][64 + 4], Uim[KC][64 + 4], Usm[KC][64 + 4];  // U12 chunk: [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -508,11 +512,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         v3[x][y][j] = v.im - v.re;
       }
   // global -> register prefetch of the next K chunk overlaps the MFMA work
-  // on the current one; each thread moves 2 elements of L21 and of U12
-  cx<T> pl[2], pu[2];
+  // on the current one; each thread moves NP elements of L21 and of U12
+  cx<T> pl[NP], pu[NP];
   auto gload = [&](int kk) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NP; ++t) {
       const int e = tid + 256 * t;
       const int k = e % KC, rr = e / KC;  // row-major L21: k contiguous
       const int gr = r0 + rr, gk = kk + k;
@@ -525,7 +529,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   gload(0);
   for (int kk = 0; kk < nb; kk += KC) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NP; ++t) {
       const int e = tid + 256 * t;
       const int k = e % KC, rr = e / KC;
       Lre[k][rr] = pl[t].re;
@@ -538,7 +542,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
     __syncthreads();
     if (kk + KC < nb) gload(kk + KC);
-#pragma unroll 1
+#pragma unroll 2
     for (int k4 = 0; k4 < KC; k4 += 4) {
       const int kx = k4 + (lane >> 4), lx = lane & 15;
       T lr[2], li[2], ls[2], ur[2], ui[2], us[2];
