@@ -686,13 +686,14 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
       return fail(c, PMLBIE_EDEVICE, "build: work list overflow");
     c->counters[4] = 0;
     c->counters[5] = 0;
-    c->cnt_far_big = use_sg ? 0 : counts[2];
+    // the main pass lists its long-grid far pairs once per unordered pair
+    c->cnt_far_big = use_sg ? 0 : 2LL * counts[2];
     c->counters[6] = (double)c->cnt_far_big;
     if (use_sg) {
       run_surrogate(c, wf.geom, wf.dest, counts[2], n2, ms, nd.W);
     } else if (counts[2] > 0) {
-      launch_list_far(c->nt_far, wf.geom, wf.dest, 0, counts[2], M, m0, c->k1, c->k2, c->tw_far.p, c->A.p, n2, ms,
-                      nd.W, nullptr, &c->cp, c->stream);
+      launch_list_far_sym(c->nt_far, wf.geom, wf.dest, counts[2], nd, M, m0, c->k1, c->k2, c->tw_far.p, c->A.p, n2,
+                          ms, nd.W, c->cp, c->stream);
       HIPCHK(hipGetLastError());
     }
     c->stage_ms[1] = t_far.stop();

@@ -78,6 +78,11 @@ void launch_grid_classify(const NodesDev& nd, const ClassParams& cp, WorkList fa
                           WorkList direct, WorkList split_big, hipStream_t st);
 // Far pairs of an explicit list; with cp, the pairs the classification marks
 // coarse are sampled on the half-length grid, as in the main grid.
+// The long-grid far pairs the main pass lists once per unordered pair (i, l):
+// both orderings into A (modes m0..M).
+void launch_list_far_sym(int nt, const PairGeom* geom, const int2* dest, long count, const NodesDev& nd, int M,
+                         int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
+                         const ClassParams& cp, hipStream_t st);
 void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                      int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride,
                      const double* W, zd* raw, const ClassParams* cp, hipStream_t st);

@@ -231,22 +231,74 @@ __device__ __forceinline__ void emit_strided(zd* base, long mstride, int m0, int
 // LDS, S and K_a are transformed together and emitted to a (S also to b),
 // then K_b alone to b.  Two of the four complex exponentials and two of the
 // eight transforms of two separate pairs are saved.  The coarse grid and the
-// weights follow far_pair.  LDS: K_b at [0, H), S and K_a at [H, 3H), the
-// exchange area of the transform from H on (S and K_a are in registers by
-// then); within far_lds<R>() for R <= 16.
+// weights follow far_pair.  LDS for R <= 16: K_b at [0, H), S and K_a at
+// [H, 3H), the exchange area of the transform from H on (S and K_a are in
+// registers by then); for R = 32: S, K_a, K_b at [0, 3H) and the exchange area
+// after them.  Within far_lds<R>() either way.
 template <int R>
 __device__ __forceinline__ void far_pair_sym(const PairInv& v, zd N0b, zd N1b, zd k1, zd k2,
                                              const zd* __restrict__ tw, zd* lds, const OutSpec& o, int2 da,
                                              int2 db, bool coarse) {
   if constexpr (R > 16) {
-    // the 2048-point grid stages one sequence at a time (far_pair): the two
-    // orderings are transformed separately
-    far_pair<R>(v, k1, k2, tw, lds, o, da, coarse);
-    PairInv vb = v;
-    vb.N0 = N0b;
-    vb.N1 = N1b;
-    __syncthreads();
-    far_pair<R>(vb, k1, k2, tw, lds, o, db, coarse);
+    // the 2048-point grid: S, K_a, K_b staged at [0, 3H), each transformed
+    // alone with the exchange area E after them (a sequence of 32 slots per
+    // lane is all the registers hold)
+    constexpr int L = 64 * R, H = L / 2 + 1;
+    zd* Sg = lds;
+    zd* Ka = lds + H;
+    zd* Kb = lds + 2 * H;
+    zd* E = lds + 3 * H;
+    const int ns = coarse ? L / 4 : L / 2 + 1;
+    const double w4pi = (coarse ? 2.0 : 1.0) * (0.25 / PMLBIE_PI);
+    const double scale = 2.0 * PMLBIE_PI / L;
+    const double fa = 2.0 * o.W[da.y] * scale, fb = 2.0 * o.W[db.y] * scale;
+    zd* const pa = o.A + (2L * da.x) * o.n2 + 2L * da.y;
+    zd* const pb = o.A + (2L * db.x) * o.n2 + 2L * db.y;
+    const int b = threadIdx.x & 63;
+#pragma unroll 1
+    for (int w = 0; w < 2; ++w) {
+      const zd k = w == 0 ? k1 : k2;
+#pragma unroll 1
+      for (int q = b; q < ns; q += 64) {
+        const int j = coarse ? 2 * q + 1 : q;
+        const double s2 = tw_s2<R>(tw, j);
+        const FarGeo f = far_geo(v.d2 + s2 * v.c4);
+        const zd kR = k * f.R;
+        const zd ikR{-kR.im, kR.re};
+        const zd e = expi(kR) * (f.iR * w4pi);
+        Sg[j] = e;
+        Ka[j] = (v.N0 + s2 * v.N1) * e * (ikR - 1.0) * f.iR2;
+        Kb[j] = (N0b + s2 * N1b) * e * (ikR - 1.0) * f.iR2;
+        if (coarse) {
+          const zd z0{0.0, 0.0};
+          Sg[j - 1] = z0;
+          Ka[j - 1] = z0;
+          Kb[j - 1] = z0;
+        }
+      }
+      if (coarse && b == 0) {
+        const zd z0{0.0, 0.0};
+        Sg[L / 2] = z0;
+        Ka[L / 2] = z0;
+        Kb[L / 2] = z0;
+      }
+      __syncthreads();
+      const long row = w * o.n2;
+#pragma unroll 1
+      for (int sq = 0; sq < 3; ++sq) {
+        zd x[1][R];
+        load_even<R, 1>(lds + sq * H, x);
+        fft_wave<R, 1>(x, E, tw);
+        if (sq == 0) {
+          emit_strided<R>(pa + row + 1, o.mstride, o.m0, o.M, -fa, x[0]);
+          emit_strided<R>(pb + row + 1, o.mstride, o.m0, o.M, -fb, x[0]);
+        } else if (sq == 1) {
+          emit_strided<R>(pa + row, o.mstride, o.m0, o.M, fa, x[0]);
+        } else {
+          emit_strided<R>(pb + row, o.mstride, o.m0, o.M, fb, x[0]);
+        }
+      }
+    }
     return;
   }
   constexpr int L = 64 * R, H = L / 2 + 1;
@@ -362,7 +414,10 @@ __global__ __launch_bounds__(64) void k_grid_far(NodesDev nd, ClassParams cp, zd
     bool coarse = false;
     const int cls = classify(g, v, cp, &coarse);
     if (cls != CLASS_FAR) {
-      if (threadIdx.x < 2) {
+      // far pairs on the long grid are listed once (i, l), i < l, and
+      // transformed in both orderings from the list (k_list_far_sym); the
+      // other classes list both orderings
+      if (threadIdx.x < (cls == CLASS_FAR_BIG ? 1 : 2)) {
         WorkList& wl = cls == CLASS_SPLIT ? split
                        : (cls == CLASS_DIRECT ? direct : (cls == CLASS_FAR_BIG ? far_big : split_big));
         const unsigned slot = atomicAdd(wl.count, 1u);
@@ -458,6 +513,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     bool coarse = false;
     if (use_coarse) (void)classify(g, v, cp, &coarse);
     far_pair<R>(v, k1, k2, tw, lds, o, dest[first + t], coarse);
+  }
+}
+
+// The long-grid far pairs of the main pass, one entry (i, l) per unordered
+// pair: both orderings from one set of samples (far_pair_sym); the normal of
+// node i gives the double-layer numerator of the ordering (l, i).
+template <int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 16 ? 2 : 1))) void k_list_far_sym(
+    const PairGeom* __restrict__ geom, const int2* __restrict__ dest, long count, NodesDev nd, zd k1, zd k2,
+    const zd* __restrict__ tw, OutSpec o, ClassParams cp) {
+  __shared__ zd lds[far_lds<R>()];
+  for (long t = blockIdx.x; t < count; t += gridDim.x) {
+    const PairGeom g = geom[t];
+    const int2 d = dest[t];
+    const PairInv v = pair_invariants(g);
+    bool coarse = false;
+    (void)classify(g, v, cp, &coarse);
+    const zd nrb{nd.nr_re[d.x], nd.nr_im[d.x]}, nzb{nd.nz_re[d.x], nd.nz_im[d.x]};
+    const zd N0b = nrb * g.drho + nzb * g.dz;  // -(n_i . (r~_l - r~_i))
+    const zd N1b = 2.0 * (nrb * g.rs);
+    far_pair_sym<R>(v, N0b, N1b, k1, k2, tw, lds, o, d, make_int2(d.y, d.x), coarse);
+    __syncthreads();
   }
 }
 
@@ -1025,6 +1102,26 @@ void launch_list_far(int nt, const PairGeom* geom, const int2* dest, long first,
     case 512: launch_list_far_t<8>(geom, dest, first, count, k1, k2, tw, o, cp, st); break;
     case 1024: launch_list_far_t<16>(geom, dest, first, count, k1, k2, tw, o, cp, st); break;
     case 2048: launch_list_far_t<32>(geom, dest, first, count, k1, k2, tw, o, cp, st); break;
+    default: break;
+  }
+}
+
+template <int R>
+static void launch_list_far_sym_t(const PairGeom* geom, const int2* dest, long count, const NodesDev& nd, zd k1,
+                                  zd k2, const zd* tw, const OutSpec& o, const ClassParams& cp, hipStream_t st) {
+  int grid = (int)std::min<long>(count, 256L * 128);
+  hipLaunchKernelGGL(k_list_far_sym<R>, dim3(grid), dim3(64), 0, st, geom, dest, count, nd, k1, k2, tw, o, cp);
+}
+
+void launch_list_far_sym(int nt, const PairGeom* geom, const int2* dest, long count, const NodesDev& nd, int M,
+                         int m0, zd k1, zd k2, const zd* tw, zd* A, long n2, long mstride, const double* W,
+                         const ClassParams& cp, hipStream_t st) {
+  if (count <= 0) return;
+  OutSpec o{A, n2, mstride, W, nullptr, M, m0};
+  switch (nt) {
+    case 512: launch_list_far_sym_t<8>(geom, dest, count, nd, k1, k2, tw, o, cp, st); break;
+    case 1024: launch_list_far_sym_t<16>(geom, dest, count, nd, k1, k2, tw, o, cp, st); break;
+    case 2048: launch_list_far_sym_t<32>(geom, dest, count, nd, k1, k2, tw, o, cp, st); break;
     default: break;
   }
 }
