@@ -718,7 +718,7 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
 // rows [r0, r1) of b -= A[rows][k0 .. k0+nb) * b[k0 .. k0+nb) for every
 // right-hand side: 64 rows per workgroup, LDS-staged tiles, lane per row
 // (rows16.h); grid (row blocks of 64, matrices).
-template <typename T, typename TB>
+template <typename T, typename TB, bool MM>
 __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ A, long ms, int n,
                                                       int k0, int nb, cx<TB>* __restrict__ B,
                                                       int nrhs, int r0, int r1) {
@@ -728,7 +728,7 @@ __global__ __launch_bounds__(256) void k_solve_update(const cx<T>* __restrict__ 
   zd acc[4];
   bool ow;
   int og;
-  rows16_acc<T>(a, n, rbase, r1, k0, k0 + nb, nrhs,
+  rows16_acc<T, MM>(a, n, rbase, r1, k0, k0 + nb, nrhs,
                 [&](int s2, int c) {
                   const cx<TB> v = b[(long)s2 * n + c];
                   return zd{(double)v.re, (double)v.im};
@@ -868,13 +868,15 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
 template <typename T, typename TB>
 void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv, cx<TB>* B,
                       int nrhs, hipStream_t st) {
+  // off-diagonal block updates: the matrix-core form for 9 to 16 vectors
+  auto upd = nrhs > 8 ? &k_solve_update<T, TB, true> : &k_solve_update<T, TB, false>;
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
     hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
                        B, nrhs, 0);
     const int r0 = k0 + nb, r1 = n;
     if (r1 > r0)
-      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((r1 - r0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0,
+      hipLaunchKernelGGL(upd, dim3((r1 - r0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0,
                          st, A, ms, n, k0, nb, B, nrhs, r0, r1);
   }
   for (int k0 = ((n - 1) / LU_NB) * LU_NB; k0 >= 0; k0 -= LU_NB) {
@@ -882,7 +884,7 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
     hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
                        B, nrhs, 1);
     if (k0 > 0)
-      hipLaunchKernelGGL((k_solve_update<T, TB>), dim3((k0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0, st,
+      hipLaunchKernelGGL(upd, dim3((k0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0, st,
                          A, ms, n, k0, nb, B, nrhs, 0, k0);
   }
 }

@@ -32,6 +32,7 @@ __global__ void k_rhs_gather_point(const zd* __restrict__ raw, const int* __rest
 // Alow_i is the lower-medium equation [K2 - D2, -S2] of node i (row i of
 // Alow at Alow + n * lstride + i * rstride).  64 rows per workgroup, every
 // right-hand side at once (rows16.h); grid (row blocks, modes).
+template <bool MM>
 __global__ __launch_bounds__(256) void k_lower_rhs(const zd* __restrict__ Alow, long lstride, long rstride,
                                                    int N, int nrhs, const zd* __restrict__ b1,
                                                    const zd* __restrict__ b2, zd* __restrict__ rhs) {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_lower_rhs(const zd* __restrict__ Alow, 
   zd acc[4];
   bool ow;
   int og;
-  rows16_acc<double>(a, rstride, rbase, N, 0, 2 * N, nrhs,
+  rows16_acc<double, MM>(a, rstride, rbase, N, 0, 2 * N, nrhs,
                      [&](int s, int c) { return (c & 1) ? x2[(long)s * N + (c >> 1)] : x1[(long)s * N + (c >> 1)]; },
                      acc, ow, og);
   const int lane = threadIdx.x & 63;
@@ -163,6 +164,7 @@ __global__ void k_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, long 
 // sides (A row-major n x n per mode), 64 rows per workgroup with every
 // right-hand side at once (rows16.h: A read once, lane per row); rs2 receives
 // |r_i|^2 for the convergence test.  Grid (row blocks, modes).
+template <bool MM>
 __global__ __launch_bounds__(256) void k_residual(const zd* __restrict__ A, long ms, int n,
                                                   int nrhs, const zd* __restrict__ x,
                                                   const zd* __restrict__ rhs, zd* __restrict__ r,
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_residual(const zd* __restrict__ A, long
   zd acc[4];
   bool ow;
   int og;
-  rows16_acc<double>(a, n, rbase, n, 0, n, nrhs, [&](int s, int c) { return xm[(long)s * n + c]; }, acc, ow, og);
+  rows16_acc<double, MM>(a, n, rbase, n, 0, n, nrhs, [&](int s, int c) { return xm[(long)s * n + c]; }, acc, ow, og);
   const int lane = threadIdx.x & 63;
   const int i = rbase + lane;
   if (i >= n || !ow) return;
@@ -240,8 +242,8 @@ void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st) {
 }
 void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd* x, const zd* rhs,
                      zd* r, double* rs2, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3((n + R16_ROWS - 1) / R16_ROWS, modes), dim3(256), 0, st, A, ms, n, nrhs,
-                     x, rhs, r, rs2);
+  hipLaunchKernelGGL(nrhs > 8 ? k_residual<true> : k_residual<false>, dim3((n + R16_ROWS - 1) / R16_ROWS, modes),
+                     dim3(256), 0, st, A, ms, n, nrhs, x, rhs, r, rs2);
 }
 void launch_sumsq(const double* sq, int n, int nvec, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sumsq, dim3(nvec), dim3(256), 0, st, sq, n, out);
@@ -261,7 +263,7 @@ void launch_rhs_gather_point(const zd* raw, const int* rmap, int npt, int N, int
 }
 void launch_lower_rhs(const zd* Alow, long lstride, long rstride, int N, int modes, int nrhs, const zd* b1,
                       const zd* b2, zd* rhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_lower_rhs, dim3((N + R16_ROWS - 1) / R16_ROWS, modes), dim3(256), 0, st, Alow, lstride,
+  hipLaunchKernelGGL(nrhs > 8 ? k_lower_rhs<true> : k_lower_rhs<false>, dim3((N + R16_ROWS - 1) / R16_ROWS, modes), dim3(256), 0, st, Alow, lstride,
                      rstride, N, nrhs, b1, b2, rhs);
 }
 void launch_deinterleave(const zd* A, long n2, zd* out, hipStream_t st) {
