@@ -254,8 +254,11 @@ int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
  * [5] LU total, [6] LU trailing updates, [7] solve total, [8] right-hand
  * sides, [9] refinement, [10] build total; and counters (host, 16 doubles):
  * [0] refinement iterations, [1] final relative residual, [2] real flops of
- * all LU trailing updates (8 per complex multiply-add), [3] number of
- * trailing-update launches (stage [6] is the sum of their durations),
+ * all LU trailing updates (algorithmic: 8 per complex multiply-add; the
+ * matrix cores execute 6 of them, the complex product being formed from
+ * three real ones), [3] number of LU steps with a trailing update (stage [6]
+ * sums, per step, the interval of its two launches: the next block's columns
+ * and the rest),
  * [4] far pairs offered to the surrogate, [5] pairs whose surrogate modes
  * were accepted, [6] far pairs transformed on the full angle grid (the others
  * on the shortest grid that holds modes 0..m_max, when that is shorter). */

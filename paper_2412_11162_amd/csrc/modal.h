@@ -64,11 +64,12 @@ struct NearJob {
   int target, panel, q0, q1;
 };
 
-// The main grid over all node pairs off the near panels: far pairs are
-// transformed in place, split and direct pairs appended to their lists.
-// The pass runs on the grid of cp.nt_small when it is set (tw its
-// twiddles), on cp.nt_far otherwise; far pairs that need the full grid go to
-// far_big.
+// The main grid over the unordered node pairs off the near panels: far pairs
+// are transformed in place in both orderings, split and direct pairs appended
+// to their lists in both orderings.  The pass runs on the grid of
+// cp.nt_small when it is set (tw its twiddles), on cp.nt_far otherwise; far
+// pairs that need the full grid go to far_big once per unordered pair (i, l),
+// i < l (launch_list_far_sym).
 void launch_grid_far(const NodesDev& nd, const ClassParams& cp, zd k1, zd k2,
                      const zd* tw, zd* A, long mstride, int m0, const double* W, WorkList split,
                      WorkList direct, WorkList far_big, WorkList split_big, hipStream_t st);
