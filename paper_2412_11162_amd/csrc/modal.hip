@@ -768,25 +768,31 @@ __global__ __launch_bounds__(64) void k_direct(const PairGeom* __restrict__ geom
       int np = 0;
       // graded breakpoints around c = re0 (both sides), then uniform pieces
       double c = re0;
-      // left side [0, c]
+      // left side [0, c]: the walk from c toward 0 runs twice, first counting
+      // its non-empty pieces, then storing each at its place in increasing
+      // order (no private array: it would live in scratch memory)
       {
-        double bl[128];
-        int nb = 0;
-        double x = c;
-        double h = hmin;
-        while (x > 0.0 && nb < 120) {
-          double step = fmin(h, hmax);
-          double nx = fmax(0.0, x - step);
-          bl[nb++] = nx;
-          x = nx;
-          h *= 2.0;
+        int nl = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+          int q = 0, nb = 0;
+          double x = c, h = hmin;
+          while (x > 0.0 && nb < 120) {
+            const double step = fmin(h, hmax);
+            const double nx = fmax(0.0, x - step);
+            ++nb;
+            if (x > nx) {
+              if (pass) {
+                pa[nl - 1 - q] = nx;
+                pb[nl - 1 - q] = x;
+              }
+              ++q;
+            }
+            x = nx;
+            h *= 2.0;
+          }
+          nl = q;
         }
-        // pieces from 0 up to c in increasing order
-        for (int q = nb - 1; q >= 0; --q) {
-          double b = q == 0 ? c : bl[q - 1];
-          double a = bl[q];
-          if (b > a && np < DIRECT_MAX_PIECES) { pa[np] = a; pb[np] = b; ++np; }
-        }
+        np = nl;
       }
       // right side [c, pi]
       {
