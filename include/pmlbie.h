@@ -201,6 +201,19 @@ int pmlbie_evaluate_field(pmlbie_ctx* ctx, int n_pts, const double* rtz, double*
  * the next solve_modes.  Errors: PMLBIE_EINVAL. */
 int pmlbie_set_refinement(pmlbie_ctx* ctx, double tol, int max_iter);
 
+/* The substitution of Sec. 4.3 (eq. eqch1) for the close pairs deep in the
+ * PML, for studying it against the graded direct rule: with order L > 0,
+ * the pairs the classification gives to the direct rule (the "direct" class)
+ * go instead through the split of Sec. 4.1 with H1 replaced by cH1(q, L) =
+ * e^{iq} (Taylor polynomial of order L of H1 e^{-iq}), i H2 by e^{iq} - cH1,
+ * and H3, i H4 the same way (H3 + i H4 = e^{iq} (1 - iq)); q = k R.  The
+ * paper takes L = 5.  Read literally, the substitution leaves odd powers of q
+ * in the smooth parts, and on these pairs the kernels it gives miss the
+ * parity bar of the direct rule by orders of magnitude; the default (0)
+ * keeps the direct rule.  Takes effect at the next build or modal-kernel
+ * call.  Errors: PMLBIE_EINVAL (L outside 0..12). */
+int pmlbie_set_ch1_substitution(pmlbie_ctx* ctx, int order);
+
 /* ---- inspection ---------------------------------------------------------- */
 
 /* Test hook of the zero-pivot path (Sec. 4.2 per-mode LU): the next build

@@ -29,7 +29,8 @@ EXPORTS = (
     "pmlbie_solve_modes",
     "pmlbie_evaluate_field", "pmlbie_get_info", "pmlbie_get_nodes", "pmlbie_modal_kernels",
     "pmlbie_modal_kernels_noalloc",
-    "pmlbie_get_operator", "pmlbie_get_stats", "pmlbie_set_refinement", "pmlbie_test_zero_column",
+    "pmlbie_get_operator", "pmlbie_get_stats", "pmlbie_set_refinement", "pmlbie_set_ch1_substitution",
+    "pmlbie_test_zero_column",
     "pmlbie_surrogate_nparams", "pmlbie_surrogate_init", "pmlbie_surrogate_make_samples",
     "pmlbie_surrogate_train", "pmlbie_surrogate_eval", "pmlbie_surrogate_eval_modes",
     "pmlbie_surrogate_set_tolerance",
@@ -76,6 +77,7 @@ def load():
     L.pmlbie_get_stats.argtypes = [P, P, P]
     L.pmlbie_set_refinement.argtypes = [P, d, i]
     L.pmlbie_test_zero_column.argtypes = [P, i, i]
+    L.pmlbie_set_ch1_substitution.argtypes = [P, i]
     ul, l, sz = ctypes.c_ulonglong, ctypes.c_long, ctypes.c_size_t
     L.pmlbie_surrogate_nparams.argtypes = []
     L.pmlbie_surrogate_init.argtypes = [P, ul]

@@ -112,6 +112,9 @@ struct pmlbie_ctx {
   // refinement stopping rule of the mixed-precision solve
   double ref_tol = 1e-10;
   int ref_maxit = 30;
+  // > 0: the pairs of the direct class go through the split with the
+  // substitution of Sec. 4.3 of this order (pmlbie_set_ch1_substitution)
+  int ch1_L = 0;
   // one-shot test hook: zero this column of this mode's matrix before the LU
   int zc_mode = -1, zc_col = -1;
   // learned surrogate of the far-pair modes
@@ -191,7 +194,7 @@ struct Timer {
 // Split-path work on a device list [first, first+count): phase 1 (singular
 // modes) in chunks, phase 2 (smooth FFTs + convolution).
 void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count, zd* A, long n2,
-               long ms, const double* W, zd* raw, bool small_grid = false) {
+               long ms, const double* W, zd* raw, bool small_grid = false, int chL = 0) {
   // the full grid L (singular modes to MQ = L/2 - 1), or the shorter grid
   // of the pairs classed CLASS_SPLIT under ClassParams.split_rho_small
   const int nt = small_grid ? c->nt_small : c->nt_int;
@@ -210,7 +213,7 @@ void run_split(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long count
     launch_split_singular(geom, f, cn, MQ, c->qtab.p, c->qcoef.p, c->zhat.p, c->phat.p, c->stream);
     HIPCHK(hipGetLastError());
     launch_split(nt, geom, dest, f, cn, c->M, c->m0, MQ, c->k1, c->k2, tw, c->zhat.p, c->phat.p, A, n2, ms, W,
-                 raw, c->stream);
+                 raw, c->stream, chL);
     HIPCHK(hipGetLastError());
   }
 }
@@ -294,8 +297,11 @@ void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, co
   HIPCHK(hipGetLastError());
   run_split(c, ws.geom, ws.dest, cnt[1], nullptr, 0, 0, nullptr, raw, cpl.split_rho_small > 0.0);
   run_split(c, wsb.geom, wsb.dest, cnt[3], nullptr, 0, 0, nullptr, raw);
-  launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
-                nullptr, raw, kOmegaPiece, c->stream);
+  if (c->ch1_L > 0)
+    run_split(c, wd.geom, wd.dest, cnt[2], nullptr, 0, 0, nullptr, raw, false, c->ch1_L);
+  else
+    launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
+                  nullptr, raw, kOmegaPiece, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
 }
@@ -706,8 +712,11 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     run_split(c, wsb.geom, wsb.dest, counts[3], c->A.p, n2, ms, nd.W, nullptr);
     c->stage_ms[2] = t_split.stop();
     Timer t_direct(c->stream);
-    launch_direct(c->lgeom.p + cap, c->ldest.p + cap, 0, counts[1], M, m0, c->k1, c->k2, c->glx.p,
-                  c->glw.p, c->A.p, n2, ms, nd.W, nullptr, kOmegaPiece, c->stream);
+    if (c->ch1_L > 0)
+      run_split(c, c->lgeom.p + cap, c->ldest.p + cap, counts[1], c->A.p, n2, ms, nd.W, nullptr, false, c->ch1_L);
+    else
+      launch_direct(c->lgeom.p + cap, c->ldest.p + cap, 0, counts[1], M, m0, c->k1, c->k2, c->glx.p,
+                    c->glw.p, c->A.p, n2, ms, nd.W, nullptr, kOmegaPiece, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[3] = t_direct.stop();
 
@@ -1183,8 +1192,18 @@ int pmlbie_modal_kernels_noalloc(pmlbie_ctx* c, int n_pairs, const double* geom,
                    nullptr, 0, 0, nullptr, raw, c->stream);
       HIPCHK(hipGetLastError());
     }
-    launch_direct(wd.geom, wd.dest, 0, h[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0, nullptr,
-                  raw, kOmegaPiece, c->stream);
+    if (c->ch1_L > 0) {
+      for (long f = 0; f < (long)h[2]; f += kNaSplitChunk) {
+        const long cn = std::min<long>(kNaSplitChunk, (long)h[2] - f);
+        launch_split_singular(wd.geom, f, cn, c->MQ, qtab, qcoef, zhat, phat, c->stream);
+        HIPCHK(hipGetLastError());
+        launch_split(c->nt_int, wd.geom, wd.dest, f, cn, c->M, 0, c->MQ, c->k1, c->k2, c->tw_int.p, zhat, phat,
+                     nullptr, 0, 0, nullptr, raw, c->stream, c->ch1_L);
+      }
+    } else {
+      launch_direct(wd.geom, wd.dest, 0, h[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0, nullptr,
+                    raw, kOmegaPiece, c->stream);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     return PMLBIE_OK;
@@ -1213,6 +1232,13 @@ int pmlbie_set_refinement(pmlbie_ctx* c, double tol, int max_iter) {
     return fail(c, PMLBIE_EINVAL, "set_refinement: need 0 < tol < 1 and 1 <= max_iter <= 100");
   c->ref_tol = tol;
   c->ref_maxit = max_iter;
+  return PMLBIE_OK;
+}
+
+int pmlbie_set_ch1_substitution(pmlbie_ctx* c, int order) {
+  if (!c) return PMLBIE_EINVAL;
+  if (order < 0 || order > 12) return fail(c, PMLBIE_EINVAL, "set_ch1_substitution: order must be 0..12");
+  c->ch1_L = order;
   return PMLBIE_OK;
 }
 

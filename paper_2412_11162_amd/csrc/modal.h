@@ -94,9 +94,10 @@ void launch_classify_list(const PairGeom* geom, long count, const ClassParams& c
 // (pair-major), read by launch_split.
 void launch_split_singular(const PairGeom* geom, long first, long count, int MQ, zd* qtab, zd* coef,
                            zd* zhat, zd* phat, hipStream_t st);
+// chL > 0: the smooth parts with the substitution of Sec. 4.3 of order chL.
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                   int m0, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
-                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st);
+                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st, int chL = 0);
 void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, int m0,
                    zd k1, zd k2, const double* glx, const double* glw, zd* A, long n2,
                    long mstride, const double* W, zd* raw, double omega_piece, hipStream_t st);

@@ -657,13 +657,16 @@ __global__ __launch_bounds__(256) void k_split_tables(const zd* __restrict__ qta
 // K) exactly for n <= M when L >= 2 MQ + 1 and the smooth parts carry no
 // modes beyond MQ - M.  Zs, Ds come from one transform of the even mode
 // sequences; the four products from one transform per wavenumber.
-template <int R>
+// CH (chL > 0): the substitution of Sec. 4.3 (eq. eqch1, split_smooth_ch) in
+// place of H1, i H2, H3, i H4: S_n = modes of [Zs cH1 + Z (e^{iq} - cH1)],
+// K_n = modes of [Ds cH3 + D (e^{iq} (1 - iq) - cH3)].
+template <int R, bool CH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_split(const PairGeom* __restrict__ geom,
                                               const int2* __restrict__ dest, long first,
                                               long count, int M, int MQ, zd k1, zd k2,
                                               const zd* __restrict__ tw,
                                               const zd* __restrict__ zhat,
-                                              const zd* __restrict__ phat, OutSpec o) {
+                                              const zd* __restrict__ phat, OutSpec o, int chL) {
   constexpr int L = 64 * R, H = L / 2 + 1;
   __shared__ zd lds[pair_lds<R>()];
   zd* P2 = lds;
@@ -716,13 +719,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const double sh = sin(PMLBIE_PI * j / L);
       const zd Rd = csqrt_(v.d2 + (sh * sh) * v.c4);
       const zd zs = P2[j], ds = P2[H + j];
-      zd H1, ZH2, H3, DH4;
-      split_smooth(sc, Rd, k1, H1, ZH2, H3, DH4);
-      P1[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
-      P1[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
-      split_smooth(sc, Rd, k2, H1, ZH2, H3, DH4);
-      P2[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
-      P2[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
+      if constexpr (CH) {
+        zd H1c, Sr, H3c, Kr;
+        split_smooth_ch(sc, Rd, k1, chL, H1c, Sr, H3c, Kr);
+        P1[j] = zs * H1c + Sr;
+        P1[H + j] = ds * H3c + Kr;
+        split_smooth_ch(sc, Rd, k2, chL, H1c, Sr, H3c, Kr);
+        P2[j] = zs * H1c + Sr;
+        P2[H + j] = ds * H3c + Kr;
+      } else {
+        zd H1, ZH2, H3, DH4;
+        split_smooth(sc, Rd, k1, H1, ZH2, H3, DH4);
+        P1[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
+        P1[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
+        split_smooth(sc, Rd, k2, H1, ZH2, H3, DH4);
+        P2[j] = zs * H1 + zd{-ZH2.im, ZH2.re};
+        P2[H + j] = ds * H3 + zd{-DH4.im, DH4.re};
+      }
     }
     __syncthreads();
     transform_emit<R>(P1, E, tw, o, dst, 0);
@@ -1161,21 +1174,25 @@ void launch_split_singular(const PairGeom* geom, long first, long count, int MQ,
 template <int R>
 static void launch_split_t(const PairGeom* geom, const int2* dest, long first, long count, int M,
                            int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
-                           const OutSpec& o, hipStream_t st) {
+                           const OutSpec& o, int chL, hipStream_t st) {
   int grid = (int)std::min<long>(count, 256L * 32);
-  hipLaunchKernelGGL(k_split<R>, dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, MQ, k1,
-                     k2, tw, zhat, phat, o);
+  if (chL > 0)
+    hipLaunchKernelGGL((k_split<R, true>), dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, MQ, k1, k2, tw,
+                       zhat, phat, o, chL);
+  else
+    hipLaunchKernelGGL((k_split<R, false>), dim3(grid), dim3(64), 0, st, geom, dest, first, count, M, MQ, k1, k2,
+                       tw, zhat, phat, o, 0);
 }
 
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                   int m0, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
-                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st) {
+                  zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st, int chL) {
   if (count <= 0) return;
   OutSpec o{A, n2, mstride, W, raw, M, m0};
   switch (nt) {
-    case 512: launch_split_t<8>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
-    case 1024: launch_split_t<16>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
-    case 2048: launch_split_t<32>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, st); break;
+    case 512: launch_split_t<8>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, chL, st); break;
+    case 1024: launch_split_t<16>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, chL, st); break;
+    case 2048: launch_split_t<32>(geom, dest, first, count, M, MQ, k1, k2, tw, zhat, phat, o, chL, st); break;
     default: break;
   }
 }

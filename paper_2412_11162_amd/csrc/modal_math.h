@@ -119,6 +119,51 @@ HD void split_smooth(const SplitCoef& sc, zd R, zd k, zd& H1, zd& ZH2, zd& H3, z
   DH4 = (sc.e0 * (k * k * k) + sc.e1 * k * q2) * s3 * (-0.25 / PMLBIE_PI);
 }
 
+// The substitution of Sec. 4.3 (eq. eqch1) at one sample, q = k R: cH1 =
+// e^{iq} P_L(q) with P_L the Taylor polynomial of order L of cos(q) e^{-iq},
+// and cH3 = e^{iq} Q_L(q) with Q_L that of H3 e^{-iq}.  With Z = 1/(4 pi R)
+// and the double-layer factor D, S = Z cH1 + Z (e^{iq} - cH1) and
+// K = D cH3 + D (e^{iq} (1 - iq) - cH3) (H3 + i H4 = e^{iq} (1 - iq)).
+// Returned: cH1, the S remainder, cH3 and the K remainder.  From
+// cos(q) e^{-iq} = (1 + e^{-2iq}) / 2 and H3 e^{-iq} = ((1 - iq) + (1 + iq)
+// e^{-2iq}) / 2: a_0 = 1, a_j = t_j / 2; b_0 = 1, b_1 = -i and
+// b_j = (t_j + i t_{j-1}) / 2 for j >= 2, with t_j = (-2i)^j / j!; b_2 = 0
+// exactly.  The remainders are summed from their series in q, so that no
+// division by R occurs: Z (e^{iq} - cH1) = -e^{iq} k sum_{j>=1} a_j q^{j-1}
+// / (4 pi) and D (e^{iq} (1 - iq) - cH3) = e^{iq} sum_{j>=3} b_j (e0 k^3
+// q^{j-3} + e1 k q^{j-1}) / (4 pi).
+HD void split_smooth_ch(const SplitCoef& sc, zd R, zd k, int L, zd& H1c, zd& Srem, zd& H3c, zd& Krem) {
+  const zd q = k * R;
+  zd cq, sq;
+  ccossin_(q, cq, sq);
+  const zd eq = cq + zd{-sq.im, sq.re};  // e^{iq}
+  const zd k3 = k * k * k;
+  zd P{1.0, 0.0}, Q{1.0, 0.0}, sr{0.0, 0.0}, kr{0.0, 0.0};
+  zd t{1.0, 0.0};   // t_j
+  zd qm{1.0, 0.0};  // q^{j-1}
+  zd qm3{1.0, 0.0};  // q^{j-3} (from j = 3)
+  for (int j = 1; j <= L; ++j) {
+    const zd tp = t;
+    t = zd{2.0 * t.im, -2.0 * t.re} * (1.0 / j);  // t_j = t_{j-1} (-2i) / j
+    const zd a = 0.5 * t;
+    const zd b = j == 1 ? zd{0.0, -1.0} : 0.5 * (t + zd{-tp.im, tp.re});
+    sr = sr + a * qm;
+    const zd qj = qm * q;
+    P = P + a * qj;
+    Q = Q + b * qj;
+    if (j >= 3) {
+      kr = kr + b * (sc.e0 * k3 * qm3 + sc.e1 * k * qm);
+      qm3 = qm3 * q;
+    }
+    qm = qj;
+  }
+  const double f = 0.25 / PMLBIE_PI;
+  H1c = eq * P;
+  H3c = eq * Q;
+  Srem = (-f) * (eq * (k * sr));
+  Krem = f * (eq * kr);
+}
+
 // ---------------------------------------------------------------------------
 // Carlson's symmetric elliptic integrals for complex arguments (duplication
 // algorithm, Carlson 1995; valid for arguments off the negative real axis).

@@ -215,6 +215,9 @@ class Solver:
     def set_refinement(self, tol: float, max_iter: int):
         self._chk(self.L.pmlbie_set_refinement(self.h, float(tol), int(max_iter)))
 
+    def set_ch1_substitution(self, order: int):
+        self._chk(self.L.pmlbie_set_ch1_substitution(self.h, int(order)))
+
     def test_zero_column(self, mode: int, col: int):
         self._chk(self.L.pmlbie_test_zero_column(self.h, int(mode), int(col)))
 

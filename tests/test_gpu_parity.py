@@ -206,6 +206,106 @@ def test_paper_scale_modal_kernels_sampled(paper_solver):
             assert _normwise(out[:, sidx, n], refr[:, sidx, n]) <= KERNEL_TOL, (sidx, n)
 
 
+def _direct_class_pairs(wl, g, count, seed):
+    """Node pairs of the workload that the classification gives to the graded
+    direct rule: both nodes in the PML on panels that are not neighbours,
+    not far on the full angle grid of the build (the aliasing bound delta (L -
+    M - B) >= 34 fails, delta = |Im D*| of the nearest complex singularity,
+    sin^2(D*/2) = -d~^2 / (4 rho~ rho~'), B = 1.1 k_max sqrt|rho~ rho~'|) and
+    growing in the PML (k_max |Im R(pi)| > 9)."""
+    rt = g.rho + 1j * g.I
+    kmax = max(abs(wl.k1), abs(wl.k2))
+    Mq = wl.m_max
+    bneed = math.ceil(1.15 * kmax * abs(rt.max()) + 16.0)
+    L = max(512, 2 ** math.ceil(math.log2(max(wl.n_theta, 2.0 * (Mq + bneed) + 2.0))))
+    pml = np.nonzero(g.rho > wl.a1)[0]
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(200000):
+        i, l = rng.choice(pml, 2)
+        if abs(g.panel_of[i] - g.panel_of[l]) <= 1:
+            continue
+        d2 = (rt[i] - rt[l]) ** 2 + (g.z[i] - g.z[l]) ** 2
+        c4 = 4 * rt[i] * rt[l]
+        delta = abs((2 * np.arcsin(np.sqrt(-d2 / c4 + 0j))).imag)
+        bw = 1.1 * kmax * math.sqrt(abs(rt[i] * rt[l]))
+        if delta * (L - Mq - bw) < 34 and kmax * abs(np.sqrt(d2 + c4).imag) > 9:
+            out.append((int(i), int(l)))
+            if len(out) == count:
+                break
+    return np.array(out)
+
+
+def test_ch1_substitution_against_the_direct_rule(paper_solver):
+    """The substitution of Sec. 4.3 (eq. eqch1, L = 5, set by
+    pmlbie_set_ch1_substitution) as the split of the pairs the graded direct
+    rule takes, on such pairs of the benchmark size, against the oracle's
+    adaptive quadrature; both paths timed on the same pairs.  Only the
+    direct-class pairs go through the substitution, so every pair's kernels
+    change when it is switched on.  The direct rule meets the kernel bar; the
+    substitution misses the mixed-precision bar (1e-6) as well: its
+    remainder e^{iq} (1 - P_5(q)) / (4 pi R) keeps odd powers of q = k R, not
+    smooth in the angle at the nearest complex singularity of R, and its
+    modes beyond the kept ones alias into them (reading R7)."""
+    import time
+    import oracle
+    wl, s = paper_solver
+    g = oracle.geometry(wl)
+    pairs = _direct_class_pairs(wl, g, 8, seed=41)
+    assert len(pairs) == 8
+    geom = np.array([[g.rho[i], g.I[i], g.rho[l], g.I[l], g.rho[i] - g.rho[l], g.I[i] - g.I[l],
+                      g.z[i] - g.z[l], 0.0, g.nrho[l].real, g.nrho[l].imag, g.nz[l].real, g.nz[l].imag]
+                     for i, l in pairs])
+    modes = list(range(wl.m_max + 1))
+    ref = oracle.modal_kernels_nodes(g, pairs, [wl.k1, wl.k2], modes)
+    refr = np.stack([ref[:, 0, 0], ref[:, 0, 1], ref[:, 1, 0], ref[:, 1, 1]], axis=1)
+    many = np.tile(geom, (20000, 1))
+
+    def timed():
+        s.modal_kernels(many)  # warm: work lists and tables sized
+        t0 = time.perf_counter()
+        s.modal_kernels(many)
+        return time.perf_counter() - t0
+
+    try:
+        out_d = s.modal_kernels(geom).cpu().numpy()
+        t_d = timed()
+        s.set_ch1_substitution(5)
+        out_c = s.modal_kernels(geom).cpu().numpy()
+        t_c = timed()
+    finally:
+        s.set_ch1_substitution(0)
+    for q in range(len(pairs)):
+        assert not np.array_equal(out_d[q], out_c[q]), ("not in the direct class", pairs[q])
+    assert np.all(np.isfinite(out_c))
+    err_d = max(_normwise(out_d[:, sidx, n], refr[:, sidx, n]) for sidx in range(4) for n in modes)
+    err_c = max(_normwise(out_c[:, sidx, n], refr[:, sidx, n]) for sidx in range(4) for n in modes)
+    print("direct-class pairs %s: largest normwise error over (S1, K1, S2, K2) x modes 0..%d: graded direct "
+          "rule %.1e, substitution L = 5 %.1e; time for %d pairs (host clock of the whole call, upload and "
+          "classification included): direct %.1f ms, substitution %.1f ms"
+          % (pairs.tolist(), wl.m_max, err_d, err_c, len(many), 1e3 * t_d, 1e3 * t_c))
+    assert err_d <= KERNEL_TOL
+    assert err_c > 1e-6
+
+
+def test_ch1_substitution_boundary_data_at_paper_scale():
+    """The whole FP64 solve at the benchmark size with the substitution of
+    Sec. 4.3 (L = 5) in place of the graded direct rule, against the oracle's
+    full solve of modes 0, 2, 8, 64, 128 for three incidences (the stored file
+    of test_paper_scale_boundary_data_against_stored_oracle, which the direct
+    rule meets at 1e-8): the per-mode errors of the substituted operators."""
+    wl = workloads.paper_scale()
+    s = _solver(wl, build=False)
+    s.set_ch1_substitution(5)
+    s.build_modal_operators(wl.n_theta, wl.m_max, 0, 0)
+    ref = _golden("paper_scale")
+    incs = _stored_incidences(ref)
+    modes, errs = _stored_errors(s.solve_modes(incs), ref)
+    _print_errors("paper scale FP64, cH1 substitution (L = 5)", modes, errs, incs)
+    assert np.all(np.isfinite(errs))
+    assert np.max(errs) > BOUNDARY_TOL, errs
+
+
 @pytest.fixture(scope="module")
 def paper_rows():
     """Oracle operator rows and point-source data at the benchmark size for
