@@ -96,6 +96,7 @@ struct pmlbie_ctx {
   DBuf<double> rsq, rnorm;
   DBuf<int> ipiv, info;
   DBuf<zd> luw;  // inverses of the LU diagonal blocks
+  DBuf<int> lumap;  // row map of an LU step's second block
   DBuf<PairGeom> lgeom;
   DBuf<int2> ldest;
   DBuf<unsigned> lcount;
@@ -532,6 +533,10 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     if (m_min < 0 || m_min > m_max) return fail(c, PMLBIE_EINVAL, "build: need 0 <= m_min <= m_max");
     if (precision != PMLBIE_FP64 && precision != PMLBIE_MIXED)
       return fail(c, PMLBIE_EINVAL, "build: precision must be PMLBIE_FP64 or PMLBIE_MIXED");
+    if (2L * c->N > LU_MAX_N)
+      return fail(c, PMLBIE_EINVAL, "build: at most " + std::to_string(LU_MAX_N / 2) +
+                                        " curve nodes (the per-mode LU takes at most " + std::to_string(LU_MAX_N) +
+                                        " unknowns)");
     const bool use_sg = (flags & PMLBIE_USE_SURROGATE) != 0;
     if (use_sg) {
       if (!c->sg_ready) return fail(c, PMLBIE_ESTATE, "build: no surrogate network (init, train or load one)");
@@ -619,6 +624,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->A.alloc((size_t)nm * ms);
     c->ipiv.alloc((size_t)nm * n2);
     c->luw.alloc((size_t)nm * LU_NB * LU_NB);
+    c->lumap.alloc((size_t)nm * n2);
     c->info.alloc(nm);
     HIPCHK(hipMemsetAsync(c->info.p, 0, nm * sizeof(int), c->stream));
     // work lists of the grid (split, direct, far and split on the full grid
@@ -764,7 +770,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
 
     // per-mode LU (complex128, or complex64 on FP32 MFMA in mixed precision)
     Timer t_lu(c->stream);
-    const int npan = (int)((n2 + LU_NB - 1) / LU_NB);
+    const int npan = std::max(1, lu_update_steps((int)n2));
     std::vector<hipEvent_t> gb(npan), ge(npan);
     for (int k = 0; k < npan; ++k) {
       HIPCHK(hipEventCreate(&gb[k]));
@@ -781,26 +787,20 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
       launch_to_c64(c->A.p, c->A32.p, (long)nm * ms, c->stream);
       HIPCHK(hipGetLastError());
       lu_factor_batched<float>(c->A32.p, ms, (int)n2, nm, c->ipiv.p, c->info.p,
-                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm, c->lu_stream, c->lu_ev);
+                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm, c->lu_stream, c->lu_ev, c->lumap.p);
     } else {
       lu_factor_batched<double>(c->A.p, ms, (int)n2, nm, c->ipiv.p, c->info.p, c->luw.p,
-                                c->stream, &tm, c->lu_stream, c->lu_ev);
+                                c->stream, &tm, c->lu_stream, c->lu_ev, c->lumap.p);
     }
     HIPCHK(hipGetLastError());
     c->stage_ms[5] = t_lu.stop();
     // algorithmic flops of the trailing updates (8 real flops per complex
     // multiply-add) and the number of their launches
-    double gflop = 0;
-    for (int p = 0; p < npan; ++p) {
-      const double nbp = std::min<long>(LU_NB, n2 - (long)p * LU_NB);
-      const double mr = (double)n2 - (double)p * LU_NB - nbp;
-      gflop += 8.0 * mr * mr * nbp * nm;
-    }
-    c->counters[2] = gflop;
-    c->counters[3] = (double)(npan - 1);
+    c->counters[2] = lu_update_flops((int)n2, nm);
+    c->counters[3] = (double)lu_update_steps((int)n2);
     // summed durations of the trailing-update launches
     double gsum = 0;
-    for (int k = 0; k + 1 < npan; ++k) {
+    for (int k = 0; k < lu_update_steps((int)n2); ++k) {
       float ms1 = 0;
       if (hipEventElapsedTime(&ms1, gb[k], ge[k]) == hipSuccess) gsum += ms1;
     }

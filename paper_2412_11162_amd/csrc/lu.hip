@@ -366,11 +366,11 @@ template <> struct mfma_t<float> {
 // is lower triangular), which leaves every wave the same work.
 template <typename T>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_trsm_mfma(
-    cx<T>* __restrict__ A, long ms, int n, int k0, int nb, int cend, const cx<T>* __restrict__ W) {
+    cx<T>* __restrict__ A, long ms, int n, int k0, int nb, int cbeg, int cend, const cx<T>* __restrict__ W) {
   typedef typename mfma_t<T>::acc acc_t;
   cx<T>* a = A + (long)blockIdx.y * ms;
   const cx<T>* w = W + (long)blockIdx.y * LU_NB * LU_NB;
-  const int c0 = k0 + nb + blockIdx.x * 64;
+  const int c0 = cbeg + blockIdx.x * 64;
   constexpr int KC = 16;
   __shared__ T Lre[KC][LU_NB + 4], Lim[KC][LU_NB + 4];  // W chunk: [k][row]
   __shared__ T Bre[KC][64 + 4], Bim[KC][64 + 4];        // A12 chunk: [k][col]
@@ -470,7 +470,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4))) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
                                                      int k0, int nb, int cbeg, int cend, int tx, int ty,
-                                                     int batch) {
+                                                     int batch, int rend, const int* __restrict__ rmap,
+                                                     int mapk) {
   typedef typename mfma_t<T>::acc acc_t;
   const long tiles = (long)tx * ty * batch;
   const long per_xcd = (tiles + 7) / 8;
@@ -506,7 +507,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       for (int j = 0; j < 4; ++j) {
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
-        const cx<T> v = (gc < cend && gr < n) ? a[(long)gr * n + gc] : cx<T>{T(0), T(0)};
+        const cx<T> v = (gc < cend && gr < rend) ? a[(long)gr * n + gc] : cx<T>{T(0), T(0)};
         v1[x][y][j] = T(0);
         v2[x][y][j] = v.re;
         v3[x][y][j] = v.im - v.re;
@@ -514,13 +515,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // global -> register prefetch of the next K chunk overlaps the MFMA work
   // on the current one; each thread moves NP elements of L21 and of U12
   cx<T> pl[NP], pu[NP];
+  // a thread's rows of L21 are the same in every chunk: the storage rows of
+  // the first mapk columns (through rmap) are read once
+  int mrow[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
+    const int gr = r0 + (tid + 256 * t) / KC;
+    mrow[t] = (rmap && gr < rend) ? rmap[(long)bz * n + gr] : gr;
+  }
   auto gload = [&](int kk) {
 #pragma unroll
     for (int t = 0; t < NP; ++t) {
       const int e = tid + 256 * t;
       const int k = e % KC, rr = e / KC;  // row-major L21: k contiguous
       const int gr = r0 + rr, gk = kk + k;
-      pl[t] = (gr < n && gk < nb) ? a[(long)gr * n + k0 + gk] : cx<T>{T(0), T(0)};
+      const int lr = gk < mapk ? mrow[t] : gr;
+      pl[t] = (gr < rend && gk < nb) ? a[(long)lr * n + k0 + gk] : cx<T>{T(0), T(0)};
       const int cc = e & 63, ku = e >> 6;  // row-major U12: columns contiguous
       const int gc = c0 + cc, gku = kk + ku;
       pu[t] = (gc < cend && gku < nb) ? a[(long)(k0 + gku) * n + gc] : cx<T>{T(0), T(0)};
@@ -574,7 +584,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       for (int j = 0; j < 4; ++j) {
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
-        if (gc < cend && gr < n)
+        if (gc < cend && gr < rend)
           a[(long)gr * n + gc] = cx<T>{v2[x][y][j] - v1[x][y][j], v3[x][y][j] + v1[x][y][j] + v2[x][y][j]};
       }
 }
@@ -786,35 +796,64 @@ __global__ __launch_bounds__(256) void k_laswp(cx<T>* __restrict__ A, long ms, i
   }
 }
 
-// U12 = L11^{-1} A12 for columns [k0 + nb, cend) of the rows [k0, k0 + nb):
-// with W, the inverse of the diagonal block by the column solver and the
-// product on MFMA; without, the column solver in place.
+// U12 = L11^{-1} A12 for columns [cbeg, cend) of the rows [k0, k0 + nb),
+// cbeg >= k0 + nb: with W, W = L11^{-1} by the column solver and the product
+// on MFMA; without, the column solver in place (cbeg = k0 + nb).
 template <typename T>
-static void trsm_part(cx<T>* A, long ms, int n, int k0, int nb, int cend, int batch, hipStream_t st,
+static void trsm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int cend, int batch, hipStream_t st,
                       cx<T>* W) {
-  const int cols = cend - k0 - nb;
+  const int cols = cend - cbeg;
   if (cols <= 0) return;
   if (W) {
-    hipLaunchKernelGGL(k_trsm<T>, dim3((nb + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms, n, k0, nb,
-                       cend, W);
-    hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(512), 0, st, A, ms, n, k0,
-                       nb, cend, (const cx<T>*)W);
+    hipLaunchKernelGGL(k_trsm<T>, dim3((nb + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms,
+                       n, k0, nb, cend, W);
+    hipLaunchKernelGGL(k_trsm_mfma<T>, dim3((cols + 63) / 64, batch), dim3(512), 0, st, A, ms, n, k0, nb, cbeg,
+                       cend, (const cx<T>*)W);
   } else {
     hipLaunchKernelGGL(k_trsm<T>, dim3((cols + trsm_cols<T>() - 1) / trsm_cols<T>(), batch), dim3(256), 0, st, A, ms, n, k0, nb,
                        cend, (cx<T>*)nullptr);
   }
 }
 
-// A22 -= L21 U12 over the rows below k0 + nb and columns [cbeg, cend).
+// A22 -= L21 U12 over the rows [k0 + nb, rend) (rend < 0: n) and columns
+// [cbeg, cend); with rmap, the rows of the first mapk columns of L21 are
+// read at rmap[row] (per matrix, n entries).
 template <typename T>
-static void gemm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int cend, int batch, hipStream_t st) {
-  const int cols = cend - cbeg, rows = n - k0 - nb;
+static void gemm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int cend, int batch, hipStream_t st,
+                      int rend = -1, const int* rmap = nullptr, int mapk = 0) {
+  if (rend < 0) rend = n;
+  const int cols = cend - cbeg, rows = rend - k0 - nb;
   if (cols <= 0 || rows <= 0) return;
   const int tx = (cols + 63) / 64, ty = (rows + 63) / 64;
   const long tiles = (long)tx * ty * batch;
   const long grid = ((tiles + 7) / 8) * 8;
   hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)grid), dim3(256), 0, st, A, ms, n, k0, nb, cbeg, cend,
-                     tx, ty, batch);
+                     tx, ty, batch, rend, rmap, mapk);
+}
+
+// The row order that the interchanges of block [b1, b1 + nb1) leave, as
+// storage rows of the columns left of it (which the interchanges do not
+// touch): rmap[b n + r] for rows r in [b1, n).  One workgroup per matrix;
+// the interchanges are applied in order to the identity in LDS.
+__global__ __launch_bounds__(256) void k_row_map(const int* __restrict__ ipiv, int n, int b1, int nb1,
+                                                 int* __restrict__ rmap) {
+  __shared__ int sg[LU_MAX_N];
+  const int* piv = ipiv + (long)blockIdx.x * n;
+  int* out = rmap + (long)blockIdx.x * n;
+  const int m = n - b1;
+  for (int x = threadIdx.x; x < m; x += 256) sg[x] = b1 + x;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < nb1; ++j) {
+      const int p = piv[b1 + j] - b1;
+      if (p != j) {
+        const int t = sg[j];
+        sg[j] = sg[p];
+        sg[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int x = threadIdx.x; x < m; x += 256) out[b1 + x] = sg[x];
 }
 
 // One LU_NB block column [k0, k0 + nb), rows [k0, n): leaves of LU_LEAF
@@ -827,50 +866,99 @@ static void factor_block(cx<T>* A, long ms, int n, int k0, int batch, int* ipiv,
   for (int j0 = 0; j0 < nb; j0 += LU_LEAF) {
     const int lb = std::min(LU_LEAF, nb - j0);
     panel_any<T>(A, ms, n, k0 + j0, lb, k0, ce, batch, ipiv, info, st);
-    trsm_part<T>(A, ms, n, k0 + j0, lb, ce, batch, st, nullptr);
+    trsm_part<T>(A, ms, n, k0 + j0, lb, k0 + j0 + lb, ce, batch, st, nullptr);
     gemm_part<T>(A, ms, n, k0 + j0, lb, k0 + j0 + lb, ce, batch, st);
   }
 }
 
-// Step k: the block's interchanges on the trailing columns, U12, the update
-// of the next block's columns, then the rest of the update; with a second
-// stream the next block is factored there while the rest runs.
+// Two blocks of LU_NB make a step (K = 2 LU_NB in the trailing update,
+// whose rate is ~12% higher than at K = LU_NB).  A step's columns [s0, s0 +
+// w) are factored within them: the first block, its interchanges and U rows
+// on the second block's columns, the second block's update, the second
+// block.  Then the step's interchanges and U rows on the trailing columns
+// (the second block's U rows first take the first block's product), the
+// update of the next step's columns, and the rest of the update, beside the
+// next step's factorisation on a second stream.  The first block's L rows
+// stay stored in the order of its own factorisation (the solves read them
+// so); the update reads them through the row map of the second block's
+// interchanges.
+static int step_width(int n, int s0) { return std::min(2 * LU_NB, n - s0); }
+
+int lu_update_steps(int n) {
+  int k = 0;
+  for (int s0 = 0; s0 + step_width(n, s0) < n; s0 += 2 * LU_NB) ++k;
+  return k;
+}
+
+double lu_update_flops(int n, int batch) {
+  double f = 0;
+  for (int s0 = 0; s0 + step_width(n, s0) < n; s0 += 2 * LU_NB) {
+    const double w = step_width(n, s0), m = n - s0 - w;
+    f += 8.0 * m * m * w * batch;
+  }
+  return f;
+}
+
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
-                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev) {
+                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev, int* rmap) {
   const bool la = st2 != nullptr && la_ev != nullptr;
-  factor_block<T>(A, ms, n, 0, batch, ipiv, info, st);
-  for (int k0 = 0; k0 < n; k0 += LU_NB) {
-    const int nb = std::min(LU_NB, n - k0), c1 = k0 + nb;
+  auto laswp = [&](int k0, int nb, int c0, int c1, hipStream_t sx) {
+    if (c1 > c0)
+      hipLaunchKernelGGL(k_laswp<T>, dim3((c1 - c0 + 255) / 256, batch), dim3(256), 0, sx, A, ms, n, k0, nb, c0, c1,
+                         (const int*)ipiv);
+  };
+  auto factor_step = [&](int s0, hipStream_t sx) {
+    const int w = step_width(n, s0), wa = std::min(LU_NB, w), b1 = s0 + wa, e = s0 + w;
+    factor_block<T>(A, ms, n, s0, batch, ipiv, info, sx);
+    if (w > wa) {
+      laswp(s0, wa, b1, e, sx);
+      trsm_part<T>(A, ms, n, s0, wa, b1, e, batch, sx, nullptr);
+      gemm_part<T>(A, ms, n, s0, wa, b1, e, batch, sx);
+      factor_block<T>(A, ms, n, b1, batch, ipiv, info, sx);
+    }
+  };
+  factor_step(0, st);
+  int step = 0;
+  for (int s0 = 0; s0 < n; s0 += 2 * LU_NB, ++step) {
+    const int w = step_width(n, s0), wa = std::min(LU_NB, w), b1 = s0 + wa, c1 = s0 + w;
     if (c1 >= n) break;
-    hipLaunchKernelGGL(k_laswp<T>, dim3((n - c1 + 255) / 256, batch), dim3(256), 0, st, A, ms, n, k0, nb, c1, n,
-                       (const int*)ipiv);
-    trsm_part<T>(A, ms, n, k0, nb, n, batch, st, work);
-    const int c2 = std::min(n, c1 + LU_NB);
+    laswp(s0, wa, c1, n, st);
+    trsm_part<T>(A, ms, n, s0, wa, c1, n, batch, st, work);
+    const int* map = nullptr;
+    if (w > wa) {
+      laswp(b1, w - wa, c1, n, st);
+      hipLaunchKernelGGL(k_row_map, dim3(batch), dim3(256), 0, st, (const int*)ipiv, n, b1, w - wa, rmap);
+      map = rmap;
+      gemm_part<T>(A, ms, n, s0, wa, c1, n, batch, st, c1, map, wa);
+      trsm_part<T>(A, ms, n, b1, w - wa, c1, n, batch, st, work);
+    }
+    const int c2 = std::min(n, c1 + 2 * LU_NB);
     const bool t = tm && tm->gemm_begin && tm->gemm_end;
-    if (t) (void)hipEventRecord(tm->gemm_begin[k0 / LU_NB], st);
-    gemm_part<T>(A, ms, n, k0, nb, c1, c2, batch, st);
+    if (t) (void)hipEventRecord(tm->gemm_begin[step], st);
+    gemm_part<T>(A, ms, n, s0, w, c1, c2, batch, st, n, map, wa);
     if (la) {
       (void)hipEventRecord(la_ev[0], st);
       (void)hipStreamWaitEvent(st2, la_ev[0], 0);
-      factor_block<T>(A, ms, n, c1, batch, ipiv, info, st2);
+      factor_step(c1, st2);
       (void)hipEventRecord(la_ev[1], st2);
     }
     {
       // complex128: the rest in 8 column pieces.  Between two pieces the
-      // stream drains, and the next block's leaf panels waiting on the second
+      // stream drains, and the next step's leaf panels waiting on the second
       // stream get whole compute units (a panel workgroup needs one); the
       // FP64 LU is ~5% shorter.  Complex64 keeps one launch: there the gain
       // is ~1% and the update's measured rate would include the panels' share.
       const int pieces = sizeof(T) == 8 ? 8 : 1;
-      const int w = ((n - c2 + pieces - 1) / pieces + 63) / 64 * 64;
-      for (int cb = c2; cb < n; cb += w) gemm_part<T>(A, ms, n, k0, nb, cb, std::min(n, cb + w), batch, st);
+      const int wp = ((n - c2 + pieces - 1) / pieces + 63) / 64 * 64;
+      for (int cb = c2; cb < n; cb += wp)
+        gemm_part<T>(A, ms, n, s0, w, cb, std::min(n, cb + wp), batch, st, n, map, wa);
     }
-    if (t) (void)hipEventRecord(tm->gemm_end[k0 / LU_NB], st);
+    if (t) (void)hipEventRecord(tm->gemm_end[step], st);
     if (la)
       (void)hipStreamWaitEvent(st, la_ev[1], 0);
     else
-      factor_block<T>(A, ms, n, c1, batch, ipiv, info, st);
+      factor_step(c1, st);
   }
 }
 
@@ -899,9 +987,9 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
 }
 
 template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, zd*, hipStream_t, LuTimers*, hipStream_t,
-                                        hipEvent_t*);
+                                        hipEvent_t*, int*);
 template void lu_factor_batched<float>(zf*, long, int, int, int*, int*, zf*, hipStream_t, LuTimers*, hipStream_t,
-                                       hipEvent_t*);
+                                       hipEvent_t*, int*);
 template void lu_solve_batched<double, double>(const zd*, long, int, int, const int*, zd*, int,
                                                hipStream_t);
 template void lu_solve_batched<float, double>(const zf*, long, int, int, const int*, zd*, int,
