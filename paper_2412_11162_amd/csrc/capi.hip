@@ -254,7 +254,7 @@ void run_surrogate(pmlbie_ctx* c, const PairGeom* geom, const int2* dest, long c
 // Explicit pair list (host) -> raw modal values raw[q][s][n]: upload, classify
 // on the device into far / split / direct lists, run the three paths.
 void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts,
-                       const int* medium = nullptr, int Nm = 0, bool two_grids = false);
+                       const int* medium = nullptr, int Nm = 0, bool two_grids = false, int m_lo = 0);
 
 void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long long* counts) {
   const size_t tot = g.size();
@@ -266,9 +266,10 @@ void run_pair_list(pmlbie_ctx* c, const std::vector<PairGeom>& g, zd* raw, long 
 
 // The same with the pair geometry already in c->xgeom.  With medium (field
 // points, rows q = p * Nm + l), the far pairs get the kernels of their point's
-// medium only.
+// medium only.  m_lo: the lowest mode the caller reads (the direct rule may
+// leave the modes below it unwritten).
 void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, const int* medium, int Nm,
-                       bool two_grids) {
+                       bool two_grids, int m_lo) {
   if (tot == 0) return;
   c->lgeom.alloc(4 * tot > c->lgeom.n ? 4 * tot : c->lgeom.n);
   c->ldest.alloc(4 * tot > c->ldest.n ? 4 * tot : c->ldest.n);
@@ -301,7 +302,7 @@ void run_pair_list_dev(pmlbie_ctx* c, size_t tot, zd* raw, long long* counts, co
   if (c->ch1_L > 0)
     run_split(c, wd.geom, wd.dest, cnt[2], nullptr, 0, 0, nullptr, raw, false, c->ch1_L);
   else
-    launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, 0, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
+    launch_direct(wd.geom, wd.dest, 0, cnt[2], c->M, m_lo, c->k1, c->k2, c->glx.p, c->glw.p, nullptr, 0, 0,
                   nullptr, raw, kOmegaPiece, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -733,7 +734,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->cnt_aux = (long long)ageom.size();
     c->raw.alloc(std::max<size_t>(ageom.size(), 1) * 4 * (M + 1));
     long long dummy[3] = {0, 0, 0};
-    run_pair_list_dev(c, ageom.size(), c->raw.p, dummy, nullptr, 0, true);
+    run_pair_list_dev(c, ageom.size(), c->raw.p, dummy, nullptr, 0, true, m0);
     launch_near(c->jobs.p, (int)ajobs.size(), c->coef.p, c->raw.p, M, m0, c->A.p, n2, ms, c->stream);
     HIPCHK(hipGetLastError());
     c->stage_ms[4] = t_near.stop();

@@ -98,6 +98,9 @@ void launch_split_singular(const PairGeom* geom, long first, long count, int MQ,
 void launch_split(int nt, const PairGeom* geom, const int2* dest, long first, long count, int M,
                   int m0, int MQ, zd k1, zd k2, const zd* tw, const zd* zhat, const zd* phat,
                   zd* A, long n2, long mstride, const double* W, zd* raw, hipStream_t st, int chL = 0);
+// Graded direct rule, modes m0..M; with raw output (A null) the modes from m0
+// rounded down to 16 up to M are written, so a caller reading every mode
+// passes m0 = 0.
 void launch_direct(const PairGeom* geom, const int2* dest, long first, long count, int M, int m0,
                    zd k1, zd k2, const double* glx, const double* glw, zd* A, long n2,
                    long mstride, const double* W, zd* raw, double omega_piece, hipStream_t st);

@@ -767,6 +767,7 @@ __global__ __launch_bounds__(64) void k_direct(const PairGeom* __restrict__ geom
   __shared__ double cw[64][18];  // cos(j D) j = 0..16, then weight
   const int lane = threadIdx.x;
   const int ga = lane >> 4, gm = lane & 15;
+  const int mb = o.m0 & ~15;
   for (long t = blockIdx.x; t < count; t += gridDim.x) {
     const PairGeom g = geom[first + t];
     const int2 dst = dest[first + t];
@@ -823,8 +824,9 @@ __global__ __launch_bounds__(64) void k_direct(const PairGeom* __restrict__ geom
     }
     __syncthreads();
     const int nnodes = npieces * 16;
-    for (int pass = 0; pass * 16 * DIRECT_MPL <= M; ++pass) {
-      const int nbase = pass * 16 * DIRECT_MPL;
+    // passes of 144 modes from the first mode the caller keeps (rounded down
+    // to the recurrence stride), so a batch of at most 129 modes takes one
+    for (int nbase = mb; nbase <= M; nbase += 16 * DIRECT_MPL) {
       zd acc[DIRECT_MPL][4];
 #pragma unroll
       for (int r = 0; r < DIRECT_MPL; ++r)
@@ -869,7 +871,7 @@ __global__ __launch_bounds__(64) void k_direct(const PairGeom* __restrict__ geom
           const double c16 = cw[u][16];
           // cos(g D) and cos((g - 16) D) = cos((16 - g) D), then advance to nbase
           double cprev = cw[u][16 - gm], ccur = cw[u][gm];
-          for (int r = 0; r < pass * DIRECT_MPL; ++r) {
+          for (int r = 0; r < nbase / 16; ++r) {
             double cn = 2.0 * c16 * ccur - cprev;
             cprev = ccur;
             ccur = cn;
@@ -929,6 +931,7 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
   // weighted by the 16 Lagrange coefficients of its auxiliary point
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int sq = e / (M + 1), n = e % (M + 1);
+    if (n < o.m0) continue;  // raw values below the batch need not be there
     zd acc[16];
 #pragma unroll
     for (int l = 0; l < 16; ++l) acc[l] = zd{0.0, 0.0};
@@ -938,7 +941,6 @@ __global__ __launch_bounds__(256) void k_near(const NearJob* __restrict__ jobs, 
 #pragma unroll
       for (int l = 0; l < 16; ++l) acc[l] = acc[l] + c[l] * r;
     }
-    if (n < o.m0) continue;
     const long i = J.target;
     zd* An = o.A + (long)(n - o.m0) * o.mstride;
     // K entries carry the identity term, S entries the minus sign
