@@ -596,61 +596,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 //   panel's row interchanges to b and solves the unit lower diagonal block;
 //   (2) many workgroups update the rows below, one wavefront per row.
 //   backward: (3) the upper diagonal block, (4) the rows above.
-// Columns [j0, j0 + jn) of the diagonal block, rows [r_lo, r_hi), into Lb.
+// Columns [j0, j0 + jn) of the diagonal block, rows [r_lo, r_hi), into Lb,
+// by 256 threads: a thread issues all of its loads before its first LDS
+// store, so their latencies overlap instead of adding up.
 template <typename T>
 __device__ __forceinline__ void stage_cols(const cx<T>* __restrict__ a, int n, int k0, int r_lo, int r_hi,
                                            int j0, int jn, cx<T> (*Lb)[33]) {
-  for (int e = r_lo * 32 + threadIdx.x; e < r_hi * 32; e += blockDim.x) {
+  constexpr int PER = LU_NB * 32 / 256;
+  cx<T> v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = r_lo * 32 + (int)threadIdx.x + 256 * i;
     const int r = e >> 5, jj = e & 31;
-    Lb[r][jj] = jj < jn ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
+    v[i] = (e < r_hi * 32 && jj < jn) ? a[(long)(k0 + r) * n + k0 + j0 + jj] : cx<T>{T(0), T(0)};
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = r_lo * 32 + (int)threadIdx.x + 256 * i;
+    if (e < r_hi * 32) Lb[e >> 5][e & 31] = v[i];
   }
 }
 
 // Triangle of a 32-column block of the diagonal block, solved by one
 // wavefront without barriers: lane l holds the entries (row j0 + (l & 31),
-// rhs 2 t + (l >> 5)) in slot t, so the entry (row j0 + jj, same rhs) of
-// slot t sits in lane (l & 32) + jj, slot t.  Lower: unit diagonal, forward;
-// upper: divided by the diagonal, backward.
-template <typename T, typename TB, bool UPPER>
+// rhs 2 t + (l >> 5)) in slot t < NT (NT >= (nrhs + 1) / 2, slots beyond the
+// right-hand sides hold zeros), so the entry (row j0 + jj, same rhs) of slot
+// t sits in lane (l & 32) + jj, slot t.  Lower: unit diagonal, forward;
+// upper: divided by the diagonal, backward.  A step's NT broadcasts are
+// issued together, then the NT updates.
+template <typename T, typename TB, bool UPPER, int NT>
 __device__ __forceinline__ void tri_wave(cx<T> (*Lb)[33], cx<TB> (*yb)[LU_MAX_RHS], int j0, int jn,
                                          int nrhs) {
-  constexpr int NT = LU_MAX_RHS / 2;
   const int lane = threadIdx.x & 63, rr = lane & 31, hs = lane >> 5;
-  const int nt = (nrhs + 1) >> 1;
   cx<TB> y[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int s2 = 2 * t + hs;
-    y[t] = (t < nt && rr < jn && s2 < nrhs) ? yb[j0 + rr][s2] : cx<TB>{TB(0), TB(0)};
+    y[t] = (rr < jn && s2 < nrhs) ? yb[j0 + rr][s2] : cx<TB>{TB(0), TB(0)};
+  }
+  // upper: each lane's own row's diagonal inverse, once (y / d is y * inv(d))
+  cx<TB> dinv{TB(0), TB(0)};
+  if (UPPER && rr < jn) {
+    const cx<T> d = Lb[j0 + rr][rr];
+    dinv = inv(cx<TB>{(TB)d.re, (TB)d.im});
   }
   for (int q = 0; q < jn; ++q) {
     const int jj = UPPER ? jn - 1 - q : q;
     const cx<T> lj = Lb[j0 + rr][jj];
-    if (UPPER) {
-      const cx<T> d = Lb[j0 + jj][jj];
-      const cx<TB> dd{(TB)d.re, (TB)d.im};
+    if (UPPER && rr == jj) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        if (t < nt && rr == jj) y[t] = y[t] / dd;
+      for (int t = 0; t < NT; ++t) y[t] = y[t] * dinv;
     }
     const int src = (lane & 32) + jj;
     const bool below = UPPER ? rr < jj : (rr > jj && rr < jn);
+    cx<TB> yj[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t < nt) {
-        const cx<TB> yj{__shfl(y[t].re, src), __shfl(y[t].im, src)};
-        if (below) y[t] = y[t] - cx<TB>{(TB)lj.re, (TB)lj.im} * yj;
-      }
+    for (int t = 0; t < NT; ++t) yj[t] = cx<TB>{__shfl(y[t].re, src), __shfl(y[t].im, src)};
+    if (below) {
+      const cx<TB> l{(TB)lj.re, (TB)lj.im};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) y[t] = y[t] - l * yj[t];
     }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int s2 = 2 * t + hs;
-    if (t < nt && rr < jn && s2 < nrhs) yb[j0 + rr][s2] = y[t];
+    if (rr < jn && s2 < nrhs) yb[j0 + rr][s2] = y[t];
   }
 }
 
-template <typename T, typename TB>
+template <typename T, typename TB, int NT>
 __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A, long ms, int n,
                                                     int k0, int nb, const int* __restrict__ ipiv,
                                                     cx<TB>* __restrict__ B, int nrhs, int upper) {
@@ -661,34 +676,78 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
   constexpr int JB = 32;
   __shared__ cx<TB> yb[LU_NB][LU_MAX_RHS];
   __shared__ cx<T> Lb[LU_NB][JB + 1];  // a block of JB columns of the diagonal block
+  __shared__ cx<TB> ext[LU_NB][LU_MAX_RHS];  // pivot rows below the panel
+  __shared__ int pv[LU_NB], slot[LU_NB];
   static_assert(JB == 32, "tri_wave holds 32 rows per half wavefront");
-  for (int e = tid; e < nb * nrhs; e += 256) yb[e % nb][e / nb] = b[(long)(e / nb) * n + k0 + e % nb];
+  constexpr int PERB = LU_NB * LU_MAX_RHS / 256;
+  {
+    cx<TB> v[PERB];
+#pragma unroll
+    for (int i = 0; i < PERB; ++i) {
+      const int e = tid + 256 * i;
+      v[i] = e < nb * nrhs ? b[(long)(e / nb) * n + k0 + e % nb] : cx<TB>{TB(0), TB(0)};
+    }
+#pragma unroll
+    for (int i = 0; i < PERB; ++i) {
+      const int e = tid + 256 * i;
+      if (e < nb * nrhs) yb[e % nb][e / nb] = v[i];
+    }
+  }
   __syncthreads();
   if (!upper) {
-    // the panel's row interchanges, in order; rows inside the panel are
-    // exchanged in LDS, a pivot row below the panel in memory
-    if (tid < nrhs) {
-      cx<TB>* v = b + (long)tid * n;
-      for (int j = 0; j < nb; ++j) {
-        const int p = piv[k0 + j] - k0;
-        if (p == j) continue;
-        const cx<TB> t0 = yb[j][tid];
-        if (p < nb) {
-          yb[j][tid] = yb[p][tid];
-          yb[p][tid] = t0;
-        } else {
-          yb[j][tid] = v[k0 + p];
-          v[k0 + p] = t0;
-        }
+    // the panel's row interchanges, in order.  A pivot row p below the panel
+    // is read once into ext[slot] (slot: the first interchange naming p),
+    // the interchanges then run in LDS, and the rows below are written back.
+    if (tid < nb) pv[tid] = piv[k0 + tid] - k0;
+    __syncthreads();
+    if (tid < nb) {
+      const int p = pv[tid];
+      int sl = tid;
+      if (p >= nb)
+        for (int i = 0; i < tid; ++i)
+          if (pv[i] == p) {
+            sl = i;
+            break;
+          }
+      slot[tid] = sl;
+    }
+    __syncthreads();
+    {
+      cx<TB> v[PERB];
+#pragma unroll
+      for (int i = 0; i < PERB; ++i) {
+        const int e = tid + 256 * i, j = e % nb;
+        v[i] = (e < nb * nrhs && pv[j] >= nb && slot[j] == j) ? b[(long)(e / nb) * n + k0 + pv[j]]
+                                                               : cx<TB>{TB(0), TB(0)};
+      }
+#pragma unroll
+      for (int i = 0; i < PERB; ++i) {
+        const int e = tid + 256 * i;
+        if (e < nb * nrhs) ext[e % nb][e / nb] = v[i];
       }
     }
     __syncthreads();
+    if (tid < nrhs) {
+      for (int j = 0; j < nb; ++j) {
+        const int p = pv[j];
+        if (p == j) continue;
+        cx<TB>& o = p < nb ? yb[p][tid] : ext[slot[j]][tid];
+        const cx<TB> t0 = yb[j][tid];
+        yb[j][tid] = o;
+        o = t0;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * nrhs; e += 256) {
+      const int j = e % nb;
+      if (pv[j] >= nb && slot[j] == j) b[(long)(e / nb) * n + k0 + pv[j]] = ext[j][e / nb];
+    }
     for (int j0 = 0; j0 < nb; j0 += JB) {
       const int jn = min(JB, nb - j0);
       stage_cols(a, n, k0, j0, nb, j0, jn, Lb);
       __syncthreads();
       // the triangle of the block: one wavefront, register-held entries
-      if (tid < 64) tri_wave<T, TB, false>(Lb, yb, j0, jn, nrhs);
+      if (tid < 64) tri_wave<T, TB, false, NT>(Lb, yb, j0, jn, nrhs);
       __syncthreads();
       // rows below the block inside the panel: a rank-jn update
       for (int e = tid; e < (nb - j0 - jn) * nrhs; e += 256) {
@@ -707,7 +766,7 @@ __global__ __launch_bounds__(256) void k_solve_diag(const cx<T>* __restrict__ A,
       const int j0 = max(0, j1 - JB), jn = j1 - j0;
       stage_cols(a, n, k0, 0, j1, j0, jn, Lb);
       __syncthreads();
-      if (tid < 64) tri_wave<T, TB, true>(Lb, yb, j0, jn, nrhs);
+      if (tid < 64) tri_wave<T, TB, true, NT>(Lb, yb, j0, jn, nrhs);
       __syncthreads();
       // rows above the block: a rank-jn update
       for (int e = tid; e < j0 * nrhs; e += 256) {
@@ -967,10 +1026,14 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
                       int nrhs, hipStream_t st) {
   // off-diagonal block updates: the matrix-core form for 9 to 16 vectors
   auto upd = nrhs > 8 ? &k_solve_update<T, TB, true> : &k_solve_update<T, TB, false>;
+  // diagonal blocks: (nrhs + 1) / 2 slots a lane, rounded up to 1, 2, 4 or 8
+  auto diag = nrhs > 8   ? &k_solve_diag<T, TB, 8>
+              : nrhs > 4 ? &k_solve_diag<T, TB, 4>
+              : nrhs > 2 ? &k_solve_diag<T, TB, 2>
+                         : &k_solve_diag<T, TB, 1>;
   for (int k0 = 0; k0 < n; k0 += LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
-    hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
-                       B, nrhs, 0);
+    hipLaunchKernelGGL(diag, dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv, B, nrhs, 0);
     const int r0 = k0 + nb, r1 = n;
     if (r1 > r0)
       hipLaunchKernelGGL(upd, dim3((r1 - r0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0,
@@ -978,8 +1041,7 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
   }
   for (int k0 = ((n - 1) / LU_NB) * LU_NB; k0 >= 0; k0 -= LU_NB) {
     const int nb = std::min(LU_NB, n - k0);
-    hipLaunchKernelGGL((k_solve_diag<T, TB>), dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv,
-                       B, nrhs, 1);
+    hipLaunchKernelGGL(diag, dim3(batch), dim3(256), 0, st, A, ms, n, k0, nb, ipiv, B, nrhs, 1);
     if (k0 > 0)
       hipLaunchKernelGGL(upd, dim3((k0 + R16_ROWS - 1) / R16_ROWS, batch), dim3(256), 0, st,
                          A, ms, n, k0, nb, B, nrhs, 0, k0);
