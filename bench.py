@@ -30,14 +30,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+def update_source_digest() -> str:
+    """Digest of the trailing-update kernel and of the LU schedule that splits
+    its launches (both change the HBM bytes per step)."""
+    src = open(os.path.join(ROOT, "paper_2412_11162_amd", "csrc", "lu.hip")).read()
+    parts = []
+    for head in ("void k_gemm_update(", "void lu_factor_batched("):
+        a = src.index(head)
+        parts.append(src[a:src.index("\n}\n", a)])
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
+
+
 def gemm_traffic_record(profile: str, kernel: str):
     """HBM bytes per launch of the trailing-update kernel from a committed
     rocprofv3 counter summary (profiles/<profile>.md), or None when the kernel
-    source has changed since the counters were taken (the record carries a
-    digest of it)."""
-    src = open(os.path.join(ROOT, "paper_2412_11162_amd", "csrc", "lu.hip")).read()
-    a = src.index("void k_gemm_update(")
-    digest = hashlib.sha256(src[a:src.index("\n}\n", a)].encode()).hexdigest()[:16]
+    or the LU schedule has changed since the counters were taken (the record
+    carries a digest of both)."""
+    digest = update_source_digest()
     path = os.path.join(ROOT, "profiles", profile + ".md")
     if not os.path.exists(path):
         return None

@@ -1003,12 +1003,12 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
       (void)hipEventRecord(la_ev[1], st2);
     }
     {
-      // complex128: the rest in 8 column pieces.  Between two pieces the
-      // stream drains, and the next step's leaf panels waiting on the second
-      // stream get whole compute units (a panel workgroup needs one); the
-      // FP64 LU is ~5% shorter.  Complex64 keeps one launch: there the gain
-      // is ~1% and the update's measured rate would include the panels' share.
-      const int pieces = sizeof(T) == 8 ? 8 : 1;
+      // the rest in 8 column pieces.  Between two pieces the stream drains,
+      // and the next step's leaf panels waiting on the second stream get
+      // whole compute units (a panel workgroup needs one): the LU is ~5%
+      // (complex128) and ~4% (complex64) shorter, while the update's measured
+      // interval includes the panels' share of the machine.
+      const int pieces = 8;
       const int wp = ((n - c2 + pieces - 1) / pieces + 63) / 64 * 64;
       for (int cb = c2; cb < n; cb += wp)
         gemm_part<T>(A, ms, n, s0, w, cb, std::min(n, cb + wp), batch, st, n, map, wa);
