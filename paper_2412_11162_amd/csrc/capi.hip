@@ -96,7 +96,7 @@ struct pmlbie_ctx {
   DBuf<double> rsq, rnorm;
   DBuf<int> ipiv, info;
   DBuf<zd> luw;  // inverses of the LU diagonal blocks
-  DBuf<int> lumap;  // row map of an LU step's second block
+  DBuf<int> lumap;  // row maps of an LU step's second block, then (mixed) of the first step
   DBuf<PairGeom> lgeom;
   DBuf<int2> ldest;
   DBuf<unsigned> lcount;
@@ -625,7 +625,7 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     c->A.alloc((size_t)nm * ms);
     c->ipiv.alloc((size_t)nm * n2);
     c->luw.alloc((size_t)nm * LU_NB * LU_NB);
-    c->lumap.alloc((size_t)nm * n2);
+    c->lumap.alloc(2 * (size_t)nm * n2);
     c->info.alloc(nm);
     HIPCHK(hipMemsetAsync(c->info.p, 0, nm * sizeof(int), c->stream));
     // work lists of the grid (split, direct, far and split on the full grid
@@ -784,11 +784,12 @@ int pmlbie_build_modal_operators_range(pmlbie_ctx* c, int n_theta, int m_min, in
     for (hipEvent_t& e : c->lu_ev)
       if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (mixed) {
+      // the complex64 copy is filled from the FP64 operators inside the LU's
+      // first step (its second row map in lumap's second half)
       c->A32.alloc((size_t)nm * ms);
-      launch_to_c64(c->A.p, c->A32.p, (long)nm * ms, c->stream);
-      HIPCHK(hipGetLastError());
       lu_factor_batched<float>(c->A32.p, ms, (int)n2, nm, c->ipiv.p, c->info.p,
-                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm, c->lu_stream, c->lu_ev, c->lumap.p);
+                               reinterpret_cast<zf*>(c->luw.p), c->stream, &tm, c->lu_stream, c->lu_ev, c->lumap.p,
+                               c->A.p, c->lumap.p + (size_t)nm * n2);
     } else {
       lu_factor_batched<double>(c->A.p, ms, (int)n2, nm, c->ipiv.p, c->info.p, c->luw.p,
                                 c->stream, &tm, c->lu_stream, c->lu_ev, c->lumap.p);

@@ -28,9 +28,16 @@ struct LuTimers {
 // With st2 (a second stream) and la_ev (two events), the next step's columns
 // are factored on st2 beside the rest of each trailing update; the work is
 // complete when st is (st waits for st2 before every step).
+// With src (FP64 matrices of the same shape, left unchanged), A need not be
+// filled on entry: for complex64 it is filled from src rounded to T during
+// the first step (its columns; its rows in the order of its interchanges;
+// the rest by its trailing update, which reads C from src), so no separate
+// pass demotes the matrices (complex128 copies src first).  smap: batch * n
+// ints (that row order), used only with src.
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
-                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev, int* rmap);
+                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev, int* rmap,
+                       const zd* src = nullptr, int* smap = nullptr);
 
 // The timed trailing updates of lu_factor_batched: their number, and their
 // algorithmic flops over `batch` matrices (8 real flops per complex

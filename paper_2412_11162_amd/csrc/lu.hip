@@ -471,7 +471,8 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4))) void k_gemm_update(cx<T>* __restrict__ A, long ms, int n,
                                                      int k0, int nb, int cbeg, int cend, int tx, int ty,
                                                      int batch, int rend, const int* __restrict__ rmap,
-                                                     int mapk) {
+                                                     int mapk, const cx<double>* __restrict__ csrc,
+                                                     const int* __restrict__ cmap) {
   typedef typename mfma_t<T>::acc acc_t;
   const long tiles = (long)tx * ty * batch;
   const long per_xcd = (tiles + 7) / 8;
@@ -497,7 +498,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = (wid & 1) * 32, wc = (wid >> 1) * 32;
   // the accumulators start from C (loaded before the K loop, so its latency
-  // overlaps the first chunk) and the products are subtracted
+  // overlaps the first chunk) and the products are subtracted; with csrc, C
+  // is read from the FP64 matrices, row r at row cmap[r], and rounded to T
+  // (complex64 only: the complex128 kernel keeps its registers)
   acc_t v1[2][2], v2[2][2], v3[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -507,7 +510,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       for (int j = 0; j < 4; ++j) {
         const int gr = r0 + wr + 16 * x + mfma_t<T>::rowof(lane, j);
         const int gc = c0 + wc + 16 * y + (lane & 15);
-        const cx<T> v = (gc < cend && gr < rend) ? a[(long)gr * n + gc] : cx<T>{T(0), T(0)};
+        cx<T> v{T(0), T(0)};
+        if (gc < cend && gr < rend) {
+          if constexpr (sizeof(T) == 4) {
+            if (csrc) {
+              const cx<double> w = csrc[(long)bz * ms + (long)cmap[(long)bz * n + gr] * n + gc];
+              v = cx<T>{(T)w.re, (T)w.im};
+            } else {
+              v = a[(long)gr * n + gc];
+            }
+          } else {
+            v = a[(long)gr * n + gc];
+          }
+        }
         v1[x][y][j] = T(0);
         v2[x][y][j] = v.re;
         v3[x][y][j] = v.im - v.re;
@@ -879,7 +894,8 @@ static void trsm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int ce
 // read at rmap[row] (per matrix, n entries).
 template <typename T>
 static void gemm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int cend, int batch, hipStream_t st,
-                      int rend = -1, const int* rmap = nullptr, int mapk = 0) {
+                      int rend = -1, const int* rmap = nullptr, int mapk = 0, const cx<double>* csrc = nullptr,
+                      const int* cmap = nullptr) {
   if (rend < 0) rend = n;
   const int cols = cend - cbeg, rows = rend - k0 - nb;
   if (cols <= 0 || rows <= 0) return;
@@ -887,7 +903,25 @@ static void gemm_part(cx<T>* A, long ms, int n, int k0, int nb, int cbeg, int ce
   const long tiles = (long)tx * ty * batch;
   const long grid = ((tiles + 7) / 8) * 8;
   hipLaunchKernelGGL(k_gemm_update<T>, dim3((unsigned)grid), dim3(256), 0, st, A, ms, n, k0, nb, cbeg, cend,
-                     tx, ty, batch, rend, rmap, mapk);
+                     tx, ty, batch, rend, rmap, mapk, csrc, cmap);
+}
+
+// D = S rounded to T over rows [r0, r1) x columns [c0, c1) of every matrix
+// (grid y = matrix); with rmap, row r of D is read from row rmap[r] of S
+// (per matrix, n entries).
+template <typename T>
+__global__ __launch_bounds__(256) void k_demote(const cx<double>* __restrict__ S, cx<T>* __restrict__ D, long ms,
+                                                int n, int r0, int r1, int c0, int c1,
+                                                const int* __restrict__ rmap) {
+  const long cw = c1 - c0, cnt = (long)(r1 - r0) * cw;
+  const cx<double>* s = S + (long)blockIdx.y * ms;
+  cx<T>* d = D + (long)blockIdx.y * ms;
+  const int* mp = rmap ? rmap + (long)blockIdx.y * n : nullptr;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (long)gridDim.x * 256) {
+    const int r = r0 + (int)(e / cw), c = c0 + (int)(e % cw);
+    const cx<double> v = s[(long)(mp ? mp[r] : r) * n + c];
+    d[(long)r * n + c] = cx<T>{(T)v.re, (T)v.im};
+  }
 }
 
 // The row order that the interchanges of block [b1, b1 + nb1) leave, as
@@ -960,8 +994,15 @@ double lu_update_flops(int n, int batch) {
 
 template <typename T>
 void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info, cx<T>* work,
-                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev, int* rmap) {
+                       hipStream_t st, LuTimers* tm, hipStream_t st2, hipEvent_t* la_ev, int* rmap,
+                       const cx<double>* src, int* smap) {
   const bool la = st2 != nullptr && la_ev != nullptr;
+  auto demote = [&](int r0, int r1, int c0, int c1, const int* map) {
+    const long cnt = (long)(r1 - r0) * (c1 - c0);
+    if (cnt <= 0) return;
+    const unsigned gx = (unsigned)std::min<long>((cnt + 255) / 256, 64);
+    hipLaunchKernelGGL(k_demote<T>, dim3(gx, batch), dim3(256), 0, st, src, A, ms, n, r0, r1, c0, c1, map);
+  };
   auto laswp = [&](int k0, int nb, int c0, int c1, hipStream_t sx) {
     if (c1 > c0)
       hipLaunchKernelGGL(k_laswp<T>, dim3((c1 - c0 + 255) / 256, batch), dim3(256), 0, sx, A, ms, n, k0, nb, c0, c1,
@@ -977,16 +1018,31 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
       factor_block<T>(A, ms, n, b1, batch, ipiv, info, sx);
     }
   };
+  // with src, A is filled from it: complex64 starts with the first step's
+  // columns and takes the rest inside the first step; complex128 (whose
+  // update kernel does not read src) copies all of it first
+  const bool fused = src != nullptr && sizeof(T) == 4;
+  if (src) demote(0, n, 0, fused ? step_width(n, 0) : n, nullptr);
   factor_step(0, st);
   int step = 0;
   for (int s0 = 0; s0 < n; s0 += 2 * LU_NB, ++step) {
     const int w = step_width(n, s0), wa = std::min(LU_NB, w), b1 = s0 + wa, c1 = s0 + w;
     if (c1 >= n) break;
-    laswp(s0, wa, c1, n, st);
+    // with src, the first step takes the rows [0, w) of the columns right of
+    // it from src in the row order its interchanges leave (smap: the step's
+    // w interchanges applied in order to the identity) instead of applying
+    // the interchanges; its trailing update reads C from src in that order
+    const bool from_src = fused && s0 == 0;
+    if (from_src) {
+      hipLaunchKernelGGL(k_row_map, dim3(batch), dim3(256), 0, st, (const int*)ipiv, n, 0, w, smap);
+      demote(0, w, c1, n, smap);
+    } else {
+      laswp(s0, wa, c1, n, st);
+    }
     trsm_part<T>(A, ms, n, s0, wa, c1, n, batch, st, work);
     const int* map = nullptr;
     if (w > wa) {
-      laswp(b1, w - wa, c1, n, st);
+      if (!from_src) laswp(b1, w - wa, c1, n, st);
       hipLaunchKernelGGL(k_row_map, dim3(batch), dim3(256), 0, st, (const int*)ipiv, n, b1, w - wa, rmap);
       map = rmap;
       gemm_part<T>(A, ms, n, s0, wa, c1, n, batch, st, c1, map, wa);
@@ -995,7 +1051,9 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
     const int c2 = std::min(n, c1 + 2 * LU_NB);
     const bool t = tm && tm->gemm_begin && tm->gemm_end;
     if (t) (void)hipEventRecord(tm->gemm_begin[step], st);
-    gemm_part<T>(A, ms, n, s0, w, c1, c2, batch, st, n, map, wa);
+    const cx<double>* csrc = from_src ? src : nullptr;
+    const int* cmap = from_src ? smap : nullptr;
+    gemm_part<T>(A, ms, n, s0, w, c1, c2, batch, st, n, map, wa, csrc, cmap);
     if (la) {
       (void)hipEventRecord(la_ev[0], st);
       (void)hipStreamWaitEvent(st2, la_ev[0], 0);
@@ -1011,7 +1069,7 @@ void lu_factor_batched(cx<T>* A, long ms, int n, int batch, int* ipiv, int* info
       const int pieces = 8;
       const int wp = ((n - c2 + pieces - 1) / pieces + 63) / 64 * 64;
       for (int cb = c2; cb < n; cb += wp)
-        gemm_part<T>(A, ms, n, s0, w, cb, std::min(n, cb + wp), batch, st, n, map, wa);
+        gemm_part<T>(A, ms, n, s0, w, cb, std::min(n, cb + wp), batch, st, n, map, wa, csrc, cmap);
     }
     if (t) (void)hipEventRecord(tm->gemm_end[step], st);
     if (la)
@@ -1049,9 +1107,9 @@ void lu_solve_batched(const cx<T>* A, long ms, int n, int batch, const int* ipiv
 }
 
 template void lu_factor_batched<double>(zd*, long, int, int, int*, int*, zd*, hipStream_t, LuTimers*, hipStream_t,
-                                        hipEvent_t*, int*);
+                                        hipEvent_t*, int*, const zd*, int*);
 template void lu_factor_batched<float>(zf*, long, int, int, int*, int*, zf*, hipStream_t, LuTimers*, hipStream_t,
-                                       hipEvent_t*, int*);
+                                       hipEvent_t*, int*, const zd*, int*);
 template void lu_solve_batched<double, double>(const zd*, long, int, int, const int*, zd*, int,
                                                hipStream_t);
 template void lu_solve_batched<float, double>(const zf*, long, int, int, const int*, zd*, int,

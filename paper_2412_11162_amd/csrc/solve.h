@@ -17,7 +17,6 @@ void launch_lower_rhs(const zd* Alow, long lstride, long rstride, int N, int mod
 void launch_deinterleave(const zd* A, long n2, zd* out, hipStream_t st);
 void launch_outputs(const zd* x, const zd* b1, const zd* b2, int N, int M, int nrhs, zd* u1, zd* p1,
                     zd* u2, zd* p2, hipStream_t st);
-void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st);
 void launch_zero_column(zd* A, long n, int col, hipStream_t st);
 void launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd* x, const zd* rhs,

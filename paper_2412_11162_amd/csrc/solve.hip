@@ -152,14 +152,6 @@ __global__ __launch_bounds__(256) void k_field(const zd* __restrict__ raw, const
   if (tid < nrhs) out[(long)tid * ldo + p] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
 }
 
-// FP64 -> FP32 copy of the operators (complex128 -> complex64).
-__global__ void k_to_c64(const zd* __restrict__ src, zf* __restrict__ dst, long count) {
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x) {
-    const zd v = src[e];
-    dst[e] = zf{(float)v.re, (float)v.im};
-  }
-}
-
 // Residual of the FP64 systems: r = rhs - A x for all modes and right-hand
 // sides (A row-major n x n per mode), 64 rows per workgroup with every
 // right-hand side at once (rows16.h: A read once, lane per row); rs2 receives
@@ -236,9 +228,6 @@ void launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
 }
 void launch_zero_column(zd* A, long n, int col, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_column, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, n, col);
-}
-void launch_to_c64(const zd* src, zf* dst, long count, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_c64, dim3(256 * 32), dim3(256), 0, st, src, dst, count);
 }
 void launch_residual(const zd* A, long ms, int n, int modes, int nrhs, const zd* x, const zd* rhs,
                      zd* r, double* rs2, hipStream_t st) {
