@@ -143,6 +143,35 @@ def test_tiny_multiple_incidences_point_and_plane(tiny_ref):
         assert np.max(errs) <= BOUNDARY_TOL, (inc, errs)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nrhs", [5, 8])
+def test_tiny_five_to_eight_right_hand_sides(tiny_ref, nrhs, precision):
+    """Five to eight right-hand sides in one solve (each lane of a diagonal
+    block's triangle then holds four of them): every one against the
+    oracle's solve and against the same source solved alone."""
+    import oracle
+    from paper_2412_11162_amd._binding import PMLBIE_FP64, PMLBIE_MIXED
+    wl, g, A, _ = tiny_ref
+    modes = list(range(wl.m_max + 1))
+    pool = [("point", 0.3, 1.0), ("plane", 0.4), ("point", 0.8, 0.7), ("plane", 1.2),
+            ("point", 1.6, 1.3), ("plane", 0.9), ("point", 0.5, 1.8), ("plane", 0.2)]
+    incs = pool[:nrhs]
+    s = _solver(wl, precision=PMLBIE_FP64 if precision == "fp64" else PMLBIE_MIXED)
+    out = s.solve_modes(incs)
+    for r, inc in enumerate(incs):
+        if inc[0] == "plane":
+            b1, b2 = oracle.rhs_plane_wave(g, modes, inc[1])
+        else:
+            b1, b2 = oracle.rhs_point_source(g, modes, inc[1], inc[2])
+        ref = oracle.solve(g, modes, b1, b2, A=A)[:4]
+        got = [o[:, r, :].cpu().numpy() for o in out]
+        errs = _boundary_err(got, ref)
+        assert np.max(errs) <= (BOUNDARY_TOL if precision == "fp64" else 1e-6), (inc, errs)
+        alone = [o[:, 0, :].cpu().numpy() for o in s.solve_modes([inc])]
+        errs = _boundary_err(got, alone)
+        assert np.max(errs) <= (1e-12 if precision == "fp64" else 1e-8), (inc, errs)
+
+
 # ------------------------------------------------- small workload (cfg of the paper's small case)
 
 def test_small_boundary_data_against_stored_oracle():
