@@ -172,6 +172,22 @@ def test_tiny_five_to_eight_right_hand_sides(tiny_ref, nrhs, precision):
         assert np.max(errs) <= (1e-12 if precision == "fp64" else 1e-8), (inc, errs)
 
 
+@pytest.mark.parametrize("nps", [48, 80])
+def test_mixed_ragged_lu_steps_against_fp64(nps):
+    """Mixed precision at 384 and 640 unknowns per mode (the LU's steps of
+    256 columns end in a ragged one; the complex64 copy is filled inside the
+    first step): the boundary data against the FP64 build's."""
+    from paper_2412_11162_amd._binding import PMLBIE_FP64, PMLBIE_MIXED
+    wl = workloads.tiny().with_(nodes_per_segment=nps)
+    inc = [("point", 0.3, 1.0), ("plane", 0.7)]
+    ref = [o.cpu().numpy() for o in _solver(wl, precision=PMLBIE_FP64).solve_modes(inc)]
+    got = [o.cpu().numpy() for o in _solver(wl, precision=PMLBIE_MIXED).solve_modes(inc)]
+    assert ref[0].shape[2] == 4 * nps
+    for r in range(len(inc)):
+        errs = _boundary_err([g[:, r, :] for g in got], [x[:, r, :] for x in ref])
+        assert np.max(errs) <= 1e-8, (nps, inc[r], errs)
+
+
 # ------------------------------------------------- small workload (cfg of the paper's small case)
 
 def test_small_boundary_data_against_stored_oracle():
