@@ -270,8 +270,9 @@ int pmlbie_get_operator(pmlbie_ctx* ctx, int mode, void* d_out);
  * all LU trailing updates (algorithmic: 8 per complex multiply-add; the
  * matrix cores execute 6 of them, the complex product being formed from
  * three real ones), [3] number of LU steps with a trailing update (stage [6]
- * sums, per step, the interval of its two launches: the next block's columns
- * and the rest),
+ * sums, per step, the interval of its launches: the next step's columns, then
+ * the rest in column pieces, between which the next step's factorisation
+ * runs),
  * [4] far pairs offered to the surrogate, [5] pairs whose surrogate modes
  * were accepted, [6] far pairs transformed on the full angle grid (the others
  * on the shortest grid that holds modes 0..m_max, when that is shorter). */
